@@ -1,0 +1,275 @@
+"""Pins of the CPU reference against facts that do not depend on it.
+
+* Slater-Condon elements and phases against explicit second-quantised operator
+  application on full CI spaces (oracle.dense);
+* the screened PT2 energy against dense linear algebra on the same spaces;
+* limits stated in the paper: eps2 = 0 keeps exactly the non-zero elements
+  (definition of P, section II), V = full CI gives E2 = 0, eps2^d = eps2 makes
+  the stochastic part vanish (section II.B);
+* the stochastic estimator's exact multinomial expectation equals the
+  deterministic sum (stochastic PT2 equation);
+* gradients: Euler's identity for a degree-2 homogeneous function, dense
+  linear algebra, and binary128 finite differences;
+* closed-form excitation counts and the paper's Cr2 Hilbert-space size.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dense, ref
+from synth import generator as G
+from tests import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _space(n, na, nb, seed):
+    x = G.make_small(n, na, nb, 2, 1, seed)
+    dets, index, H = dense.hamiltonian(n, na, nb, x.h1, x.eri)
+    W = np.array([dense.to_words(d, n) for d in dets], dtype=np.uint64)
+    return x, dets, index, H, W
+
+
+@pytest.fixture(scope="module")
+def space_227():
+    return _space(7, 3, 2, 11)
+
+
+@pytest.fixture(scope="module")
+def space_226():
+    return _space(6, 2, 2, 12)
+
+
+@pytest.mark.parametrize("fix", ["space_226", "space_227"])
+def test_slater_condon_matches_second_quantisation(fix, request):
+    x, dets, index, H, W = request.getfixturevalue(fix)
+    n, na, nb = x.wl.n_orb, x.wl.n_alpha, x.wl.n_beta
+    Ho = np.array([[ref.hij(n, na, nb, x.h1, x.eri, W[a], W[i]) for i in range(len(W))]
+                   for a in range(len(W))])
+    assert np.abs(Ho - H).max() < 1e-12
+    # Hermitian bit for bit (8-fold symmetric integrals, mirrored evaluation order)
+    assert np.array_equal(Ho, Ho.T)
+    # more than double excitations vanish exactly
+    for a, i in itertools.product(range(0, len(W), 7), range(0, len(W), 5)):
+        diff = sum(bin(int(W[a][k]) ^ int(W[i][k])).count("1") for k in range(4))
+        if diff > 4:
+            assert Ho[a, i] == 0.0 and abs(H[a, i]) < 1e-15
+
+
+def test_diagonal_matches_second_quantisation(space_227):
+    x, dets, index, H, W = space_227
+    d = np.array([ref.diag(7, 3, 2, x.h1, x.eri, w) for w in W])
+    assert np.abs(d - np.diag(H)).max() < 1e-12
+
+
+def _random_v(rng, nfci, nv):
+    return np.sort(rng.choice(nfci, size=nv, replace=False))
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-4, 3e-3])
+def test_e2_matches_dense_linear_algebra(space_227, eps2):
+    x, dets, index, H, W = space_227
+    rng = np.random.default_rng(5)
+    v = _random_v(rng, len(dets), 40)
+    c = rng.standard_normal(40)
+    c /= np.linalg.norm(c)
+    e0 = float(np.min(np.diag(H))) - 0.5
+    r = ref.pt2_det(7, 3, 2, x.h1, x.eri, W[v], c, e0, eps2)
+    want = dense.e2_dense(H, v, c, e0, eps2)
+    assert abs(r.e2 - want) <= 1e-12 * max(1.0, abs(want))
+    # connection set: outside V with at least one kept term, |H_ai c_i| > eps2
+    outside = np.setdiff1d(np.arange(len(dets)), v)
+    mask = np.abs(H[np.ix_(outside, v)] * c[None, :]) > eps2
+    dense_set = {dets[k] for k in outside[mask.any(axis=1)]}
+    oracle_set = {dense.from_words(k, 7) for k in r.keys}
+    if eps2 == 0.0:
+        # exactly the determinants with a non-zero element (section II, P)
+        assert oracle_set == dense_set
+    else:
+        # away from ties the sets agree; ties |H c| == eps2 have measure zero
+        assert len(oracle_set ^ dense_set) == 0
+    assert r.n_terms == int(mask.sum()) or eps2 > 0
+
+
+def test_full_space_gives_zero(space_226):
+    x, dets, index, H, W = space_226
+    c = np.linalg.eigh(H)[1][:, 0]
+    r = ref.pt2_det(6, 2, 2, x.h1, x.eri, W, c, -10.0, 0.0)
+    assert r.e2 == 0.0 and r.n_unique == 0 and r.n_terms == 0
+    assert r.n_terms_gen > 0  # every connection lands inside V
+
+
+def test_single_reference(space_227):
+    x, dets, index, H, W = space_227
+    hf = G.hf_det(3, 2)
+    k = index[dense.from_words(hf, 7)]
+    ehf = H[k, k]
+    r = ref.pt2_det(7, 3, 2, x.h1, x.eri, hf[None, :], np.array([1.0]), ehf, 0.0)
+    others = [a for a in range(len(dets)) if a != k and H[a, k] != 0.0]
+    want = sum(H[a, k] ** 2 / (ehf - H[a, a]) for a in others)
+    assert abs(r.e2 - want) <= 1e-12 * abs(want)
+    assert r.n_unique == len(others) == dense.n_excitations_closed_form(7, 3, 2)
+
+
+def test_screening_limits_and_invariances():
+    x = I.small(10, 3, 3, 150, 3, 3)
+    n = 10
+    base = ref.pt2_det(n, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e-4)
+    huge = ref.pt2_det(n, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e3)
+    assert huge.e2 == 0.0 and huge.n_unique == 0
+    # sets shrink monotonically with eps2
+    prev = None
+    for eps in [0.0, 1e-6, 1e-4, 1e-3, 1e-2]:
+        r = ref.pt2_det(n, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps)
+        s = {tuple(k) for k in r.keys}
+        if prev is not None:
+            assert s <= prev
+        prev = s
+    # c -> -c leaves every A_a^2 bit for bit
+    neg = ref.pt2_det(n, 3, 3, x.h1, x.eri, x.dets, -x.c, x.e0, 1e-4)
+    assert neg.e2 == base.e2 and np.array_equal(neg.A, -base.A)
+    # permuting V changes only the summation order
+    perm = np.random.default_rng(1).permutation(len(x.c))
+    pr = ref.pt2_det(n, 3, 3, x.h1, x.eri, x.dets[perm], x.c[perm], x.e0, 1e-4)
+    assert abs(pr.e2 - base.e2) <= 1e-14 * abs(base.e2)
+    assert pr.n_terms == base.n_terms and np.array_equal(pr.keys, base.keys)
+
+
+def test_from_a_side_matches_forward():
+    x = I.small(10, 3, 3, 150, 3, 4)
+    r = ref.pt2_det(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e-5)
+    sel = np.random.default_rng(0).choice(r.n_unique, size=60, replace=False)
+    A, D, cnt, inv = ref.pt2_at(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e-5, r.keys[sel])
+    assert np.array_equal(A, r.A[sel]) and np.array_equal(D, r.D[sel])
+    assert np.array_equal(cnt, r.counts[sel]) and not inv.any()
+    _, _, _, inv2 = ref.pt2_at(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e-5, x.dets[:5])
+    assert inv2.all()
+
+
+@pytest.mark.parametrize("shape", [(6, 2, 2), (7, 3, 2), (12, 4, 4), (40, 8, 8), (66, 3, 2)])
+def test_excitation_counts_closed_form(shape):
+    n, na, nb = shape
+    rng = np.random.default_rng(n)
+    h1 = np.zeros((n, n))
+    eri = np.zeros((n, n, n, n))
+    # scattered occupations exercise both words of a spin string when n > 64
+    occa = np.sort(rng.choice(n, size=na, replace=False))
+    occb = np.sort(rng.choice(n, size=nb, replace=False))
+    if n > 64:
+        occa[-1] = n - 1
+    a = G.occ_to_words(occa[None, :])[0]
+    b = G.occ_to_words(occb[None, :])[0]
+    d = np.array([a[0], a[1], b[0], b[1]], dtype=np.uint64)
+    cnt = ref.count_excitations(n, na, nb, h1, eri, d)
+    assert cnt == dense.n_excitations_closed_form(n, na, nb)  # positive: all distinct
+
+
+def test_paper_hilbert_space_dimension():
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        g = json.load(f)["cr2_hilbert_space"]
+    s = g["shape"]
+    dim = math.comb(s["n_orb"], s["n_alpha"]) * math.comb(s["n_orb"], s["n_beta"])
+    assert float(f"{dim:.{g['significant_figures'] - 1}e}") == g["value"]
+    assert abs(dim - 4.7233e29) / dim < 1e-4
+
+
+def _multisets(nv, nd):
+    for combo in itertools.combinations_with_replacement(range(nv), nd):
+        yield combo
+
+
+def test_stochastic_estimator_is_unbiased():
+    x = I.small(8, 2, 2, 6, 2, 21)
+    n = 8
+    c = x.c
+    p = np.abs(c) / np.abs(c).sum()
+    eps2 = 2e-3
+    det = ref.pt2_det(n, 2, 2, x.h1, x.eri, x.dets, c, x.e0, eps2)
+    for nd in (2, 3, 4):
+        expect = 0.0
+        for combo in _multisets(len(c), nd):
+            w = np.bincount(combo, minlength=len(c))
+            prob = math.factorial(nd) * np.prod([p[i] ** w[i] / math.factorial(w[i])
+                                                  for i in range(len(c))])
+            draws = np.array(combo, dtype=np.uint32)[None, :]
+            s = ref.pt2_sample(n, 2, 2, x.h1, x.eri, x.dets, c, x.e0, eps2, 1e30, draws)[0]
+            expect += prob * s
+        assert abs(expect - det.e2) <= 1e-12 * abs(det.e2), (nd, expect, det.e2)
+
+
+def test_stochastic_deterministic_limit():
+    x = I.small(10, 3, 3, 80, 3, 22)
+    rng = np.random.default_rng(3)
+    draws = rng.integers(0, 80, size=(4, 30)).astype(np.uint32)
+    out = ref.pt2_sample(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e-4, 1e-4, draws)
+    assert np.all(out == 0.0)
+
+
+def test_gradient_pins(space_227):
+    x, dets, index, H, W = space_227
+    rng = np.random.default_rng(9)
+    v = _random_v(rng, len(dets), 50)
+    c = rng.standard_normal(50)
+    c /= np.linalg.norm(c)
+    e0 = float(np.min(np.diag(H))) - 0.3
+    eps2 = 1e-3
+    coords = np.arange(50)
+    r = ref.pt2_det(7, 3, 2, x.h1, x.eri, W[v], c, e0, eps2, grad=True, fd_coords=coords,
+                    fd_de0_step=1e-5)
+    # Euler: E2 is homogeneous of degree 2 in c at a fixed mask
+    assert abs(np.dot(c, r.grad) - 2 * r.e2) <= 1e-12 * abs(r.e2)
+    # dense: g = 2 (H_PV * mask)^T (A / D)
+    outside = np.setdiff1d(np.arange(len(dets)), v)
+    hpv = H[np.ix_(outside, v)]
+    mask = np.abs(hpv * c[None, :]) > eps2
+    A = (hpv * mask) @ c
+    D = e0 - np.diag(H)[outside]
+    keep = mask.any(axis=1)
+    g = 2 * ((hpv * mask)[keep]).T @ (A[keep] / D[keep])
+    assert np.abs(g - r.grad).max() <= 1e-11 * np.abs(g).max()
+    # binary128 central differences with the mask frozen
+    assert np.abs(r.fd - r.grad).max() <= 1e-12 * np.abs(r.grad).max()
+    de0 = -np.sum(A[keep] ** 2 / D[keep] ** 2)
+    assert abs(r.de2_de0 - de0) <= 1e-12 * abs(de0)
+    assert abs(r.fd_de0 - r.de2_de0) <= 1e-9 * abs(de0)
+
+
+def test_energy_helper_matches_dense(space_227):
+    x, dets, index, H, W = space_227
+    rng = np.random.default_rng(4)
+    v = _random_v(rng, len(dets), 60)
+    c = rng.standard_normal(60)
+    c /= np.linalg.norm(c)
+    e = ref.energy(7, 3, 2, x.h1, x.eri, W[v], c)
+    assert abs(e - c @ H[np.ix_(v, v)] @ c) < 1e-12
+    # MP1-like amplitudes: <a|H|ref> / (E_ref - H_aa)
+    hf = G.hf_det(3, 2)
+    k = index[dense.from_words(hf, 7)]
+    mask = np.array([1 if (i != k and H[i, k] != 0.0) else 0 for i in range(len(dets))], np.uint8)
+    amp = ref.mp1(7, 3, 2, x.h1, x.eri, W, mask, hf)
+    sel = np.nonzero(mask)[0]
+    want = H[sel, k] / (H[k, k] - np.diag(H)[sel])
+    assert np.abs(amp - want).max() < 1e-12 * np.abs(want).max()
+
+
+def test_validation_errors():
+    x = I.small(8, 2, 2, 20, 2, 1)
+    bad = x.dets.copy()
+    bad[3] = bad[2]
+    with pytest.raises(ref.OracleError) as e:
+        ref.pt2_det(8, 2, 2, x.h1, x.eri, bad, x.c, x.e0, 0.0)
+    assert e.value.code == -4
+    bad = x.dets.copy()
+    bad[1, 0] |= np.uint64(1 << 7)
+    with pytest.raises(ref.OracleError) as e:
+        ref.pt2_det(8, 2, 2, x.h1, x.eri, bad, x.c, x.e0, 0.0)
+    assert e.value.code == -3
+    c = x.c.copy()
+    c[4] = np.nan
+    with pytest.raises(ref.OracleError) as e:
+        ref.pt2_det(8, 2, 2, x.h1, x.eri, x.dets, c, x.e0, 0.0)
+    assert e.value.code == -5

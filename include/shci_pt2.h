@@ -1,0 +1,198 @@
+/*
+ * shci_pt2.h -- screened Epstein-Nesbet PT2 energy on one AMD Instinct MI355X
+ * (gfx950), C ABI.
+ *
+ * The library evaluates the second-order perturbative correction of selected
+ * configuration interaction (paper, section II.B):
+ *
+ *   E2(eps2) = sum_{a in P} ( sum^{(eps2)}_{i in V} H_ai c_i )^2 / (E0 - H_aa)
+ *
+ * where V is the variational space, P the determinants outside V reached from
+ * V by single and double excitations, and the inner sum keeps only the terms
+ * with |H_ai c_i| > eps2 (screened PT2 equation; the strict inequality makes
+ * eps2 = 0 keep exactly the non-zero elements, the definition of P in
+ * section II).  H_aa is the Epstein-Nesbet zeroth-order energy of a
+ * (partition equation).
+ *
+ * Inputs (the problem statement of section II.B):
+ *   - determinants as bit strings: uint64 [n_det][4] =
+ *     (alpha_lo, alpha_hi, beta_lo, beta_hi); orbital p of a spin sits at bit
+ *     (p & 63) of word (p >> 6) of that spin (section V.A);
+ *   - coefficients c [n_det], FP64;
+ *   - one-electron integrals h1 [n][n] and two-electron integrals in
+ *     chemists' notation (pq|rs) at eri[((p*n+q)*n+r)*n+s], FP64, real
+ *     orbitals, symmetric under all eight index permutations;
+ *   - E0 (used in every denominator) and the screening threshold(s).
+ *
+ * Conventions: spin orbitals are ordered alpha_0..alpha_{n-1},
+ * beta_0..beta_{n-1}; a same-spin double p<q -> r<s is p->r then q->s.
+ *
+ * Memory: every pointer marked "device" must be device memory of the current
+ * HIP device; "host" pointers are host memory.  All input and output buffers
+ * are owned by the caller.  The context owns the integral-derived tables and a
+ * grow-only device workspace, both freed by shci_pt2_ctx_destroy.
+ *
+ * Streams: all work is enqueued on `stream` (a hipStream_t, NULL = default
+ * stream).  Calls that return host scalars synchronise that stream before
+ * returning.
+ *
+ * Errors: every entry point returns an shci_status; nothing is thrown across
+ * the ABI.  shci_pt2_last_error() returns a thread-local message for the last
+ * non-OK status of the calling thread.  Inputs are never modified.
+ *
+ * Concurrency: a context may be used by one call at a time (its workspace is
+ * shared by all calls on it).
+ */
+#ifndef SHCI_PT2_H
+#define SHCI_PT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shci_pt2_ctx shci_pt2_ctx;
+
+/* Arithmetic of the off-diagonal part.  SHCI_FP64: everything in binary64.
+ * SHCI_FP32C: products H_ai c_i and the per-determinant sums A_a in binary32
+ * with compensated (TwoSum) accumulation; H_aa, E0 - H_aa and the E2
+ * reduction stay binary64.  Screening decisions are binary64 in both modes,
+ * so both produce the same connection set. */
+enum shci_precision { SHCI_FP64 = 0, SHCI_FP32C = 1 };
+
+enum shci_status {
+  SHCI_OK = 0,
+  SHCI_ERR_ARG = -1,        /* bad argument (NULL pointer, negative size, eps2 < 0, ...) */
+  SHCI_ERR_NORB = -2,       /* n_orb / electron counts outside the supported range */
+  SHCI_ERR_DET = -3,        /* a determinant has a wrong electron count or a bit >= n_orb */
+  SHCI_ERR_DUP = -4,        /* two determinants of V are equal */
+  SHCI_ERR_NONFINITE = -5,  /* NaN or Inf in c, E0 or the integrals */
+  SHCI_ERR_WORKSPACE = -6,  /* device memory exhausted, or the problem exceeds a size limit */
+  SHCI_ERR_SINGULAR = -7,   /* some kept a has E0 - H_aa == 0 exactly */
+  SHCI_ERR_HIP = -8         /* a HIP runtime call failed */
+};
+
+/* Statistics of one call (host struct). */
+typedef struct {
+  int64_t n_terms;       /* screened terms (i, a) with a outside V */
+  int64_t n_terms_gen;   /* screened terms including a inside V */
+  int64_t n_unique;      /* |P(eps2)|, distinct a outside V with >= 1 kept term */
+  int64_t n_intruder;    /* kept a with E0 - H_aa > 0 */
+  double min_abs_denom;  /* min |E0 - H_aa| over kept a (+inf if none) */
+  int32_t n_buckets;     /* hash buckets used by the grouping step */
+  int32_t n_retries;     /* re-partitions after a bucket overflow */
+  double ms_gen;         /* excitation generation (count + write) */
+  double ms_sort;        /* hash partition passes */
+  double ms_reduce;      /* bucket sort, segmented reduce, diagonal, E2 reduction */
+  double ms_total;       /* whole call, device time on `stream` */
+} shci_pt2_stats;
+
+/* Optional device outputs of shci_pt2_det (any pointer may be NULL).
+ * Unique determinants a outside V, in an unspecified but deterministic order:
+ *   u_keys [u_cap][4] uint64 (same layout as the input dets), u_A [u_cap]
+ *   (A_a = sum of kept H_ai c_i), u_D [u_cap] (E0 - H_aa), u_cnt [u_cap]
+ *   (kept terms of a).  u_n receives the number of unique a (host value); if
+ *   it exceeds u_cap only u_cap entries are written.
+ * Raw terms (a inside V included), in generation order:
+ *   t_keys [t_cap][4], t_i [t_cap] (index of the source det), t_val [t_cap]
+ *   (H_ai c_i, FP64, or the FP32 product widened in SHCI_FP32C).  t_n receives
+ *   the number of terms (host value). */
+typedef struct {
+  uint64_t* u_keys;
+  double* u_A;
+  double* u_D;
+  int32_t* u_cnt;
+  int64_t u_cap;
+  int64_t u_n;
+  uint64_t* t_keys;
+  uint32_t* t_i;
+  double* t_val;
+  int64_t t_cap;
+  int64_t t_n;
+} shci_pt2_export;
+
+/* Creates a context for n_orb spatial orbitals (1 <= n_orb <= 127) and
+ * n_alpha, n_beta electrons (each in [1, n_orb - 1]).  h1 and eri are device
+ * pointers (FP64, layout above); they are read during this call only.  Builds
+ * on the device:
+ *   - the heat-bath tables: for every occupied spatial pair, the matrix
+ *     elements of all double excitations from it, sorted by decreasing
+ *     magnitude with their target pair (section II.A, heat-bath screening,
+ *     used again for eps2 in section II.B):
+ *       same spin, pair p<q: all r<s outside {p,q}, value (pr|qs) - (ps|qr);
+ *       opposite spin, pair (p_alpha, q_beta): all r != p, s != q, value (pr|qs);
+ *     ties are ordered by ascending (r, s);
+ *   - single-excitation tables (pr|kk) - (pk|kr), (pr|kk) and an upper bound
+ *     of |H_ai| per (p, r);
+ *   - diagonal tables (pp|qq), (pq|qp).
+ * Returns SHCI_ERR_NONFINITE if an integral is not finite. */
+int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, const double* eri,
+                        void* stream, shci_pt2_ctx** out);
+
+/* Frees the context, its tables and its workspace.  NULL is ignored. */
+void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx);
+
+/* Caps the context's device workspace (bytes; 0 = no cap).  Calls whose
+ * working set would exceed the cap fail with SHCI_ERR_WORKSPACE. */
+int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes);
+
+/* Deterministic screened PT2 (screened PT2 equation).
+ *   dets  device uint64 [n_det][4], unique, with n_alpha / n_beta electrons;
+ *   c     device FP64 [n_det];
+ *   e0    E0 of every denominator; eps2 >= 0 the screening threshold;
+ *   precision  SHCI_FP64 or SHCI_FP32C;
+ *   e2    host, receives E2; st host, nullable; ex host struct, nullable.
+ * The result is deterministic: repeated calls give identical bits.
+ * SHCI_ERR_SINGULAR is returned (with e2 = +-inf or nan) if a kept a has
+ * E0 - H_aa == 0 exactly; intruders with E0 - H_aa > 0 are counted, not
+ * rejected. */
+int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                 double e0, double eps2, int precision, void* stream, double* e2,
+                 shci_pt2_stats* st, shci_pt2_export* ex);
+
+/* Stochastic part of the semistochastic PT2 (semistochastic and stochastic
+ * PT2 equations).  For each sample s of n_draws draws (indices into V, drawn
+ * with replacement with p_i = |c_i| / sum_j |c_j|, the sampling-probability
+ * equation), with w_i the multiplicity of det i in the sample:
+ *   S_s(e) = sum_{a not in V} [ (sum_i w_i c_i H_ai / p_i)^2
+ *            + sum_i (w_i (N_d - 1)/p_i - w_i^2/p_i^2) c_i^2 H_ai^2 ]
+ *            / ((E0 - H_aa) N_d (N_d - 1)),
+ * the inner sums over the distinct dets of the sample whose term passes
+ * |H_ai c_i| > e, and per_sample[s] = S_s(eps2) - S_s(eps2_d), both
+ * thresholds evaluated on the same samples in one pass.  The semistochastic
+ * estimate is E2 = E2_det(eps2_d) + mean_s per_sample[s].
+ *   draws   device uint32 [n_samples][n_draws], each < n_det;
+ *   eps2 <= eps2_d; n_draws >= 2; n_samples >= 1;
+ *   per_sample  device FP64 [n_samples];
+ *   mean, sem   host, nullable: mean and standard error (sd / sqrt(n_samples))
+ *               of per_sample (sem = 0 when n_samples == 1). */
+int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                    double e0, double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
+                    const uint32_t* draws, int precision, void* stream, double* per_sample,
+                    double* mean, double* sem, shci_pt2_stats* st);
+
+/* Gradient of the deterministic screened E2 with the screening mask held at
+ * the given c:
+ *   dE2/dc_i = sum_{a: (i,a) kept, a not in V} 2 H_ai A_a / (E0 - H_aa)
+ *   dE2/dE0  = -sum_a A_a^2 / (E0 - H_aa)^2.
+ * The forward pass runs first (precision as in shci_pt2_det); the adjoint
+ * regenerates the connections of every i and looks up 2 A_a / D_a, so no
+ * per-term storage is kept.  de2_dc: device FP64 [n_det]; e2, de2_de0: host,
+ * nullable. */
+int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                  double e0, double eps2, int precision, void* stream, double* e2,
+                  double* de2_dc, double* de2_de0, shci_pt2_stats* st);
+
+/* Message for the last non-OK status returned to the calling thread. */
+const char* shci_pt2_last_error(void);
+
+/* Library version string. */
+const char* shci_pt2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHCI_PT2_H */

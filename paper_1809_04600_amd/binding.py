@@ -1,0 +1,223 @@
+"""ctypes binding of libshci_pt2.so (argument marshalling only).
+
+Every step of the computation runs in the library's HIP kernels; PyTorch
+supplies device memory and the current stream.  There is no CPU fallback:
+importing this module without the built library raises at first use.
+
+Determinants are passed as int64 tensors of shape [N, 4] holding the uint64
+words (alpha_lo, alpha_hi, beta_lo, beta_hi) bit for bit.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshci_pt2.so")
+
+SHCI_FP64 = 0
+SHCI_FP32C = 1
+_PREC = {"fp64": SHCI_FP64, "fp32c": SHCI_FP32C, SHCI_FP64: SHCI_FP64, SHCI_FP32C: SHCI_FP32C}
+
+STATUS = {0: "SHCI_OK", -1: "SHCI_ERR_ARG", -2: "SHCI_ERR_NORB", -3: "SHCI_ERR_DET",
+          -4: "SHCI_ERR_DUP", -5: "SHCI_ERR_NONFINITE", -6: "SHCI_ERR_WORKSPACE",
+          -7: "SHCI_ERR_SINGULAR", -8: "SHCI_ERR_HIP"}
+
+
+class ShciError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_terms", C.c_int64), ("n_terms_gen", C.c_int64), ("n_unique", C.c_int64),
+                ("n_intruder", C.c_int64), ("min_abs_denom", C.c_double),
+                ("n_buckets", C.c_int32), ("n_retries", C.c_int32),
+                ("ms_gen", C.c_double), ("ms_sort", C.c_double), ("ms_reduce", C.c_double),
+                ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Export(C.Structure):
+    _fields_ = [("u_keys", C.c_void_p), ("u_A", C.c_void_p), ("u_D", C.c_void_p),
+                ("u_cnt", C.c_void_p), ("u_cap", C.c_int64), ("u_n", C.c_int64),
+                ("t_keys", C.c_void_p), ("t_i", C.c_void_p), ("t_val", C.c_void_p),
+                ("t_cap", C.c_int64), ("t_n", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "paper_1809_04600_amd/build.sh")
+        L = C.CDLL(LIB_PATH)
+        p, i, i64, d = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        L.shci_pt2_last_error.restype = C.c_char_p
+        L.shci_pt2_version.restype = C.c_char_p
+        L.shci_pt2_ctx_create.argtypes = [i, i, i, p, p, p, C.POINTER(p)]
+        L.shci_pt2_ctx_create.restype = i
+        L.shci_pt2_ctx_destroy.argtypes = [p]
+        L.shci_pt2_ctx_destroy.restype = None
+        L.shci_pt2_ctx_set_workspace_limit.argtypes = [p, C.c_size_t]
+        L.shci_pt2_ctx_set_workspace_limit.restype = i
+        L.shci_pt2_det.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), C.POINTER(Stats),
+                                   C.POINTER(Export)]
+        L.shci_pt2_det.restype = i
+        L.shci_pt2_sample.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, i, p, p,
+                                      C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
+        L.shci_pt2_sample.restype = i
+        L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), p, C.POINTER(d),
+                                    C.POINTER(Stats)]
+        L.shci_pt2_grad.restype = i
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise ShciError(code, lib().shci_pt2_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, shape=None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {shape}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class DetResult:
+    e2: float
+    stats: dict
+    unique: dict | None = None
+    terms: dict | None = None
+
+
+class Context:
+    """Integral set on the device plus the library's tables (shci_pt2_ctx)."""
+
+    def __init__(self, h1: torch.Tensor, eri: torch.Tensor, n_alpha: int, n_beta: int):
+        n = h1.shape[0]
+        self.n, self.na, self.nb = n, n_alpha, n_beta
+        h1 = h1.contiguous()
+        eri = eri.contiguous()
+        ptr = C.c_void_p()
+        _check(lib().shci_pt2_ctx_create(n, n_alpha, n_beta, _dev(h1, torch.float64, (n, n), "h1"),
+                                         _dev(eri, torch.float64, (n, n, n, n), "eri"), _stream(),
+                                         C.byref(ptr)))
+        self._ptr = ptr
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            lib().shci_pt2_ctx_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_workspace_limit(self, nbytes: int):
+        _check(lib().shci_pt2_ctx_set_workspace_limit(self._ptr, nbytes))
+
+    def _inputs(self, dets, c):
+        nd = c.shape[0]
+        return _dev(dets, torch.int64, (nd, 4), "dets"), _dev(c, torch.float64, (nd,), "c"), nd
+
+    def det(self, dets, c, e0, eps2, precision="fp64", unique_cap=0, terms_cap=0) -> DetResult:
+        pd, pc, nd = self._inputs(dets, c)
+        e2 = C.c_double()
+        st = Stats()
+        ex = None
+        bufs = {}
+        if unique_cap or terms_cap:
+            ex = Export()
+            dev = c.device
+            if unique_cap:
+                bufs["u_keys"] = torch.zeros((unique_cap, 4), dtype=torch.int64, device=dev)
+                bufs["u_A"] = torch.zeros(unique_cap, dtype=torch.float64, device=dev)
+                bufs["u_D"] = torch.zeros(unique_cap, dtype=torch.float64, device=dev)
+                bufs["u_cnt"] = torch.zeros(unique_cap, dtype=torch.int32, device=dev)
+                ex.u_keys = bufs["u_keys"].data_ptr()
+                ex.u_A = bufs["u_A"].data_ptr()
+                ex.u_D = bufs["u_D"].data_ptr()
+                ex.u_cnt = bufs["u_cnt"].data_ptr()
+                ex.u_cap = unique_cap
+            if terms_cap:
+                bufs["t_keys"] = torch.zeros((terms_cap, 4), dtype=torch.int64, device=dev)
+                bufs["t_i"] = torch.zeros(terms_cap, dtype=torch.int32, device=dev)
+                bufs["t_val"] = torch.zeros(terms_cap, dtype=torch.float64, device=dev)
+                ex.t_keys = bufs["t_keys"].data_ptr()
+                ex.t_i = bufs["t_i"].data_ptr()
+                ex.t_val = bufs["t_val"].data_ptr()
+                ex.t_cap = terms_cap
+        _check(lib().shci_pt2_det(self._ptr, pd, pc, nd, float(e0), float(eps2), _PREC[precision],
+                                  _stream(), C.byref(e2), C.byref(st),
+                                  C.byref(ex) if ex is not None else None))
+        r = DetResult(e2.value, st.as_dict())
+        if ex is not None and unique_cap:
+            m = min(ex.u_n, unique_cap)
+            r.unique = {"n": ex.u_n, "keys": bufs["u_keys"][:m], "A": bufs["u_A"][:m],
+                        "D": bufs["u_D"][:m], "cnt": bufs["u_cnt"][:m]}
+        if ex is not None and terms_cap:
+            m = min(ex.t_n, terms_cap)
+            r.terms = {"n": ex.t_n, "keys": bufs["t_keys"][:m], "i": bufs["t_i"][:m],
+                       "val": bufs["t_val"][:m]}
+        return r
+
+    def grad(self, dets, c, e0, eps2, precision="fp64"):
+        pd, pc, nd = self._inputs(dets, c)
+        g = torch.empty(nd, dtype=torch.float64, device=c.device)
+        e2 = C.c_double()
+        de0 = C.c_double()
+        st = Stats()
+        _check(lib().shci_pt2_grad(self._ptr, pd, pc, nd, float(e0), float(eps2), _PREC[precision],
+                                   _stream(), C.byref(e2), C.c_void_p(g.data_ptr()), C.byref(de0),
+                                   C.byref(st)))
+        return e2.value, g, de0.value, st.as_dict()
+
+    def sample(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64"):
+        pd, pc, nd = self._inputs(dets, c)
+        ns, ndraw = draws.shape
+        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
+        out = torch.empty(ns, dtype=torch.float64, device=c.device)
+        mean = C.c_double()
+        sem = C.c_double()
+        st = Stats()
+        _check(lib().shci_pt2_sample(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_d),
+                                     ns, ndraw, pdr, _PREC[precision], _stream(),
+                                     C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
+                                     C.byref(st)))
+        return out, mean.value, sem.value, st.as_dict()
+
+
+def dets_tensor(dets_u64, device="cuda"):
+    """numpy uint64 [N,4] -> int64 device tensor with the same bits."""
+    import numpy as np
+    a = np.ascontiguousarray(dets_u64, dtype=np.uint64).view(np.int64)
+    return torch.from_numpy(a).to(device)
+
+
+def dets_numpy(t: torch.Tensor):
+    """int64 tensor -> numpy uint64 with the same bits."""
+    return t.detach().cpu().numpy().view("uint64")

@@ -1,0 +1,913 @@
+// Host side of the C ABI declared in include/shci_pt2.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/shci_pt2.h"
+#include "group.hpp"
+#include "scan.hpp"
+
+using namespace shci;
+
+namespace {
+
+thread_local char g_msg[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return fail(SHCI_ERR_HIP, "%s failed: %s (%s:%d)", #x, hipGetErrorString(e_),  \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define CHK(...)                    \
+  do {                              \
+    int s_ = (__VA_ARGS__);         \
+    if (s_ != SHCI_OK) return s_;   \
+  } while (0)
+
+// grow-only device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes, size_t limit) {
+    if (bytes <= cap) return SHCI_OK;
+    if (limit && bytes > limit)
+      return fail(SHCI_ERR_WORKSPACE, "workspace of %zu bytes exceeds the limit of %zu", bytes, limit);
+    if (p) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return fail(SHCI_ERR_HIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+      (void)hipFree(p);
+      p = nullptr;
+      cap = 0;
+    }
+    size_t want = bytes + bytes / 8 + (1u << 20);
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return fail(SHCI_ERR_WORKSPACE, "cannot allocate %zu bytes of device workspace", bytes);
+      }
+      want = bytes;
+    }
+    cap = want;
+    return SHCI_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// bump allocator over a DevBuf (two passes: size, then carve)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return r;
+  }
+};
+
+int ceil_log2(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct shci_pt2_ctx {
+  int device = 0;
+  Tables T;
+  DevBuf tables, small, big;
+  size_t ws_limit = 0;
+  uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
+  DevResult* dres = nullptr;
+  hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+constexpr int GEN_BLOCKS_PER_CU = 8;
+
+int num_cus(int dev) {
+  static int cus = 0;
+  if (!cus) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+int key_words(int n, int sbits) { return (2 * n + sbits + 1 + 63) / 64; }
+
+// ----------------------------------------------------------------------------
+// Small device utilities
+// ----------------------------------------------------------------------------
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_zero_result(DevResult* r) {
+  r->e2 = 0.0;
+  r->de0 = 0.0;
+  r->mind = INFINITY;
+  r->nterm = r->ngen = r->nuniq = r->nintr = r->nzero = 0;
+  r->overflow = 0;
+  r->flags = 0;
+}
+
+// flags: 1 bad det, 2 non-finite c, 4 duplicate, 8 hash set full, 16 draw out of range
+__global__ void k_validate(const uint64_t* dets, const double* c, int64_t nd, int n, int na, int nb,
+                           uint32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd) return;
+  uint64_t m0, m1;
+  low_mask(n, m0, m1);
+  const uint64_t a0 = dets[4 * i], a1 = dets[4 * i + 1], b0 = dets[4 * i + 2], b1 = dets[4 * i + 3];
+  bool ok = (__popcll(a0) + __popcll(a1) == na) && (__popcll(b0) + __popcll(b1) == nb);
+  ok = ok && !(a0 & ~m0) && !(a1 & ~m1) && !(b0 & ~m0) && !(b1 & ~m1);
+  if (!ok) atomicOr(flag, 1u);
+  const double v = c[i];
+  if (!(v - v == 0.0)) atomicOr(flag, 2u);
+}
+
+// deterministic sum of |c| (fixed per-thread chunks, fixed tree)
+__global__ void __launch_bounds__(1024) k_sum_abs(const double* c, int64_t nd, double* out) {
+  __shared__ double r[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (nd + 1023) / 1024;
+  double s = 0.0;
+  for (int64_t i = t * chunk; i < min(nd, (int64_t)(t + 1) * chunk); ++i) s += fabs(c[i]);
+  r[t] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) r[t] += r[t + o];
+    __syncthreads();
+  }
+  if (t == 0) *out = r[0];
+}
+
+// Per sample: sort the draws in LDS, run-length encode, write (det, weight)
+// at [s * nd + k] and the number of distinct dets.
+constexpr int MAX_DRAWS = 4096;
+__global__ void __launch_bounds__(256) k_sample_items(const uint32_t* draws, int32_t nd, int64_t ndet,
+                                                     uint32_t* it_det, uint32_t* it_w, uint32_t* ucount,
+                                                     uint32_t* flag) {
+  __shared__ SortBufs<MAX_DRAWS> B;
+  __shared__ SplitScratch S;
+  __shared__ uint32_t scan_sh[256];
+  __shared__ uint16_t heads[MAX_DRAWS + 1];
+  const int t = threadIdx.x;
+  const int s = blockIdx.x;
+  S.wcnt[0][t] = S.wcnt[1][t] = S.wcnt[2][t] = S.wcnt[3][t] = 0;
+  for (int j = t; j < nd; j += 256) {
+    uint32_t v = draws[(int64_t)s * nd + j];
+    if ((int64_t)v >= ndet) {
+      atomicOr(flag, 16u);
+      v = 0;
+    }
+    B.h2a[j] = v;
+    B.ia[j] = (uint16_t)j;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 4; ++pass) {
+    const int sh = pass * 8;
+    if ((pass & 1) == 0)
+      lds_pass<MAX_DRAWS>(nd, B.h2a, B.ia, B.h2b, B.ib, S, scan_sh,
+                          [&](int j) { return (B.h2a[j] >> sh) & 0xffu; });
+    else
+      lds_pass<MAX_DRAWS>(nd, B.h2b, B.ib, B.h2a, B.ia, S, scan_sh,
+                          [&](int j) { return (B.h2b[j] >> sh) & 0xffu; });
+  }
+  const int per = (nd + 255) / 256;
+  const int j_lo = t * per, j_hi = min(nd, j_lo + per);
+  uint32_t cnt = 0;
+  for (int j = j_lo; j < j_hi; ++j) cnt += (j == 0) || (B.h2a[j] != B.h2a[j - 1]);
+  uint32_t tot;
+  uint32_t idx = block_scan256(cnt, scan_sh, &tot);
+  for (int j = j_lo; j < j_hi; ++j)
+    if ((j == 0) || (B.h2a[j] != B.h2a[j - 1])) heads[idx++] = (uint16_t)j;
+  if (t == 0) heads[tot] = (uint16_t)nd;
+  __syncthreads();
+  for (uint32_t u = t; u < tot; u += 256) {
+    it_det[(int64_t)s * nd + u] = B.h2a[heads[u]];
+    it_w[(int64_t)s * nd + u] = (uint32_t)(heads[u + 1] - heads[u]);
+  }
+  if (t == 0) ucount[s] = tot;
+}
+
+__global__ void k_sample_compact(const uint32_t* it_det, const uint32_t* it_w, const uint32_t* ucount,
+                                 const uint64_t* uoff, int32_t nd, int32_t s0, uint32_t* o_det,
+                                 uint32_t* o_w, uint32_t* o_s) {
+  const int s = blockIdx.x;
+  const uint64_t base = uoff[s];
+  for (uint32_t u = threadIdx.x; u < ucount[s]; u += blockDim.x) {
+    o_det[base + u] = it_det[(int64_t)s * nd + u];
+    o_w[base + u] = it_w[(int64_t)s * nd + u];
+    o_s[base + u] = (uint32_t)(s - s0);
+  }
+}
+
+// Unique export: copy the non-V uniques of every bucket to dense arrays.
+template <int KW>
+__global__ void k_export_uniq(Uniq U, const int32_t* nseg, const uint64_t* boff, int64_t nb, int n,
+                              uint64_t* keys, double* A, double* D, int32_t* cnt, int64_t cap) {
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint64_t lo = U.start[b];
+    const int ns = nseg[b];
+    // non-V uniques before each: sequential scan by thread 0 into the loop below
+    uint64_t o = boff[b];
+    for (int s = 0; s < ns; ++s) {
+      const int32_t c = U.cnt[lo + s];
+      if (c < 0) continue;
+      if (threadIdx.x == 0 && (int64_t)o < cap) {
+        uint64_t k[KW];
+#pragma unroll
+        for (int w = 0; w < KW; ++w) k[w] = U.k[w][lo + s];
+        uint64_t a0, a1, b0, b1;
+        unpack_det<KW>(k, n, a0, a1, b0, b1);
+        keys[4 * o] = a0;
+        keys[4 * o + 1] = a1;
+        keys[4 * o + 2] = b0;
+        keys[4 * o + 3] = b1;
+        A[o] = U.A[lo + s];
+        D[o] = U.D[lo + s];
+        cnt[o] = c;
+      }
+      ++o;
+    }
+  }
+}
+
+template <int KW, typename VT>
+__global__ void k_export_terms(Recs R, int64_t nrec, int n, uint64_t* keys, uint32_t* idx, double* val,
+                               int64_t cap) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nrec && j < cap;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t k[KW];
+#pragma unroll
+    for (int w = 0; w < KW; ++w) k[w] = R.k[w][j];
+    uint64_t a0, a1, b0, b1;
+    unpack_det<KW>(k, n, a0, a1, b0, b1);
+    keys[4 * j] = a0;
+    keys[4 * j + 1] = a1;
+    keys[4 * j + 2] = b0;
+    keys[4 * j + 3] = b1;
+    idx[j] = R.pay[j];
+    val[j] = (double)static_cast<const VT*>(R.v)[j];
+  }
+}
+
+__global__ void k_nonv_counts(const Partials P, int64_t nb, uint64_t* out) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x)
+    out[b] = (uint64_t)P.nuniq[b];
+}
+
+// ----------------------------------------------------------------------------
+// One evaluation (deterministic or one chunk of samples)
+// ----------------------------------------------------------------------------
+struct Job {
+  shci_pt2_ctx* ctx;
+  hipStream_t st;
+  const uint64_t* dets;
+  const double* c;
+  int64_t ndet;
+  double e0, eps2, eps2_d;
+  int precision;
+  bool sample;
+  int sbits;
+  int32_t nsamp;   // samples in this chunk
+  double nd;       // draws per sample
+  double sum_abs;  // device pointer value read by the kernels is passed by value
+  // items (sample mode)
+  const uint32_t* it_det = nullptr;
+  const uint32_t* it_w = nullptr;
+  const uint32_t* it_s = nullptr;
+  int64_t n_items;
+  // options
+  bool want_u = false;
+  bool want_pay = false;
+  double* per_sample = nullptr;  // device [nsamp]
+  double* grad = nullptr;        // device [ndet]
+  shci_pt2_export* ex = nullptr;
+  // results
+  DevResult res;
+  int32_t nbucket = 0, retries = 0;
+  float ms_gen = 0, ms_sort = 0, ms_reduce = 0;
+};
+
+template <int KW, typename VT, bool SAMPLE>
+int run_job(Job& J) {
+  shci_pt2_ctx* X = J.ctx;
+  const Tables& T = X->T;
+  const int n = T.n;
+  hipStream_t st = J.st;
+  constexpr int C = (KW <= 2) ? 2048 : 1024;
+  const int auxbit = 2 * n + J.sbits;
+  const int cus = num_cus(X->device);
+
+  // ---- small workspace: counts, offsets, hash set of V, scan scratch ----
+  const int64_t ni = J.n_items;
+  uint64_t vcap = 1024;
+  while (vcap < 2 * (uint64_t)J.ndet) vcap <<= 1;
+  auto plan_small = [&](Carver& cv, uint32_t** counts, uint64_t** offs, uint64_t** vtab, ScanTmp* sc,
+                        uint64_t** total) {
+    *counts = cv.take<uint32_t>(ni + 1);
+    *offs = cv.take<uint64_t>(ni + 1);
+    *vtab = cv.take<uint64_t>(vcap);
+    *total = cv.take<uint64_t>(4);
+    sc->carve(cv, ni + 1);
+  };
+  uint32_t* counts;
+  uint64_t *offs, *vtab, *total;
+  ScanTmp sc;
+  {
+    Carver cv(nullptr);
+    plan_small(cv, &counts, &offs, &vtab, &sc, &total);
+    CHK(X->small.ensure(cv.off, X->ws_limit));
+  }
+  {
+    Carver cv(X->small.p);
+    plan_small(cv, &counts, &offs, &vtab, &sc, &total);
+  }
+  uint32_t* dflag = X->dflag;
+  uint32_t* counter = X->dflag + 1;
+  uint32_t* overflow = X->dflag + 2;
+
+  HIPCHK(hipEventRecord(X->ev[0], st));
+  k_fill_u32<<<1, 64, 0, st>>>(dflag, 4, 0u);
+  k_validate<<<(int)((J.ndet + 255) / 256), 256, 0, st>>>(J.dets, J.c, J.ndet, n, T.na, T.nb, dflag);
+  VSet V;
+  V.tab = vtab;
+  V.mask = vcap - 1;
+  V.dets = J.dets;
+  k_fill_u64<<<std::min<int64_t>(4096, (vcap + 255) / 256), 256, 0, st>>>(vtab, (int64_t)vcap, ~0ull);
+  k_vset_insert<KW><<<(int)((J.ndet + 255) / 256), 256, 0, st>>>(V, J.ndet, n, dflag);
+
+  GenArgs g{};
+  g.n = n;
+  g.na = T.na;
+  g.nb = T.nb;
+  g.dets = J.dets;
+  g.c = J.c;
+  g.n_items = ni;
+  g.it_det = J.it_det;
+  g.it_w = J.it_w;
+  g.it_s = J.it_s;
+  g.sum_abs = J.sum_abs;
+  g.nd = J.nd;
+  g.eps2 = J.eps2;
+  g.eps2_d = J.eps2_d;
+  g.T = T;
+  g.counts = counts;
+  g.offs = offs;
+  g.counter = counter;
+  g.sbits = J.sbits;
+  g.auxbit = auxbit;
+  const int gen_grid = cus * GEN_BLOCKS_PER_CU;
+  k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
+  k_gen<KW, GEN_COUNT, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+  HIPCHK(hipGetLastError());
+  CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, total, st));
+  uint64_t hostv[2] = {0, 0};
+  uint32_t hflags = 0;
+  HIPCHK(hipMemcpyAsync(hostv, total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&hflags, dflag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflags & 1u) return fail(SHCI_ERR_DET, "a determinant has a wrong electron count or an orbital >= n_orb");
+  if (hflags & 2u) return fail(SHCI_ERR_NONFINITE, "c contains a non-finite value");
+  if (hflags & 4u) return fail(SHCI_ERR_DUP, "the variational space contains a duplicate determinant");
+  if (hflags & 8u) return fail(SHCI_ERR_WORKSPACE, "hash set of V overflowed");
+  const int64_t nrec = (int64_t)hostv[0];
+  if (nrec >= (int64_t)0xffffffffll)
+    return fail(SHCI_ERR_WORKSPACE, "%lld screened terms exceed the 2^32-1 records of one pass",
+                (long long)nrec);
+
+  // ---- plan the grouping ----
+  GroupPlan G;
+  G.sbits = J.sbits;
+  {
+    const int64_t per_sample_rec = SAMPLE ? std::max<int64_t>(1, nrec / std::max(1, J.nsamp)) : nrec;
+    G.bits_hash = std::min(26, std::max(0, ceil_log2((uint64_t)((per_sample_rec + C / 2 - 1) / (C / 2)))));
+  }
+
+  for (int attempt = 0;; ++attempt) {
+    G.nbits = G.bits_hash + G.sbits;
+    G.nbucket = (int64_t)1 << G.nbits;
+    const int npass = (G.nbits + 7) / 8;
+    const int64_t ntiles = std::max<int64_t>(1, (nrec + PTILE - 1) / PTILE);
+    const bool v2 = SAMPLE;
+    const bool pay = J.want_pay;
+    auto plan_big = [&](Carver& cv, Recs* A, Recs* B, uint32_t** hist, uint32_t** hoffs, ScanTmp* hsc,
+                        Partials* P, Uniq* U, uint64_t** boff) {
+      for (int w = 0; w < KW; ++w) A->k[w] = cv.take<uint64_t>(nrec);
+      A->v = cv.take<VT>(nrec);
+      A->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
+      A->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
+      if (npass > 0) {
+        for (int w = 0; w < KW; ++w) B->k[w] = cv.take<uint64_t>(nrec);
+        B->v = cv.take<VT>(nrec);
+        B->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
+        B->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
+      }
+      *hist = cv.take<uint32_t>((size_t)256 * ntiles);
+      *hoffs = cv.take<uint32_t>((size_t)256 * ntiles + 1);
+      hsc->carve(cv, std::max<int64_t>((int64_t)256 * ntiles, G.nbucket + 1));
+      const int64_t nb = G.nbucket;
+      P->e2 = cv.take<double>(nb);
+      P->de0 = cv.take<double>(nb);
+      P->nterm = cv.take<int64_t>(nb);
+      P->ngen = cv.take<int64_t>(nb);
+      P->nuniq = cv.take<int32_t>(nb);
+      P->nintr = cv.take<int32_t>(nb);
+      P->nzero = cv.take<int32_t>(nb);
+      P->mind = cv.take<double>(nb);
+      P->nseg = cv.take<int32_t>(nb);
+      if (J.want_u) {
+        for (int w = 0; w < KW; ++w) U->k[w] = cv.take<uint64_t>(nrec);
+        U->h2 = cv.take<uint32_t>(nrec);
+        U->A = cv.take<double>(nrec);
+        U->D = cv.take<double>(nrec);
+        U->g = cv.take<double>(nrec);
+        U->cnt = cv.take<int32_t>(nrec);
+        U->start = cv.take<uint64_t>(nb + 1);
+        *boff = cv.take<uint64_t>(nb + 1);
+      }
+    };
+    Recs A, B;
+    uint32_t *hist, *hoffs;
+    ScanTmp hsc;
+    Partials P;
+    Uniq U;
+    uint64_t* boff = nullptr;
+    {
+      Carver cv(nullptr);
+      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff);
+      CHK(X->big.ensure(cv.off, X->ws_limit));
+      Carver cv2(X->big.p);
+      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff);
+    }
+    {
+      // ---- generation (write pass; repeated after a re-plan, same records) ----
+      g.out = A;
+      k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
+      k_gen<KW, GEN_WRITE, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+      HIPCHK(hipGetLastError());
+      if (J.ex && J.ex->t_keys && J.ex->t_cap > 0 && pay) {
+        k_export_terms<KW, VT><<<1024, 256, 0, st>>>(A, nrec, n, J.ex->t_keys, J.ex->t_i, J.ex->t_val,
+                                                      J.ex->t_cap);
+      }
+    }
+    HIPCHK(hipEventRecord(X->ev[1], st));
+    // ---- hash partition (LSD over the bucket id) ----
+    Recs* cur = &A;
+    Recs* oth = &B;
+    {
+      int shift = 0;
+      for (int pass = 0; pass < npass; ++pass) {
+        const int dbits = G.nbits / npass + (pass < G.nbits % npass ? 1 : 0);
+        PassArgs pa{};
+        pa.in = *cur;
+        pa.out = *oth;
+        pa.n = nrec;
+        pa.G = G;
+        pa.nbits_n = n;
+        pa.auxbit = auxbit;
+        pa.shift = shift;
+        pa.dbits = dbits;
+        pa.hist = hist;
+        pa.offs = hoffs;
+        pa.ntiles = (int)ntiles;
+        k_part_hist<KW><<<(int)ntiles, 256, 0, st>>>(pa);
+        CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
+        if (pay)
+          k_part_scatter<KW, VT, SAMPLE, true><<<(int)ntiles, 256, 0, st>>>(pa);
+        else
+          k_part_scatter<KW, VT, SAMPLE, false><<<(int)ntiles, 256, 0, st>>>(pa);
+        HIPCHK(hipGetLastError());
+        std::swap(cur, oth);
+        shift += dbits;
+      }
+    }
+    HIPCHK(hipEventRecord(X->ev[2], st));
+    // ---- bucket reduce ----
+    RedArgs ra{};
+    ra.in = *cur;
+    ra.nrec = nrec;
+    ra.G = G;
+    ra.n = n;
+    ra.auxbit = auxbit;
+    ra.e0 = J.e0;
+    ra.nd = J.nd;
+    ra.hpp = T.hpp;
+    ra.jtri = T.jtri;
+    ra.sstri = T.sstri;
+    ra.V = V;
+    ra.P = P;
+    ra.U = U;
+    ra.overflow = overflow;
+    ra.want_u = J.want_u ? 1 : 0;
+    const size_t diag_bytes = (size_t)(n + n * n) * sizeof(double);
+    const size_t static_bytes = sizeof(RedShared<KW, C, SAMPLE, VT>);
+    size_t dyn = 0;
+    if (static_bytes + diag_bytes <= 160 * 1024) {
+      dyn = diag_bytes;
+      ra.diag_in_lds = 1;
+    }
+    HIPCHK(hipFuncSetAttribute((const void*)k_reduce<KW, C, SAMPLE, VT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<size_t>(dyn, 8)));
+    k_fill_u32<<<1, 64, 0, st>>>(overflow, 1, 0u);
+    const int64_t rgrid = std::min<int64_t>(G.nbucket, (int64_t)cus * 2);
+    k_reduce<KW, C, SAMPLE, VT><<<(int)rgrid, 256, std::max<size_t>(dyn, 8), st>>>(ra);
+    HIPCHK(hipGetLastError());
+    k_zero_result<<<1, 1, 0, st>>>(X->dres);
+    if (SAMPLE) {
+      k_final<<<J.nsamp, 1024, 0, st>>>(P, G.nbucket, 0, J.nsamp, overflow, dflag, X->dres, J.per_sample,
+                                         (int64_t)1 << G.bits_hash);
+    } else {
+      k_final<<<1, 1024, 0, st>>>(P, G.nbucket, 0, 1, overflow, dflag, X->dres, nullptr, 0);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(X->ev[3], st));
+    uint32_t hov = 0;
+    HIPCHK(hipMemcpyAsync(&J.res, X->dres, sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&hov, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hov) {
+      // a bucket held more records than fit in LDS: plan again with one more
+      // hash bit; the write pass regenerates the same records
+      if (G.bits_hash >= 30 || attempt >= 6)
+        return fail(SHCI_ERR_WORKSPACE, "a perturbative determinant has more kept terms than one bucket holds");
+      G.bits_hash += 1;
+      J.retries++;
+      continue;
+    }
+    float ms;
+    HIPCHK(hipEventElapsedTime(&ms, X->ev[0], X->ev[1]));
+    J.ms_gen = ms;
+    HIPCHK(hipEventElapsedTime(&ms, X->ev[1], X->ev[2]));
+    J.ms_sort = ms;
+    HIPCHK(hipEventElapsedTime(&ms, X->ev[2], X->ev[3]));
+    J.ms_reduce = ms;
+    J.nbucket = (int32_t)G.nbucket;
+
+    if (J.want_u && J.grad) {
+      LookupArgs L;
+      L.U = U;
+      L.nseg = P.nseg;
+      L.G = G;
+      g.L = L;
+      g.grad = J.grad;
+      k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
+      k_gen<KW, GEN_GRAD, false, VT><<<gen_grid, 256, 0, st>>>(g);
+      HIPCHK(hipGetLastError());
+    }
+    if (J.want_u && J.ex && J.ex->u_keys) {
+      k_nonv_counts<<<256, 256, 0, st>>>(P, G.nbucket, boff);
+      CHK(scan_exclusive<uint64_t, uint64_t>(boff, boff, G.nbucket, hsc, nullptr, st));
+      k_export_uniq<KW><<<1024, 64, 0, st>>>(U, P.nseg, boff, G.nbucket, n, J.ex->u_keys, J.ex->u_A,
+                                             J.ex->u_D, J.ex->u_cnt, J.ex->u_cap);
+      HIPCHK(hipGetLastError());
+    }
+    if (J.ex) {
+      J.ex->u_n = J.res.nuniq;
+      J.ex->t_n = nrec;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return SHCI_OK;
+  }
+}
+
+template <typename VT, bool SAMPLE>
+int dispatch_kw(Job& J) {
+  const int kw = key_words(J.ctx->T.n, J.sbits);
+  switch (kw) {
+    case 1: return run_job<1, VT, SAMPLE>(J);
+    case 2: return run_job<2, VT, SAMPLE>(J);
+    case 3: return run_job<3, VT, SAMPLE>(J);
+    case 4: return run_job<4, VT, SAMPLE>(J);
+    default: return fail(SHCI_ERR_NORB, "key of %d words unsupported", kw);
+  }
+}
+
+int dispatch(Job& J) {
+  if (J.sample)
+    return J.precision == SHCI_FP32C ? dispatch_kw<float, true>(J) : dispatch_kw<double, true>(J);
+  return J.precision == SHCI_FP32C ? dispatch_kw<float, false>(J) : dispatch_kw<double, false>(J);
+}
+
+int common_checks(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                  double eps2, int precision) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
+  if (!dets || !c) return fail(SHCI_ERR_ARG, "dets or c is NULL");
+  if (n_det < 1) return fail(SHCI_ERR_ARG, "n_det must be >= 1");
+  if (n_det >= (int64_t)0xffffffffll) return fail(SHCI_ERR_ARG, "n_det must be < 2^32-1");
+  if (!std::isfinite(e0)) return fail(SHCI_ERR_NONFINITE, "E0 is not finite");
+  if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(SHCI_ERR_ARG, "eps2 must be finite and >= 0");
+  if (precision != SHCI_FP64 && precision != SHCI_FP32C) return fail(SHCI_ERR_ARG, "unknown precision");
+  HIPCHK(hipSetDevice(ctx->device));
+  return SHCI_OK;
+}
+
+void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
+  if (!st) return;
+  st->n_terms = J.res.nterm;
+  st->n_terms_gen = J.res.ngen;
+  st->n_unique = J.res.nuniq;
+  st->n_intruder = J.res.nintr;
+  st->min_abs_denom = J.res.mind;
+  st->n_buckets = J.nbucket;
+  st->n_retries = J.retries;
+  st->ms_gen = J.ms_gen;
+  st->ms_sort = J.ms_sort;
+  st->ms_reduce = J.ms_reduce;
+  st->ms_total = ms_total;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* shci_pt2_last_error(void) { return g_msg; }
+
+const char* shci_pt2_version(void) { return "shci_pt2 0.1 (gfx950)"; }
+
+int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, const double* eri, void* stream,
+                        shci_pt2_ctx** out) {
+  if (!out) return fail(SHCI_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!h1 || !eri) return fail(SHCI_ERR_ARG, "h1 or eri is NULL");
+  if (n_orb < 2 || n_orb > 127) return fail(SHCI_ERR_NORB, "n_orb must be in [2, 127]");
+  if (n_alpha < 1 || n_alpha >= n_orb || n_beta < 1 || n_beta >= n_orb)
+    return fail(SHCI_ERR_NORB, "electron counts must be in [1, n_orb - 1]");
+  shci_pt2_ctx* X = new (std::nothrow) shci_pt2_ctx();
+  if (!X) return fail(SHCI_ERR_WORKSPACE, "out of host memory");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto bail = [&](int code) {
+    shci_pt2_ctx_destroy(X);
+    return code;
+  };
+  if (hipGetDevice(&X->device) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipGetDevice failed"));
+  Tables& T = X->T;
+  const int n = n_orb;
+  T.n = n;
+  T.na = n_alpha;
+  T.nb = n_beta;
+  T.nss = n * (n - 1) / 2;
+  T.lss = (int64_t)(n - 2) * (n - 3) / 2;
+  T.los = (int64_t)(n - 1) * (n - 1);
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  const int64_t nhb = (int64_t)T.nss * T.lss + n2 * T.los;
+  auto plan = [&](Carver& cv) {
+    T.h1 = cv.take<double>(n2);
+    T.sD = cv.take<double>(n3);
+    T.sJ = cv.take<double>(n3);
+    T.ubound = cv.take<double>(n2);
+    T.hpp = cv.take<double>(n);
+    T.jtri = cv.take<double>(n * (n + 1) / 2);
+    T.sstri = cv.take<double>(n * (n - 1) / 2 + 1);
+    T.hb_val = cv.take<double>(nhb);
+    T.hb_rs = cv.take<uint16_t>(nhb);
+    T.hb_max = cv.take<double>(T.nss + n2);
+    X->dflag = cv.take<uint32_t>(16);
+    X->dres = cv.take<DevResult>(1);
+  };
+  {
+    Carver cv(nullptr);
+    plan(cv);
+    int s = X->tables.ensure(cv.off, 0);
+    if (s) return bail(s);
+    Carver cv2(X->tables.p);
+    plan(cv2);
+  }
+  for (auto& e : X->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+  if (hipMemcpyAsync(T.h1, h1, n2 * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return bail(fail(SHCI_ERR_HIP, "copy of h1 failed"));
+  k_fill_u32<<<1, 64, 0, st>>>(X->dflag, 16, 0u);
+  if (build_tables(T, h1, eri, st, X->dflag) != 0)
+    return bail(fail(SHCI_ERR_HIP, "table build launch failed: %s", hipGetErrorString(hipGetLastError())));
+  uint32_t hf = 0;
+  if (hipMemcpyAsync(&hf, X->dflag, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return bail(fail(SHCI_ERR_HIP, "table build failed"));
+  if (hf) return bail(fail(SHCI_ERR_NONFINITE, "an integral is not finite"));
+  *out = X;
+  return SHCI_OK;
+}
+
+void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  ctx->tables.release();
+  ctx->small.release();
+  ctx->big.release();
+  delete ctx;
+}
+
+int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
+  ctx->ws_limit = bytes;
+  return SHCI_OK;
+}
+
+int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                 double eps2, int precision, void* stream, double* e2, shci_pt2_stats* st,
+                 shci_pt2_export* ex) {
+  CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  if (!e2) return fail(SHCI_ERR_ARG, "e2 is NULL");
+  Job J{};
+  J.ctx = ctx;
+  J.st = static_cast<hipStream_t>(stream);
+  J.dets = dets;
+  J.c = c;
+  J.ndet = n_det;
+  J.e0 = e0;
+  J.eps2 = eps2;
+  J.eps2_d = INFINITY;
+  J.precision = precision;
+  J.sample = false;
+  J.sbits = 0;
+  J.nsamp = 1;
+  J.nd = 0.0;
+  J.n_items = n_det;
+  J.ex = ex;
+  J.want_u = ex && ex->u_keys;
+  J.want_pay = ex && ex->t_keys;
+  CHK(dispatch(J));
+  float tot = 0.f;
+  (void)hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[3]);
+  *e2 = J.res.e2;
+  fill_stats(st, J, tot);
+  if (J.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                               (long long)J.res.nzero);
+  return SHCI_OK;
+}
+
+int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                  double eps2, int precision, void* stream, double* e2, double* de2_dc, double* de2_de0,
+                  shci_pt2_stats* st) {
+  CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  if (!de2_dc) return fail(SHCI_ERR_ARG, "de2_dc is NULL");
+  Job J{};
+  J.ctx = ctx;
+  J.st = static_cast<hipStream_t>(stream);
+  J.dets = dets;
+  J.c = c;
+  J.ndet = n_det;
+  J.e0 = e0;
+  J.eps2 = eps2;
+  J.eps2_d = INFINITY;
+  J.precision = precision;
+  J.nsamp = 1;
+  J.n_items = n_det;
+  J.want_u = true;
+  J.grad = de2_dc;
+  CHK(dispatch(J));
+  float tot = 0.f;
+  (void)hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[3]);
+  if (e2) *e2 = J.res.e2;
+  if (de2_de0) *de2_de0 = J.res.de0;
+  fill_stats(st, J, tot);
+  if (J.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                               (long long)J.res.nzero);
+  return SHCI_OK;
+}
+
+int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                    double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
+                    int precision, void* stream, double* per_sample, double* mean, double* sem,
+                    shci_pt2_stats* st) {
+  CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  if (!draws || !per_sample) return fail(SHCI_ERR_ARG, "draws or per_sample is NULL");
+  if (n_samples < 1 || n_draws < 2) return fail(SHCI_ERR_ARG, "need n_samples >= 1 and n_draws >= 2");
+  if (n_draws > MAX_DRAWS) return fail(SHCI_ERR_ARG, "n_draws must be <= %d", MAX_DRAWS);
+  if (!(eps2_d >= eps2)) return fail(SHCI_ERR_ARG, "eps2_d must be >= eps2");
+  const int sbits = std::max(1, ceil_log2((uint64_t)n_samples));
+  if (2 * ctx->T.n + sbits + 1 > 256) return fail(SHCI_ERR_NORB, "too many samples for this n_orb");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // items: distinct dets per sample
+  DevBuf items;
+  const int64_t cap = (int64_t)n_samples * n_draws;
+  {
+    size_t bytes = 0;
+    Carver cv(nullptr);
+    cv.take<uint32_t>(cap);
+    cv.take<uint32_t>(cap);
+    cv.take<uint32_t>(n_samples + 1);
+    cv.take<uint64_t>(n_samples + 1);
+    cv.take<uint32_t>(cap);
+    cv.take<uint32_t>(cap);
+    cv.take<uint32_t>(cap);
+    cv.take<double>(4);
+    ScanTmp tmp;
+    tmp.carve(cv, n_samples + 1);
+    bytes = cv.off;
+    CHK(items.ensure(bytes, 0));
+  }
+  Carver cv(items.p);
+  uint32_t* t_det = cv.take<uint32_t>(cap);
+  uint32_t* t_w = cv.take<uint32_t>(cap);
+  uint32_t* ucount = cv.take<uint32_t>(n_samples + 1);
+  uint64_t* uoff = cv.take<uint64_t>(n_samples + 1);
+  uint32_t* o_det = cv.take<uint32_t>(cap);
+  uint32_t* o_w = cv.take<uint32_t>(cap);
+  uint32_t* o_s = cv.take<uint32_t>(cap);
+  double* dsum = cv.take<double>(4);
+  ScanTmp tmp;
+  tmp.carve(cv, n_samples + 1);
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    items.release();
+    return code;
+  };
+  k_fill_u32<<<1, 64, 0, s>>>(ctx->dflag, 4, 0u);
+  k_sample_items<<<n_samples, 256, 0, s>>>(draws, n_draws, n_det, t_det, t_w, ucount, ctx->dflag);
+  k_sum_abs<<<1, 1024, 0, s>>>(c, n_det, dsum);
+  uint64_t* tot = uoff + n_samples;
+  int sc = scan_exclusive<uint32_t, uint64_t>(ucount, uoff, n_samples, tmp, tot, s);
+  if (sc) return done(sc);
+  k_sample_compact<<<n_samples, 256, 0, s>>>(t_det, t_w, ucount, uoff, n_draws, 0, o_det, o_w, o_s);
+  uint64_t hn = 0;
+  double hsum = 0.0;
+  uint32_t hf = 0;
+  if (hipMemcpyAsync(&hn, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hsum, dsum, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(fail(SHCI_ERR_HIP, "sample preparation failed"));
+  if (hf & 16u) return done(fail(SHCI_ERR_ARG, "a draw is >= n_det"));
+  if (!(hsum > 0.0) || !std::isfinite(hsum)) return done(fail(SHCI_ERR_NONFINITE, "sum |c| is not positive and finite"));
+  Job J{};
+  J.ctx = ctx;
+  J.st = s;
+  J.dets = dets;
+  J.c = c;
+  J.ndet = n_det;
+  J.e0 = e0;
+  J.eps2 = eps2;
+  J.eps2_d = eps2_d;
+  J.precision = precision;
+  J.sample = true;
+  J.sbits = sbits;
+  J.nsamp = n_samples;
+  J.nd = (double)n_draws;
+  J.sum_abs = hsum;
+  J.it_det = o_det;
+  J.it_w = o_w;
+  J.it_s = o_s;
+  J.n_items = (int64_t)hn;
+  J.per_sample = per_sample;
+  int r = dispatch(J);
+  if (r) return done(r);
+  std::vector<double> ps(n_samples);
+  if (hipMemcpyAsync(ps.data(), per_sample, n_samples * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(fail(SHCI_ERR_HIP, "copy of per-sample results failed"));
+  double m = 0.0;
+  for (double v : ps) m += v;
+  m /= n_samples;
+  double var = 0.0;
+  for (double v : ps) var += (v - m) * (v - m);
+  if (mean) *mean = m;
+  if (sem) *sem = n_samples > 1 ? std::sqrt(var / (n_samples - 1)) / std::sqrt((double)n_samples) : 0.0;
+  float tt = 0.f;
+  (void)hipEventElapsedTime(&tt, ctx->ev[0], ctx->ev[3]);
+  fill_stats(st, J, tt);
+  if (J.res.nzero) return done(fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                                    (long long)J.res.nzero));
+  return done(SHCI_OK);
+}
+
+}  // extern "C"

@@ -1,0 +1,369 @@
+// Excitation generator: one wavefront per source determinant (or per distinct
+// sampled determinant), persistent waves pulling work from an atomic counter.
+//
+// For each source det i it emits every single and double excitation a with
+// |H_ai| |c_i| > eps2 (screened PT2 equation, section II.B):
+//  * singles p->r: a per-(p,r) upper bound of |H_ai| skips hopeless pairs;
+//    survivors get the exact element h_pr + sum_k [...] accumulated in a
+//    fixed order (occupied alpha ascending, then occupied beta ascending);
+//  * doubles: for every occupied pair the heat-bath list of that pair is
+//    walked 64 entries at a time, in decreasing |value|, and the walk stops at
+//    the first entry that fails the screen (section II.A, heat-bath traversal
+//    with early exit).  Entries whose target orbitals are occupied are skipped.
+//  * fermion signs come from popcounts of the occupied bits between the
+//    orbitals involved; a same-spin double is p->r then q->s.
+// Lane-parallel emission uses ballot + mbcnt compaction, so the record order
+// is fixed by (source index, generation order) and the run is deterministic.
+#pragma once
+#include "kernels.hpp"
+
+namespace shci {
+
+enum GenMode { GEN_COUNT = 0, GEN_WRITE = 1, GEN_GRAD = 2 };
+
+struct VSet {
+  uint64_t* tab = nullptr;  // slots: fingerprint << 32 | index; ~0 = empty
+  uint64_t mask = 0;
+  const uint64_t* dets = nullptr;
+};
+
+struct LookupArgs {
+  Uniq U;
+  const int32_t* nseg = nullptr;
+  GroupPlan G;
+};
+
+struct GenArgs {
+  int n, na, nb;
+  const uint64_t* dets;
+  const double* c;
+  int64_t n_items;
+  // sample mode: distinct sampled determinants
+  const uint32_t* it_det;
+  const uint32_t* it_w;
+  const uint32_t* it_s;
+  double sum_abs;
+  double nd;
+  double eps2, eps2_d;
+  Tables T;
+  uint32_t* counts;
+  const uint64_t* offs;
+  Recs out;
+  uint32_t* counter;
+  int sbits, auxbit;
+  LookupArgs L;
+  double* grad;
+};
+
+SHCI_DEV int tri_inv(int u) {
+  // largest y with y(y-1)/2 <= u
+  int y = (int)floorf((1.0f + sqrtf(1.0f + 8.0f * (float)u)) * 0.5f);
+  while (y * (y - 1) / 2 > u) --y;
+  while ((y + 1) * y / 2 <= u) ++y;
+  return y;
+}
+
+// Find g = 2 A_a / D_a of a unique key (aux bit already clear).  Returns 0
+// if the key is not stored (members of V are stored with g = 0).
+template <int KW>
+SHCI_DEV double lookup_g(const uint64_t (&key)[KW], const LookupArgs& L) {
+  uint64_t h = hash_key<KW>(key);
+  const int bh = L.G.bits_hash;
+  uint64_t b = bh ? (h >> (64 - bh)) : 0ull;
+  uint32_t h2 = (uint32_t)((h << bh) >> 32);
+  uint64_t lo = L.U.start[b];
+  int cnt = L.nseg[b];
+  int a = 0, z = cnt;
+  while (a < z) {
+    int m = (a + z) >> 1;
+    if (L.U.h2[lo + m] < h2)
+      a = m + 1;
+    else
+      z = m;
+  }
+  for (int j = a; j < cnt && L.U.h2[lo + j] == h2; ++j) {
+    bool eq = true;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) eq = eq && (L.U.k[w][lo + j] == key[w]);
+    if (eq) return L.U.g[lo + j];
+  }
+  return 0.0;
+}
+
+template <int KW, int MODE, bool SAMPLE, typename VT>
+__global__ void __launch_bounds__(256) k_gen(GenArgs a) {
+  __shared__ uint8_t s_lists[4][4][128];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  uint8_t* occA = s_lists[wv][0];
+  uint8_t* virA = s_lists[wv][1];
+  uint8_t* occB = s_lists[wv][2];
+  uint8_t* virB = s_lists[wv][3];
+  const int n = a.n, na = a.na, nb = a.nb, va = n - a.na, vb = n - a.nb;
+  const double eps2 = a.eps2;
+  const Tables& T = a.T;
+
+  for (;;) {
+    uint32_t got = 0;
+    if (lane == 0) got = atomicAdd(a.counter, 1u);
+    const int64_t item = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)got);
+    if (item >= a.n_items) break;
+
+    int64_t i = item;
+    double w = 1.0;
+    uint32_t sid = 0;
+    if constexpr (SAMPLE) {
+      i = a.it_det[item];
+      w = (double)a.it_w[item];
+      sid = a.it_s[item];
+    }
+    const uint64_t A0 = a.dets[4 * i + 0], A1 = a.dets[4 * i + 1];
+    const uint64_t B0 = a.dets[4 * i + 2], B1 = a.dets[4 * i + 3];
+    const double ci = a.c[i];
+    const double absc = fabs(ci);
+    double pr = 1.0;
+    if constexpr (SAMPLE) pr = absc / a.sum_abs;
+
+    // occupied / virtual lists of both spins in LDS (wave-private)
+    {
+      const bool inlo = lane < n, inhi = lane + 64 < n;
+      const bool oa0 = inlo && ((A0 >> lane) & 1ull), oa1 = inhi && ((A1 >> lane) & 1ull);
+      const bool ob0 = inlo && ((B0 >> lane) & 1ull), ob1 = inhi && ((B1 >> lane) & 1ull);
+      uint64_t m;
+      m = ballot(oa0);
+      if (oa0) occA[rank_below(m)] = (uint8_t)lane;
+      int c0 = __popcll(m);
+      m = ballot(oa1);
+      if (oa1) occA[c0 + rank_below(m)] = (uint8_t)(lane + 64);
+      m = ballot(inlo && !oa0);
+      if (inlo && !oa0) virA[rank_below(m)] = (uint8_t)lane;
+      c0 = __popcll(m);
+      m = ballot(inhi && !oa1);
+      if (inhi && !oa1) virA[c0 + rank_below(m)] = (uint8_t)(lane + 64);
+      m = ballot(ob0);
+      if (ob0) occB[rank_below(m)] = (uint8_t)lane;
+      c0 = __popcll(m);
+      m = ballot(ob1);
+      if (ob1) occB[c0 + rank_below(m)] = (uint8_t)(lane + 64);
+      m = ballot(inlo && !ob0);
+      if (inlo && !ob0) virB[rank_below(m)] = (uint8_t)lane;
+      c0 = __popcll(m);
+      m = ballot(inhi && !ob1);
+      if (inhi && !ob1) virB[c0 + rank_below(m)] = (uint8_t)(lane + 64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    uint64_t obase = 0;
+    if constexpr (MODE == GEN_WRITE) obase = a.offs[item];
+    uint64_t cursor = 0;  // uniform
+    double gacc = 0.0;
+
+    auto emit = [&](bool keep, uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, double H) {
+      const uint64_t bal = ballot(keep);
+      if constexpr (MODE == GEN_COUNT) {
+        cursor += (uint64_t)__popcll(bal);
+      } else if constexpr (MODE == GEN_WRITE) {
+        if (keep) {
+          uint64_t key[KW];
+          pack_det<KW>(key, x0, x1, y0, y1, n);
+          const uint64_t pos = obase + cursor + (uint64_t)rank_below(bal);
+          if constexpr (SAMPLE) {
+            put_bits<KW>(key, (uint64_t)sid, 0ull, 2 * n);
+            if (fabs(H) * absc > a.eps2_d) put_bits<KW>(key, 1ull, 0ull, a.auxbit);
+            const double ch = ci * H;
+            const double xv = w * ch / pr;
+            const double yv = (w * (a.nd - 1.0) / pr - w * w / (pr * pr)) * ch * ch;
+            static_cast<VT*>(a.out.v)[pos] = (VT)xv;
+            static_cast<VT*>(a.out.v2)[pos] = (VT)yv;
+          } else {
+            VT t;
+            if constexpr (sizeof(VT) == 4)
+              t = (float)H * (float)ci;
+            else
+              t = H * ci;
+            static_cast<VT*>(a.out.v)[pos] = t;
+          }
+#pragma unroll
+          for (int q = 0; q < KW; ++q) a.out.k[q][pos] = key[q];
+          if (a.out.pay) a.out.pay[pos] = (uint32_t)i;
+        }
+        cursor += (uint64_t)__popcll(bal);
+      } else {  // GEN_GRAD
+        if (keep) {
+          uint64_t key[KW];
+          pack_det<KW>(key, x0, x1, y0, y1, n);
+          gacc += H * lookup_g<KW>(key, a.L);
+        }
+      }
+    };
+
+    // ---------------- singles ----------------
+    const int nsa = na * va, nsing = nsa + nb * vb;
+    for (int j0 = 0; j0 < nsing; j0 += 64) {
+      const int j = j0 + lane;
+      const bool valid = j < nsing;
+      const bool alpha = j < nsa;
+      int p = 0, r = 0;
+      if (valid) {
+        if (alpha) {
+          p = occA[j / va];
+          r = virA[j % va];
+        } else {
+          const int jj = j - nsa;
+          p = occB[jj / vb];
+          r = virB[jj % vb];
+        }
+      }
+      const bool cand = valid && (T.ubound[p * n + r] * absc > eps2);
+      double H = 0.0;
+      if (cand) {
+        const size_t pr_off = (size_t)p * n + r;
+        const size_t nn = (size_t)n * n;
+        double acc = T.h1[pr_off];
+        for (int kk = 0; kk < na; ++kk) {
+          const int k = occA[kk];
+          if (alpha) {
+            if (k != p) acc = acc + T.sD[k * nn + pr_off];
+          } else {
+            acc = acc + T.sJ[k * nn + pr_off];
+          }
+        }
+        for (int kk = 0; kk < nb; ++kk) {
+          const int k = occB[kk];
+          if (!alpha) {
+            if (k != p) acc = acc + T.sD[k * nn + pr_off];
+          } else {
+            acc = acc + T.sJ[k * nn + pr_off];
+          }
+        }
+        const int par = alpha ? between(A0, A1, p, r) : between(B0, B1, p, r);
+        H = (par & 1) ? -acc : acc;
+      }
+      const bool keep = cand && (fabs(H) * absc > eps2);
+      uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
+      if (alpha) {
+        flip(x0, x1, p);
+        flip(x0, x1, r);
+      } else {
+        flip(y0, y1, p);
+        flip(y0, y1, r);
+      }
+      emit(keep, x0, x1, y0, y1, H);
+    }
+
+    // ---------------- doubles ----------------
+    const int caa = na * (na - 1) / 2, cbb = nb * (nb - 1) / 2;
+    const int npairs = caa + cbb + na * nb;
+    for (int u0 = 0; u0 < npairs; u0 += 64) {
+      const int u = u0 + lane;
+      bool need = false;
+      if (u < npairs) {
+        int key;
+        if (u < caa) {
+          const int y = tri_inv(u), x = u - y * (y - 1) / 2;
+          const int p = occA[x], q = occA[y];
+          key = q * (q - 1) / 2 + p;
+        } else if (u < caa + cbb) {
+          const int v = u - caa;
+          const int y = tri_inv(v), x = v - y * (y - 1) / 2;
+          const int p = occB[x], q = occB[y];
+          key = q * (q - 1) / 2 + p;
+        } else {
+          const int v = u - caa - cbb;
+          const int p = occA[v / nb], q = occB[v % nb];
+          key = T.nss + p * n + q;
+        }
+        need = T.hb_max[key] * absc > eps2;
+      }
+      uint64_t todo = ballot(need);
+      while (todo) {
+        const int jb = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1ull;
+        const int uu = u0 + jb;  // uniform
+        int p, q, type;          // type 0: alpha-alpha, 1: beta-beta, 2: alpha-beta
+        if (uu < caa) {
+          const int y = tri_inv(uu), x = uu - y * (y - 1) / 2;
+          p = occA[x];
+          q = occA[y];
+          type = 0;
+        } else if (uu < caa + cbb) {
+          const int v = uu - caa;
+          const int y = tri_inv(v), x = v - y * (y - 1) / 2;
+          p = occB[x];
+          q = occB[y];
+          type = 1;
+        } else {
+          const int v = uu - caa - cbb;
+          p = occA[v / nb];
+          q = occB[v % nb];
+          type = 2;
+        }
+        int64_t off, len;
+        if (type < 2) {
+          off = (int64_t)(q * (q - 1) / 2 + p) * T.lss;
+          len = T.lss;
+        } else {
+          off = (int64_t)T.nss * T.lss + (int64_t)(p * n + q) * T.los;
+          len = T.los;
+        }
+        for (int64_t e0 = 0; e0 < len; e0 += 64) {
+          const int64_t e = e0 + lane;
+          double v = 0.0;
+          uint16_t rs = 0;
+          if (e < len) {
+            v = T.hb_val[off + e];
+            rs = T.hb_rs[off + e];
+          }
+          const bool pass = (e < len) && (fabs(v) * absc > eps2);
+          const uint64_t pb = ballot(pass);
+          if (pb == 0ull) break;
+          const int r = rs & 0xff, s = rs >> 8;
+          bool keep = pass;
+          uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
+          int par = 0;
+          if (type == 0) {
+            keep = keep && !occ(A0, A1, r) && !occ(A0, A1, s);
+            par = between(x0, x1, p, r);
+            flip(x0, x1, p);
+            flip(x0, x1, r);
+            par += between(x0, x1, q, s);
+            flip(x0, x1, q);
+            flip(x0, x1, s);
+          } else if (type == 1) {
+            keep = keep && !occ(B0, B1, r) && !occ(B0, B1, s);
+            par = between(y0, y1, p, r);
+            flip(y0, y1, p);
+            flip(y0, y1, r);
+            par += between(y0, y1, q, s);
+            flip(y0, y1, q);
+            flip(y0, y1, s);
+          } else {
+            keep = keep && !occ(A0, A1, r) && !occ(B0, B1, s);
+            par = between(A0, A1, p, r) + between(B0, B1, q, s);
+            flip(x0, x1, p);
+            flip(x0, x1, r);
+            flip(y0, y1, q);
+            flip(y0, y1, s);
+          }
+          const double H = (par & 1) ? -v : v;
+          emit(keep, x0, x1, y0, y1, H);
+          if (pb != ~0ull) break;
+        }
+      }
+    }
+
+    if constexpr (MODE == GEN_COUNT) {
+      if (lane == 0) a.counts[item] = (uint32_t)cursor;
+    }
+    if constexpr (MODE == GEN_GRAD) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) gacc += __shfl_xor(gacc, o);
+      if (lane == 0) a.grad[i] = gacc;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+}  // namespace shci

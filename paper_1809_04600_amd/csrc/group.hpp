@@ -1,0 +1,706 @@
+// Grouping of screened terms by perturbative determinant a, and the reduction
+// of each group to its contribution A_a^2 / (E0 - H_aa).
+//
+// The paper accumulates the partial sums A_a = sum_i H_ai c_i in a concurrent
+// hash table (section V.C).  Here the terms are materialised as records
+// (packed key of a, value) and grouped by sorting instead:
+//  1. a least-significant-digit radix partition of the records on the bucket
+//     id (the top bits of a 64-bit hash of the key; in sample mode the sample
+//     id sits above them), 8 bits per pass, stable;
+//  2. per bucket, in LDS: an LSD radix sort on the next 32 hash bits (4 passes
+//     of 8 bits, stable), with a fallback to a full-key LSD sort when two
+//     different keys of a bucket share those bits, so equal keys become
+//     adjacent; then a segmented reduction in record order (deterministic);
+//  3. members of V are dropped by a lookup in a hash set of V; H_aa is
+//     evaluated from LDS copies of h_pp, (pp|qq) and (pp|qq)-(pq|qp); the
+//     contribution and dE2/dE0 term are summed per bucket in a fixed order;
+//  4. the bucket partials are summed by a fixed-shape tree.
+#pragma once
+#include "gen.hpp"
+
+namespace shci {
+
+constexpr int PTILE_ITEMS = 16;               // records per thread per partition tile
+constexpr int PTILE = 256 * PTILE_ITEMS;      // records per partition tile
+
+template <int KW>
+SHCI_DEV void load_key(const Recs& r, int64_t idx, uint64_t (&k)[KW]) {
+#pragma unroll
+  for (int w = 0; w < KW; ++w) k[w] = r.k[w][idx];
+}
+
+// bucket id of a key (aux bit cleared) and its 64-bit hash
+template <int KW>
+SHCI_DEV uint64_t bucket_id(const uint64_t (&k)[KW], const GroupPlan& G, int n, uint64_t& h) {
+  h = hash_key<KW>(k);
+  uint64_t b = G.bits_hash ? (h >> (64 - G.bits_hash)) : 0ull;
+  if (G.sbits) {
+    uint64_t s0, s1;
+    get_bits<KW>(k, 2 * n, G.sbits, s0, s1);
+    b |= s0 << G.bits_hash;
+  }
+  return b;
+}
+
+SHCI_DEV uint32_t sort_hash(uint64_t h, const GroupPlan& G) {
+  return (uint32_t)((h << G.bits_hash) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Block-level stable multisplit of up to 256 items per round (8-bit digits).
+// run[d] holds the next free slot of digit d; wcnt is per-wave scratch that
+// must be zero on entry and is left zero.
+// ---------------------------------------------------------------------------
+struct SplitScratch {
+  uint32_t run[256];
+  uint16_t wcnt[4][256];
+};
+
+SHCI_DEV uint32_t split_round(SplitScratch& S, bool valid, uint32_t d, int dbits) {
+  const int wv = threadIdx.x >> 6;
+  uint64_t peers = ballot(valid);
+  for (int b = 0; b < dbits; ++b) {
+    const bool on = (d >> b) & 1u;
+    const uint64_t bb = ballot(on);
+    peers &= on ? bb : ~bb;
+  }
+  const int r = rank_below(peers);
+  if (valid && r == 0) S.wcnt[wv][d] = (uint16_t)__popcll(peers);
+  __syncthreads();
+  uint32_t pos = 0;
+  if (valid) {
+    pos = S.run[d] + (uint32_t)r;
+    for (int w = 0; w < wv; ++w) pos += S.wcnt[w][d];
+  }
+  __syncthreads();
+  {
+    const int t = threadIdx.x;
+    S.run[t] += (uint32_t)S.wcnt[0][t] + S.wcnt[1][t] + S.wcnt[2][t] + S.wcnt[3][t];
+    S.wcnt[0][t] = S.wcnt[1][t] = S.wcnt[2][t] = S.wcnt[3][t] = 0;
+  }
+  __syncthreads();
+  return pos;
+}
+
+// ---------------------------------------------------------------------------
+// Partition pass kernels
+// ---------------------------------------------------------------------------
+struct PassArgs {
+  Recs in, out;
+  int64_t n;
+  GroupPlan G;
+  int nbits_n;  // orbitals (for the sample-id position)
+  int auxbit;
+  int shift, dbits;
+  uint32_t* hist;        // [2^dbits][ntiles]
+  const uint32_t* offs;  // exclusive scan of hist
+  int ntiles;
+};
+
+template <int KW>
+__global__ void __launch_bounds__(256) k_part_hist(PassArgs a) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * PTILE;
+  const uint32_t dmask = (1u << a.dbits) - 1u;
+  for (int j = 0; j < PTILE_ITEMS; ++j) {
+    const int64_t idx = base + (int64_t)j * 256 + threadIdx.x;
+    if (idx < a.n) {
+      uint64_t k[KW];
+      load_key<KW>(a.in, idx, k);
+      clear_aux<KW>(k, a.auxbit);
+      uint64_t h;
+      const uint64_t b = bucket_id<KW>(k, a.G, a.nbits_n, h);
+      atomicAdd(&cnt[(uint32_t)(b >> a.shift) & dmask], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (1 << a.dbits)) a.hist[(int64_t)threadIdx.x * a.ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+template <int KW, typename VT, bool V2, bool PAY>
+__global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
+  __shared__ SplitScratch S;
+  __shared__ uint32_t base_off[256];
+  const int t = threadIdx.x;
+  S.run[t] = 0;
+  S.wcnt[0][t] = S.wcnt[1][t] = S.wcnt[2][t] = S.wcnt[3][t] = 0;
+  base_off[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + blockIdx.x] : 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * PTILE;
+  const uint32_t dmask = (1u << a.dbits) - 1u;
+  for (int j = 0; j < PTILE_ITEMS; ++j) {
+    const int64_t idx = base + (int64_t)j * 256 + t;
+    const bool valid = idx < a.n;
+    uint64_t k[KW];
+    uint32_t d = 0;
+    if (valid) {
+      load_key<KW>(a.in, idx, k);
+      uint64_t kc[KW];
+#pragma unroll
+      for (int w = 0; w < KW; ++w) kc[w] = k[w];
+      clear_aux<KW>(kc, a.auxbit);
+      uint64_t h;
+      d = (uint32_t)(bucket_id<KW>(kc, a.G, a.nbits_n, h) >> a.shift) & dmask;
+    }
+    const uint32_t r = split_round(S, valid, d, a.dbits);
+    if (valid) {
+      const int64_t pos = (int64_t)base_off[d] + (r);
+#pragma unroll
+      for (int w = 0; w < KW; ++w) a.out.k[w][pos] = k[w];
+      static_cast<VT*>(a.out.v)[pos] = static_cast<const VT*>(a.in.v)[idx];
+      if constexpr (V2) static_cast<VT*>(a.out.v2)[pos] = static_cast<const VT*>(a.in.v2)[idx];
+      if constexpr (PAY) a.out.pay[pos] = a.in.pay[idx];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bucket reduce
+// ---------------------------------------------------------------------------
+struct RedArgs {
+  Recs in;
+  int64_t nrec;
+  GroupPlan G;
+  int n, auxbit;
+  double e0, nd;
+  const double* hpp;
+  const double* jtri;
+  const double* sstri;
+  int diag_in_lds;
+  VSet V;
+  Partials P;
+  Uniq U;
+  uint32_t* overflow;
+  int want_u;
+};
+
+template <int KW>
+SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
+  const uint64_t h = hash_key<KW>(k);
+  uint64_t slot = h & V.mask;
+  const uint32_t fp = (uint32_t)(h >> 32);
+  for (uint64_t probe = 0; probe <= V.mask; ++probe) {
+    const uint64_t e = V.tab[slot];
+    if (e == ~0ull) return false;
+    if ((uint32_t)(e >> 32) == fp) {
+      const uint64_t i = e & 0xffffffffull;
+      uint64_t dk[KW];
+      pack_det<KW>(dk, V.dets[4 * i], V.dets[4 * i + 1], V.dets[4 * i + 2], V.dets[4 * i + 3], n);
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < KW; ++w) eq = eq && (dk[w] == k[w]);
+      if (eq) return true;
+    }
+    slot = (slot + 1) & V.mask;
+  }
+  return false;
+}
+
+template <int KW>
+__global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd) return;
+  uint64_t k[KW];
+  pack_det<KW>(k, V.dets[4 * i], V.dets[4 * i + 1], V.dets[4 * i + 2], V.dets[4 * i + 3], n);
+  const uint64_t h = hash_key<KW>(k);
+  const uint32_t fp = (uint32_t)(h >> 32);
+  const uint64_t entry = ((uint64_t)fp << 32) | (uint64_t)i;
+  uint64_t slot = h & V.mask;
+  for (uint64_t probe = 0; probe <= V.mask; ++probe) {
+    const unsigned long long old =
+        atomicCAS((unsigned long long*)&V.tab[slot], ~0ull, (unsigned long long)entry);
+    if (old == ~0ull) return;
+    if ((uint32_t)(old >> 32) == fp) {
+      const uint64_t j = old & 0xffffffffull;
+      bool eq = true;
+      for (int w = 0; w < 4; ++w) eq = eq && (V.dets[4 * j + w] == V.dets[4 * i + w]);
+      if (eq) {
+        atomicOr(flag, 4u);
+        return;
+      }
+    }
+    slot = (slot + 1) & V.mask;
+  }
+  atomicOr(flag, 8u);  // table full (cannot happen at load <= 1/2)
+}
+
+// H_aa from LDS tables, in the order: h_pp over alpha then beta, same-spin
+// pairs (alpha, then beta), then alpha x beta pairs.
+SHCI_DEV double diag_energy(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const double* hpp,
+                            const double* jtri, const double* sstri) {
+  double e = 0.0;
+  uint64_t m0 = a0, m1 = a1;
+  while (m0 | m1) {
+    const int p = m0 ? __ffsll((unsigned long long)m0) - 1 : 64 + __ffsll((unsigned long long)m1) - 1;
+    if (m0) m0 &= m0 - 1; else m1 &= m1 - 1;
+    e = e + hpp[p];
+  }
+  m0 = b0; m1 = b1;
+  while (m0 | m1) {
+    const int p = m0 ? __ffsll((unsigned long long)m0) - 1 : 64 + __ffsll((unsigned long long)m1) - 1;
+    if (m0) m0 &= m0 - 1; else m1 &= m1 - 1;
+    e = e + hpp[p];
+  }
+  for (int sp = 0; sp < 2; ++sp) {
+    uint64_t x0 = sp ? b0 : a0, x1 = sp ? b1 : a1;
+    while (x0 | x1) {
+      const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
+      if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
+      uint64_t y0 = x0, y1 = x1;  // orbitals above p
+      while (y0 | y1) {
+        const int q = y0 ? __ffsll((unsigned long long)y0) - 1 : 64 + __ffsll((unsigned long long)y1) - 1;
+        if (y0) y0 &= y0 - 1; else y1 &= y1 - 1;
+        e = e + sstri[q * (q - 1) / 2 + p];
+      }
+    }
+  }
+  uint64_t x0 = a0, x1 = a1;
+  while (x0 | x1) {
+    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
+    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
+    uint64_t y0 = b0, y1 = b1;
+    while (y0 | y1) {
+      const int q = y0 ? __ffsll((unsigned long long)y0) - 1 : 64 + __ffsll((unsigned long long)y1) - 1;
+      if (y0) y0 &= y0 - 1; else y1 &= y1 - 1;
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      e = e + jtri[hi * (hi + 1) / 2 + lo];
+    }
+  }
+  return e;
+}
+
+// exclusive scan of 256 values held one per thread; returns the prefix,
+// total in *tot (all threads)
+SHCI_DEV uint32_t block_scan256(uint32_t v, uint32_t* sh, uint32_t* tot) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    uint32_t x = (t >= o) ? sh[t - o] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  *tot = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+template <int C>
+struct SortBufs {
+  uint32_t h2a[C], h2b[C];
+  uint16_t ia[C], ib[C];
+};
+
+// one stable 8-bit LSD pass over M items: (sh, si) -> (dh, di)
+template <int C, class DigitF>
+SHCI_DEV void lds_pass(int M, const uint32_t* sh, const uint16_t* si, uint32_t* dh, uint16_t* di,
+                       SplitScratch& S, uint32_t* scan_sh, DigitF digit) {
+  const int t = threadIdx.x;
+  S.run[t] = 0;
+  __syncthreads();
+  for (int j = t; j < M; j += 256) atomicAdd(&S.run[digit(j)], 1u);
+  __syncthreads();
+  uint32_t tot;
+  const uint32_t start = block_scan256(S.run[t], scan_sh, &tot);
+  __syncthreads();
+  S.run[t] = start;
+  __syncthreads();
+  for (int j0 = 0; j0 < M; j0 += 256) {
+    const int j = j0 + t;
+    const bool valid = j < M;
+    const uint32_t d = valid ? digit(j) : 0u;
+    const uint32_t pos = split_round(S, valid, d, 8);
+    if (valid) {
+      dh[pos] = sh[j];
+      di[pos] = si[j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int KW, int C, bool SAMPLE, typename VT>
+struct RedShared {
+  uint64_t key[KW][C];
+  VT v[C];
+  VT v2[SAMPLE ? C : 1];
+  SortBufs<C> sb;
+  uint16_t seg[C + 1];
+  SplitScratch S;
+  uint32_t scan[256];
+  double red[256];
+  double red2[256];
+  int64_t ired[256];
+  int64_t ired2[256];
+  int32_t ired3[256];
+  int32_t ired4[256];
+  int32_t ired5[256];
+  double dmin[256];
+  uint64_t lohi[2];
+  uint32_t flag;
+  uint32_t nseg;
+};
+
+template <int KW, int C, bool SAMPLE, typename VT>
+__global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
+  extern __shared__ double s_diag[];
+  __shared__ RedShared<KW, C, SAMPLE, VT> R;
+  const int t = threadIdx.x;
+  const int n = a.n;
+  R.S.wcnt[0][t] = R.S.wcnt[1][t] = R.S.wcnt[2][t] = R.S.wcnt[3][t] = 0;
+  // diagonal tables: h_pp [n], (pp|qq) triangle incl. diagonal, J-K triangle excl.
+  const double* s_hpp = a.hpp;
+  const double* s_jt = a.jtri;
+  const double* s_st = a.sstri;
+  if (a.diag_in_lds) {
+    double* h = s_diag;
+    double* jt = s_diag + n;
+    double* st = jt + n * (n + 1) / 2;
+    for (int x = t; x < n; x += 256) h[x] = a.hpp[x];
+    for (int x = t; x < n * (n + 1) / 2; x += 256) jt[x] = a.jtri[x];
+    for (int x = t; x < n * (n - 1) / 2; x += 256) st[x] = a.sstri[x];
+    s_hpp = h;
+    s_jt = jt;
+    s_st = st;
+  }
+  __syncthreads();
+
+  const int64_t nb = a.G.nbucket;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    // bucket bounds by binary search on the (sorted) bucket ids
+    if (t < 2) {
+      const uint64_t target = (uint64_t)b + (uint64_t)t;
+      int64_t lo = 0, hi = a.nrec;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        uint64_t k[KW];
+        load_key<KW>(a.in, mid, k);
+        clear_aux<KW>(k, a.auxbit);
+        uint64_t h;
+        if (bucket_id<KW>(k, a.G, n, h) < target)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      R.lohi[t] = (uint64_t)lo;
+    }
+    if (t == 0) R.flag = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)R.lohi[0];
+    const int M = (int)((int64_t)R.lohi[1] - lo);
+    if (M > C) {
+      if (t == 0) {
+        atomicOr(a.overflow, 1u);
+        a.P.e2[b] = 0.0;
+        a.P.de0[b] = 0.0;
+        a.P.nterm[b] = 0;
+        a.P.ngen[b] = 0;
+        a.P.nuniq[b] = 0;
+        a.P.nintr[b] = 0;
+        a.P.nzero[b] = 0;
+        a.P.mind[b] = INFINITY;
+        a.P.nseg[b] = 0;
+        if (a.want_u) a.U.start[b] = (uint64_t)lo;
+      }
+      __syncthreads();
+      continue;
+    }
+    // load records
+    for (int j = t; j < M; j += 256) {
+      uint64_t k[KW];
+      load_key<KW>(a.in, lo + j, k);
+#pragma unroll
+      for (int w = 0; w < KW; ++w) R.key[w][j] = k[w];
+      R.v[j] = static_cast<const VT*>(a.in.v)[lo + j];
+      if constexpr (SAMPLE) R.v2[j] = static_cast<const VT*>(a.in.v2)[lo + j];
+      clear_aux<KW>(k, a.auxbit);
+      R.sb.h2a[j] = sort_hash(hash_key<KW>(k), a.G);
+      R.sb.ia[j] = (uint16_t)j;
+    }
+    __syncthreads();
+    // LSD sort on the 32-bit in-bucket hash
+    for (int pass = 0; pass < 4; ++pass) {
+      const int sh = pass * 8;
+      if ((pass & 1) == 0)
+        lds_pass<C>(M, R.sb.h2a, R.sb.ia, R.sb.h2b, R.sb.ib, R.S, R.scan,
+                    [&](int j) { return (R.sb.h2a[j] >> sh) & 0xffu; });
+      else
+        lds_pass<C>(M, R.sb.h2b, R.sb.ib, R.sb.h2a, R.sb.ia, R.S, R.scan,
+                    [&](int j) { return (R.sb.h2b[j] >> sh) & 0xffu; });
+    }
+    auto key_eq = [&](int x, int y) {
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < KW; ++w) {
+        uint64_t kx = R.key[w][x], ky = R.key[w][y];
+        if (w == (a.auxbit >> 6)) {
+          kx &= ~(1ull << (a.auxbit & 63));
+          ky &= ~(1ull << (a.auxbit & 63));
+        }
+        eq = eq && (kx == ky);
+      }
+      return eq;
+    };
+    // different keys sharing the 32 hash bits: sort by the full key first
+    for (int j = t + 1; j < M; j += 256)
+      if (R.sb.h2a[j] == R.sb.h2a[j - 1] && !key_eq(R.sb.ia[j], R.sb.ia[j - 1])) R.flag = 1;
+    __syncthreads();
+    if (R.flag) {
+      // restart from load order: h2a/ia were permuted; rebuild identity order
+      for (int j = t; j < M; j += 256) {
+        uint64_t k[KW];
+#pragma unroll
+        for (int w = 0; w < KW; ++w) k[w] = R.key[w][j];
+        clear_aux<KW>(k, a.auxbit);
+        R.sb.h2a[j] = sort_hash(hash_key<KW>(k), a.G);
+        R.sb.ia[j] = (uint16_t)j;
+      }
+      __syncthreads();
+      const int keybits = a.auxbit;  // all grouping bits lie below the aux bit
+      const int kpasses = (keybits + 7) / 8;
+      bool in_a = true;
+      for (int pass = 0; pass < kpasses + 4; ++pass) {
+        auto digit_key = [&](int j) -> uint32_t {
+          const int idx = in_a ? R.sb.ia[j] : R.sb.ib[j];
+          const int bit = pass * 8;
+          const int w = bit >> 6, o = bit & 63;
+          uint64_t x = 0;
+#pragma unroll
+          for (int q = 0; q < KW; ++q)
+            if (q == w) x = R.key[q][idx];
+          uint32_t dgt = (uint32_t)(x >> o) & 0xffu;
+          // stay below the aux bit
+          const int hi = keybits - bit;
+          if (hi < 8) dgt &= (1u << hi) - 1u;
+          return dgt;
+        };
+        auto digit_h2 = [&](int j) -> uint32_t {
+          const uint32_t hv = in_a ? R.sb.h2a[j] : R.sb.h2b[j];
+          return (hv >> ((pass - kpasses) * 8)) & 0xffu;
+        };
+        if (pass < kpasses) {
+          if (in_a)
+            lds_pass<C>(M, R.sb.h2a, R.sb.ia, R.sb.h2b, R.sb.ib, R.S, R.scan, digit_key);
+          else
+            lds_pass<C>(M, R.sb.h2b, R.sb.ib, R.sb.h2a, R.sb.ia, R.S, R.scan, digit_key);
+        } else {
+          if (in_a)
+            lds_pass<C>(M, R.sb.h2a, R.sb.ia, R.sb.h2b, R.sb.ib, R.S, R.scan, digit_h2);
+          else
+            lds_pass<C>(M, R.sb.h2b, R.sb.ib, R.sb.h2a, R.sb.ia, R.S, R.scan, digit_h2);
+        }
+        in_a = !in_a;
+      }
+      if (!in_a) {
+        for (int j = t; j < M; j += 256) {
+          R.sb.h2a[j] = R.sb.h2b[j];
+          R.sb.ia[j] = R.sb.ib[j];
+        }
+        __syncthreads();
+      }
+    }
+    // segment heads in sorted order -> segment starts
+    const int per = (M + 255) / 256;
+    const int j_lo = t * per, j_hi = min(M, j_lo + per);
+    uint32_t cnt = 0;
+    for (int j = j_lo; j < j_hi; ++j) cnt += (j == 0) || !key_eq(R.sb.ia[j], R.sb.ia[j - 1]);
+    uint32_t nsg;
+    uint32_t sidx = block_scan256(cnt, R.scan, &nsg);
+    for (int j = j_lo; j < j_hi; ++j)
+      if ((j == 0) || !key_eq(R.sb.ia[j], R.sb.ia[j - 1])) R.seg[sidx++] = (uint16_t)j;
+    if (t == 0) R.seg[nsg] = (uint16_t)M;
+    __syncthreads();
+
+    double e2p = 0.0, de0p = 0.0, dmn = INFINITY;
+    int64_t nterm = 0, ngen = 0;
+    int32_t nuniq = 0, nintr = 0, nzero = 0;
+    for (uint32_t s = t; s < nsg; s += 256) {
+      const int j0 = R.seg[s], j1 = R.seg[s + 1];
+      const int first = R.sb.ia[j0];
+      double X = 0.0, Y = 0.0, Xd = 0.0, Yd = 0.0;
+      if constexpr (sizeof(VT) == 4) {
+        float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sxd = 0.f, cxd = 0.f, syd = 0.f, cyd = 0.f;
+        for (int j = j0; j < j1; ++j) {
+          const int id = R.sb.ia[j];
+          two_sum_f32(sx, cx, (float)R.v[id]);
+          if constexpr (SAMPLE) {
+            two_sum_f32(sy, cy, (float)R.v2[id]);
+            if ((R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
+              two_sum_f32(sxd, cxd, (float)R.v[id]);
+              two_sum_f32(syd, cyd, (float)R.v2[id]);
+            }
+          }
+        }
+        X = (double)sx + (double)cx;
+        Y = (double)sy + (double)cy;
+        Xd = (double)sxd + (double)cxd;
+        Yd = (double)syd + (double)cyd;
+      } else {
+        for (int j = j0; j < j1; ++j) {
+          const int id = R.sb.ia[j];
+          X = X + (double)R.v[id];
+          if constexpr (SAMPLE) {
+            Y = Y + (double)R.v2[id];
+            if ((R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
+              Xd = Xd + (double)R.v[id];
+              Yd = Yd + (double)R.v2[id];
+            }
+          }
+        }
+      }
+      uint64_t k[KW];
+#pragma unroll
+      for (int w = 0; w < KW; ++w) k[w] = R.key[w][first];
+      clear_aux<KW>(k, a.auxbit);
+      uint64_t a0, a1, b0, b1;
+      unpack_det<KW>(k, n, a0, a1, b0, b1);
+      uint64_t dk[KW];
+      pack_det<KW>(dk, a0, a1, b0, b1, n);  // det bits only (no sample id)
+      const bool inv = vset_contains<KW>(a.V, dk, n);
+      const int cntk = j1 - j0;
+      ngen += cntk;
+      double Dd = 0.0, g = 0.0;
+      if (!inv) {
+        const double haa = diag_energy(a0, a1, b0, b1, s_hpp, s_jt, s_st);
+        Dd = a.e0 - haa;
+        double contrib;
+        if constexpr (SAMPLE)
+          contrib = ((X * X + Y) - (Xd * Xd + Yd)) / (Dd * a.nd * (a.nd - 1.0));
+        else
+          contrib = X * X / Dd;
+        e2p += contrib;
+        de0p += -(X * X) / (Dd * Dd);
+        g = 2.0 * X / Dd;
+        nterm += cntk;
+        nuniq += 1;
+        nintr += Dd > 0.0;
+        nzero += Dd == 0.0;
+        dmn = fmin(dmn, fabs(Dd));
+      }
+      if (a.want_u) {
+        const int64_t o = lo + s;
+#pragma unroll
+        for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
+        a.U.h2[o] = R.sb.h2a[j0];
+        a.U.A[o] = X;
+        a.U.D[o] = Dd;
+        a.U.g[o] = g;
+        a.U.cnt[o] = inv ? -cntk : cntk;
+      }
+    }
+    // fixed-shape block reductions
+    R.red[t] = e2p;
+    R.red2[t] = de0p;
+    R.ired[t] = nterm;
+    R.ired2[t] = ngen;
+    R.ired3[t] = nuniq;
+    R.ired4[t] = nintr;
+    R.ired5[t] = nzero;
+    R.dmin[t] = dmn;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) {
+        R.red[t] += R.red[t + o];
+        R.red2[t] += R.red2[t + o];
+        R.ired[t] += R.ired[t + o];
+        R.ired2[t] += R.ired2[t + o];
+        R.ired3[t] += R.ired3[t + o];
+        R.ired4[t] += R.ired4[t + o];
+        R.ired5[t] += R.ired5[t + o];
+        R.dmin[t] = fmin(R.dmin[t], R.dmin[t + o]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      a.P.e2[b] = R.red[0];
+      a.P.de0[b] = R.red2[0];
+      a.P.nterm[b] = R.ired[0];
+      a.P.ngen[b] = R.ired2[0];
+      a.P.nuniq[b] = R.ired3[0];
+      a.P.nintr[b] = R.ired4[0];
+      a.P.nzero[b] = R.ired5[0];
+      a.P.mind[b] = R.dmin[0];
+      a.P.nseg[b] = (int32_t)nsg;
+      if (a.want_u) a.U.start[b] = (uint64_t)lo;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Final reductions (one block; fixed order)
+// ---------------------------------------------------------------------------
+struct DevResult {
+  double e2, de0, mind;
+  int64_t nterm, ngen, nuniq, nintr, nzero;
+  uint32_t overflow, flags;
+};
+
+__global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t seg_lo, int64_t seg_n,
+                                                const uint32_t* overflow, const uint32_t* flags,
+                                                DevResult* res, double* per_sample, int64_t per_seg) {
+  // sums buckets [seg_lo + s*per_seg, ...) per segment s when per_sample != NULL,
+  // or everything into res
+  __shared__ double r1[1024], r2[1024], r3[1024];
+  __shared__ int64_t i1[1024], i2[1024], i3[1024], i4[1024], i5[1024];
+  const int t = threadIdx.x;
+  const int64_t lo = per_sample ? seg_lo + (int64_t)blockIdx.x * per_seg : 0;
+  const int64_t cnt = per_sample ? per_seg : nb;
+  const int64_t chunk = (cnt + 1023) / 1024;
+  const int64_t b0 = lo + t * chunk, b1 = min(lo + cnt, b0 + chunk);
+  double e = 0.0, d = 0.0, mn = INFINITY;
+  int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
+  for (int64_t b = b0; b < b1; ++b) {
+    e += P.e2[b];
+    d += P.de0[b];
+    mn = fmin(mn, P.mind[b]);
+    nt += P.nterm[b];
+    ng += P.ngen[b];
+    nu += P.nuniq[b];
+    ni += P.nintr[b];
+    nz += P.nzero[b];
+  }
+  r1[t] = e; r2[t] = d; r3[t] = mn;
+  i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) {
+      r1[t] += r1[t + o];
+      r2[t] += r2[t + o];
+      r3[t] = fmin(r3[t], r3[t + o]);
+      i1[t] += i1[t + o];
+      i2[t] += i2[t + o];
+      i3[t] += i3[t + o];
+      i4[t] += i4[t + o];
+      i5[t] += i5[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (per_sample) {
+      per_sample[blockIdx.x] = r1[0];
+      // statistics accumulate over the per-sample blocks
+      atomicAdd((unsigned long long*)&res->nterm, (unsigned long long)i1[0]);
+      atomicAdd((unsigned long long*)&res->ngen, (unsigned long long)i2[0]);
+      atomicAdd((unsigned long long*)&res->nuniq, (unsigned long long)i3[0]);
+      atomicAdd((unsigned long long*)&res->nintr, (unsigned long long)i4[0]);
+      atomicAdd((unsigned long long*)&res->nzero, (unsigned long long)i5[0]);
+    } else {
+      res->e2 = r1[0];
+      res->de0 = r2[0];
+      res->mind = r3[0];
+      res->nterm = i1[0];
+      res->ngen = i2[0];
+      res->nuniq = i3[0];
+      res->nintr = i4[0];
+      res->nzero = i5[0];
+      res->overflow = *overflow;
+      res->flags = *flags;
+    }
+  }
+}
+
+}  // namespace shci

@@ -83,10 +83,16 @@ typedef struct {
   double min_abs_denom;  /* min |E0 - H_aa| over kept a (+inf if none) */
   int32_t n_buckets;     /* hash buckets used by the grouping step */
   int32_t n_retries;     /* re-partitions after a bucket overflow */
-  double ms_gen;         /* excitation generation (count + write) */
+  double ms_gen;         /* validation, hash set of V, excitation generation (count + write) */
   double ms_sort;        /* hash partition passes */
   double ms_reduce;      /* bucket sort, segmented reduce, diagonal, E2 reduction */
   double ms_total;       /* whole call, device time on `stream` */
+  double ms_k_count;     /* generator kernel, count pass */
+  double ms_k_write;     /* generator kernel, write pass */
+  double ms_k_reduce;    /* bucket reduce kernel */
+  int64_t n_records;     /* records materialised (screened terms, members of V included) */
+  int32_t key_words;     /* 64-bit words per packed key */
+  int32_t value_bytes;   /* bytes per record value (8 FP64, 4 FP32C; x2 in sample mode) */
 } shci_pt2_stats;
 
 /* Optional device outputs of shci_pt2_det (any pointer may be NULL).

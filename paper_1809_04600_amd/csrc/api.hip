@@ -106,7 +106,7 @@ struct shci_pt2_ctx {
   size_t ws_limit = 0;
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
   DevResult* dres = nullptr;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[10] = {};
 };
 
 namespace {
@@ -322,7 +322,9 @@ struct Job {
   // results
   DevResult res;
   int32_t nbucket = 0, retries = 0;
-  float ms_gen = 0, ms_sort = 0, ms_reduce = 0;
+  float ms_gen = 0, ms_sort = 0, ms_reduce = 0, ms_k_count = 0, ms_k_write = 0, ms_k_reduce = 0;
+  int64_t nrec = 0;
+  int kw = 0, vbytes = 0;
 };
 
 template <int KW, typename VT, bool SAMPLE>
@@ -395,7 +397,9 @@ int run_job(Job& J) {
   g.auxbit = auxbit;
   const int gen_grid = cus * GEN_BLOCKS_PER_CU;
   k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
+  HIPCHK(hipEventRecord(X->ev[4], st));
   k_gen<KW, GEN_COUNT, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+  HIPCHK(hipEventRecord(X->ev[5], st));
   HIPCHK(hipGetLastError());
   CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, total, st));
   uint64_t hostv[2] = {0, 0};
@@ -480,7 +484,9 @@ int run_job(Job& J) {
       // ---- generation (write pass; repeated after a re-plan, same records) ----
       g.out = A;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
+      HIPCHK(hipEventRecord(X->ev[6], st));
       k_gen<KW, GEN_WRITE, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+      HIPCHK(hipEventRecord(X->ev[7], st));
       HIPCHK(hipGetLastError());
       if (J.ex && J.ex->t_keys && J.ex->t_cap > 0 && pay) {
         k_export_terms<KW, VT><<<1024, 256, 0, st>>>(A, nrec, n, J.ex->t_keys, J.ex->t_i, J.ex->t_val,
@@ -547,7 +553,9 @@ int run_job(Job& J) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<size_t>(dyn, 8)));
     k_fill_u32<<<1, 64, 0, st>>>(overflow, 1, 0u);
     const int64_t rgrid = std::min<int64_t>(G.nbucket, (int64_t)cus * 2);
+    HIPCHK(hipEventRecord(X->ev[8], st));
     k_reduce<KW, C, SAMPLE, VT><<<(int)rgrid, 256, std::max<size_t>(dyn, 8), st>>>(ra);
+    HIPCHK(hipEventRecord(X->ev[9], st));
     HIPCHK(hipGetLastError());
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
     if (SAMPLE) {
@@ -578,6 +586,15 @@ int run_job(Job& J) {
     J.ms_sort = ms;
     HIPCHK(hipEventElapsedTime(&ms, X->ev[2], X->ev[3]));
     J.ms_reduce = ms;
+    HIPCHK(hipEventElapsedTime(&ms, X->ev[4], X->ev[5]));
+    J.ms_k_count = ms;
+    HIPCHK(hipEventElapsedTime(&ms, X->ev[6], X->ev[7]));
+    J.ms_k_write = ms;
+    HIPCHK(hipEventElapsedTime(&ms, X->ev[8], X->ev[9]));
+    J.ms_k_reduce = ms;
+    J.nrec = nrec;
+    J.kw = KW;
+    J.vbytes = (int)sizeof(VT) * (SAMPLE ? 2 : 1);
     J.nbucket = (int32_t)G.nbucket;
 
     if (J.want_u && J.grad) {
@@ -651,6 +668,12 @@ void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
   st->ms_sort = J.ms_sort;
   st->ms_reduce = J.ms_reduce;
   st->ms_total = ms_total;
+  st->ms_k_count = J.ms_k_count;
+  st->ms_k_write = J.ms_k_write;
+  st->ms_k_reduce = J.ms_k_reduce;
+  st->n_records = J.nrec;
+  st->key_words = J.kw;
+  st->value_bytes = J.vbytes;
 }
 
 }  // namespace

@@ -11,6 +11,7 @@
 
 #include "../../include/shci_pt2.h"
 #include "group.hpp"
+#include "reduce_wave.hpp"
 #include "scan.hpp"
 
 using namespace shci;
@@ -106,6 +107,8 @@ struct shci_pt2_ctx {
   size_t ws_limit = 0;
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
   DevResult* dres = nullptr;
+  double* ref_f = nullptr;  // [2n] orbital energies of the reference det
+  double* ref_e = nullptr;
   hipEvent_t ev[10] = {};
 };
 
@@ -421,7 +424,7 @@ int run_job(Job& J) {
   G.sbits = J.sbits;
   {
     const int64_t per_sample_rec = SAMPLE ? std::max<int64_t>(1, nrec / std::max(1, J.nsamp)) : nrec;
-    G.bits_hash = std::min(26, std::max(0, ceil_log2((uint64_t)((per_sample_rec + C / 2 - 1) / (C / 2)))));
+    G.bits_hash = std::min(26, std::max(0, ceil_log2((uint64_t)((per_sample_rec + 127) / 128))));
   }
 
   for (int attempt = 0;; ++attempt) {
@@ -432,7 +435,8 @@ int run_job(Job& J) {
     const bool v2 = SAMPLE;
     const bool pay = J.want_pay;
     auto plan_big = [&](Carver& cv, Recs* A, Recs* B, uint32_t** hist, uint32_t** hoffs, ScanTmp* hsc,
-                        Partials* P, Uniq* U, uint64_t** boff) {
+                        Partials* P, Uniq* U, uint64_t** boff, uint32_t** bidarr, uint64_t** bst,
+                        uint32_t** slow, Partials* Pq) {
       for (int w = 0; w < KW; ++w) A->k[w] = cv.take<uint64_t>(nrec);
       A->v = cv.take<VT>(nrec);
       A->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
@@ -443,6 +447,9 @@ int run_job(Job& J) {
         B->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
         B->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
       }
+      *bidarr = cv.take<uint32_t>(npass > 0 ? nrec : 1);
+      *bst = cv.take<uint64_t>(G.nbucket + 1);
+      *slow = cv.take<uint32_t>(G.nbucket + 1);
       *hist = cv.take<uint32_t>((size_t)256 * ntiles);
       *hoffs = cv.take<uint32_t>((size_t)256 * ntiles + 1);
       hsc->carve(cv, std::max<int64_t>((int64_t)256 * ntiles, G.nbucket + 1));
@@ -456,6 +463,14 @@ int run_job(Job& J) {
       P->nzero = cv.take<int32_t>(nb);
       P->mind = cv.take<double>(nb);
       P->nseg = cv.take<int32_t>(nb);
+      Pq->e2 = cv.take<double>(1024);
+      Pq->de0 = cv.take<double>(1024);
+      Pq->nterm = cv.take<int64_t>(1024);
+      Pq->ngen = cv.take<int64_t>(1024);
+      Pq->nuniq = cv.take<int32_t>(1024);
+      Pq->nintr = cv.take<int32_t>(1024);
+      Pq->nzero = cv.take<int32_t>(1024);
+      Pq->mind = cv.take<double>(1024);
       if (J.want_u) {
         for (int w = 0; w < KW; ++w) U->k[w] = cv.take<uint64_t>(nrec);
         U->h2 = cv.take<uint32_t>(nrec);
@@ -470,15 +485,18 @@ int run_job(Job& J) {
     Recs A, B;
     uint32_t *hist, *hoffs;
     ScanTmp hsc;
-    Partials P;
+    Partials P, Pq;
     Uniq U;
     uint64_t* boff = nullptr;
+    uint32_t* bidarr = nullptr;
+    uint64_t* bst = nullptr;
+    uint32_t* slow = nullptr;
     {
       Carver cv(nullptr);
-      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff);
+      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq);
       CHK(X->big.ensure(cv.off, X->ws_limit));
       Carver cv2(X->big.p);
-      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff);
+      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq);
     }
     {
       // ---- generation (write pass; repeated after a re-plan, same records) ----
@@ -513,6 +531,7 @@ int run_job(Job& J) {
         pa.hist = hist;
         pa.offs = hoffs;
         pa.ntiles = (int)ntiles;
+        pa.bid_out = (pass == npass - 1) ? bidarr : nullptr;
         k_part_hist<KW><<<(int)ntiles, 256, 0, st>>>(pa);
         CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
         if (pay)
@@ -523,6 +542,13 @@ int run_job(Job& J) {
         std::swap(cur, oth);
         shift += dbits;
       }
+    }
+    if (npass > 0) {
+      const int64_t m = nrec + 1;
+      k_bucket_bounds<<<(int)std::min<int64_t>(8192, (m + 255) / 256), 256, 0, st>>>(bidarr, nrec, G.nbucket, bst);
+    } else {
+      const uint64_t hb[2] = {0, (uint64_t)nrec};
+      HIPCHK(hipMemcpyAsync(bst, hb, sizeof hb, hipMemcpyHostToDevice, st));
     }
     HIPCHK(hipEventRecord(X->ev[2], st));
     // ---- bucket reduce ----
@@ -542,19 +568,45 @@ int run_job(Job& J) {
     ra.U = U;
     ra.overflow = overflow;
     ra.want_u = J.want_u ? 1 : 0;
-    const size_t diag_bytes = (size_t)(n + n * n) * sizeof(double);
+    ra.bstart = bst;
+    ra.ref_det = J.dets;
+    ra.ref_f = X->ref_f;
+    ra.ref_e = X->ref_e;
+    ra.ne = T.na + T.nb;
+    k_diag_ref<<<1, 256, 0, st>>>(J.dets, n, T.hpp, T.jtri, T.sstri, X->ref_f, X->ref_e);
+    uint32_t* slow_count = X->dflag + 3;
+    const size_t diag_bytes = (size_t)(3 * n + n * n) * sizeof(double);
     const size_t static_bytes = sizeof(RedShared<KW, C, SAMPLE, VT>);
     size_t dyn = 0;
     if (static_bytes + diag_bytes <= 160 * 1024) {
       dyn = diag_bytes;
       ra.diag_in_lds = 1;
     }
+    WaveRedArgs wa;
+    wa.r = ra;
+    wa.bstart = bst;
+    wa.slow_list = slow;
+    wa.slow_count = slow_count;
+    const size_t wstatic = sizeof(WaveStage<KW, SAMPLE, VT>) * WRED_WAVES;
+    size_t wdyn = 0;
+    if (wstatic + diag_bytes <= 160 * 1024) wdyn = diag_bytes;
+    wa.r.diag_in_lds = wdyn ? 1 : 0;
+    HIPCHK(hipFuncSetAttribute((const void*)k_reduce_wave<KW, SAMPLE, VT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<size_t>(wdyn, 8)));
     HIPCHK(hipFuncSetAttribute((const void*)k_reduce<KW, C, SAMPLE, VT>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<size_t>(dyn, 8)));
     k_fill_u32<<<1, 64, 0, st>>>(overflow, 1, 0u);
-    const int64_t rgrid = std::min<int64_t>(G.nbucket, (int64_t)cus * 2);
+    k_fill_u32<<<1, 64, 0, st>>>(slow_count, 1, 0u);
     HIPCHK(hipEventRecord(X->ev[8], st));
-    k_reduce<KW, C, SAMPLE, VT><<<(int)rgrid, 256, std::max<size_t>(dyn, 8), st>>>(ra);
+    {
+      const int64_t wblocks = std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * 8);
+      k_reduce_wave<KW, SAMPLE, VT><<<(int)wblocks, 64 * WRED_WAVES, std::max<size_t>(wdyn, 8), st>>>(wa);
+    }
+    // buckets the wavefront kernel could not take: block kernel with a full-key sort
+    ra.blist = slow;
+    ra.nlist = slow_count;
+    k_reduce<KW, C, SAMPLE, VT><<<(int)std::min<int64_t>(G.nbucket, (int64_t)cus * 2), 256,
+                                  std::max<size_t>(dyn, 8), st>>>(ra);
     HIPCHK(hipEventRecord(X->ev[9], st));
     HIPCHK(hipGetLastError());
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
@@ -562,7 +614,11 @@ int run_job(Job& J) {
       k_final<<<J.nsamp, 1024, 0, st>>>(P, G.nbucket, 0, J.nsamp, overflow, dflag, X->dres, J.per_sample,
                                          (int64_t)1 << G.bits_hash);
     } else {
-      k_final<<<1, 1024, 0, st>>>(P, G.nbucket, 0, 1, overflow, dflag, X->dres, nullptr, 0);
+      const int64_t fchunk = std::max<int64_t>(256, (G.nbucket + 1023) / 1024);
+      const int64_t fblocks = (G.nbucket + fchunk - 1) / fchunk;
+      Partials Q = Pq;
+      k_final_partial<<<(int)fblocks, 256, 0, st>>>(P, G.nbucket, fchunk, Q);
+      k_final<<<1, 1024, 0, st>>>(Q, fblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(X->ev[3], st));
@@ -723,6 +779,8 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     T.hb_max = cv.take<double>(T.nss + n2);
     X->dflag = cv.take<uint32_t>(16);
     X->dres = cv.take<DevResult>(1);
+    X->ref_f = cv.take<double>(2 * n);
+    X->ref_e = cv.take<double>(1);
   };
   {
     Carver cv(nullptr);

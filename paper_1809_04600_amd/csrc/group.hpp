@@ -95,6 +95,7 @@ struct PassArgs {
   uint32_t* hist;        // [2^dbits][ntiles]
   const uint32_t* offs;  // exclusive scan of hist
   int ntiles;
+  uint32_t* bid_out;     // last pass: bucket id of every output record (nullable)
 };
 
 template <int KW>
@@ -135,6 +136,7 @@ __global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
     const bool valid = idx < a.n;
     uint64_t k[KW];
     uint32_t d = 0;
+    uint64_t bidv = 0;
     if (valid) {
       load_key<KW>(a.in, idx, k);
       uint64_t kc[KW];
@@ -142,7 +144,8 @@ __global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
       for (int w = 0; w < KW; ++w) kc[w] = k[w];
       clear_aux<KW>(kc, a.auxbit);
       uint64_t h;
-      d = (uint32_t)(bucket_id<KW>(kc, a.G, a.nbits_n, h) >> a.shift) & dmask;
+      bidv = bucket_id<KW>(kc, a.G, a.nbits_n, h);
+      d = (uint32_t)(bidv >> a.shift) & dmask;
     }
     const uint32_t r = split_round(S, valid, d, a.dbits);
     if (valid) {
@@ -152,6 +155,7 @@ __global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
       static_cast<VT*>(a.out.v)[pos] = static_cast<const VT*>(a.in.v)[idx];
       if constexpr (V2) static_cast<VT*>(a.out.v2)[pos] = static_cast<const VT*>(a.in.v2)[idx];
       if constexpr (PAY) a.out.pay[pos] = a.in.pay[idx];
+      if (a.bid_out) a.bid_out[pos] = (uint32_t)bidv;
     }
   }
 }
@@ -174,6 +178,13 @@ struct RedArgs {
   Uniq U;
   uint32_t* overflow;
   int want_u;
+  const uint64_t* ref_det;  // reference determinant for H_aa (first det of V)
+  const double* ref_f;      // [2n] orbital energies relative to it
+  const double* ref_e;      // its energy
+  int ne;                   // electrons
+  const uint64_t* bstart;   // [nbucket + 1] bucket start offsets (nullable: binary search)
+  const uint32_t* blist;    // buckets to process (nullable: all)
+  const uint32_t* nlist;    // device count of blist
 };
 
 template <int KW>
@@ -271,6 +282,109 @@ SHCI_DEV double diag_energy(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, 
   return e;
 }
 
+// Sum of W over pairs (x in mask X, y in mask Y), W = tab at the triangle
+// index of (x, y); `strict` skips the diagonal-free case x == y.
+SHCI_DEV double pair_sum_cross(uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, const double* tri,
+                               bool diag_incl) {
+  double e = 0.0;
+  while (x0 | x1) {
+    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
+    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
+    uint64_t m0 = y0, m1 = y1;
+    while (m0 | m1) {
+      const int q = m0 ? __ffsll((unsigned long long)m0) - 1 : 64 + __ffsll((unsigned long long)m1) - 1;
+      if (m0) m0 &= m0 - 1; else m1 &= m1 - 1;
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      e += diag_incl ? tri[hi * (hi + 1) / 2 + lo] : tri[hi * (hi - 1) / 2 + lo];
+    }
+  }
+  return e;
+}
+
+// sum of S over pairs p < q inside one mask
+SHCI_DEV double pair_sum_within(uint64_t x0, uint64_t x1, const double* sstri) {
+  double e = 0.0;
+  while (x0 | x1) {
+    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
+    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
+    uint64_t y0 = x0, y1 = x1;
+    while (y0 | y1) {
+      const int q = y0 ? __ffsll((unsigned long long)y0) - 1 : 64 + __ffsll((unsigned long long)y1) - 1;
+      if (y0) y0 &= y0 - 1; else y1 &= y1 - 1;
+      e += sstri[q * (q - 1) / 2 + p];
+    }
+  }
+  return e;
+}
+
+SHCI_DEV double mask_sum(uint64_t x0, uint64_t x1, const double* f) {
+  double e = 0.0;
+  while (x0 | x1) {
+    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
+    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
+    e += f[p];
+  }
+  return e;
+}
+
+// Reference determinant R with its energy E_R and orbital energies
+// F_p(sigma) = h_pp + sum_{q in R_sigma, q != p} [(pp|qq) - (pq|qp)] + sum_{q in R_other} (pp|qq).
+struct DiagRef {
+  uint64_t r[4];
+  double e;
+  const double* f;  // [2n]: alpha block then beta block
+};
+
+// H_aa written relative to R.  With particles P = a \ R and holes Q = R \ a
+// (spin orbitals) and W the pair energy (J - K for equal spins, J otherwise):
+//   E(a) = E(R) + sum_{x in P} F_x - sum_{y in Q} F_y - sum_{x in P, y in Q} W_xy
+//          + sum_{x<x' in P} W_xx' + sum_{y<y' in Q} W_yy',
+// an exact rearrangement of the sum over occupied pairs.  Used when a is
+// close to R (fewer table reads than the direct sum); otherwise the direct
+// O(n_e^2) sum is used.
+SHCI_DEV double diag_energy_rel(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const DiagRef& R,
+                                int n, int ne, const double* hpp, const double* jtri, const double* sstri) {
+  const uint64_t pa0 = a0 & ~R.r[0], pa1 = a1 & ~R.r[1], pb0 = b0 & ~R.r[2], pb1 = b1 & ~R.r[3];
+  const uint64_t ha0 = R.r[0] & ~a0, ha1 = R.r[1] & ~a1, hb0 = R.r[2] & ~b0, hb1 = R.r[3] & ~b1;
+  const int l = __popcll(pa0) + __popcll(pa1) + __popcll(pb0) + __popcll(pb1);
+  if (3 * l * l + 2 * l >= ne * (ne + 1) / 2) return diag_energy(a0, a1, b0, b1, hpp, jtri, sstri);
+  double e = R.e;
+  e += mask_sum(pa0, pa1, R.f) + mask_sum(pb0, pb1, R.f + n);
+  e -= mask_sum(ha0, ha1, R.f) + mask_sum(hb0, hb1, R.f + n);
+  double pp = pair_sum_within(pa0, pa1, sstri) + pair_sum_within(pb0, pb1, sstri) +
+              pair_sum_cross(pa0, pa1, pb0, pb1, jtri, true);
+  double hh = pair_sum_within(ha0, ha1, sstri) + pair_sum_within(hb0, hb1, sstri) +
+              pair_sum_cross(ha0, ha1, hb0, hb1, jtri, true);
+  double ph = pair_sum_cross(pa0, pa1, ha0, ha1, sstri, false) + pair_sum_cross(pb0, pb1, hb0, hb1, sstri, false) +
+              pair_sum_cross(pa0, pa1, hb0, hb1, jtri, true) + pair_sum_cross(pb0, pb1, ha0, ha1, jtri, true);
+  return e + pp + hh - ph;
+}
+
+// F_p(sigma) and E(R) for the reference determinant (one block)
+__global__ void k_diag_ref(const uint64_t* ref, int n, const double* hpp, const double* jtri,
+                           const double* sstri, double* f, double* er) {
+  const uint64_t r0 = ref[0], r1 = ref[1], r2 = ref[2], r3 = ref[3];
+  for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) {
+    const int p = t % n, sp = t / n;
+    double v = hpp[p];
+    for (int q = 0; q < n; ++q) {
+      const bool inA = occ(r0, r1, q), inB = occ(r2, r3, q);
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      const double j = jtri[hi * (hi + 1) / 2 + lo];
+      const double s = (p == q) ? 0.0 : sstri[hi * (hi - 1) / 2 + lo];
+      if (sp == 0) {
+        if (inA && q != p) v += s;
+        if (inB) v += j;
+      } else {
+        if (inB && q != p) v += s;
+        if (inA) v += j;
+      }
+    }
+    f[t] = v;
+  }
+  if (threadIdx.x == 0) *er = diag_energy(r0, r1, r2, r3, hpp, jtri, sstri);
+}
+
 // exclusive scan of 256 values held one per thread; returns the prefix,
 // total in *tot (all threads)
 SHCI_DEV uint32_t block_scan256(uint32_t v, uint32_t* sh, uint32_t* tot) {
@@ -348,6 +462,7 @@ template <int KW, int C, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
   extern __shared__ double s_diag[];
   __shared__ RedShared<KW, C, SAMPLE, VT> R;
+  if (a.blist && (int64_t)*a.nlist <= (int64_t)blockIdx.x) return;
   const int t = threadIdx.x;
   const int n = a.n;
   R.S.wcnt[0][t] = R.S.wcnt[1][t] = R.S.wcnt[2][t] = R.S.wcnt[3][t] = 0;
@@ -368,10 +483,16 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
   }
   __syncthreads();
 
-  const int64_t nb = a.G.nbucket;
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    // bucket bounds by binary search on the (sorted) bucket ids
-    if (t < 2) {
+  const int64_t nb = a.blist ? (int64_t)*a.nlist : a.G.nbucket;
+  for (int64_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const int64_t b = a.blist ? (int64_t)a.blist[bi] : bi;
+    if (a.bstart) {
+      if (t < 2) {
+        int64_t v = (int64_t)a.bstart[b + t];
+        R.lohi[t] = (uint64_t)(v < 0 ? 0 : (v > a.nrec ? a.nrec : v));
+      }
+    } else if (t < 2) {
+      // bucket bounds by binary search on the (sorted) bucket ids
       const uint64_t target = (uint64_t)b + (uint64_t)t;
       int64_t lo = 0, hi = a.nrec;
       while (lo < hi) {
@@ -390,7 +511,8 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
     if (t == 0) R.flag = 0;
     __syncthreads();
     const int64_t lo = (int64_t)R.lohi[0];
-    const int M = (int)((int64_t)R.lohi[1] - lo);
+    const int64_t hi_ = (int64_t)R.lohi[1];
+    const int M = (int)(hi_ > lo ? hi_ - lo : 0);
     if (M > C) {
       if (t == 0) {
         atomicOr(a.overflow, 1u);
@@ -564,7 +686,11 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       ngen += cntk;
       double Dd = 0.0, g = 0.0;
       if (!inv) {
-        const double haa = diag_energy(a0, a1, b0, b1, s_hpp, s_jt, s_st);
+        DiagRef DR;
+        for (int w = 0; w < 4; ++w) DR.r[w] = a.ref_det[w];
+        DR.e = *a.ref_e;
+        DR.f = a.ref_f;
+        const double haa = diag_energy_rel(a0, a1, b0, b1, DR, n, a.ne, s_hpp, s_jt, s_st);
         Dd = a.e0 - haa;
         double contrib;
         if constexpr (SAMPLE)
@@ -633,6 +759,54 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
 // ---------------------------------------------------------------------------
 // Final reductions (one block; fixed order)
 // ---------------------------------------------------------------------------
+// first level of the final reduction: block b sums buckets [b*chunk, ...)
+// into slot b of Q (same layout as Partials); fixed order
+__global__ void __launch_bounds__(256) k_final_partial(Partials P, int64_t nb, int64_t chunk, Partials Q) {
+  __shared__ double r1[256], r2[256], r3[256];
+  __shared__ int64_t i1[256], i2[256], i3[256], i4[256], i5[256];
+  const int t = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(nb, lo + chunk);
+  double e = 0.0, d = 0.0, mn = INFINITY;
+  int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
+  for (int64_t b = lo + t; b < hi; b += 256) {
+    e += P.e2[b];
+    d += P.de0[b];
+    mn = fmin(mn, P.mind[b]);
+    nt += P.nterm[b];
+    ng += P.ngen[b];
+    nu += P.nuniq[b];
+    ni += P.nintr[b];
+    nz += P.nzero[b];
+  }
+  r1[t] = e; r2[t] = d; r3[t] = mn;
+  i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      r1[t] += r1[t + o];
+      r2[t] += r2[t + o];
+      r3[t] = fmin(r3[t], r3[t + o]);
+      i1[t] += i1[t + o];
+      i2[t] += i2[t + o];
+      i3[t] += i3[t + o];
+      i4[t] += i4[t + o];
+      i5[t] += i5[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int b = blockIdx.x;
+    Q.e2[b] = r1[0];
+    Q.de0[b] = r2[0];
+    Q.mind[b] = r3[0];
+    Q.nterm[b] = i1[0];
+    Q.ngen[b] = i2[0];
+    Q.nuniq[b] = (int32_t)i3[0];
+    Q.nintr[b] = (int32_t)i4[0];
+    Q.nzero[b] = (int32_t)i5[0];
+  }
+}
+
 struct DevResult {
   double e2, de0, mind;
   int64_t nterm, ngen, nuniq, nintr, nzero;

@@ -1,0 +1,325 @@
+// Bucket reduce, one wavefront per bucket.
+//
+// After the hash partition a bucket holds on average ~128 records (at most
+// WCAP are handled here).  A wavefront stages the bucket in its own LDS slice,
+// sorts 64-bit keys (the hash bits below the bucket id, with the record's
+// position in the low byte) by a bitonic network in registers, so equal
+// determinants become adjacent in record order; segment heads then sum their
+// segment sequentially, look the determinant up in the hash set of V,
+// evaluate H_aa from the LDS diagonal tables and accumulate the contribution.
+// No block-wide barrier is involved.  Buckets that are larger than WCAP, or in
+// which two different determinants share all sorted hash bits, are listed for
+// the block kernel (k_reduce), which sorts by the full key.
+#pragma once
+#include "group.hpp"
+
+namespace shci {
+
+constexpr int WCAP = 256;       // records per wavefront bucket
+constexpr int WRED_WAVES = 4;   // wavefronts per block
+
+SHCI_DEV uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const int lo = __shfl_xor((int)(uint32_t)v, m);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// ascending bitonic sort of R*64 keys held as v[r] at element r*64 + lane
+template <int R>
+SHCI_DEV void wave_bitonic(uint64_t (&v)[R]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        const bool up = (e & k) == 0;
+        if (j >= 64) {
+          const int rp = r ^ (j >> 6);
+          if (rp > r) {
+            const uint64_t x = v[r], y = v[rp];
+            const bool sw = up ? (x > y) : (x < y);
+            v[r] = sw ? y : x;
+            v[rp] = sw ? x : y;
+          }
+        } else {
+          const uint64_t p = shfl_xor_u64(v[r], j);
+          const bool lower = (lane & j) == 0;
+          const uint64_t mn = v[r] < p ? v[r] : p;
+          const uint64_t mx = v[r] < p ? p : v[r];
+          v[r] = (lower == up) ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
+template <int KW, bool SAMPLE, typename VT>
+struct WaveStage {
+  uint64_t key[KW][WCAP];
+  VT v[WCAP];
+  VT v2[SAMPLE ? WCAP : 1];
+  uint64_t sk[WCAP];
+};
+
+struct WaveRedArgs {
+  RedArgs r;
+  const uint64_t* bstart;  // [nbucket + 1]
+  uint32_t* slow_list;     // buckets for the block kernel
+  uint32_t* slow_count;
+};
+
+template <int KW, bool SAMPLE, typename VT, int R>
+SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, int64_t b, int64_t lo,
+                          int M, const double* hpp, const double* jt, const double* st,
+                          const DiagRef& DR) {
+  const RedArgs& a = A.r;
+  const int lane = lane_id();
+  const int n = a.n;
+  const int bh = a.G.bits_hash;
+  uint64_t sk[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = r * 64 + lane;
+    sk[r] = ~0ull;
+    if (j < M) {
+      uint64_t k[KW];
+      load_key<KW>(a.in, lo + j, k);
+#pragma unroll
+      for (int w = 0; w < KW; ++w) W.key[w][j] = k[w];
+      W.v[j] = static_cast<const VT*>(a.in.v)[lo + j];
+      if constexpr (SAMPLE) W.v2[j] = static_cast<const VT*>(a.in.v2)[lo + j];
+      clear_aux<KW>(k, a.auxbit);
+      const uint64_t h = hash_key<KW>(k);
+      sk[r] = (((h << bh) & ~0xffull)) | (uint64_t)j;
+    }
+  }
+  wave_bitonic<R>(sk);
+#pragma unroll
+  for (int r = 0; r < R; ++r) W.sk[r * 64 + lane] = sk[r];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  auto key_eq = [&](int x, int y) {
+    bool eq = true;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) {
+      uint64_t kx = W.key[w][x], ky = W.key[w][y];
+      if (w == (a.auxbit >> 6)) {
+        kx &= ~(1ull << (a.auxbit & 63));
+        ky &= ~(1ull << (a.auxbit & 63));
+      }
+      eq = eq && (kx == ky);
+    }
+    return eq;
+  };
+  // heads, and a check that equal sort bits mean equal determinants
+  bool head[R];
+  bool clash = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = r * 64 + lane;
+    head[r] = false;
+    if (e < M) {
+      if (e == 0) {
+        head[r] = true;
+      } else {
+        const uint64_t cur = W.sk[e], prv = W.sk[e - 1];
+        if ((cur >> 8) != (prv >> 8)) {
+          head[r] = true;
+        } else if (!key_eq((int)(cur & 0xff), (int)(prv & 0xff))) {
+          clash = true;
+        }
+      }
+    }
+  }
+  if (ballot(clash)) {
+    if (lane == 0) {
+      const uint32_t s = atomicAdd(A.slow_count, 1u);
+      A.slow_list[s] = (uint32_t)b;
+    }
+    return;
+  }
+  uint64_t hb[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) hb[r] = ballot(head[r]);
+  int nbefore = 0;
+  double e2p = 0.0, de0p = 0.0, dmn = INFINITY;
+  int64_t nterm = 0, ngen = 0;
+  int32_t nuniq = 0, nintr = 0, nzero = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (head[r]) {
+      const int e0 = r * 64 + lane;
+      int e1 = e0 + 1;
+      while (e1 < M && (W.sk[e1] >> 8) == (W.sk[e0] >> 8)) ++e1;
+      const int first = (int)(W.sk[e0] & 0xff);
+      double X = 0.0, Y = 0.0, Xd = 0.0, Yd = 0.0;
+      if constexpr (sizeof(VT) == 4) {
+        float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sxd = 0.f, cxd = 0.f, syd = 0.f, cyd = 0.f;
+        for (int e = e0; e < e1; ++e) {
+          const int id = (int)(W.sk[e] & 0xff);
+          two_sum_f32(sx, cx, (float)W.v[id]);
+          if constexpr (SAMPLE) {
+            two_sum_f32(sy, cy, (float)W.v2[id]);
+            if ((W.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
+              two_sum_f32(sxd, cxd, (float)W.v[id]);
+              two_sum_f32(syd, cyd, (float)W.v2[id]);
+            }
+          }
+        }
+        X = (double)sx + (double)cx;
+        Y = (double)sy + (double)cy;
+        Xd = (double)sxd + (double)cxd;
+        Yd = (double)syd + (double)cyd;
+      } else {
+        for (int e = e0; e < e1; ++e) {
+          const int id = (int)(W.sk[e] & 0xff);
+          X = X + (double)W.v[id];
+          if constexpr (SAMPLE) {
+            Y = Y + (double)W.v2[id];
+            if ((W.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
+              Xd = Xd + (double)W.v[id];
+              Yd = Yd + (double)W.v2[id];
+            }
+          }
+        }
+      }
+      uint64_t k[KW];
+#pragma unroll
+      for (int w = 0; w < KW; ++w) k[w] = W.key[w][first];
+      clear_aux<KW>(k, a.auxbit);
+      uint64_t a0, a1, b0, b1;
+      unpack_det<KW>(k, n, a0, a1, b0, b1);
+      uint64_t dk[KW];
+      pack_det<KW>(dk, a0, a1, b0, b1, n);
+      const bool inv = vset_contains<KW>(a.V, dk, n);
+      const int cntk = e1 - e0;
+      ngen += cntk;
+      double Dd = 0.0, g = 0.0;
+      if (!inv) {
+        const double haa = diag_energy_rel(a0, a1, b0, b1, DR, n, a.ne, hpp, jt, st);
+        Dd = a.e0 - haa;
+        double contrib;
+        if constexpr (SAMPLE)
+          contrib = ((X * X + Y) - (Xd * Xd + Yd)) / (Dd * a.nd * (a.nd - 1.0));
+        else
+          contrib = X * X / Dd;
+        e2p += contrib;
+        de0p += -(X * X) / (Dd * Dd);
+        g = 2.0 * X / Dd;
+        nterm += cntk;
+        nuniq += 1;
+        nintr += Dd > 0.0;
+        nzero += Dd == 0.0;
+        dmn = fmin(dmn, fabs(Dd));
+      }
+      if (a.want_u) {
+        const int64_t o = lo + nbefore + rank_below(hb[r]);
+#pragma unroll
+        for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
+        a.U.h2[o] = (uint32_t)(W.sk[e0] >> 32);
+        a.U.A[o] = X;
+        a.U.D[o] = Dd;
+        a.U.g[o] = g;
+        a.U.cnt[o] = inv ? -cntk : cntk;
+      }
+    }
+    nbefore += __popcll(hb[r]);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    e2p += __shfl_xor(e2p, o);
+    de0p += __shfl_xor(de0p, o);
+    dmn = fmin(dmn, __shfl_xor(dmn, o));
+    nterm += __shfl_xor(nterm, o);
+    ngen += __shfl_xor(ngen, o);
+    nuniq += __shfl_xor(nuniq, o);
+    nintr += __shfl_xor(nintr, o);
+    nzero += __shfl_xor(nzero, o);
+  }
+  if (lane == 0) {
+    a.P.e2[b] = e2p;
+    a.P.de0[b] = de0p;
+    a.P.nterm[b] = nterm;
+    a.P.ngen[b] = ngen;
+    a.P.nuniq[b] = nuniq;
+    a.P.nintr[b] = nintr;
+    a.P.nzero[b] = nzero;
+    a.P.mind[b] = dmn;
+    a.P.nseg[b] = nbefore;
+    if (a.want_u) a.U.start[b] = (uint64_t)lo;
+  }
+}
+
+template <int KW, bool SAMPLE, typename VT>
+__global__ void __launch_bounds__(64 * WRED_WAVES) k_reduce_wave(WaveRedArgs A) {
+  extern __shared__ double s_diag[];
+  __shared__ WaveStage<KW, SAMPLE, VT> WS[WRED_WAVES];
+  const RedArgs& a = A.r;
+  const int t = threadIdx.x;
+  const int n = a.n;
+  const double* hpp = a.hpp;
+  const double* jt = a.jtri;
+  const double* st = a.sstri;
+  if (a.diag_in_lds) {
+    double* h = s_diag;
+    double* j2 = s_diag + n;
+    double* s2 = j2 + n * (n + 1) / 2;
+    for (int x = t; x < n; x += blockDim.x) h[x] = a.hpp[x];
+    for (int x = t; x < n * (n + 1) / 2; x += blockDim.x) j2[x] = a.jtri[x];
+    for (int x = t; x < n * (n - 1) / 2; x += blockDim.x) s2[x] = a.sstri[x];
+    hpp = h;
+    jt = j2;
+    st = s2;
+  }
+  DiagRef DR;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) DR.r[w] = a.ref_det[w];
+  DR.e = *a.ref_e;
+  DR.f = a.ref_f;
+  if (a.diag_in_lds) {
+    double* f2 = s_diag + n + n * (n + 1) / 2 + n * (n - 1) / 2;
+    for (int x = t; x < 2 * n; x += blockDim.x) f2[x] = a.ref_f[x];
+    DR.f = f2;
+  }
+  __syncthreads();
+  const int wv = t >> 6;
+  const int lane = t & 63;
+  WaveStage<KW, SAMPLE, VT>& W = WS[wv];
+  const int64_t nwaves = (int64_t)gridDim.x * WRED_WAVES;
+  for (int64_t b = (int64_t)blockIdx.x * WRED_WAVES + wv; b < a.G.nbucket; b += nwaves) {
+    const int64_t lo = (int64_t)A.bstart[b];
+    const int64_t M = (int64_t)A.bstart[b + 1] - lo;
+    if (M > WCAP) {
+      if (lane == 0) {
+        const uint32_t s = atomicAdd(A.slow_count, 1u);
+        A.slow_list[s] = (uint32_t)b;
+      }
+      continue;
+    }
+    if (M <= 64)
+      wave_bucket<KW, SAMPLE, VT, 1>(A, W, b, lo, (int)M, hpp, jt, st, DR);
+    else if (M <= 128)
+      wave_bucket<KW, SAMPLE, VT, 2>(A, W, b, lo, (int)M, hpp, jt, st, DR);
+    else
+      wave_bucket<KW, SAMPLE, VT, 4>(A, W, b, lo, (int)M, hpp, jt, st, DR);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// bucket start offsets from the bucket id of every record (records are
+// sorted by bucket id): start[x] = first record with bucket id >= x
+__global__ void k_bucket_bounds(const uint32_t* bid, int64_t nrec, int64_t nbucket, uint64_t* start) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= nrec;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cur = (j < nrec) ? (int64_t)bid[j] : nbucket;
+    const int64_t prv = (j > 0) ? (int64_t)bid[j - 1] : -1;
+    for (int64_t x = prv + 1; x <= cur; ++x) start[x] = (uint64_t)j;
+  }
+}
+
+}  // namespace shci

@@ -64,7 +64,8 @@ def test_terms_bit_exact_small(small_sys, eps2):
     # H_ai c_i bit for bit
     assert np.array_equal(gv[go], (o.term_h * x.c[o.term_i])[oo])
     A, D, oA, oD = _check_unique(r.unique, o)
-    assert np.array_equal(D, oD)  # same H_aa summation order
+    # H_aa is summed in another order on the GPU (relative to a reference det)
+    assert np.abs(D - oD).max() <= 1e-12 * max(1.0, np.abs(oD).max())
     assert np.abs(A - oA).max() <= 1e-13
     assert abs(r.e2 - o.e2) <= E2_TOL_FP64
     s = r.stats
@@ -121,7 +122,7 @@ def test_w1_fp64_full(w1):
     A, D, oA, oD = _check_unique(r.unique, o)
     assert r.stats["n_terms"] == o.n_terms and r.stats["n_terms_gen"] == o.n_terms_gen
     assert abs(r.e2 - o.e2) <= E2_TOL_FP64
-    assert np.array_equal(D, oD)
+    assert np.abs(D - oD).max() <= 1e-12 * np.abs(oD).max()
 
 
 def test_w1_fp32c_full(w1):

@@ -107,8 +107,6 @@ struct shci_pt2_ctx {
   size_t ws_limit = 0;
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
   DevResult* dres = nullptr;
-  double* ref_f = nullptr;  // [2n] orbital energies of the reference det
-  double* ref_e = nullptr;
   hipEvent_t ev[10] = {};
 };
 
@@ -436,7 +434,7 @@ int run_job(Job& J) {
     const bool pay = J.want_pay;
     auto plan_big = [&](Carver& cv, Recs* A, Recs* B, uint32_t** hist, uint32_t** hoffs, ScanTmp* hsc,
                         Partials* P, Uniq* U, uint64_t** boff, uint32_t** bidarr, uint64_t** bst,
-                        uint32_t** slow, Partials* Pq) {
+                        uint32_t** slow, Partials* Pq, Partials* Pw) {
       for (int w = 0; w < KW; ++w) A->k[w] = cv.take<uint64_t>(nrec);
       A->v = cv.take<VT>(nrec);
       A->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
@@ -463,6 +461,15 @@ int run_job(Job& J) {
       P->nzero = cv.take<int32_t>(nb);
       P->mind = cv.take<double>(nb);
       P->nseg = cv.take<int32_t>(nb);
+      const int64_t nw = (int64_t)cus * 8 * WRED_WAVES;
+      Pw->e2 = cv.take<double>(nw);
+      Pw->de0 = cv.take<double>(nw);
+      Pw->nterm = cv.take<int64_t>(nw);
+      Pw->ngen = cv.take<int64_t>(nw);
+      Pw->nuniq = cv.take<int32_t>(nw);
+      Pw->nintr = cv.take<int32_t>(nw);
+      Pw->nzero = cv.take<int32_t>(nw);
+      Pw->mind = cv.take<double>(nw);
       Pq->e2 = cv.take<double>(1024);
       Pq->de0 = cv.take<double>(1024);
       Pq->nterm = cv.take<int64_t>(1024);
@@ -485,7 +492,7 @@ int run_job(Job& J) {
     Recs A, B;
     uint32_t *hist, *hoffs;
     ScanTmp hsc;
-    Partials P, Pq;
+    Partials P, Pq, Pw;
     Uniq U;
     uint64_t* boff = nullptr;
     uint32_t* bidarr = nullptr;
@@ -493,10 +500,10 @@ int run_job(Job& J) {
     uint32_t* slow = nullptr;
     {
       Carver cv(nullptr);
-      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq);
+      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq, &Pw);
       CHK(X->big.ensure(cv.off, X->ws_limit));
       Carver cv2(X->big.p);
-      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq);
+      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq, &Pw);
     }
     {
       // ---- generation (write pass; repeated after a re-plan, same records) ----
@@ -560,9 +567,7 @@ int run_job(Job& J) {
     ra.auxbit = auxbit;
     ra.e0 = J.e0;
     ra.nd = J.nd;
-    ra.hpp = T.hpp;
-    ra.jtri = T.jtri;
-    ra.sstri = T.sstri;
+    ra.diag = T.diag;
     ra.V = V;
     ra.P = P;
     ra.U = U;
@@ -570,43 +575,44 @@ int run_job(Job& J) {
     ra.want_u = J.want_u ? 1 : 0;
     ra.bstart = bst;
     ra.ref_det = J.dets;
-    ra.ref_f = X->ref_f;
-    ra.ref_e = X->ref_e;
     ra.ne = T.na + T.nb;
-    k_diag_ref<<<1, 256, 0, st>>>(J.dets, n, T.hpp, T.jtri, T.sstri, X->ref_f, X->ref_e);
+    k_diag_ref<<<1, 256, 0, st>>>(J.dets, n, T.na + T.nb, T.diag);
     uint32_t* slow_count = X->dflag + 3;
-    const size_t diag_bytes = (size_t)(3 * n + n * n) * sizeof(double);
-    const size_t static_bytes = sizeof(RedShared<KW, C, SAMPLE, VT>);
-    size_t dyn = 0;
-    if (static_bytes + diag_bytes <= 160 * 1024) {
-      dyn = diag_bytes;
-      ra.diag_in_lds = 1;
-    }
+    const size_t diag_bytes = (size_t)diag_table_doubles(n) * sizeof(double);
+    const bool red_lds = sizeof(RedShared<KW, C, SAMPLE, VT>) + diag_bytes <= 160 * 1024;
+    const bool wave_lds = sizeof(WaveStage<KW, SAMPLE, VT>) * WRED_WAVES + diag_bytes <= 160 * 1024;
+    const int64_t wblocks = std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * 8);
     WaveRedArgs wa;
     wa.r = ra;
     wa.bstart = bst;
     wa.slow_list = slow;
     wa.slow_count = slow_count;
-    const size_t wstatic = sizeof(WaveStage<KW, SAMPLE, VT>) * WRED_WAVES;
-    size_t wdyn = 0;
-    if (wstatic + diag_bytes <= 160 * 1024) wdyn = diag_bytes;
-    wa.r.diag_in_lds = wdyn ? 1 : 0;
-    HIPCHK(hipFuncSetAttribute((const void*)k_reduce_wave<KW, SAMPLE, VT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<size_t>(wdyn, 8)));
-    HIPCHK(hipFuncSetAttribute((const void*)k_reduce<KW, C, SAMPLE, VT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<size_t>(dyn, 8)));
+    wa.Pw = Pw;
     k_fill_u32<<<1, 64, 0, st>>>(overflow, 1, 0u);
     k_fill_u32<<<1, 64, 0, st>>>(slow_count, 1, 0u);
     HIPCHK(hipEventRecord(X->ev[8], st));
     {
-      const int64_t wblocks = std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * 8);
-      k_reduce_wave<KW, SAMPLE, VT><<<(int)wblocks, 64 * WRED_WAVES, std::max<size_t>(wdyn, 8), st>>>(wa);
+      if (wave_lds) {
+        HIPCHK(hipFuncSetAttribute((const void*)k_reduce_wave<KW, SAMPLE, VT, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_bytes));
+        k_reduce_wave<KW, SAMPLE, VT, true><<<(int)wblocks, 64 * WRED_WAVES, diag_bytes, st>>>(wa);
+      } else {
+        k_reduce_wave<KW, SAMPLE, VT, false><<<(int)wblocks, 64 * WRED_WAVES, 0, st>>>(wa);
+      }
     }
     // buckets the wavefront kernel could not take: block kernel with a full-key sort
     ra.blist = slow;
     ra.nlist = slow_count;
-    k_reduce<KW, C, SAMPLE, VT><<<(int)std::min<int64_t>(G.nbucket, (int64_t)cus * 2), 256,
-                                  std::max<size_t>(dyn, 8), st>>>(ra);
+    {
+      const int rgrid = (int)std::min<int64_t>(G.nbucket, (int64_t)cus * 2);
+      if (red_lds) {
+        HIPCHK(hipFuncSetAttribute((const void*)k_reduce<KW, C, SAMPLE, VT, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_bytes));
+        k_reduce<KW, C, SAMPLE, VT, true><<<rgrid, 256, diag_bytes, st>>>(ra);
+      } else {
+        k_reduce<KW, C, SAMPLE, VT, false><<<rgrid, 256, 0, st>>>(ra);
+      }
+    }
     HIPCHK(hipEventRecord(X->ev[9], st));
     HIPCHK(hipGetLastError());
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
@@ -614,11 +620,19 @@ int run_job(Job& J) {
       k_final<<<J.nsamp, 1024, 0, st>>>(P, G.nbucket, 0, J.nsamp, overflow, dflag, X->dres, J.per_sample,
                                          (int64_t)1 << G.bits_hash);
     } else {
-      const int64_t fchunk = std::max<int64_t>(256, (G.nbucket + 1023) / 1024);
+      // bucket partials (only the block kernel's buckets are non-zero) and
+      // per-wavefront partials, summed in a fixed order
+      const int64_t fchunk = std::max<int64_t>(256, (G.nbucket + 511) / 512);
       const int64_t fblocks = (G.nbucket + fchunk - 1) / fchunk;
-      Partials Q = Pq;
+      const int64_t nwv = wblocks * WRED_WAVES;
+      const int64_t wchunk = std::max<int64_t>(256, (nwv + 511) / 512);
+      const int64_t wfblocks = (nwv + wchunk - 1) / wchunk;
+      Partials Q = Pq, Q2 = Pq;
+      Q2.e2 += fblocks; Q2.de0 += fblocks; Q2.nterm += fblocks; Q2.ngen += fblocks;
+      Q2.nuniq += fblocks; Q2.nintr += fblocks; Q2.nzero += fblocks; Q2.mind += fblocks;
       k_final_partial<<<(int)fblocks, 256, 0, st>>>(P, G.nbucket, fchunk, Q);
-      k_final<<<1, 1024, 0, st>>>(Q, fblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0);
+      k_final_partial<<<(int)wfblocks, 256, 0, st>>>(Pw, nwv, wchunk, Q2);
+      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(X->ev[3], st));
@@ -771,16 +785,16 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     T.sD = cv.take<double>(n3);
     T.sJ = cv.take<double>(n3);
     T.ubound = cv.take<double>(n2);
-    T.hpp = cv.take<double>(n);
-    T.jtri = cv.take<double>(n * (n + 1) / 2);
-    T.sstri = cv.take<double>(n * (n - 1) / 2 + 1);
+    T.diag = cv.take<double>(diag_table_doubles(n));
+    T.hpp = T.diag;
+    T.jtri = T.diag + n;
+    T.sstri = T.diag + n + n * (n + 1) / 2;
     T.hb_val = cv.take<double>(nhb);
     T.hb_rs = cv.take<uint16_t>(nhb);
     T.hb_max = cv.take<double>(T.nss + n2);
     X->dflag = cv.take<uint32_t>(16);
     X->dres = cv.take<DevResult>(1);
-    X->ref_f = cv.take<double>(2 * n);
-    X->ref_e = cv.take<double>(1);
+
   };
   {
     Carver cv(nullptr);

@@ -4,6 +4,8 @@
 #include <stdint.h>
 
 #define SHCI_DEV __device__ __forceinline__
+// pure bit manipulation, also usable in host code (unit tests)
+#define SHCI_HD __host__ __device__ __forceinline__
 
 namespace shci {
 
@@ -14,7 +16,7 @@ constexpr int WAVE = 64;
 // the bucket id (top bits), the in-bucket sort key (next 32 bits) and the
 // variational-space hash set.
 // ---------------------------------------------------------------------------
-SHCI_DEV uint64_t fmix64(uint64_t k) {
+SHCI_HD uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;
   k *= 0xff51afd7ed558ccdull;
   k ^= k >> 33;
@@ -24,7 +26,7 @@ SHCI_DEV uint64_t fmix64(uint64_t k) {
 }
 
 template <int KW>
-SHCI_DEV uint64_t hash_key(const uint64_t (&k)[KW]) {
+SHCI_HD uint64_t hash_key(const uint64_t (&k)[KW]) {
   uint64_t h = 0x243f6a8885a308d3ull;
 #pragma unroll
   for (int w = 0; w < KW; ++w) h = fmix64(h ^ k[w]);
@@ -37,7 +39,7 @@ SHCI_DEV uint64_t hash_key(const uint64_t (&k)[KW]) {
 // one auxiliary flag bit at 2n+sbits.  KW 64-bit words hold it.
 // ---------------------------------------------------------------------------
 template <int KW>
-SHCI_DEV void put_bits(uint64_t (&k)[KW], uint64_t v0, uint64_t v1, int off) {
+SHCI_HD void put_bits(uint64_t (&k)[KW], uint64_t v0, uint64_t v1, int off) {
   // OR the 128-bit value (v0 | v1<<64) into k at bit offset off
   const int w = off >> 6, b = off & 63;
 #pragma unroll
@@ -51,7 +53,7 @@ SHCI_DEV void put_bits(uint64_t (&k)[KW], uint64_t v0, uint64_t v1, int off) {
 }
 
 template <int KW>
-SHCI_DEV void get_bits(const uint64_t (&k)[KW], int off, int nbits, uint64_t& v0, uint64_t& v1) {
+SHCI_HD void get_bits(const uint64_t (&k)[KW], int off, int nbits, uint64_t& v0, uint64_t& v1) {
   // extract nbits (<= 128) starting at bit off
   const int w = off >> 6, b = off & 63;
   uint64_t x0 = 0, x1 = 0, x2 = 0;
@@ -71,32 +73,62 @@ SHCI_DEV void get_bits(const uint64_t (&k)[KW], int off, int nbits, uint64_t& v0
   }
 }
 
+// key = alpha | beta << n, in closed form (1 <= n <= 127; the branch on
+// n >= 64 is uniform across a wavefront)
 template <int KW>
-SHCI_DEV void pack_det(uint64_t (&k)[KW], uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1,
+SHCI_HD void pack_det(uint64_t (&k)[KW], uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1,
                        int n) {
+  uint64_t o0, o1, o2, o3;
+  if (n < 64) {
+    o0 = b0 << n;
+    o1 = (b1 << n) | (b0 >> (64 - n));
+    o2 = b1 >> (64 - n);
+    o3 = 0ull;
+  } else {
+    const int t = n - 64;
+    o0 = 0ull;
+    o1 = b0 << t;
+    o2 = t ? ((b1 << t) | (b0 >> (64 - t))) : b1;
+    o3 = t ? (b1 >> (64 - t)) : 0ull;
+  }
+  const uint64_t w[4] = {a0 | o0, a1 | o1, o2, o3};
 #pragma unroll
-  for (int j = 0; j < KW; ++j) k[j] = 0;
-  put_bits<KW>(k, a0, a1, 0);
-  put_bits<KW>(k, b0, b1, n);
+  for (int j = 0; j < KW; ++j) k[j] = w[j];
 }
 
 template <int KW>
-SHCI_DEV void unpack_det(const uint64_t (&k)[KW], int n, uint64_t& a0, uint64_t& a1, uint64_t& b0,
+SHCI_HD void unpack_det(const uint64_t (&k)[KW], int n, uint64_t& a0, uint64_t& a1, uint64_t& b0,
                          uint64_t& b1) {
-  get_bits<KW>(k, 0, n, a0, a1);
-  get_bits<KW>(k, n, n, b0, b1);
+  uint64_t w[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+  for (int j = 0; j < KW; ++j) w[j] = k[j];
+  const uint64_t m0 = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+  const uint64_t m1 = (n <= 64) ? 0ull : ((n >= 128) ? ~0ull : ((1ull << (n - 64)) - 1ull));
+  a0 = w[0] & m0;
+  a1 = w[1] & m1;
+  uint64_t r0, r1;
+  if (n < 64) {
+    r0 = (w[0] >> n) | (w[1] << (64 - n));
+    r1 = (w[1] >> n) | (w[2] << (64 - n));
+  } else {
+    const int t = n - 64;
+    r0 = t ? ((w[1] >> t) | (w[2] << (64 - t))) : w[1];
+    r1 = t ? ((w[2] >> t) | (w[3] << (64 - t))) : w[2];
+  }
+  b0 = r0 & m0;
+  b1 = r1 & m1;
 }
 
 // mask of the grouping bits (everything below the auxiliary flag)
 template <int KW>
-SHCI_DEV void clear_aux(uint64_t (&k)[KW], int auxbit) {
+SHCI_HD void clear_aux(uint64_t (&k)[KW], int auxbit) {
 #pragma unroll
   for (int j = 0; j < KW; ++j)
     if (j == (auxbit >> 6)) k[j] &= ~(1ull << (auxbit & 63));
 }
 
 template <int KW>
-SHCI_DEV bool aux_set(const uint64_t (&k)[KW], int auxbit) {
+SHCI_HD bool aux_set(const uint64_t (&k)[KW], int auxbit) {
   bool r = false;
 #pragma unroll
   for (int j = 0; j < KW; ++j)
@@ -107,7 +139,7 @@ SHCI_DEV bool aux_set(const uint64_t (&k)[KW], int auxbit) {
 // ---------------------------------------------------------------------------
 // Spin strings (2 words) and fermion signs.
 // ---------------------------------------------------------------------------
-SHCI_DEV void low_mask(int x, uint64_t& m0, uint64_t& m1) {
+SHCI_HD void low_mask(int x, uint64_t& m0, uint64_t& m1) {
   // bits [0, x), 0 <= x <= 128
   if (x >= 64) {
     m0 = ~0ull;
@@ -119,23 +151,22 @@ SHCI_DEV void low_mask(int x, uint64_t& m0, uint64_t& m1) {
 }
 
 // occupied orbitals of (s0,s1) strictly between p and r
-SHCI_DEV int between(uint64_t s0, uint64_t s1, int p, int r) {
+SHCI_HD int between(uint64_t s0, uint64_t s1, int p, int r) {
   int lo = p < r ? p : r, hi = p < r ? r : p;
   uint64_t h0, h1, l0, l1;
   low_mask(hi, h0, h1);
   low_mask(lo + 1, l0, l1);
-  return __popcll(s0 & h0 & ~l0) + __popcll(s1 & h1 & ~l1);
+  return __builtin_popcountll(s0 & h0 & ~l0) + __builtin_popcountll(s1 & h1 & ~l1);
 }
 
-SHCI_DEV bool occ(uint64_t s0, uint64_t s1, int p) {
+SHCI_HD bool occ(uint64_t s0, uint64_t s1, int p) {
   return ((p < 64 ? s0 : s1) >> (p & 63)) & 1ull;
 }
 
-SHCI_DEV void flip(uint64_t& s0, uint64_t& s1, int p) {
-  if (p < 64)
-    s0 ^= 1ull << p;
-  else
-    s1 ^= 1ull << (p - 64);
+SHCI_HD void flip(uint64_t& s0, uint64_t& s1, int p) {
+  const uint64_t b = 1ull << (p & 63);
+  s0 ^= (p < 64) ? b : 0ull;
+  s1 ^= (p < 64) ? 0ull : b;
 }
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 //  4. the bucket partials are summed by a fixed-shape tree.
 #pragma once
 #include "gen.hpp"
+#include "diag.hpp"
 
 namespace shci {
 
@@ -169,27 +170,23 @@ struct RedArgs {
   GroupPlan G;
   int n, auxbit;
   double e0, nd;
-  const double* hpp;
-  const double* jtri;
-  const double* sstri;
-  int diag_in_lds;
+  const double* diag;  // packed diagonal table (diag.hpp layout, reference part filled)
   VSet V;
   Partials P;
   Uniq U;
   uint32_t* overflow;
   int want_u;
   const uint64_t* ref_det;  // reference determinant for H_aa (first det of V)
-  const double* ref_f;      // [2n] orbital energies relative to it
-  const double* ref_e;      // its energy
   int ne;                   // electrons
   const uint64_t* bstart;   // [nbucket + 1] bucket start offsets (nullable: binary search)
   const uint32_t* blist;    // buckets to process (nullable: all)
   const uint32_t* nlist;    // device count of blist
 };
 
+// membership of a packed determinant key (det bits only) in the hash set of V;
+// h is hash_key(k)
 template <int KW>
-SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
-  const uint64_t h = hash_key<KW>(k);
+SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
   uint64_t slot = h & V.mask;
   const uint32_t fp = (uint32_t)(h >> 32);
   for (uint64_t probe = 0; probe <= V.mask; ++probe) {
@@ -207,6 +204,11 @@ SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
     slot = (slot + 1) & V.mask;
   }
   return false;
+}
+
+template <int KW>
+SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
+  return vset_contains_h<KW>(V, k, hash_key<KW>(k), n);
 }
 
 template <int KW>
@@ -235,154 +237,6 @@ __global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
     slot = (slot + 1) & V.mask;
   }
   atomicOr(flag, 8u);  // table full (cannot happen at load <= 1/2)
-}
-
-// H_aa from LDS tables, in the order: h_pp over alpha then beta, same-spin
-// pairs (alpha, then beta), then alpha x beta pairs.
-SHCI_DEV double diag_energy(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const double* hpp,
-                            const double* jtri, const double* sstri) {
-  double e = 0.0;
-  uint64_t m0 = a0, m1 = a1;
-  while (m0 | m1) {
-    const int p = m0 ? __ffsll((unsigned long long)m0) - 1 : 64 + __ffsll((unsigned long long)m1) - 1;
-    if (m0) m0 &= m0 - 1; else m1 &= m1 - 1;
-    e = e + hpp[p];
-  }
-  m0 = b0; m1 = b1;
-  while (m0 | m1) {
-    const int p = m0 ? __ffsll((unsigned long long)m0) - 1 : 64 + __ffsll((unsigned long long)m1) - 1;
-    if (m0) m0 &= m0 - 1; else m1 &= m1 - 1;
-    e = e + hpp[p];
-  }
-  for (int sp = 0; sp < 2; ++sp) {
-    uint64_t x0 = sp ? b0 : a0, x1 = sp ? b1 : a1;
-    while (x0 | x1) {
-      const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
-      if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
-      uint64_t y0 = x0, y1 = x1;  // orbitals above p
-      while (y0 | y1) {
-        const int q = y0 ? __ffsll((unsigned long long)y0) - 1 : 64 + __ffsll((unsigned long long)y1) - 1;
-        if (y0) y0 &= y0 - 1; else y1 &= y1 - 1;
-        e = e + sstri[q * (q - 1) / 2 + p];
-      }
-    }
-  }
-  uint64_t x0 = a0, x1 = a1;
-  while (x0 | x1) {
-    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
-    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
-    uint64_t y0 = b0, y1 = b1;
-    while (y0 | y1) {
-      const int q = y0 ? __ffsll((unsigned long long)y0) - 1 : 64 + __ffsll((unsigned long long)y1) - 1;
-      if (y0) y0 &= y0 - 1; else y1 &= y1 - 1;
-      const int lo = p < q ? p : q, hi = p < q ? q : p;
-      e = e + jtri[hi * (hi + 1) / 2 + lo];
-    }
-  }
-  return e;
-}
-
-// Sum of W over pairs (x in mask X, y in mask Y), W = tab at the triangle
-// index of (x, y); `strict` skips the diagonal-free case x == y.
-SHCI_DEV double pair_sum_cross(uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, const double* tri,
-                               bool diag_incl) {
-  double e = 0.0;
-  while (x0 | x1) {
-    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
-    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
-    uint64_t m0 = y0, m1 = y1;
-    while (m0 | m1) {
-      const int q = m0 ? __ffsll((unsigned long long)m0) - 1 : 64 + __ffsll((unsigned long long)m1) - 1;
-      if (m0) m0 &= m0 - 1; else m1 &= m1 - 1;
-      const int lo = p < q ? p : q, hi = p < q ? q : p;
-      e += diag_incl ? tri[hi * (hi + 1) / 2 + lo] : tri[hi * (hi - 1) / 2 + lo];
-    }
-  }
-  return e;
-}
-
-// sum of S over pairs p < q inside one mask
-SHCI_DEV double pair_sum_within(uint64_t x0, uint64_t x1, const double* sstri) {
-  double e = 0.0;
-  while (x0 | x1) {
-    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
-    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
-    uint64_t y0 = x0, y1 = x1;
-    while (y0 | y1) {
-      const int q = y0 ? __ffsll((unsigned long long)y0) - 1 : 64 + __ffsll((unsigned long long)y1) - 1;
-      if (y0) y0 &= y0 - 1; else y1 &= y1 - 1;
-      e += sstri[q * (q - 1) / 2 + p];
-    }
-  }
-  return e;
-}
-
-SHCI_DEV double mask_sum(uint64_t x0, uint64_t x1, const double* f) {
-  double e = 0.0;
-  while (x0 | x1) {
-    const int p = x0 ? __ffsll((unsigned long long)x0) - 1 : 64 + __ffsll((unsigned long long)x1) - 1;
-    if (x0) x0 &= x0 - 1; else x1 &= x1 - 1;
-    e += f[p];
-  }
-  return e;
-}
-
-// Reference determinant R with its energy E_R and orbital energies
-// F_p(sigma) = h_pp + sum_{q in R_sigma, q != p} [(pp|qq) - (pq|qp)] + sum_{q in R_other} (pp|qq).
-struct DiagRef {
-  uint64_t r[4];
-  double e;
-  const double* f;  // [2n]: alpha block then beta block
-};
-
-// H_aa written relative to R.  With particles P = a \ R and holes Q = R \ a
-// (spin orbitals) and W the pair energy (J - K for equal spins, J otherwise):
-//   E(a) = E(R) + sum_{x in P} F_x - sum_{y in Q} F_y - sum_{x in P, y in Q} W_xy
-//          + sum_{x<x' in P} W_xx' + sum_{y<y' in Q} W_yy',
-// an exact rearrangement of the sum over occupied pairs.  Used when a is
-// close to R (fewer table reads than the direct sum); otherwise the direct
-// O(n_e^2) sum is used.
-SHCI_DEV double diag_energy_rel(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const DiagRef& R,
-                                int n, int ne, const double* hpp, const double* jtri, const double* sstri) {
-  const uint64_t pa0 = a0 & ~R.r[0], pa1 = a1 & ~R.r[1], pb0 = b0 & ~R.r[2], pb1 = b1 & ~R.r[3];
-  const uint64_t ha0 = R.r[0] & ~a0, ha1 = R.r[1] & ~a1, hb0 = R.r[2] & ~b0, hb1 = R.r[3] & ~b1;
-  const int l = __popcll(pa0) + __popcll(pa1) + __popcll(pb0) + __popcll(pb1);
-  if (3 * l * l + 2 * l >= ne * (ne + 1) / 2) return diag_energy(a0, a1, b0, b1, hpp, jtri, sstri);
-  double e = R.e;
-  e += mask_sum(pa0, pa1, R.f) + mask_sum(pb0, pb1, R.f + n);
-  e -= mask_sum(ha0, ha1, R.f) + mask_sum(hb0, hb1, R.f + n);
-  double pp = pair_sum_within(pa0, pa1, sstri) + pair_sum_within(pb0, pb1, sstri) +
-              pair_sum_cross(pa0, pa1, pb0, pb1, jtri, true);
-  double hh = pair_sum_within(ha0, ha1, sstri) + pair_sum_within(hb0, hb1, sstri) +
-              pair_sum_cross(ha0, ha1, hb0, hb1, jtri, true);
-  double ph = pair_sum_cross(pa0, pa1, ha0, ha1, sstri, false) + pair_sum_cross(pb0, pb1, hb0, hb1, sstri, false) +
-              pair_sum_cross(pa0, pa1, hb0, hb1, jtri, true) + pair_sum_cross(pb0, pb1, ha0, ha1, jtri, true);
-  return e + pp + hh - ph;
-}
-
-// F_p(sigma) and E(R) for the reference determinant (one block)
-__global__ void k_diag_ref(const uint64_t* ref, int n, const double* hpp, const double* jtri,
-                           const double* sstri, double* f, double* er) {
-  const uint64_t r0 = ref[0], r1 = ref[1], r2 = ref[2], r3 = ref[3];
-  for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) {
-    const int p = t % n, sp = t / n;
-    double v = hpp[p];
-    for (int q = 0; q < n; ++q) {
-      const bool inA = occ(r0, r1, q), inB = occ(r2, r3, q);
-      const int lo = p < q ? p : q, hi = p < q ? q : p;
-      const double j = jtri[hi * (hi + 1) / 2 + lo];
-      const double s = (p == q) ? 0.0 : sstri[hi * (hi - 1) / 2 + lo];
-      if (sp == 0) {
-        if (inA && q != p) v += s;
-        if (inB) v += j;
-      } else {
-        if (inB && q != p) v += s;
-        if (inA) v += j;
-      }
-    }
-    f[t] = v;
-  }
-  if (threadIdx.x == 0) *er = diag_energy(r0, r1, r2, r3, hpp, jtri, sstri);
 }
 
 // exclusive scan of 256 values held one per thread; returns the prefix,
@@ -458,29 +312,21 @@ struct RedShared {
   uint32_t nseg;
 };
 
-template <int KW, int C, bool SAMPLE, typename VT>
+template <int KW, int C, bool SAMPLE, typename VT, bool LDS>
 __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
-  extern __shared__ double s_diag[];
   __shared__ RedShared<KW, C, SAMPLE, VT> R;
   if (a.blist && (int64_t)*a.nlist <= (int64_t)blockIdx.x) return;
   const int t = threadIdx.x;
   const int n = a.n;
   R.S.wcnt[0][t] = R.S.wcnt[1][t] = R.S.wcnt[2][t] = R.S.wcnt[3][t] = 0;
-  // diagonal tables: h_pp [n], (pp|qq) triangle incl. diagonal, J-K triangle excl.
-  const double* s_hpp = a.hpp;
-  const double* s_jt = a.jtri;
-  const double* s_st = a.sstri;
-  if (a.diag_in_lds) {
-    double* h = s_diag;
-    double* jt = s_diag + n;
-    double* st = jt + n * (n + 1) / 2;
-    for (int x = t; x < n; x += 256) h[x] = a.hpp[x];
-    for (int x = t; x < n * (n + 1) / 2; x += 256) jt[x] = a.jtri[x];
-    for (int x = t; x < n * (n - 1) / 2; x += 256) st[x] = a.sstri[x];
-    s_hpp = h;
-    s_jt = jt;
-    s_st = st;
+  DiagTab<LDS> DT;
+  DT.g = a.diag;
+  DT.L = DiagLayout::make(n);
+  if constexpr (LDS) {
+    for (int x = t; x < DT.L.total; x += 256) g_lds_tab[x] = a.diag[x];
   }
+  uint64_t refd[4];
+  for (int w = 0; w < 4; ++w) refd[w] = a.ref_det[w];
   __syncthreads();
 
   const int64_t nb = a.blist ? (int64_t)*a.nlist : a.G.nbucket;
@@ -686,11 +532,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       ngen += cntk;
       double Dd = 0.0, g = 0.0;
       if (!inv) {
-        DiagRef DR;
-        for (int w = 0; w < 4; ++w) DR.r[w] = a.ref_det[w];
-        DR.e = *a.ref_e;
-        DR.f = a.ref_f;
-        const double haa = diag_energy_rel(a0, a1, b0, b1, DR, n, a.ne, s_hpp, s_jt, s_st);
+        const double haa = diag_energy<LDS>(a0, a1, b0, b1, refd, DT, a.ne);
         Dd = a.e0 - haa;
         double contrib;
         if constexpr (SAMPLE)

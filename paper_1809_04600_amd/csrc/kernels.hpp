@@ -13,8 +13,9 @@ struct Tables {
   double* sD = nullptr;      // [k][p][r] (pr|kk) - (pk|kr)
   double* sJ = nullptr;      // [k][p][r] (pr|kk)
   double* ubound = nullptr;  // [p][r]
-  double* hpp = nullptr;     // [n] h_pp
-  double* jtri = nullptr;    // (pp|qq), p <= q, at q(q+1)/2 + p
+  double* diag = nullptr;    // packed diagonal table (diag.hpp layout)
+  double* hpp = nullptr;     // = diag: h_pp
+  double* jtri = nullptr;    // = diag + n: (pp|qq), p <= q, at q(q+1)/2 + p
   double* sstri = nullptr;   // (pp|qq) - (pq|qp), p < q, at q(q-1)/2 + p
   double* hb_val = nullptr;  // signed values, sorted per key
   uint16_t* hb_rs = nullptr; // r | s << 8

@@ -62,6 +62,7 @@ struct WaveStage {
   VT v[WCAP];
   VT v2[SAMPLE ? WCAP : 1];
   uint64_t sk[WCAP];
+  uint64_t h[WCAP];  // hash of each record's key (aux bit clear)
 };
 
 struct WaveRedArgs {
@@ -69,15 +70,13 @@ struct WaveRedArgs {
   const uint64_t* bstart;  // [nbucket + 1]
   uint32_t* slow_list;     // buckets for the block kernel
   uint32_t* slow_count;
+  Partials Pw;             // per-wavefront partials (deterministic mode)
 };
 
+// stage the bucket in LDS and sort its 64-bit keys (R*64 >= M)
 template <int KW, bool SAMPLE, typename VT, int R>
-SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, int64_t b, int64_t lo,
-                          int M, const double* hpp, const double* jt, const double* st,
-                          const DiagRef& DR) {
-  const RedArgs& a = A.r;
+SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_t lo, int M) {
   const int lane = lane_id();
-  const int n = a.n;
   const int bh = a.G.bits_hash;
   uint64_t sk[R];
 #pragma unroll
@@ -93,67 +92,101 @@ SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, in
       if constexpr (SAMPLE) W.v2[j] = static_cast<const VT*>(a.in.v2)[lo + j];
       clear_aux<KW>(k, a.auxbit);
       const uint64_t h = hash_key<KW>(k);
-      sk[r] = (((h << bh) & ~0xffull)) | (uint64_t)j;
+      W.h[j] = h;
+      sk[r] = ((h << bh) & ~0xffull) | (uint64_t)j;
     }
   }
   wave_bitonic<R>(sk);
 #pragma unroll
   for (int r = 0; r < R; ++r) W.sk[r * 64 + lane] = sk[r];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
+struct SegAcc {
+  double e2p = 0.0, de0p = 0.0, dmn = INFINITY;
+  int64_t nterm = 0, ngen = 0;
+  int32_t nuniq = 0, nintr = 0, nzero = 0;
+};
+
+SHCI_DEV void wave_write_partials(const Partials& P, int64_t b, SegAcc acc) {
+  double e2p = acc.e2p, de0p = acc.de0p, dmn = acc.dmn;
+  int64_t nterm = acc.nterm, ngen = acc.ngen;
+  int32_t nuniq = acc.nuniq, nintr = acc.nintr, nzero = acc.nzero;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    e2p += __shfl_xor(e2p, o);
+    de0p += __shfl_xor(de0p, o);
+    dmn = fmin(dmn, __shfl_xor(dmn, o));
+    nterm += __shfl_xor(nterm, o);
+    ngen += __shfl_xor(ngen, o);
+    nuniq += __shfl_xor(nuniq, o);
+    nintr += __shfl_xor(nintr, o);
+    nzero += __shfl_xor(nzero, o);
+  }
+  if (lane_id() == 0) {
+    P.e2[b] = e2p;
+    P.de0[b] = de0p;
+    P.nterm[b] = nterm;
+    P.ngen[b] = ngen;
+    P.nuniq[b] = nuniq;
+    P.nintr[b] = nintr;
+    P.nzero[b] = nzero;
+    P.mind[b] = dmn;
+  }
+}
+
+SHCI_DEV void wave_zero_partials(const Partials& P, int64_t b) {
+  P.e2[b] = 0.0;
+  P.de0[b] = 0.0;
+  P.nterm[b] = 0;
+  P.ngen[b] = 0;
+  P.nuniq[b] = 0;
+  P.nintr[b] = 0;
+  P.nzero[b] = 0;
+  P.mind[b] = INFINITY;
+}
+
+// Returns false if the bucket was handed to the block kernel.  Contributions
+// accumulate in acc (per lane); in sample mode the caller reduces acc per
+// bucket, otherwise once per wavefront at the end.
+template <int KW, bool SAMPLE, typename VT, bool LDS>
+SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_t b, int64_t lo, int M,
+                          const DiagTab<LDS>& DT, const uint64_t (&ref)[4], uint32_t* slow_list,
+                          uint32_t* slow_count, SegAcc& acc) {
+  const int lane = lane_id();
+  const int n = a.n;
+  const int aw = a.auxbit >> 6;
+  const uint64_t am = 1ull << (a.auxbit & 63);
   auto key_eq = [&](int x, int y) {
     bool eq = true;
 #pragma unroll
     for (int w = 0; w < KW; ++w) {
       uint64_t kx = W.key[w][x], ky = W.key[w][y];
-      if (w == (a.auxbit >> 6)) {
-        kx &= ~(1ull << (a.auxbit & 63));
-        ky &= ~(1ull << (a.auxbit & 63));
+      if (w == aw) {
+        kx &= ~am;
+        ky &= ~am;
       }
       eq = eq && (kx == ky);
     }
     return eq;
   };
-  // heads, and a check that equal sort bits mean equal determinants
-  bool head[R];
+  // equal sort bits must mean equal determinants
   bool clash = false;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = r * 64 + lane;
-    head[r] = false;
-    if (e < M) {
-      if (e == 0) {
-        head[r] = true;
-      } else {
-        const uint64_t cur = W.sk[e], prv = W.sk[e - 1];
-        if ((cur >> 8) != (prv >> 8)) {
-          head[r] = true;
-        } else if (!key_eq((int)(cur & 0xff), (int)(prv & 0xff))) {
-          clash = true;
-        }
-      }
-    }
+#pragma unroll 1
+  for (int e = lane + 1; e < M; e += 64) {
+    const uint64_t cur = W.sk[e], prv = W.sk[e - 1];
+    if ((cur >> 8) == (prv >> 8) && !key_eq((int)(cur & 0xff), (int)(prv & 0xff))) clash = true;
   }
   if (ballot(clash)) {
-    if (lane == 0) {
-      const uint32_t s = atomicAdd(A.slow_count, 1u);
-      A.slow_list[s] = (uint32_t)b;
-    }
-    return;
+    if (lane == 0) slow_list[atomicAdd(slow_count, 1u)] = (uint32_t)b;
+    return false;
   }
-  uint64_t hb[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) hb[r] = ballot(head[r]);
   int nbefore = 0;
-  double e2p = 0.0, de0p = 0.0, dmn = INFINITY;
-  int64_t nterm = 0, ngen = 0;
-  int32_t nuniq = 0, nintr = 0, nzero = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (head[r]) {
-      const int e0 = r * 64 + lane;
+#pragma unroll 1
+  for (int base = 0; base < M; base += 64) {
+    const int e0 = base + lane;
+    const bool head = e0 < M && (e0 == 0 || (W.sk[e0] >> 8) != (W.sk[e0 - 1] >> 8));
+    const uint64_t hb = ballot(head);
+    if (head) {
       int e1 = e0 + 1;
       while (e1 < M && (W.sk[e1] >> 8) == (W.sk[e0] >> 8)) ++e1;
       const int first = (int)(W.sk[e0] & 0xff);
@@ -165,7 +198,7 @@ SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, in
           two_sum_f32(sx, cx, (float)W.v[id]);
           if constexpr (SAMPLE) {
             two_sum_f32(sy, cy, (float)W.v2[id]);
-            if ((W.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
+            if (W.key[aw][id] & am) {
               two_sum_f32(sxd, cxd, (float)W.v[id]);
               two_sum_f32(syd, cyd, (float)W.v2[id]);
             }
@@ -181,7 +214,7 @@ SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, in
           X = X + (double)W.v[id];
           if constexpr (SAMPLE) {
             Y = Y + (double)W.v2[id];
-            if ((W.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
+            if (W.key[aw][id] & am) {
               Xd = Xd + (double)W.v[id];
               Yd = Yd + (double)W.v2[id];
             }
@@ -194,31 +227,37 @@ SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, in
       clear_aux<KW>(k, a.auxbit);
       uint64_t a0, a1, b0, b1;
       unpack_det<KW>(k, n, a0, a1, b0, b1);
-      uint64_t dk[KW];
-      pack_det<KW>(dk, a0, a1, b0, b1, n);
-      const bool inv = vset_contains<KW>(a.V, dk, n);
+      bool inv;
+      if constexpr (SAMPLE) {
+        uint64_t dk[KW];
+        pack_det<KW>(dk, a0, a1, b0, b1, n);
+        inv = vset_contains<KW>(a.V, dk, n);
+      } else {
+        inv = vset_contains_h<KW>(a.V, k, W.h[first], n);  // key holds det bits only
+      }
       const int cntk = e1 - e0;
-      ngen += cntk;
+      acc.ngen += cntk;
       double Dd = 0.0, g = 0.0;
       if (!inv) {
-        const double haa = diag_energy_rel(a0, a1, b0, b1, DR, n, a.ne, hpp, jt, st);
+        const double haa = diag_energy<LDS>(a0, a1, b0, b1, ref, DT, a.ne);
         Dd = a.e0 - haa;
+        const double rd = 1.0 / Dd;
         double contrib;
         if constexpr (SAMPLE)
-          contrib = ((X * X + Y) - (Xd * Xd + Yd)) / (Dd * a.nd * (a.nd - 1.0));
+          contrib = ((X * X + Y) - (Xd * Xd + Yd)) * rd / (a.nd * (a.nd - 1.0));
         else
-          contrib = X * X / Dd;
-        e2p += contrib;
-        de0p += -(X * X) / (Dd * Dd);
-        g = 2.0 * X / Dd;
-        nterm += cntk;
-        nuniq += 1;
-        nintr += Dd > 0.0;
-        nzero += Dd == 0.0;
-        dmn = fmin(dmn, fabs(Dd));
+          contrib = X * X * rd;
+        acc.e2p += contrib;
+        acc.de0p += -(X * X) * rd * rd;
+        g = 2.0 * X * rd;
+        acc.nterm += cntk;
+        acc.nuniq += 1;
+        acc.nintr += Dd > 0.0;
+        acc.nzero += Dd == 0.0;
+        acc.dmn = fmin(acc.dmn, fabs(Dd));
       }
       if (a.want_u) {
-        const int64_t o = lo + nbefore + rank_below(hb[r]);
+        const int64_t o = lo + nbefore + rank_below(hb);
 #pragma unroll
         for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
         a.U.h2[o] = (uint32_t)(W.sk[e0] >> 32);
@@ -228,87 +267,63 @@ SHCI_DEV void wave_bucket(const WaveRedArgs& A, WaveStage<KW, SAMPLE, VT>& W, in
         a.U.cnt[o] = inv ? -cntk : cntk;
       }
     }
-    nbefore += __popcll(hb[r]);
+    nbefore += __popcll(hb);
   }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    e2p += __shfl_xor(e2p, o);
-    de0p += __shfl_xor(de0p, o);
-    dmn = fmin(dmn, __shfl_xor(dmn, o));
-    nterm += __shfl_xor(nterm, o);
-    ngen += __shfl_xor(ngen, o);
-    nuniq += __shfl_xor(nuniq, o);
-    nintr += __shfl_xor(nintr, o);
-    nzero += __shfl_xor(nzero, o);
+  if constexpr (SAMPLE) {
+    wave_write_partials(a.P, b, acc);
+    acc = SegAcc();
+  } else if (lane == 0) {
+    wave_zero_partials(a.P, b);
   }
   if (lane == 0) {
-    a.P.e2[b] = e2p;
-    a.P.de0[b] = de0p;
-    a.P.nterm[b] = nterm;
-    a.P.ngen[b] = ngen;
-    a.P.nuniq[b] = nuniq;
-    a.P.nintr[b] = nintr;
-    a.P.nzero[b] = nzero;
-    a.P.mind[b] = dmn;
     a.P.nseg[b] = nbefore;
     if (a.want_u) a.U.start[b] = (uint64_t)lo;
   }
+  return true;
 }
 
-template <int KW, bool SAMPLE, typename VT>
+template <int KW, bool SAMPLE, typename VT, bool LDS>
 __global__ void __launch_bounds__(64 * WRED_WAVES) k_reduce_wave(WaveRedArgs A) {
-  extern __shared__ double s_diag[];
   __shared__ WaveStage<KW, SAMPLE, VT> WS[WRED_WAVES];
   const RedArgs& a = A.r;
   const int t = threadIdx.x;
-  const int n = a.n;
-  const double* hpp = a.hpp;
-  const double* jt = a.jtri;
-  const double* st = a.sstri;
-  if (a.diag_in_lds) {
-    double* h = s_diag;
-    double* j2 = s_diag + n;
-    double* s2 = j2 + n * (n + 1) / 2;
-    for (int x = t; x < n; x += blockDim.x) h[x] = a.hpp[x];
-    for (int x = t; x < n * (n + 1) / 2; x += blockDim.x) j2[x] = a.jtri[x];
-    for (int x = t; x < n * (n - 1) / 2; x += blockDim.x) s2[x] = a.sstri[x];
-    hpp = h;
-    jt = j2;
-    st = s2;
+  DiagTab<LDS> DT;
+  DT.g = a.diag;
+  DT.L = DiagLayout::make(a.n);
+  if constexpr (LDS) {
+    for (int x = t; x < DT.L.total; x += blockDim.x) g_lds_tab[x] = a.diag[x];
   }
-  DiagRef DR;
+  uint64_t ref[4];
 #pragma unroll
-  for (int w = 0; w < 4; ++w) DR.r[w] = a.ref_det[w];
-  DR.e = *a.ref_e;
-  DR.f = a.ref_f;
-  if (a.diag_in_lds) {
-    double* f2 = s_diag + n + n * (n + 1) / 2 + n * (n - 1) / 2;
-    for (int x = t; x < 2 * n; x += blockDim.x) f2[x] = a.ref_f[x];
-    DR.f = f2;
-  }
+  for (int w = 0; w < 4; ++w) ref[w] = a.ref_det[w];
   __syncthreads();
   const int wv = t >> 6;
   const int lane = t & 63;
   WaveStage<KW, SAMPLE, VT>& W = WS[wv];
   const int64_t nwaves = (int64_t)gridDim.x * WRED_WAVES;
+  SegAcc acc;
   for (int64_t b = (int64_t)blockIdx.x * WRED_WAVES + wv; b < a.G.nbucket; b += nwaves) {
     const int64_t lo = (int64_t)A.bstart[b];
     const int64_t M = (int64_t)A.bstart[b + 1] - lo;
     if (M > WCAP) {
-      if (lane == 0) {
-        const uint32_t s = atomicAdd(A.slow_count, 1u);
-        A.slow_list[s] = (uint32_t)b;
-      }
+      if (lane == 0) A.slow_list[atomicAdd(A.slow_count, 1u)] = (uint32_t)b;
       continue;
     }
     if (M <= 64)
-      wave_bucket<KW, SAMPLE, VT, 1>(A, W, b, lo, (int)M, hpp, jt, st, DR);
+      wave_stage_sort<KW, SAMPLE, VT, 1>(a, W, lo, (int)M);
     else if (M <= 128)
-      wave_bucket<KW, SAMPLE, VT, 2>(A, W, b, lo, (int)M, hpp, jt, st, DR);
+      wave_stage_sort<KW, SAMPLE, VT, 2>(a, W, lo, (int)M);
     else
-      wave_bucket<KW, SAMPLE, VT, 4>(A, W, b, lo, (int)M, hpp, jt, st, DR);
+      wave_stage_sort<KW, SAMPLE, VT, 4>(a, W, lo, (int)M);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_bucket<KW, SAMPLE, VT, LDS>(a, W, b, lo, (int)M, DT, ref, A.slow_list, A.slow_count, acc);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  if constexpr (!SAMPLE) wave_write_partials(A.Pw, (int64_t)blockIdx.x * WRED_WAVES + wv, acc);
 }
 
 // bucket start offsets from the bucket id of every record (records are

@@ -103,7 +103,7 @@ int ceil_log2(uint64_t x) {
 struct shci_pt2_ctx {
   int device = 0;
   Tables T;
-  DevBuf tables, small, big;
+  DevBuf tables, small, small1, big;
   size_t ws_limit = 0;
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
   DevResult* dres = nullptr;
@@ -288,9 +288,14 @@ __global__ void k_export_terms(Recs R, int64_t nrec, int n, uint64_t* keys, uint
   }
 }
 
-__global__ void k_nonv_counts(const Partials P, int64_t nb, uint64_t* out) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x)
-    out[b] = (uint64_t)P.nuniq[b];
+// number of non-V uniques of every bucket, from the unique store
+__global__ void k_nonv_counts(Uniq U, const int32_t* nseg, int64_t nb, uint64_t* out) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = U.start[b];
+    uint64_t c = 0;
+    for (int s = 0; s < nseg[b]; ++s) c += U.cnt[lo + s] > 0;
+    out[b] = c;
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -338,29 +343,26 @@ int run_job(Job& J) {
   const int auxbit = 2 * n + J.sbits;
   const int cus = num_cus(X->device);
 
-  // ---- small workspace: counts, offsets, hash set of V, scan scratch ----
-  const int64_t ni = J.n_items;
+  // ---- phase 0: validation, hash set of V, work split per source ----
+  const int64_t nsrc = J.n_items;
   uint64_t vcap = 1024;
   while (vcap < 2 * (uint64_t)J.ndet) vcap <<= 1;
-  auto plan_small = [&](Carver& cv, uint32_t** counts, uint64_t** offs, uint64_t** vtab, ScanTmp* sc,
-                        uint64_t** total) {
-    *counts = cv.take<uint32_t>(ni + 1);
-    *offs = cv.take<uint64_t>(ni + 1);
-    *vtab = cv.take<uint64_t>(vcap);
-    *total = cv.take<uint64_t>(4);
-    sc->carve(cv, ni + 1);
+  uint32_t* nsplit;
+  uint64_t *soff, *vtab, *total;
+  ScanTmp sc0;
+  auto plan0 = [&](Carver& cv) {
+    nsplit = cv.take<uint32_t>(nsrc + 1);
+    soff = cv.take<uint64_t>(nsrc + 1);
+    vtab = cv.take<uint64_t>(vcap);
+    total = cv.take<uint64_t>(4);
+    sc0.carve(cv, nsrc + 1);
   };
-  uint32_t* counts;
-  uint64_t *offs, *vtab, *total;
-  ScanTmp sc;
   {
     Carver cv(nullptr);
-    plan_small(cv, &counts, &offs, &vtab, &sc, &total);
+    plan0(cv);
     CHK(X->small.ensure(cv.off, X->ws_limit));
-  }
-  {
-    Carver cv(X->small.p);
-    plan_small(cv, &counts, &offs, &vtab, &sc, &total);
+    Carver cv2(X->small.p);
+    plan0(cv2);
   }
   uint32_t* dflag = X->dflag;
   uint32_t* counter = X->dflag + 1;
@@ -375,6 +377,58 @@ int run_job(Job& J) {
   V.dets = J.dets;
   k_fill_u64<<<std::min<int64_t>(4096, (vcap + 255) / 256), 256, 0, st>>>(vtab, (int64_t)vcap, ~0ull);
   k_vset_insert<KW><<<(int)((J.ndet + 255) / 256), 256, 0, st>>>(V, J.ndet, n, dflag);
+  const int npairs = T.na * (T.na - 1) / 2 + T.nb * (T.nb - 1) / 2 + T.na * T.nb;
+  {
+    SplitArgs sa{};
+    sa.n = n;
+    sa.na = T.na;
+    sa.nb = T.nb;
+    sa.nss = T.nss;
+    sa.lss = T.lss;
+    sa.los = T.los;
+    sa.c = J.c;
+    sa.it_det = J.it_det;
+    sa.n_src = nsrc;
+    sa.eps2 = J.eps2;
+    sa.mag_cum = T.mag_cum;
+    sa.nsplit = nsplit;
+    k_split_count<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(sa);
+  }
+  CHK(scan_exclusive<uint32_t, uint64_t>(nsplit, soff, nsrc, sc0, total, st));
+  uint64_t hostv[2] = {0, 0};
+  uint32_t hflags = 0;
+  HIPCHK(hipMemcpyAsync(hostv, total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&hflags, dflag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflags & 1u) return fail(SHCI_ERR_DET, "a determinant has a wrong electron count or an orbital >= n_orb");
+  if (hflags & 2u) return fail(SHCI_ERR_NONFINITE, "c contains a non-finite value");
+  if (hflags & 4u) return fail(SHCI_ERR_DUP, "the variational space contains a duplicate determinant");
+  if (hflags & 8u) return fail(SHCI_ERR_WORKSPACE, "hash set of V overflowed");
+  const int64_t ni = (int64_t)hostv[0];  // work items
+  if (ni >= (int64_t)0xffffffffll) return fail(SHCI_ERR_WORKSPACE, "too many work items");
+
+  // ---- phase 1: work items, count pass ----
+  uint32_t *w_src, *w_rng, *counts;
+  uint64_t *offs, *total1;
+  double* gpart = nullptr;
+  ScanTmp sc;
+  auto plan1 = [&](Carver& cv) {
+    w_src = cv.take<uint32_t>(ni + 1);
+    w_rng = cv.take<uint32_t>(ni + 1);
+    counts = cv.take<uint32_t>(ni + 1);
+    offs = cv.take<uint64_t>(ni + 1);
+    total1 = cv.take<uint64_t>(4);
+    gpart = J.grad ? cv.take<double>(ni + 1) : nullptr;
+    sc.carve(cv, ni + 1);
+  };
+  {
+    Carver cv(nullptr);
+    plan1(cv);
+    CHK(X->small1.ensure(cv.off, X->ws_limit));
+    Carver cv2(X->small1.p);
+    plan1(cv2);
+  }
+  k_split_fill<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, nsrc, npairs, w_src, w_rng);
 
   GenArgs g{};
   g.n = n;
@@ -383,6 +437,8 @@ int run_job(Job& J) {
   g.dets = J.dets;
   g.c = J.c;
   g.n_items = ni;
+  g.w_src = w_src;
+  g.w_rng = w_rng;
   g.it_det = J.it_det;
   g.it_w = J.it_w;
   g.it_s = J.it_s;
@@ -402,16 +458,9 @@ int run_job(Job& J) {
   k_gen<KW, GEN_COUNT, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
   HIPCHK(hipEventRecord(X->ev[5], st));
   HIPCHK(hipGetLastError());
-  CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, total, st));
-  uint64_t hostv[2] = {0, 0};
-  uint32_t hflags = 0;
-  HIPCHK(hipMemcpyAsync(hostv, total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&hflags, dflag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, total1, st));
+  HIPCHK(hipMemcpyAsync(hostv, total1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (hflags & 1u) return fail(SHCI_ERR_DET, "a determinant has a wrong electron count or an orbital >= n_orb");
-  if (hflags & 2u) return fail(SHCI_ERR_NONFINITE, "c contains a non-finite value");
-  if (hflags & 4u) return fail(SHCI_ERR_DUP, "the variational space contains a duplicate determinant");
-  if (hflags & 8u) return fail(SHCI_ERR_WORKSPACE, "hash set of V overflowed");
   const int64_t nrec = (int64_t)hostv[0];
   if (nrec >= (int64_t)0xffffffffll)
     return fail(SHCI_ERR_WORKSPACE, "%lld screened terms exceed the 2^32-1 records of one pass",
@@ -673,13 +722,14 @@ int run_job(Job& J) {
       L.nseg = P.nseg;
       L.G = G;
       g.L = L;
-      g.grad = J.grad;
+      g.grad = gpart;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
       k_gen<KW, GEN_GRAD, false, VT><<<gen_grid, 256, 0, st>>>(g);
+      k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, J.grad);
       HIPCHK(hipGetLastError());
     }
     if (J.want_u && J.ex && J.ex->u_keys) {
-      k_nonv_counts<<<256, 256, 0, st>>>(P, G.nbucket, boff);
+      k_nonv_counts<<<256, 256, 0, st>>>(U, P.nseg, G.nbucket, boff);
       CHK(scan_exclusive<uint64_t, uint64_t>(boff, boff, G.nbucket, hsc, nullptr, st));
       k_export_uniq<KW><<<1024, 64, 0, st>>>(U, P.nseg, boff, G.nbucket, n, J.ex->u_keys, J.ex->u_A,
                                              J.ex->u_D, J.ex->u_cnt, J.ex->u_cap);
@@ -792,6 +842,7 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     T.hb_val = cv.take<double>(nhb);
     T.hb_rs = cv.take<uint16_t>(nhb);
     T.hb_max = cv.take<double>(T.nss + n2);
+    T.mag_cum = cv.take<double>(144);
     X->dflag = cv.take<uint32_t>(16);
     X->dres = cv.take<DevResult>(1);
 
@@ -827,6 +878,7 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
     if (e) (void)hipEventDestroy(e);
   ctx->tables.release();
   ctx->small.release();
+  ctx->small1.release();
   ctx->big.release();
   delete ctx;
 }

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef SHCI_DEV
 #define SHCI_DEV __device__ __forceinline__
+#endif
 // pure bit manipulation, also usable in host code (unit tests)
 #define SHCI_HD __host__ __device__ __forceinline__
 

@@ -61,7 +61,7 @@ SHCI_DEV uint64_t sel4(int m, uint64_t v0, uint64_t v1, uint64_t v2, uint64_t v3
 SHCI_DEV int pop_bit(uint64_t& x0, uint64_t& x1) {
   const bool lo = x0 != 0ull;
   const uint64_t w = lo ? x0 : x1;
-  const int p = __ffsll((unsigned long long)w) - 1 + (lo ? 0 : 64);
+  const int p = __builtin_ffsll((long long)w) - 1 + (lo ? 0 : 64);
   const uint64_t wn = w & (w - 1ull);
   x0 = lo ? wn : x0;
   x1 = lo ? x1 : wn;
@@ -70,7 +70,7 @@ SHCI_DEV int pop_bit(uint64_t& x0, uint64_t& x1) {
 
 // single-word version of pop_bit (all orbitals below 64)
 SHCI_DEV int pop_bit1(uint64_t& x) {
-  const int p = __ffsll((unsigned long long)x) - 1;
+  const int p = __builtin_ffsll((long long)x) - 1;
   x &= x - 1ull;
   return p;
 }
@@ -80,7 +80,7 @@ template <bool LDS>
 SHCI_DEV double diag_energy1(uint64_t a, uint64_t b, uint64_t ra, uint64_t rb, const DiagTab<LDS>& T,
                              int ne) {
   const int n = T.L.n;
-  const int l = __popcll(a & ~ra) + __popcll(b & ~rb);
+  const int l = __builtin_popcountll(a & ~ra) + __builtin_popcountll(b & ~rb);
   const bool use_ref = 3 * l * l + 2 * l < ne * (ne + 1) / 2;
   double e = 0.0;
   int fo = T.L.of;
@@ -134,14 +134,72 @@ SHCI_DEV double diag_energy1(uint64_t a, uint64_t b, uint64_t ra, uint64_t rb, c
   return e;
 }
 
+// With signs s = +1 for particles and -1 for holes, the formula above reads
+//   E(a) = E(R) + sum_x s_x F_x + sum_{x<y} s_x s_y W_xy
+// over the combined list of at most DL_MAX changed spin orbitals; the loops
+// below are fully unrolled and predicated (no divergent bit loops).
+constexpr int DL_MAX = 12;
+
+template <bool LDS>
+SHCI_DEV double diag_list(uint64_t pa0, uint64_t pa1, uint64_t pb0, uint64_t pb1, uint64_t ha0,
+                          uint64_t ha1, uint64_t hb0, uint64_t hb1, const DiagTab<LDS>& T) {
+  const int n = T.L.n;
+  int orb[DL_MAX];
+  int spn[DL_MAX];
+  double sg[DL_MAX];
+  bool ok[DL_MAX];
+#pragma unroll
+  for (int k = 0; k < DL_MAX; ++k) {
+    // next changed spin orbital, in the order P_alpha, P_beta, Q_alpha, Q_beta
+    const bool u0 = (pa0 | pa1) != 0ull, u1 = (pb0 | pb1) != 0ull, u2 = (ha0 | ha1) != 0ull,
+               u3 = (hb0 | hb1) != 0ull;
+    const int c = u0 ? 0 : (u1 ? 1 : (u2 ? 2 : (u3 ? 3 : 4)));
+    uint64_t x0 = c == 0 ? pa0 : (c == 1 ? pb0 : (c == 2 ? ha0 : hb0));
+    uint64_t x1 = c == 0 ? pa1 : (c == 1 ? pb1 : (c == 2 ? ha1 : hb1));
+    ok[k] = c < 4;
+    const int p = ok[k] ? pop_bit(x0, x1) : 0;
+    orb[k] = p;
+    spn[k] = c & 1;
+    sg[k] = c < 2 ? 1.0 : -1.0;
+    if (c == 0) { pa0 = x0; pa1 = x1; }
+    if (c == 1) { pb0 = x0; pb1 = x1; }
+    if (c == 2) { ha0 = x0; ha1 = x1; }
+    if (c == 3) { hb0 = x0; hb1 = x1; }
+  }
+  double e = T.at(T.L.oe);
+#pragma unroll
+  for (int k = 0; k < DL_MAX; ++k)
+    if (ok[k]) e += sg[k] * T.at(T.L.of + spn[k] * n + orb[k]);
+#pragma unroll
+  for (int k2 = 1; k2 < DL_MAX; ++k2) {
+    if (!ok[k2]) continue;
+#pragma unroll
+    for (int k1 = 0; k1 < k2; ++k1) {
+      const int p = orb[k1], q = orb[k2];
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      const bool same = spn[k1] == spn[k2];
+      const double w = same ? T.at(T.L.os + ((hi * (hi - 1)) >> 1) + lo)
+                            : T.at(T.L.oj + ((hi * (hi + 1)) >> 1) + lo);
+      e += (sg[k1] * sg[k2]) * w;
+    }
+  }
+  return e;
+}
+
 // H_aa for determinant a = (alpha a0:a1, beta b0:b1); r = reference det.
 template <bool LDS>
 SHCI_DEV double diag_energy(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const uint64_t (&r)[4],
                             const DiagTab<LDS>& T, int ne) {
+  {
+    const uint64_t pa0 = a0 & ~r[0], pa1 = a1 & ~r[1], pb0 = b0 & ~r[2], pb1 = b1 & ~r[3];
+    const int l = __builtin_popcountll(pa0) + __builtin_popcountll(pa1) + __builtin_popcountll(pb0) + __builtin_popcountll(pb1);
+    if (2 * l <= DL_MAX)
+      return diag_list<LDS>(pa0, pa1, pb0, pb1, r[0] & ~a0, r[1] & ~a1, r[2] & ~b0, r[3] & ~b1, T);
+  }
   if (T.L.n <= 64) return diag_energy1<LDS>(a0, b0, r[0], r[2], T, ne);
   const int n = T.L.n;
   uint64_t r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-  int l = __popcll(a0 & ~r0) + __popcll(a1 & ~r1) + __popcll(b0 & ~r2) + __popcll(b1 & ~r3);
+  int l = __builtin_popcountll(a0 & ~r0) + __builtin_popcountll(a1 & ~r1) + __builtin_popcountll(b0 & ~r2) + __builtin_popcountll(b1 & ~r3);
   const bool use_ref = 3 * l * l + 2 * l < ne * (ne + 1) / 2;
   double e = 0.0;
   if (use_ref) {
@@ -206,6 +264,35 @@ SHCI_DEV double diag_energy(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, 
   return e;
 }
 
+// plain sum over occupied pairs (reads only h, (pp|qq) and (pp|qq)-(pq|qp))
+SHCI_DEV double diag_plain(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, const double* tab,
+                           const DiagLayout& L) {
+  double e = 0.0;
+  for (int sp = 0; sp < 2; ++sp) {
+    uint64_t x0 = sp ? b0 : a0, x1 = sp ? b1 : a1;
+    while (x0 | x1) {
+      const int p = pop_bit(x0, x1);
+      e += tab[p];
+      uint64_t y0 = x0, y1 = x1;  // orbitals above p, same spin
+      while (y0 | y1) {
+        const int q = pop_bit(y0, y1);
+        e += tab[L.os + ((q * (q - 1)) >> 1) + p];
+      }
+    }
+  }
+  uint64_t x0 = a0, x1 = a1;
+  while (x0 | x1) {
+    const int p = pop_bit(x0, x1);
+    uint64_t y0 = b0, y1 = b1;
+    while (y0 | y1) {
+      const int q = pop_bit(y0, y1);
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      e += tab[L.oj + ((hi * (hi + 1)) >> 1) + lo];
+    }
+  }
+  return e;
+}
+
 // Per call: F_p(sigma) of the reference det and E(R) into the packed global
 // table (one block).
 __global__ void k_diag_ref(const uint64_t* ref, int n, int ne, double* tab) {
@@ -229,14 +316,7 @@ __global__ void k_diag_ref(const uint64_t* ref, int n, int ne, double* tab) {
     }
     tab[L.of + t] = v;
   }
-  if (threadIdx.x == 0) {
-    DiagTab<false> T;
-    T.g = tab;
-    T.L = L;
-    const uint64_t vac[4] = {0ull, 0ull, 0ull, 0ull};
-    // plain sum over occupied pairs: ne = 0 selects the empty reference
-    tab[L.oe] = diag_energy<false>(r0, r1, r2, r3, vac, T, 0);
-  }
+  if (threadIdx.x == 0) tab[L.oe] = diag_plain(r0, r1, r2, r3, tab, L);
 }
 
 }  // namespace shci

@@ -1,5 +1,6 @@
-// Excitation generator: one wavefront per source determinant (or per distinct
-// sampled determinant), persistent waves pulling work from an atomic counter.
+// Excitation generator: one wavefront per work item (a source determinant, or
+// a distinct sampled determinant, restricted to a range of its occupied
+// pairs), work items assigned round-robin to persistent wavefronts.
 //
 // For each source det i it emits every single and double excitation a with
 // |H_ai| |c_i| > eps2 (screened PT2 equation, section II.B):
@@ -37,7 +38,9 @@ struct GenArgs {
   int n, na, nb;
   const uint64_t* dets;
   const double* c;
-  int64_t n_items;
+  int64_t n_items;         // work items
+  const uint32_t* w_src;   // work item -> source (det, or distinct sampled det)
+  const uint32_t* w_rng;   // work item -> occupied-pair range [lo, hi) as lo | hi << 16
   // sample mode: distinct sampled determinants
   const uint32_t* it_det;
   const uint32_t* it_w;
@@ -93,6 +96,8 @@ SHCI_DEV double lookup_g(const uint64_t (&key)[KW], const LookupArgs& L) {
 template <int KW, int MODE, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
   __shared__ uint8_t s_lists[4][4][128];
+  __shared__ uint8_t s_plist[4][64];
+  __shared__ uint8_t s_llist[4][64];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   uint8_t* occA = s_lists[wv][0];
@@ -103,19 +108,22 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
   const double eps2 = a.eps2;
   const Tables& T = a.T;
 
-  for (;;) {
-    uint32_t got = 0;
-    if (lane == 0) got = atomicAdd(a.counter, 1u);
-    const int64_t item = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)got);
-    if (item >= a.n_items) break;
+  // work items round-robin over wavefronts (heavy sources are already split
+  // into several items, so a static assignment is balanced)
+  const int64_t nwaves_total = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t wave_gid = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  for (int64_t item = wave_gid; item < a.n_items; item += nwaves_total) {
 
-    int64_t i = item;
+    const int64_t src = a.w_src[item];
+    const uint32_t rng = a.w_rng[item];
+    const int pair_lo = (int)(rng & 0xffffu), pair_hi = (int)(rng >> 16);
+    int64_t i = src;
     double w = 1.0;
     uint32_t sid = 0;
     if constexpr (SAMPLE) {
-      i = a.it_det[item];
-      w = (double)a.it_w[item];
-      sid = a.it_s[item];
+      i = a.it_det[src];
+      w = (double)a.it_w[src];
+      sid = a.it_s[src];
     }
     const uint64_t A0 = a.dets[4 * i + 0], A1 = a.dets[4 * i + 1];
     const uint64_t B0 = a.dets[4 * i + 2], B1 = a.dets[4 * i + 3];
@@ -200,7 +208,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     };
 
     // ---------------- singles ----------------
-    const int nsa = na * va, nsing = nsa + nb * vb;
+    const int nsa = na * va, nsing = (pair_lo == 0) ? nsa + nb * vb : 0;  // singles with the first range
     for (int j0 = 0; j0 < nsing; j0 += 64) {
       const int j = j0 + lane;
       const bool valid = j < nsing;
@@ -221,22 +229,33 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
       if (cand) {
         const size_t pr_off = (size_t)p * n + r;
         const size_t nn = (size_t)n * n;
+        // h_pr, then occupied alpha ascending, then occupied beta ascending;
+        // same-spin k add (pr|kk)-(pk|kr) (k != p), other-spin k add (pr|kk).
+        // Loads are issued eight at a time; the additions keep this order.
+        const double* tabA = alpha ? T.sD : T.sJ;
+        const double* tabB = alpha ? T.sJ : T.sD;
         double acc = T.h1[pr_off];
-        for (int kk = 0; kk < na; ++kk) {
-          const int k = occA[kk];
-          if (alpha) {
-            if (k != p) acc = acc + T.sD[k * nn + pr_off];
-          } else {
-            acc = acc + T.sJ[k * nn + pr_off];
+        for (int kk0 = 0; kk0 < na; kk0 += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            v[u] = 0.0;
+            if (kk0 + u < na) v[u] = tabA[occA[kk0 + u] * nn + pr_off];
           }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (kk0 + u < na && !(alpha && occA[kk0 + u] == p)) acc = acc + v[u];
         }
-        for (int kk = 0; kk < nb; ++kk) {
-          const int k = occB[kk];
-          if (!alpha) {
-            if (k != p) acc = acc + T.sD[k * nn + pr_off];
-          } else {
-            acc = acc + T.sJ[k * nn + pr_off];
+        for (int kk0 = 0; kk0 < nb; kk0 += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            v[u] = 0.0;
+            if (kk0 + u < nb) v[u] = tabB[occB[kk0 + u] * nn + pr_off];
           }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (kk0 + u < nb && !(!alpha && occB[kk0 + u] == p)) acc = acc + v[u];
         }
         const int par = alpha ? between(A0, A1, p, r) : between(B0, B1, p, r);
         H = (par & 1) ? -acc : acc;
@@ -254,61 +273,117 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     }
 
     // ---------------- doubles ----------------
+    // Occupied pairs in windows of 64.  Pairs whose largest element can pass
+    // are probed eight at a time (8 lanes each, first 8 entries); pairs whose
+    // first 8 entries all pass are walked afterwards 64 entries at a time.
     const int caa = na * (na - 1) / 2, cbb = nb * (nb - 1) / 2;
-    const int npairs = caa + cbb + na * nb;
-    for (int u0 = 0; u0 < npairs; u0 += 64) {
+    auto decode = [&](int u, int& p, int& q, int& type, int64_t& off, int64_t& len) {
+      if (u < caa) {
+        const int y = tri_inv(u), x = u - y * (y - 1) / 2;
+        p = occA[x];
+        q = occA[y];
+        type = 0;
+      } else if (u < caa + cbb) {
+        const int v = u - caa;
+        const int y = tri_inv(v), x = v - y * (y - 1) / 2;
+        p = occB[x];
+        q = occB[y];
+        type = 1;
+      } else {
+        const int v = u - caa - cbb;
+        p = occA[v / nb];
+        q = occB[v % nb];
+        type = 2;
+      }
+      if (type < 2) {
+        off = (int64_t)(q * (q - 1) / 2 + p) * T.lss;
+        len = T.lss;
+      } else {
+        off = (int64_t)T.nss * T.lss + (int64_t)(p * n + q) * T.los;
+        len = T.los;
+      }
+    };
+    // one heat-bath entry (value v, target rs) of pair (p, q, type)
+    auto dbl = [&](bool pass, int type, int p, int q, double v, uint16_t rs) {
+      const int r = rs & 0xff, s2 = rs >> 8;
+      bool keep = pass;
+      uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
+      int par = 0;
+      if (type == 0) {
+        keep = keep && !occ(A0, A1, r) && !occ(A0, A1, s2);
+        par = between(x0, x1, p, r);
+        flip(x0, x1, p);
+        flip(x0, x1, r);
+        par += between(x0, x1, q, s2);
+        flip(x0, x1, q);
+        flip(x0, x1, s2);
+      } else if (type == 1) {
+        keep = keep && !occ(B0, B1, r) && !occ(B0, B1, s2);
+        par = between(y0, y1, p, r);
+        flip(y0, y1, p);
+        flip(y0, y1, r);
+        par += between(y0, y1, q, s2);
+        flip(y0, y1, q);
+        flip(y0, y1, s2);
+      } else {
+        keep = keep && !occ(A0, A1, r) && !occ(B0, B1, s2);
+        par = between(A0, A1, p, r) + between(B0, B1, q, s2);
+        flip(x0, x1, p);
+        flip(x0, x1, r);
+        flip(y0, y1, q);
+        flip(y0, y1, s2);
+      }
+      emit(keep, x0, x1, y0, y1, (par & 1) ? -v : v);
+    };
+    uint8_t* plist = s_plist[wv];
+    uint8_t* llist = s_llist[wv];
+    for (int u0 = pair_lo; u0 < pair_hi; u0 += 64) {
       const int u = u0 + lane;
       bool need = false;
-      if (u < npairs) {
-        int key;
-        if (u < caa) {
-          const int y = tri_inv(u), x = u - y * (y - 1) / 2;
-          const int p = occA[x], q = occA[y];
-          key = q * (q - 1) / 2 + p;
-        } else if (u < caa + cbb) {
-          const int v = u - caa;
-          const int y = tri_inv(v), x = v - y * (y - 1) / 2;
-          const int p = occB[x], q = occB[y];
-          key = q * (q - 1) / 2 + p;
-        } else {
-          const int v = u - caa - cbb;
-          const int p = occA[v / nb], q = occB[v % nb];
-          key = T.nss + p * n + q;
-        }
+      if (u < pair_hi) {
+        int p, q, type;
+        int64_t off, len;
+        decode(u, p, q, type, off, len);
+        const int key = (type < 2) ? q * (q - 1) / 2 + p : T.nss + p * n + q;
         need = T.hb_max[key] * absc > eps2;
       }
-      uint64_t todo = ballot(need);
-      while (todo) {
-        const int jb = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1ull;
-        const int uu = u0 + jb;  // uniform
-        int p, q, type;          // type 0: alpha-alpha, 1: beta-beta, 2: alpha-beta
-        if (uu < caa) {
-          const int y = tri_inv(uu), x = uu - y * (y - 1) / 2;
-          p = occA[x];
-          q = occA[y];
-          type = 0;
-        } else if (uu < caa + cbb) {
-          const int v = uu - caa;
-          const int y = tri_inv(v), x = v - y * (y - 1) / 2;
-          p = occB[x];
-          q = occB[y];
-          type = 1;
-        } else {
-          const int v = uu - caa - cbb;
-          p = occA[v / nb];
-          q = occB[v % nb];
-          type = 2;
+      const uint64_t nb_ = ballot(need);
+      const int nneed = __popcll(nb_);
+      if (need) plist[rank_below(nb_)] = (uint8_t)lane;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      int nlong = 0;
+      const int g = lane >> 3, sl = lane & 7;
+      for (int r0 = 0; r0 < nneed; r0 += 8) {
+        const int pi = r0 + g;
+        const bool active = pi < nneed;
+        int p = 0, q = 0, type = 0;
+        int64_t off = 0, len = 0;
+        if (active) decode(u0 + plist[pi], p, q, type, off, len);
+        const bool valid = active && sl < len;
+        double v = 0.0;
+        uint16_t rs = 0;
+        if (valid) {
+          v = T.hb_val[off + sl];
+          rs = T.hb_rs[off + sl];
         }
+        const bool pass = valid && (fabs(v) * absc > eps2);
+        const uint64_t pb = ballot(pass);
+        dbl(pass, type, p, q, v, rs);
+        const bool is_long = active && sl == 0 && ((pb >> (g * 8)) & 0xffull) == 0xffull && len > 8;
+        const uint64_t lb = ballot(is_long);
+        if (is_long) llist[nlong + rank_below(lb)] = plist[pi];
+        nlong += __popcll(lb);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int li = 0; li < nlong; ++li) {
+        int p, q, type;
         int64_t off, len;
-        if (type < 2) {
-          off = (int64_t)(q * (q - 1) / 2 + p) * T.lss;
-          len = T.lss;
-        } else {
-          off = (int64_t)T.nss * T.lss + (int64_t)(p * n + q) * T.los;
-          len = T.los;
-        }
-        for (int64_t e0 = 0; e0 < len; e0 += 64) {
+        decode(u0 + llist[li], p, q, type, off, len);  // uniform
+        for (int64_t e0 = 8; e0 < len; e0 += 64) {
           const int64_t e = e0 + lane;
           double v = 0.0;
           uint16_t rs = 0;
@@ -319,36 +394,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           const bool pass = (e < len) && (fabs(v) * absc > eps2);
           const uint64_t pb = ballot(pass);
           if (pb == 0ull) break;
-          const int r = rs & 0xff, s = rs >> 8;
-          bool keep = pass;
-          uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
-          int par = 0;
-          if (type == 0) {
-            keep = keep && !occ(A0, A1, r) && !occ(A0, A1, s);
-            par = between(x0, x1, p, r);
-            flip(x0, x1, p);
-            flip(x0, x1, r);
-            par += between(x0, x1, q, s);
-            flip(x0, x1, q);
-            flip(x0, x1, s);
-          } else if (type == 1) {
-            keep = keep && !occ(B0, B1, r) && !occ(B0, B1, s);
-            par = between(y0, y1, p, r);
-            flip(y0, y1, p);
-            flip(y0, y1, r);
-            par += between(y0, y1, q, s);
-            flip(y0, y1, q);
-            flip(y0, y1, s);
-          } else {
-            keep = keep && !occ(A0, A1, r) && !occ(B0, B1, s);
-            par = between(A0, A1, p, r) + between(B0, B1, q, s);
-            flip(x0, x1, p);
-            flip(x0, x1, r);
-            flip(y0, y1, q);
-            flip(y0, y1, s);
-          }
-          const double H = (par & 1) ? -v : v;
-          emit(keep, x0, x1, y0, y1, H);
+          dbl(pass, type, p, q, v, rs);
           if (pb != ~0ull) break;
         }
       }
@@ -360,9 +406,79 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     if constexpr (MODE == GEN_GRAD) {
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) gacc += __shfl_xor(gacc, o);
-      if (lane == 0) a.grad[i] = gacc;
+      if (lane == 0) a.grad[item] = gacc;  // per work item; summed per source afterwards
     }
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// dE2/dc_i = sum of the partial adjoints of the work items of source i, in
+// item order
+__global__ void k_grad_sum(const uint32_t* nsplit, const uint64_t* off, const double* part, int64_t n_src,
+                           double* grad) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  double g = 0.0;
+  for (uint32_t j = 0; j < nsplit[s]; ++j) g += part[off[s] + j];
+  grad[s] = g;
+}
+
+// Work split: a source whose heat-bath walks are long (small eps2 / |c_i|) is
+// cut into several work items over its occupied pairs, so that no wavefront
+// walks far more entries than the others.  The estimate uses, per table kind,
+// the number of entries with |value| >= 2^e (mag_cum), at e = floor(log2 t).
+constexpr double SPLIT_TARGET = 4096.0;  // estimated passing entries per work item
+
+struct SplitArgs {
+  int n, na, nb;
+  int nss;
+  int64_t lss, los;
+  const double* c;
+  const uint32_t* it_det;  // sample mode (nullable)
+  int64_t n_src;
+  double eps2;
+  const double* mag_cum;   // [2][72]: same-spin, opposite-spin
+  uint32_t* nsplit;        // [n_src]
+};
+
+SHCI_DEV int npairs_of(int na, int nb) { return na * (na - 1) / 2 + nb * (nb - 1) / 2 + na * nb; }
+
+__global__ void k_split_count(SplitArgs a) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.n_src) return;
+  const int64_t i = a.it_det ? (int64_t)a.it_det[s] : s;
+  const double absc = fabs(a.c[i]);
+  const int npairs = npairs_of(a.na, a.nb);
+  double ess = 0.0, eos = 0.0;
+  if (absc > 0.0) {
+    const double t = a.eps2 / absc;
+    if (t <= 0.0) {
+      ess = (double)a.lss;
+      eos = (double)a.los;
+    } else {
+      int e = ilogb(t);
+      e = e < -64 ? -64 : (e > 7 ? 7 : e);
+      ess = a.mag_cum[e + 64] / (a.nss > 0 ? a.nss : 1);
+      eos = a.mag_cum[72 + e + 64] / ((double)a.n * a.n);
+    }
+  }
+  const int pss = a.na * (a.na - 1) / 2 + a.nb * (a.nb - 1) / 2, pos = a.na * a.nb;
+  const double work = pss * ess + pos * eos;
+  int k = (int)ceil(work / SPLIT_TARGET);
+  k = k < 1 ? 1 : (k > npairs ? npairs : k);
+  a.nsplit[s] = (uint32_t)k;
+}
+
+__global__ void k_split_fill(const uint32_t* nsplit, const uint64_t* off, int64_t n_src, int npairs,
+                             uint32_t* w_src, uint32_t* w_rng) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n_src) return;
+  const int k = (int)nsplit[s];
+  const uint64_t o = off[s];
+  for (int j = 0; j < k; ++j) {
+    const int lo = (int)((int64_t)j * npairs / k), hi = (int)((int64_t)(j + 1) * npairs / k);
+    w_src[o + j] = (uint32_t)s;
+    w_rng[o + j] = (uint32_t)lo | ((uint32_t)hi << 16);
   }
 }
 

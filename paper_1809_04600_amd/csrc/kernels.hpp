@@ -20,6 +20,7 @@ struct Tables {
   double* hb_val = nullptr;  // signed values, sorted per key
   uint16_t* hb_rs = nullptr; // r | s << 8
   double* hb_max = nullptr;  // per key, largest |value| (0 if empty)
+  double* mag_cum = nullptr; // [2][72] entries with |value| >= 2^e, e = -64..7, per table kind
 };
 
 int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st, uint32_t* dflag);

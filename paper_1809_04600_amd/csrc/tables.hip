@@ -158,6 +158,39 @@ __global__ void __launch_bounds__(256) k_heatbath(const double* eri, int n, int 
   if (L == 0 && threadIdx.x == 0) hb_max[key] = 0.0;
 }
 
+__global__ void k_mag_clear(double* h) {
+  for (int x = threadIdx.x; x < 144; x += blockDim.x) h[x] = 0.0;
+}
+
+// histogram of log2 |value| per table kind, then cumulative from the top
+// (entries with |value| >= 2^e); used to size work items
+__global__ void k_mag_hist2(const double* hb_val, int64_t n_ss_entries, int64_t n_entries, double* hist) {
+  __shared__ unsigned int loc[144];
+  for (int x = threadIdx.x; x < 144; x += blockDim.x) loc[x] = 0u;
+  __syncthreads();
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_entries;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double m = fabs(hb_val[e]);
+    if (!(m > 0.0)) continue;
+    int x = ilogb(m);
+    x = x < -64 ? -64 : (x > 7 ? 7 : x);
+    atomicAdd(&loc[(e < n_ss_entries ? 0 : 72) + x + 64], 1u);
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < 144; x += blockDim.x)
+    if (loc[x]) atomicAdd(&hist[x], (double)loc[x]);
+}
+
+__global__ void k_mag_cum2(double* hist) {
+  if (threadIdx.x < 2) {
+    double acc = 0.0;
+    for (int x = 71; x >= 0; --x) {
+      acc += hist[threadIdx.x * 72 + x];
+      hist[threadIdx.x * 72 + x] = acc;
+    }
+  }
+}
+
 int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st, uint32_t* dflag) {
   const int n = T.n;
   const int64_t n3 = (int64_t)n * n * n, n4 = n3 * n;
@@ -174,6 +207,10 @@ int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st,
                           (int)lds) != hipSuccess)
     return -1;
   k_heatbath<<<nkeys, 256, lds, st>>>(eri, n, T.nss, T.lss, T.los, T.hb_val, T.hb_rs, T.hb_max);
+  k_mag_clear<<<1, 256, 0, st>>>(T.mag_cum);
+  const int64_t nss_e = (int64_t)T.nss * T.lss, ntot = nss_e + (int64_t)n * n * T.los;
+  k_mag_hist2<<<2048, 256, 0, st>>>(T.hb_val, nss_e, ntot, T.mag_cum);
+  k_mag_cum2<<<1, 64, 0, st>>>(T.mag_cum);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -34,7 +34,51 @@ def parse():
     ap.add_argument("--workload", default="w1")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def kernel_sources_sha256():
+    """Digest of the HIP sources: HBM counter figures taken with other sources
+    are stale and not reported."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1809_04600_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None when
+    missing or taken with other kernel sources."""
+    f = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n,
+                      "launches": 3}))
 
 
 def timed(ctx, dets, c, e0, eps2, prec, steps):
@@ -85,6 +129,9 @@ def main():
               "(the multi-GPU sharding is a design in DESIGN.md, not implemented)",
               file=sys.stderr)
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     import torch
 
     import paper_1809_04600_amd as P
@@ -145,7 +192,8 @@ def main():
                    "eps2": wl.eps2, "n_terms": n_terms, "n_records": n_rec,
                    "n_unique": s64["n_unique"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(wl.name, dom), "alg_bytes": alg[dom]},
         "e2_fp64": e2_64,
         "e2_wall_ms_fp64": w64 * 1e3,
         "fp32c": {"e2": e2_32, "e2_wall_ms": w32 * 1e3, "terms_per_s": n_terms / w32,

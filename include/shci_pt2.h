@@ -93,6 +93,7 @@ typedef struct {
   int64_t n_records;     /* records materialised (screened terms, members of V included) */
   int32_t key_words;     /* 64-bit words per packed key */
   int32_t value_bytes;   /* bytes per record value (8 FP64, 4 FP32C; x2 in sample mode) */
+  int32_t n_chunks;      /* hash batches (det, grad) or sample chunks (sample) evaluated */
 } shci_pt2_stats;
 
 /* Optional device outputs of shci_pt2_det (any pointer may be NULL).
@@ -143,6 +144,17 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx);
 /* Caps the context's device workspace (bytes; 0 = no cap).  Calls whose
  * working set would exceed the cap fail with SHCI_ERR_WORKSPACE. */
 int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes);
+
+/* Caps the screened-term records one generation pass materialises
+ * (0 = automatic: what free device memory, or the workspace cap, holds).
+ * Above the cap, shci_pt2_det and shci_pt2_grad split the perturbative
+ * determinants into 2^k hash batches (at most 256) and regenerate the terms
+ * once per batch, keeping in batch b only the a whose determinant hash has
+ * low bits b; every a is reduced whole in one batch, so E2 and the gradient
+ * are sums over batches (the paper's hash-batch decomposition of P,
+ * section IV).  shci_pt2_sample instead evaluates its samples in chunks of
+ * consecutive samples.  st->n_chunks reports the batches or chunks used. */
+int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records);
 
 /* Deterministic screened PT2 (screened PT2 equation).
  *   dets  device uint64 [n_det][4], unique, with n_alpha / n_beta electrons;

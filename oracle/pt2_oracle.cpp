@@ -704,6 +704,128 @@ double oracle_energy(int n, int na, int nb, const double* h1, const double* eri,
   return e.value();
 }
 
+// <c|H|c> for large V without visiting every pair.  Two distinct
+// determinants that differ by a single or double excitation both contain some
+// set of N-2 occupied spin orbitals (a "core"): for a double it is their common
+// occupation, for a single their common occupation minus any one orbital.
+// Every determinant is listed under each of its C(N,2) cores (the core's
+// 64-bit hash, SplitMix64's finaliser chained over the four words), the list
+// is sorted by hash, and within one hash group every pair is tested.  A pair
+// is credited only in the group of its canonical core -- the common occupation
+// with its lowest-addressed orbitals removed until N-2 remain -- so it is
+// counted exactly once even when unrelated cores share a hash value.  The
+// hash space is processed in 2^part_bits slices to bound memory.  hash_bits
+// < 64 truncates the hash (tests use it to force collisions).  Pair terms are
+// 2 c_i c_j H_ji for i < j, H_ji evaluated from the source i as in
+// oracle_energy; diagonal terms c_i^2 H_ii.  Sums are Neumaier per thread
+// (static schedules, so the result depends only on the thread count).
+static uint64_t splitmix_fin(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+static uint64_t core_hash(const uint64_t* w, int hash_bits) {
+  uint64_t h = 0x6a09e667f3bcc909ull;
+  for (int k = 0; k < 4; ++k) h = splitmix_fin(h ^ w[k]);
+  return hash_bits >= 64 ? h : (h >> (64 - hash_bits));
+}
+
+double oracle_energy_cores(int n, int na, int nb, const double* h1, const double* eri,
+                           const uint64_t* dets, const double* c, int64_t nd, int part_bits,
+                           int hash_bits, int64_t* n_pairs_out) {
+  System S{n, na, nb, h1, eri};
+  const Det* V = reinterpret_cast<const Det*>(dets);
+  const int ne = na + nb;
+  const int nthr = omp_get_max_threads();
+  if (hash_bits < part_bits) part_bits = hash_bits;
+  std::vector<Neumaier> acc(nthr);
+  std::vector<int64_t> npairs(nthr, 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nd; ++i) acc[omp_get_thread_num()].add(c[i] * c[i] * diag_value(S, V[i]));
+  const int64_t nparts = (int64_t)1 << part_bits;
+  for (int64_t part = 0; part < nparts; ++part) {
+    std::vector<std::vector<std::pair<uint64_t, uint32_t>>> buf(nthr);
+#pragma omp parallel
+    {
+      auto& b = buf[omp_get_thread_num()];
+      int pos[256];
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < nd; ++i) {
+        int m = 0;
+        for (int k = 0; k < 4; ++k)
+          for (uint64_t x = V[i].w[k]; x; x &= x - 1) pos[m++] = 64 * k + __builtin_ctzll(x);
+        for (int x = 0; x < m; ++x)
+          for (int y = x + 1; y < m; ++y) {
+            uint64_t w[4] = {V[i].w[0], V[i].w[1], V[i].w[2], V[i].w[3]};
+            w[pos[x] >> 6] &= ~(1ull << (pos[x] & 63));
+            w[pos[y] >> 6] &= ~(1ull << (pos[y] & 63));
+            const uint64_t h = core_hash(w, hash_bits);
+            const uint64_t slice = part_bits ? (h >> (hash_bits - part_bits)) : 0;
+            if ((int64_t)slice == part) b.emplace_back(h, (uint32_t)i);
+          }
+      }
+    }
+    std::vector<std::pair<uint64_t, uint32_t>> all;
+    size_t tot = 0;
+    for (auto& b : buf) tot += b.size();
+    all.reserve(tot);
+    for (auto& b : buf) {
+      all.insert(all.end(), b.begin(), b.end());
+      std::vector<std::pair<uint64_t, uint32_t>>().swap(b);
+    }
+    __gnu_parallel::sort(all.begin(), all.end());
+    std::vector<size_t> starts;
+    for (size_t k = 0; k < all.size(); ++k)
+      if (k == 0 || all[k].first != all[k - 1].first) starts.push_back(k);
+    starts.push_back(all.size());
+    const int64_t ng = (int64_t)starts.size() - 1;
+#pragma omp parallel
+    {
+      const int t = omp_get_thread_num();
+      std::vector<uint32_t> mem;
+#pragma omp for schedule(static)
+      for (int64_t g = 0; g < ng; ++g) {
+        mem.clear();
+        for (size_t k = starts[g]; k < starts[g + 1]; ++k)
+          if (mem.empty() || mem.back() != all[k].second) mem.push_back(all[k].second);
+        const uint64_t hg = all[starts[g]].first;
+        for (size_t a = 0; a < mem.size(); ++a)
+          for (size_t b = a + 1; b < mem.size(); ++b) {
+            const Det& di = V[mem[a]];
+            const Det& dj = V[mem[b]];
+            int diff = 0;
+            for (int k = 0; k < 4; ++k) diff += __builtin_popcountll(di.w[k] ^ dj.w[k]);
+            if (diff > 4) continue;
+            uint64_t w[4];
+            int common = 0;
+            for (int k = 0; k < 4; ++k) {
+              w[k] = di.w[k] & dj.w[k];
+              common += __builtin_popcountll(w[k]);
+            }
+            for (int k = 0; k < 4 && common > ne - 2; ++k)
+              while (w[k] && common > ne - 2) {
+                w[k] &= w[k] - 1;
+                --common;
+              }
+            if (core_hash(w, hash_bits) != hg) continue;
+            const double hv = hij(S, dj, di);
+            ++npairs[t];
+            if (hv != 0.0) acc[t].add(2.0 * c[mem[a]] * c[mem[b]] * hv);
+          }
+      }
+    }
+  }
+  Neumaier e;
+  int64_t np = 0;
+  for (int t = 0; t < nthr; ++t) {
+    e.add(acc[t].s);
+    e.add(acc[t].c);
+    np += npairs[t];
+  }
+  if (n_pairs_out) *n_pairs_out = np;
+  return e.value();
+}
+
 // MP1-like amplitudes H_i0 / (E_HF - H_ii) for the determinants flagged in
 // `mask` (doubles of the reference det `ref`), written in determinant order.
 void oracle_mp1(int n, int na, int nb, const double* h1, const double* eri, const uint64_t* dets,

@@ -59,6 +59,8 @@ def lib():
                                         C.c_int32, C.c_int32, _p, _p]
         L.oracle_energy.restype = _d
         L.oracle_energy.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64]
+        L.oracle_energy_cores.restype = _d
+        L.oracle_energy_cores.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _i, _i, _p]
         L.oracle_mp1.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _p, _p]
         L.oracle_max_threads.restype = _i
         _lib = L
@@ -207,6 +209,22 @@ def energy(n, na, nb, h1, eri, dets, c) -> float:
     dets = np.ascontiguousarray(dets, dtype=np.uint64)
     c = np.ascontiguousarray(c, dtype=np.float64)
     return lib().oracle_energy(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c))
+
+
+def energy_cores(n, na, nb, h1, eri, dets, c, hash_bits=64, part_bits=None):
+    """<c|H|c> through shared (N-2)-electron cores (large V); returns
+    (energy, number of connected off-diagonal pairs)."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    ne = na + nb
+    if part_bits is None:
+        entries = len(c) * ne * (ne - 1) // 2
+        part_bits = max(0, int(np.ceil(np.log2(max(1.0, entries / 4e7)))))
+    npairs = np.zeros(1, dtype=np.int64)
+    e = lib().oracle_energy_cores(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
+                                  int(part_bits), int(hash_bits), _ptr(npairs))
+    return e, int(npairs[0])
 
 
 def mp1(n, na, nb, h1, eri, dets, mask, ref) -> np.ndarray:

@@ -40,7 +40,7 @@ class Stats(C.Structure):
                 ("ms_gen", C.c_double), ("ms_sort", C.c_double), ("ms_reduce", C.c_double),
                 ("ms_total", C.c_double), ("ms_k_count", C.c_double), ("ms_k_write", C.c_double),
                 ("ms_k_reduce", C.c_double), ("n_records", C.c_int64), ("key_words", C.c_int32),
-                ("value_bytes", C.c_int32)]
+                ("value_bytes", C.c_int32), ("n_chunks", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,6 +72,8 @@ def lib():
         L.shci_pt2_ctx_destroy.restype = None
         L.shci_pt2_ctx_set_workspace_limit.argtypes = [p, C.c_size_t]
         L.shci_pt2_ctx_set_workspace_limit.restype = i
+        L.shci_pt2_ctx_set_record_limit.argtypes = [p, C.c_int64]
+        L.shci_pt2_ctx_set_record_limit.restype = i
         L.shci_pt2_det.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), C.POINTER(Stats),
                                    C.POINTER(Export)]
         L.shci_pt2_det.restype = i
@@ -141,6 +143,11 @@ class Context:
 
     def set_workspace_limit(self, nbytes: int):
         _check(lib().shci_pt2_ctx_set_workspace_limit(self._ptr, nbytes))
+
+    def set_record_limit(self, max_records: int):
+        """Records per generation pass (0 = automatic); above it the
+        deterministic paths use hash batches and sampling uses chunks."""
+        _check(lib().shci_pt2_ctx_set_record_limit(self._ptr, int(max_records)))
 
     def _inputs(self, dets, c):
         nd = c.shape[0]

@@ -105,6 +105,7 @@ struct shci_pt2_ctx {
   Tables T;
   DevBuf tables, small, small1, big;
   size_t ws_limit = 0;
+  int64_t rec_limit = 0;  // records per pass (0: from device memory)
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
   DevResult* dres = nullptr;
   hipEvent_t ev[10] = {};
@@ -301,6 +302,9 @@ __global__ void k_nonv_counts(Uniq U, const int32_t* nseg, int64_t nb, uint64_t*
 // ----------------------------------------------------------------------------
 // One evaluation (deterministic or one chunk of samples)
 // ----------------------------------------------------------------------------
+// internal status: the records of a job exceed its max_records
+constexpr int JOB_TOO_BIG = 1;
+
 struct Job {
   shci_pt2_ctx* ctx;
   hipStream_t st;
@@ -323,6 +327,9 @@ struct Job {
   bool want_u = false;
   bool want_pay = false;
   double* per_sample = nullptr;  // device [nsamp]
+  int64_t max_records = 0;       // > 0: give up after the count pass if exceeded
+  uint32_t bmask = 0, bsel = 0;  // hash batch of a (deterministic mode)
+  bool grad_accumulate = false;  // add this batch's adjoint to grad
   double* grad = nullptr;        // device [ndet]
   shci_pt2_export* ex = nullptr;
   // results
@@ -331,6 +338,7 @@ struct Job {
   float ms_gen = 0, ms_sort = 0, ms_reduce = 0, ms_k_count = 0, ms_k_write = 0, ms_k_reduce = 0;
   int64_t nrec = 0;
   int kw = 0, vbytes = 0;
+  int32_t nbatch = 1;
 };
 
 template <int KW, typename VT, bool SAMPLE>
@@ -452,6 +460,8 @@ int run_job(Job& J) {
   g.counter = counter;
   g.sbits = J.sbits;
   g.auxbit = auxbit;
+  g.bmask = J.bmask;
+  g.bsel = J.bsel;
   const int gen_grid = cus * GEN_BLOCKS_PER_CU;
   k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
   HIPCHK(hipEventRecord(X->ev[4], st));
@@ -462,6 +472,10 @@ int run_job(Job& J) {
   HIPCHK(hipMemcpyAsync(hostv, total1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const int64_t nrec = (int64_t)hostv[0];
+  if (J.max_records > 0 && nrec > J.max_records) {
+    J.nrec = nrec;
+    return JOB_TOO_BIG;
+  }
   if (nrec >= (int64_t)0xffffffffll)
     return fail(SHCI_ERR_WORKSPACE, "%lld screened terms exceed the 2^32-1 records of one pass",
                 (long long)nrec);
@@ -725,7 +739,8 @@ int run_job(Job& J) {
       g.grad = gpart;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
       k_gen<KW, GEN_GRAD, false, VT><<<gen_grid, 256, 0, st>>>(g);
-      k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, J.grad);
+      k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, J.grad,
+                                                              J.grad_accumulate ? 1 : 0);
       HIPCHK(hipGetLastError());
     }
     if (J.want_u && J.ex && J.ex->u_keys) {
@@ -794,6 +809,117 @@ void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
   st->n_records = J.nrec;
   st->key_words = J.kw;
   st->value_bytes = J.vbytes;
+  st->n_chunks = J.nbatch;
+}
+
+// Records one pass may materialise: the record limit if set, else what free
+// device memory (plus the reusable record workspace), or the workspace limit,
+// takes at `per_rec` bytes per record (two record buffers, bucket ids, the
+// unique store when kept, per-bucket arrays), after a fixed reserve for the
+// per-wavefront partials.
+int64_t record_budget(shci_pt2_ctx* X, double per_rec) {
+  if (X->rec_limit > 0) return X->rec_limit;
+  size_t fr = 0, tt = 0;
+  if (hipMemGetInfo(&fr, &tt) != hipSuccess) {
+    (void)hipGetLastError();
+    fr = 0;
+  }
+  size_t avail = fr + X->big.cap;
+  if (X->ws_limit) avail = std::min(avail, X->ws_limit);
+  const size_t reserve = (size_t)(num_cus(X->device) * 8 * WRED_WAVES + 1024) * 64 + (2u << 20);
+  avail = avail > reserve ? avail - reserve : 0;
+  const int64_t m = (int64_t)(0.75 * (double)avail / per_rec);
+  return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)1 << 31));
+}
+
+double record_bytes(int kw, int vbytes, bool pay, bool uniq) {
+  return 2.0 * (8.0 * kw + vbytes + (pay ? 4.0 : 0.0)) + 4.0 + 2.0 + (uniq ? 8.0 * kw + 40.0 : 0.0);
+}
+
+// Deterministic evaluation within the record budget.  When the screened
+// terms do not fit, they are split into B = 2^k hash batches of a (the low
+// bits of the determinant hash; the bucket id uses the high bits): batch b
+// regenerates every term and keeps those whose a falls in b, so every a is
+// reduced whole inside one batch and E2 = sum over batches of E2_b.
+int run_det_batched(const Job& proto, Job& acc) {
+  shci_pt2_ctx* X = proto.ctx;
+  const int kw = key_words(X->T.n, 0);
+  const int vb = proto.precision == SHCI_FP32C ? 4 : 8;
+  const int64_t max_rec = record_budget(X, record_bytes(kw, vb, proto.want_pay, proto.want_u));
+  uint32_t nb = 1;
+  for (;;) {
+    acc = Job{};
+    acc.res.mind = INFINITY;
+    bool again = false;
+    for (uint32_t b = 0; b < nb; ++b) {
+      Job J = proto;
+      J.bmask = nb - 1;
+      J.bsel = b;
+      J.max_records = max_rec;
+      J.grad_accumulate = b > 0;
+      shci_pt2_export exb{};
+      if (proto.ex) {
+        exb = *proto.ex;
+        const int64_t ub = std::min<int64_t>(acc.res.nuniq, exb.u_cap);
+        const int64_t tb = std::min<int64_t>(acc.nrec, exb.t_cap);
+        if (exb.u_keys) {
+          exb.u_keys += 4 * ub;
+          exb.u_A += ub;
+          exb.u_D += ub;
+          exb.u_cnt += ub;
+          exb.u_cap -= ub;
+        }
+        if (exb.t_keys) {
+          exb.t_keys += 4 * tb;
+          exb.t_i += tb;
+          exb.t_val += tb;
+          exb.t_cap -= tb;
+        }
+        J.ex = &exb;
+      }
+      const int r = dispatch(J);
+      if (r == JOB_TOO_BIG) {
+        // batches needed at this batch's size, with a margin for unevenness
+        const double need = 1.3 * (double)J.nrec * nb / (double)max_rec;
+        uint32_t nn = nb;
+        while (nn < need) nn <<= 1;
+        if (nn == nb) nn <<= 1;
+        if (nn > 256)
+          return fail(SHCI_ERR_WORKSPACE, "%lld screened terms need more than 256 hash batches of %lld records",
+                      (long long)((double)J.nrec * nb), (long long)max_rec);
+        nb = nn;
+        again = true;
+        break;
+      }
+      if (r) return r;
+      acc.res.e2 += J.res.e2;
+      acc.res.de0 += J.res.de0;
+      acc.res.nterm += J.res.nterm;
+      acc.res.ngen += J.res.ngen;
+      acc.res.nuniq += J.res.nuniq;
+      acc.res.nintr += J.res.nintr;
+      acc.res.nzero += J.res.nzero;
+      acc.res.mind = std::min(acc.res.mind, J.res.mind);
+      acc.nbucket = std::max(acc.nbucket, J.nbucket);
+      acc.retries += J.retries;
+      acc.ms_gen += J.ms_gen;
+      acc.ms_sort += J.ms_sort;
+      acc.ms_reduce += J.ms_reduce;
+      acc.ms_k_count += J.ms_k_count;
+      acc.ms_k_write += J.ms_k_write;
+      acc.ms_k_reduce += J.ms_k_reduce;
+      acc.nrec += J.nrec;
+      acc.kw = J.kw;
+      acc.vbytes = J.vbytes;
+    }
+    if (!again) break;
+  }
+  acc.nbatch = (int32_t)nb;
+  if (proto.ex) {
+    proto.ex->u_n = acc.res.nuniq;
+    proto.ex->t_n = acc.nrec;
+  }
+  return SHCI_OK;
 }
 
 }  // namespace
@@ -883,6 +1009,13 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
   delete ctx;
 }
 
+int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
+  if (max_records < 0) return fail(SHCI_ERR_ARG, "max_records must be >= 0");
+  ctx->rec_limit = max_records;
+  return SHCI_OK;
+}
+
 int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes) {
   if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
   ctx->ws_limit = bytes;
@@ -912,13 +1045,12 @@ int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64
   J.ex = ex;
   J.want_u = ex && ex->u_keys;
   J.want_pay = ex && ex->t_keys;
-  CHK(dispatch(J));
-  float tot = 0.f;
-  (void)hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[3]);
-  *e2 = J.res.e2;
-  fill_stats(st, J, tot);
-  if (J.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
-                               (long long)J.res.nzero);
+  Job R;
+  CHK(run_det_batched(J, R));
+  *e2 = R.res.e2;
+  fill_stats(st, R, R.ms_gen + R.ms_sort + R.ms_reduce);
+  if (R.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                               (long long)R.res.nzero);
   return SHCI_OK;
 }
 
@@ -941,14 +1073,13 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
   J.n_items = n_det;
   J.want_u = true;
   J.grad = de2_dc;
-  CHK(dispatch(J));
-  float tot = 0.f;
-  (void)hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[3]);
-  if (e2) *e2 = J.res.e2;
-  if (de2_de0) *de2_de0 = J.res.de0;
-  fill_stats(st, J, tot);
-  if (J.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
-                               (long long)J.res.nzero);
+  Job R;
+  CHK(run_det_batched(J, R));
+  if (e2) *e2 = R.res.e2;
+  if (de2_de0) *de2_de0 = R.res.de0;
+  fill_stats(st, R, R.ms_gen + R.ms_sort + R.ms_reduce);
+  if (R.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                               (long long)R.res.nzero);
   return SHCI_OK;
 }
 
@@ -1005,39 +1136,88 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   uint64_t* tot = uoff + n_samples;
   int sc = scan_exclusive<uint32_t, uint64_t>(ucount, uoff, n_samples, tmp, tot, s);
   if (sc) return done(sc);
-  k_sample_compact<<<n_samples, 256, 0, s>>>(t_det, t_w, ucount, uoff, n_draws, 0, o_det, o_w, o_s);
   uint64_t hn = 0;
   double hsum = 0.0;
   uint32_t hf = 0;
-  if (hipMemcpyAsync(&hn, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  std::vector<uint64_t> hoff(n_samples + 1);
+  if (hipMemcpyAsync(hoff.data(), uoff, (n_samples + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
       hipMemcpyAsync(&hsum, dsum, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return done(fail(SHCI_ERR_HIP, "sample preparation failed"));
+  hn = hoff[n_samples];
+  (void)hn;
   if (hf & 16u) return done(fail(SHCI_ERR_ARG, "a draw is >= n_det"));
   if (!(hsum > 0.0) || !std::isfinite(hsum)) return done(fail(SHCI_ERR_NONFINITE, "sum |c| is not positive and finite"));
-  Job J{};
-  J.ctx = ctx;
-  J.st = s;
-  J.dets = dets;
-  J.c = c;
-  J.ndet = n_det;
-  J.e0 = e0;
-  J.eps2 = eps2;
-  J.eps2_d = eps2_d;
-  J.precision = precision;
-  J.sample = true;
-  J.sbits = sbits;
-  J.nsamp = n_samples;
-  J.nd = (double)n_draws;
-  J.sum_abs = hsum;
-  J.it_det = o_det;
-  J.it_w = o_w;
-  J.it_s = o_s;
-  J.n_items = (int64_t)hn;
-  J.per_sample = per_sample;
-  int r = dispatch(J);
-  if (r) return done(r);
+
+  // Samples are evaluated in chunks of consecutive samples whose records fit
+  // the workspace: one generation / partition / reduce launch sequence per
+  // chunk covers all its samples (sample id in the key).  The chunk length
+  // adapts to the records per sample seen so far.
+  const int64_t max_rec =
+      record_budget(ctx, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false, false));
+  Job acc{};
+  acc.res.mind = INFINITY;
+  int64_t chunks = 0;
+  int32_t k = n_samples;  // first try: every sample in one chunk
+  for (int32_t s0 = 0; s0 < n_samples;) {
+    k = std::min<int32_t>(k, n_samples - s0);
+    k_sample_compact<<<k, 256, 0, s>>>(t_det + (int64_t)s0 * n_draws, t_w + (int64_t)s0 * n_draws,
+                                         ucount + s0, uoff + s0, n_draws, 0, o_det, o_w, o_s);
+    Job J{};
+    J.ctx = ctx;
+    J.st = s;
+    J.dets = dets;
+    J.c = c;
+    J.ndet = n_det;
+    J.e0 = e0;
+    J.eps2 = eps2;
+    J.eps2_d = eps2_d;
+    J.precision = precision;
+    J.sample = true;
+    J.sbits = std::max(1, ceil_log2((uint64_t)k));
+    J.nsamp = k;
+    J.nd = (double)n_draws;
+    J.sum_abs = hsum;
+    J.it_det = o_det + hoff[s0];
+    J.it_w = o_w + hoff[s0];
+    J.it_s = o_s + hoff[s0];
+    J.n_items = (int64_t)(hoff[s0 + k] - hoff[s0]);
+    J.per_sample = per_sample + s0;
+    J.max_records = max_rec;
+    int r = dispatch(J);
+    if (r == JOB_TOO_BIG) {
+      if (k == 1) return done(fail(SHCI_ERR_WORKSPACE, "one sample has %lld screened terms; the workspace holds %lld",
+                                   (long long)J.nrec, (long long)max_rec));
+      const double per = (double)J.nrec / k;
+      k = std::max<int32_t>(1, std::min<int32_t>(k - 1, (int32_t)(0.9 * (double)max_rec / per)));
+      continue;
+    }
+    if (r) return done(r);
+    ++chunks;
+    acc.res.nterm += J.res.nterm;
+    acc.res.ngen += J.res.ngen;
+    acc.res.nuniq += J.res.nuniq;
+    acc.res.nintr += J.res.nintr;
+    acc.res.nzero += J.res.nzero;
+    acc.res.mind = std::min(acc.res.mind, J.res.mind);
+    acc.nbucket = std::max(acc.nbucket, J.nbucket);
+    acc.retries += J.retries;
+    acc.ms_gen += J.ms_gen;
+    acc.ms_sort += J.ms_sort;
+    acc.ms_reduce += J.ms_reduce;
+    acc.ms_k_count += J.ms_k_count;
+    acc.ms_k_write += J.ms_k_write;
+    acc.ms_k_reduce += J.ms_k_reduce;
+    acc.nrec += J.nrec;
+    acc.kw = std::max(acc.kw, J.kw);
+    acc.vbytes = J.vbytes;
+    s0 += k;
+    // next chunk: as many samples as the budget allows at this chunk's rate
+    const double per = (double)std::max<int64_t>(1, J.nrec) / k;
+    k = std::max<int32_t>(1, (int32_t)std::min<double>(n_samples, 0.9 * (double)max_rec / per));
+  }
   std::vector<double> ps(n_samples);
   if (hipMemcpyAsync(ps.data(), per_sample, n_samples * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -1049,11 +1229,10 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   for (double v : ps) var += (v - m) * (v - m);
   if (mean) *mean = m;
   if (sem) *sem = n_samples > 1 ? std::sqrt(var / (n_samples - 1)) / std::sqrt((double)n_samples) : 0.0;
-  float tt = 0.f;
-  (void)hipEventElapsedTime(&tt, ctx->ev[0], ctx->ev[3]);
-  fill_stats(st, J, tt);
-  if (J.res.nzero) return done(fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
-                                    (long long)J.res.nzero));
+  fill_stats(st, acc, acc.ms_gen + acc.ms_sort + acc.ms_reduce);
+  if (st) st->n_chunks = (int32_t)chunks;  // sample chunks
+  if (acc.res.nzero) return done(fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                                      (long long)acc.res.nzero));
   return done(SHCI_OK);
 }
 

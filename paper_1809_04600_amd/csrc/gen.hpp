@@ -54,6 +54,7 @@ struct GenArgs {
   Recs out;
   uint32_t* counter;
   int sbits, auxbit;
+  uint32_t bmask, bsel;    // hash batch: keep a only if (hash(a) & bmask) == bsel
   LookupArgs L;
   double* grad;
 };
@@ -169,6 +170,13 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     double gacc = 0.0;
 
     auto emit = [&](bool keep, uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, double H) {
+      if (a.bmask) {  // uniform
+        if (keep) {
+          uint64_t hk[KW];
+          pack_det<KW>(hk, x0, x1, y0, y1, n);
+          keep = ((uint32_t)hash_key<KW>(hk) & a.bmask) == a.bsel;
+        }
+      }
       const uint64_t bal = ballot(keep);
       if constexpr (MODE == GEN_COUNT) {
         cursor += (uint64_t)__popcll(bal);
@@ -415,12 +423,12 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
 // dE2/dc_i = sum of the partial adjoints of the work items of source i, in
 // item order
 __global__ void k_grad_sum(const uint32_t* nsplit, const uint64_t* off, const double* part, int64_t n_src,
-                           double* grad) {
+                           double* grad, int accumulate) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n_src) return;
   double g = 0.0;
   for (uint32_t j = 0; j < nsplit[s]; ++j) g += part[off[s] + j];
-  grad[s] = g;
+  grad[s] = accumulate ? grad[s] + g : g;  // hash batches add in batch order
 }
 
 // Work split: a source whose heat-bath walks are long (small eps2 / |c_i|) is

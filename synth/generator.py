@@ -157,7 +157,10 @@ def _random_subset(rng, rows: int, pool: int, take: np.ndarray) -> tuple[np.ndar
         return np.zeros((rows, 0), dtype=np.int64), np.zeros((rows, 0), dtype=bool)
     keys = rng.random((rows, pool))
     perm = np.argsort(keys, axis=1, kind="stable")
-    valid = np.arange(pool)[None, :] < take[:, None]
+    # only the first max(take) columns can be selected
+    kmax = int(min(pool, max(int(take.max()), 1)))
+    perm = perm[:, :kmax]
+    valid = np.arange(kmax)[None, :] < take[:, None]
     return perm, valid
 
 

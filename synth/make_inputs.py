@@ -6,7 +6,7 @@ of the Hartree-Fock determinant and E0 = <c|H|c>.  The stored file holds those
 two items plus fingerprints of the generated arrays, so that a later run can
 check that it regenerated the same workload.
 
-Usage: python -m synth.make_inputs w0 w1 w2
+Usage: python -m synth.make_inputs w0 w1 w2 w3
 """
 from __future__ import annotations
 
@@ -26,7 +26,10 @@ def make(name: str) -> None:
     mask = G.double_of_hf_mask(x.levels)
     amp = ref.mp1(n, na, nb, x.h1, x.eri, x.dets, mask, x.dets[0])
     c = G.assemble_coefficients(x.noise, x.levels, amp)
-    e0 = ref.energy(n, na, nb, x.h1, x.eri, x.dets, c)
+    if len(c) <= 100_000:
+        e0 = ref.energy(n, na, nb, x.h1, x.eri, x.dets, c)
+    else:
+        e0, _ = ref.energy_cores(n, na, nb, x.h1, x.eri, x.dets, c)
     np.savez(data_path(name), mp1=amp, e0=np.float64(e0),
              fp_dets=fingerprint(x.dets), fp_eri=fingerprint(x.eri), fp_c=fingerprint(c))
     print(f"{name}: n_var={len(c)} doubles={len(amp)} E0={e0!r}")

@@ -220,3 +220,63 @@ def test_sample_explicit_draws():
     assert np.all(out0.cpu().numpy() == 0.0)
     out32, _, _, _ = ctx.sample(dets, c, x.e0, eps2, eps2_d, dr, "fp32c")
     assert np.abs(out32.cpu().numpy() - o).max() <= 1e-6
+
+
+def test_hash_batches_match_single_pass():
+    # records above the limit: the deterministic paths split a into hash
+    # batches; the same unique a, A_a and D_a come out, E2 and the gradient
+    # are sums over batches
+    x = I.small(12, 3, 3, 300, 3, 11)
+    ctx, dets, c = context(x)
+    eps2 = 1e-6
+    o = _oracle(x, eps2, grad=True)
+    r1 = ctx.det(dets, c, x.e0, eps2, "fp64", unique_cap=o.n_unique + 8, terms_cap=o.n_terms_gen + 8)
+    assert r1.stats["n_chunks"] == 1
+    e2g1, g1, de1, _ = ctx.grad(dets, c, x.e0, eps2, "fp64")
+    ctx.set_record_limit(o.n_terms_gen // 5)
+    try:
+        rb = ctx.det(dets, c, x.e0, eps2, "fp64", unique_cap=o.n_unique + 8, terms_cap=o.n_terms_gen + 8)
+        e2gb, gb, deb, stg = ctx.grad(dets, c, x.e0, eps2, "fp64")
+        rb32 = ctx.det(dets, c, x.e0, eps2, "fp32c")
+    finally:
+        ctx.set_record_limit(0)
+    print("batches:", rb.stats["n_chunks"], "grad batches:", stg["n_chunks"])
+    assert rb.stats["n_chunks"] >= 4 and stg["n_chunks"] >= 4
+    for k in ("n_terms", "n_terms_gen", "n_unique", "n_intruder"):
+        assert rb.stats[k] == r1.stats[k] == getattr(o, k)
+    A, D, oA, oD = _check_unique(rb.unique, o)
+    A1, D1, _, _ = _check_unique(r1.unique, o)
+    # each a is reduced whole inside one batch, in the same term order
+    assert np.array_equal(A, A1) and np.array_equal(D, D1)
+    assert rb.terms["n"] == o.n_terms_gen
+    assert abs(rb.e2 - r1.e2) <= 1e-13 * abs(r1.e2)
+    assert abs(rb.e2 - o.e2) <= E2_TOL_FP64
+    assert abs(rb32.e2 - o.e2) <= E2_TOL_FP32C
+    gb, g1 = gb.cpu().numpy(), g1.cpu().numpy()
+    assert np.abs(gb - g1).max() <= 1e-13 * np.abs(g1).max()
+    assert np.abs(gb - o.grad).max() <= 1e-10 * np.abs(o.grad).max()
+    assert abs(deb - de1) <= 1e-13 * abs(de1)
+
+
+def test_sample_chunks_match_single_pass():
+    x = I.small(10, 3, 3, 200, 3, 9)
+    ctx, dets, c = context(x)
+    rng = np.random.default_rng(7)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    draws = rng.choice(len(x.c), size=(13, 40), p=p).astype(np.uint32)
+    dr = torch.from_numpy(draws.view(np.int32)).cuda()
+    eps2, eps2_d = 1e-6, 1e-4
+    o = ref.pt2_sample(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2, eps2_d, draws)
+    out1, m1, s1, st1 = ctx.sample(dets, c, x.e0, eps2, eps2_d, dr, "fp64")
+    ctx.set_record_limit(max(1, st1["n_records"] // 6))
+    try:
+        outc, mc, sc, stc = ctx.sample(dets, c, x.e0, eps2, eps2_d, dr, "fp64")
+    finally:
+        ctx.set_record_limit(0)
+    print("sample chunks:", st1["n_chunks"], stc["n_chunks"])
+    assert stc["n_chunks"] >= 4
+    assert stc["n_terms"] == st1["n_terms"] and stc["n_records"] == st1["n_records"]
+    out1, outc = out1.cpu().numpy(), outc.cpu().numpy()
+    scale = max(1.0, np.abs(o).max())
+    assert np.abs(outc - out1).max() <= 1e-13 * scale
+    assert np.abs(outc - o).max() <= 1e-9 * scale

@@ -273,3 +273,24 @@ def test_validation_errors():
     with pytest.raises(ref.OracleError) as e:
         ref.pt2_det(8, 2, 2, x.h1, x.eri, x.dets, c, x.e0, 0.0)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("shape", [(10, 3, 3, 400, 3, 1), (14, 4, 3, 600, 4, 2), (70, 2, 2, 150, 2, 3)])
+def test_energy_through_cores_matches_pairwise(shape):
+    # <c|H|c> through shared (N-2)-electron cores: the same value as the
+    # pairwise sum, also when a short hash makes unrelated cores collide, and
+    # exactly the connected pairs of V (brute force)
+    n, na, nb, nv, lev, seed = shape
+    x = I.small(n, na, nb, nv, lev, seed)
+    e_pair = ref.energy(n, na, nb, x.h1, x.eri, x.dets, x.c)
+    e64, npairs = ref.energy_cores(n, na, nb, x.h1, x.eri, x.dets, x.c)
+    e6, npairs6 = ref.energy_cores(n, na, nb, x.h1, x.eri, x.dets, x.c, hash_bits=6, part_bits=2)
+    assert abs(e64 - e_pair) <= 1e-13 * abs(e_pair)
+    assert abs(e6 - e_pair) <= 1e-13 * abs(e_pair)
+    d = x.dets
+    diff = np.zeros((len(d), len(d)), dtype=np.int64)
+    for w in range(4):
+        xo = np.bitwise_xor(d[:, None, w], d[None, :, w])
+        diff += np.array([bin(int(v)).count("1") for v in xo.ravel()]).reshape(xo.shape)
+    brute = int(((diff > 0) & (diff <= 4)).sum() // 2)
+    assert npairs == npairs6 == brute

@@ -586,6 +586,37 @@ int oracle_pt2_at(int n, int na, int nb, const double* h1, const double* eri, co
   return 0;
 }
 
+// Kept terms (screened, a outside V) of the listed sources: for each source
+// src[k], every single and double excitation a with fabs(H_ai)*fabs(c_i) >
+// eps2 and a not in V, in enumeration order.  Writes up to cap entries
+// (key of a, H_ai, k) and returns the total number found.
+int64_t oracle_terms_of(int n, int na, int nb, const double* h1, const double* eri, const uint64_t* dets,
+                        const double* c, int64_t nd, double eps2, const int64_t* src, int64_t nsrc,
+                        uint64_t* keys, double* hv, int64_t* which, int64_t cap) {
+  System S{n, na, nb, h1, eri};
+  const Det* V = reinterpret_cast<const Det*>(dets);
+  std::unordered_set<Det, DetHash> vset(V, V + nd);
+  std::vector<std::vector<std::pair<Det, double>>> per(nsrc);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < nsrc; ++k) {
+    const int64_t i = src[k];
+    for_each_excitation(S, V[i], [&](const Det& a, double h) {
+      if (kept(h, c[i], eps2) && !vset.count(a)) per[k].emplace_back(a, h);
+    });
+  }
+  int64_t o = 0;
+  for (int64_t k = 0; k < nsrc; ++k)
+    for (auto& t : per[k]) {
+      if (o < cap) {
+        std::memcpy(&keys[4 * o], t.first.w, 32);
+        hv[o] = t.second;
+        which[o] = k;
+      }
+      ++o;
+    }
+  return o;
+}
+
 // Stochastic estimator on explicit draws (stochastic PT2 equation).  draws is
 // [ns][ndraw] indices into V; out[s] = S_s(eps2) - S_s(eps2_d), where
 // S_s(e) = sum_{a not in V} [ (sum_i w_i c_i H_ai / p_i)^2
@@ -649,31 +680,46 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
         per[u].push_back(T{a, i, x, y, kept(hval, ci, eps2_d)});
       });
     }
-    for (auto& v : per) terms.insert(terms.end(), v.begin(), v.end());
-    std::sort(terms.begin(), terms.end(), [](const T& x, const T& y) {
+    size_t total = 0;
+    for (auto& v : per) total += v.size();
+    terms.reserve(total);
+    for (auto& v : per) {
+      terms.insert(terms.end(), v.begin(), v.end());
+      std::vector<T>().swap(v);
+    }
+    __gnu_parallel::sort(terms.begin(), terms.end(), [](const T& x, const T& y) {
       if (x.a == y.a) return x.i < y.i;
       return x.a < y.a;
     });
-    Neumaier tot;
-    k = 0;
-    while (k < terms.size()) {
-      size_t j = k;
-      while (j < terms.size() && terms[j].a == terms[k].a) ++j;
-      if (!Vset.count(terms[k].a)) {
-        Acc acc;
-        for (size_t m = k; m < j; ++m) {
-          acc.X.add(terms[m].x);
-          acc.Y.add(terms[m].y);
-          if (terms[m].d) {
-            acc.Xd.add(terms[m].x);
-            acc.Yd.add(terms[m].y);
-          }
+    // one contribution per distinct a outside V, summed per thread
+    // (Neumaier) and then across threads in thread order
+    std::vector<size_t> heads;
+    for (size_t m = 0; m < terms.size(); ++m)
+      if (m == 0 || !(terms[m].a == terms[m - 1].a)) heads.push_back(m);
+    heads.push_back(terms.size());
+    const int nthr = omp_get_max_threads();
+    std::vector<Neumaier> part(nthr);
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < (int64_t)heads.size() - 1; ++g) {
+      const size_t k0 = heads[g], j = heads[g + 1];
+      if (Vset.count(terms[k0].a)) continue;
+      Acc acc;
+      for (size_t m = k0; m < j; ++m) {
+        acc.X.add(terms[m].x);
+        acc.Y.add(terms[m].y);
+        if (terms[m].d) {
+          acc.Xd.add(terms[m].x);
+          acc.Yd.add(terms[m].y);
         }
-        double X = acc.X.value(), Y = acc.Y.value(), Xd = acc.Xd.value(), Yd = acc.Yd.value();
-        double Dd = e0 - diag_value(S, terms[k].a);
-        tot.add(((X * X + Y) - (Xd * Xd + Yd)) / (Dd * Nd * (Nd - 1.0)));
       }
-      k = j;
+      double X = acc.X.value(), Y = acc.Y.value(), Xd = acc.Xd.value(), Yd = acc.Yd.value();
+      double Dd = e0 - diag_value(S, terms[k0].a);
+      part[omp_get_thread_num()].add(((X * X + Y) - (Xd * Xd + Yd)) / (Dd * Nd * (Nd - 1.0)));
+    }
+    Neumaier tot;
+    for (auto& q : part) {
+      tot.add(q.s);
+      tot.add(q.c);
     }
     out[s] = tot.value();
   }

@@ -59,6 +59,8 @@ def lib():
                                         C.c_int32, C.c_int32, _p, _p]
         L.oracle_energy.restype = _d
         L.oracle_energy.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64]
+        L.oracle_terms_of.restype = _i64
+        L.oracle_terms_of.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _p, _i64, _p, _p, _p, _i64]
         L.oracle_energy_cores.restype = _d
         L.oracle_energy_cores.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _i, _i, _p]
         L.oracle_mp1.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _p, _p]
@@ -209,6 +211,26 @@ def energy(n, na, nb, h1, eri, dets, c) -> float:
     dets = np.ascontiguousarray(dets, dtype=np.uint64)
     c = np.ascontiguousarray(c, dtype=np.float64)
     return lib().oracle_energy(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c))
+
+
+def terms_of(n, na, nb, h1, eri, dets, c, eps2, sources):
+    """Kept terms (a outside V) of the given sources: (keys [m,4] uint64,
+    H_ai [m], index into `sources` [m]), in enumeration order per source."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    src = np.ascontiguousarray(sources, dtype=np.int64)
+    cap = 1 << 16
+    while True:
+        keys = np.zeros((cap, 4), dtype=np.uint64)
+        hv = np.zeros(cap)
+        which = np.zeros(cap, dtype=np.int64)
+        m = lib().oracle_terms_of(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
+                                  float(eps2), _ptr(src), len(src), _ptr(keys), _ptr(hv),
+                                  _ptr(which), cap)
+        if m <= cap:
+            return keys[:m], hv[:m], which[:m]
+        cap = m
 
 
 def energy_cores(n, na, nb, h1, eri, dets, c, hash_bits=64, part_bits=None):

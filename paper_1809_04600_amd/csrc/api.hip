@@ -462,6 +462,10 @@ int run_job(Job& J) {
   g.auxbit = auxbit;
   g.bmask = J.bmask;
   g.bsel = J.bsel;
+  g.ref = J.dets;
+  g.Fref = T.fref;
+  g.smarg = 8.0 * (2 * n + 2 + 2 * DL_CAP) * 0x1p-53;
+  singles_ref(T, J.dets, st);
   const int gen_grid = cus * GEN_BLOCKS_PER_CU;
   k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
   HIPCHK(hipEventRecord(X->ev[4], st));
@@ -961,6 +965,7 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     T.sD = cv.take<double>(n3);
     T.sJ = cv.take<double>(n3);
     T.ubound = cv.take<double>(n2);
+    T.fref = cv.take<double>(2 * n2);
     T.diag = cv.take<double>(diag_table_doubles(n));
     T.hpp = T.diag;
     T.jtri = T.diag + n;

@@ -34,6 +34,8 @@ struct LookupArgs {
   GroupPlan G;
 };
 
+constexpr int DL_CAP = 32;  // differences from the reference kept for the singles filter
+
 struct GenArgs {
   int n, na, nb;
   const uint64_t* dets;
@@ -55,6 +57,11 @@ struct GenArgs {
   uint32_t* counter;
   int sbits, auxbit;
   uint32_t bmask, bsel;    // hash batch: keep a only if (hash(a) & bmask) == bsel
+  // singles prefilter: Fock-like elements of a reference determinant R,
+  // Fref[s][p][r] = h_pr + sum_{k in R_s, k != p} sD[k][p][r] + sum_{k in R_s'} sJ[k][p][r]
+  const uint64_t* ref;
+  const double* Fref;
+  double smarg;            // rounding margin, in units of the bound U_pr
   LookupArgs L;
   double* grad;
 };
@@ -97,6 +104,8 @@ SHCI_DEV double lookup_g(const uint64_t (&key)[KW], const LookupArgs& L) {
 template <int KW, int MODE, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
   __shared__ uint8_t s_lists[4][4][128];
+  __shared__ uint16_t s_dl[4][DL_CAP];   // differences of the source from R
+  __shared__ uint16_t s_sq[4][128];      // queue of singles candidates
   __shared__ uint8_t s_plist[4][64];
   __shared__ uint8_t s_llist[4][64];
   const int wv = threadIdx.x >> 6;
@@ -189,10 +198,11 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
             put_bits<KW>(key, (uint64_t)sid, 0ull, 2 * n);
             if (fabs(H) * absc > a.eps2_d) put_bits<KW>(key, 1ull, 0ull, a.auxbit);
             const double ch = ci * H;
+            // x and z = x^2 + y of the stochastic estimator (see SegSum)
             const double xv = w * ch / pr;
-            const double yv = (w * (a.nd - 1.0) / pr - w * w / (pr * pr)) * ch * ch;
+            const double zv = (w * (a.nd - 1.0) / pr) * ch * ch;
             static_cast<VT*>(a.out.v)[pos] = (VT)xv;
-            static_cast<VT*>(a.out.v2)[pos] = (VT)yv;
+            static_cast<VT*>(a.out.v2)[pos] = (VT)zv;
           } else {
             VT t;
             if constexpr (sizeof(VT) == 4)
@@ -216,13 +226,47 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     };
 
     // ---------------- singles ----------------
+    // The screened element is the exact one, summed in the canonical order
+    // (h_pr, occupied alpha ascending, occupied beta ascending; same-spin k
+    // add (pr|kk)-(pk|kr) for k != p, other-spin k add (pr|kk)).  Two cheap
+    // filters run first: the bound U_pr |c_i| <= eps2, then the same element
+    // evaluated relative to R (Fref plus the orbitals where the source and R
+    // differ) with a margin that covers the rounding of both sums.  Survivors
+    // are queued and evaluated exactly 64 at a time, in candidate order.
     const int nsa = na * va, nsing = (pair_lo == 0) ? nsa + nb * vb : 0;  // singles with the first range
-    for (int j0 = 0; j0 < nsing; j0 += 64) {
-      const int j = j0 + lane;
-      const bool valid = j < nsing;
-      const bool alpha = j < nsa;
-      int p = 0, r = 0;
-      if (valid) {
+    if (nsing > 0) {
+      const size_t nn = (size_t)n * n;
+      // difference list: alpha particles, alpha holes, beta particles, beta
+      // holes (entry k | spin << 7 | hole << 8)
+      int ndl = 0;
+      {
+        const uint64_t R0 = a.ref[0], R1 = a.ref[1], R2 = a.ref[2], R3 = a.ref[3];
+        const uint64_t dm[8] = {A0 & ~R0, A1 & ~R1, R0 & ~A0, R1 & ~A1,
+                                B0 & ~R2, B1 & ~R3, R2 & ~B0, R3 & ~B1};
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) tot += __popcll(dm[w]);
+        if (tot <= DL_CAP) {
+#pragma unroll
+          for (int w = 0; w < 8; ++w) {
+            const bool in = (w & 1) ? (lane + 64 < n && ((dm[w] >> lane) & 1ull)) : (lane < n && ((dm[w] >> lane) & 1ull));
+            const uint64_t m = ballot(in);
+            if (in)
+              s_dl[wv][ndl + rank_below(m)] =
+                  (uint16_t)((lane + ((w & 1) ? 64 : 0)) | ((w >> 2) << 7) | (((w >> 1) & 1) << 8));
+            ndl += __popcll(m);
+          }
+        } else {
+          ndl = -1;  // too far from R: no relative filter
+        }
+      }
+      uint16_t* sq = s_sq[wv];
+      int qn = 0;  // uniform
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      auto cand_of = [&](int j, bool& alpha, int& p, int& r) {
+        alpha = j < nsa;
         if (alpha) {
           p = occA[j / va];
           r = virA[j % va];
@@ -231,53 +275,97 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           p = occB[jj / vb];
           r = virB[jj % vb];
         }
-      }
-      const bool cand = valid && (T.ubound[p * n + r] * absc > eps2);
-      double H = 0.0;
-      if (cand) {
+      };
+      // exact evaluation and emission of queue entries [0, cnt)
+      auto process = [&](int cnt) {
+        const bool valid = lane < cnt;
+        bool alpha = true;
+        int p = 0, r = 0;
+        if (valid) cand_of((int)sq[lane], alpha, p, r);
+        double H = 0.0;
+        if (valid) {
+          const size_t pr_off = (size_t)p * n + r;
+          const double* tabA = alpha ? T.sD : T.sJ;
+          const double* tabB = alpha ? T.sJ : T.sD;
+          double acc = T.h1[pr_off];
+          for (int kk0 = 0; kk0 < na; kk0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              v[u] = 0.0;
+              if (kk0 + u < na) v[u] = tabA[occA[kk0 + u] * nn + pr_off];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (kk0 + u < na && !(alpha && occA[kk0 + u] == p)) acc = acc + v[u];
+          }
+          for (int kk0 = 0; kk0 < nb; kk0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              v[u] = 0.0;
+              if (kk0 + u < nb) v[u] = tabB[occB[kk0 + u] * nn + pr_off];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (kk0 + u < nb && !(!alpha && occB[kk0 + u] == p)) acc = acc + v[u];
+          }
+          const int par = alpha ? between(A0, A1, p, r) : between(B0, B1, p, r);
+          H = (par & 1) ? -acc : acc;
+        }
+        const bool keep = valid && (fabs(H) * absc > eps2);
+        uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
+        if (alpha) {
+          flip(x0, x1, p);
+          flip(x0, x1, r);
+        } else {
+          flip(y0, y1, p);
+          flip(y0, y1, r);
+        }
+        emit(keep, x0, x1, y0, y1, H);
+      };
+      for (int j0 = 0; j0 < nsing; j0 += 64) {
+        const int j = j0 + lane;
+        const bool valid = j < nsing;
+        bool alpha = true;
+        int p = 0, r = 0;
+        if (valid) cand_of(j, alpha, p, r);
         const size_t pr_off = (size_t)p * n + r;
-        const size_t nn = (size_t)n * n;
-        // h_pr, then occupied alpha ascending, then occupied beta ascending;
-        // same-spin k add (pr|kk)-(pk|kr) (k != p), other-spin k add (pr|kk).
-        // Loads are issued eight at a time; the additions keep this order.
-        const double* tabA = alpha ? T.sD : T.sJ;
-        const double* tabB = alpha ? T.sJ : T.sD;
-        double acc = T.h1[pr_off];
-        for (int kk0 = 0; kk0 < na; kk0 += 8) {
-          double v[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            v[u] = 0.0;
-            if (kk0 + u < na) v[u] = tabA[occA[kk0 + u] * nn + pr_off];
+        const double ub = valid ? T.ubound[pr_off] : 0.0;
+        bool maybe = valid && (ub * absc > eps2);
+        if (ndl >= 0 && maybe) {
+          const int sp = alpha ? 0 : 1;
+          double h = a.Fref[sp * nn + pr_off];
+          for (int t = 0; t < ndl; ++t) {
+            const uint32_t e = s_dl[wv][t];
+            const int k = (int)(e & 127u);
+            const bool same = (int)((e >> 7) & 1u) == sp;
+            if (same && k == p) continue;
+            const double v = (same ? T.sD : T.sJ)[k * nn + pr_off];
+            h = (e >> 8) ? h - v : h + v;
           }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (kk0 + u < na && !(alpha && occA[kk0 + u] == p)) acc = acc + v[u];
+          maybe = (fabs(h) + a.smarg * ub) * absc * (1.0 + 0x1p-50) > eps2;
         }
-        for (int kk0 = 0; kk0 < nb; kk0 += 8) {
-          double v[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            v[u] = 0.0;
-            if (kk0 + u < nb) v[u] = tabB[occB[kk0 + u] * nn + pr_off];
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (kk0 + u < nb && !(!alpha && occB[kk0 + u] == p)) acc = acc + v[u];
+        const uint64_t mb = ballot(maybe);
+        if (maybe) sq[qn + rank_below(mb)] = (uint16_t)j;
+        qn += __popcll(mb);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (qn >= 64) {
+          process(64);
+          const uint16_t rest = (lane + 64 < qn) ? sq[lane + 64] : (uint16_t)0;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (lane + 64 < qn) sq[lane] = rest;
+          qn -= 64;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        const int par = alpha ? between(A0, A1, p, r) : between(B0, B1, p, r);
-        H = (par & 1) ? -acc : acc;
       }
-      const bool keep = cand && (fabs(H) * absc > eps2);
-      uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
-      if (alpha) {
-        flip(x0, x1, p);
-        flip(x0, x1, r);
-      } else {
-        flip(y0, y1, p);
-        flip(y0, y1, r);
-      }
-      emit(keep, x0, x1, y0, y1, H);
+      if (qn > 0) process(qn);
     }
 
     // ---------------- doubles ----------------

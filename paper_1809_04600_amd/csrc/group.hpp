@@ -24,6 +24,58 @@ namespace shci {
 constexpr int PTILE_ITEMS = 16;               // records per thread per partition tile
 constexpr int PTILE = 256 * PTILE_ITEMS;      // records per partition tile
 
+// Per-a accumulation of the terms of one segment (records of equal a).
+// Deterministic mode: A = sum of t = H c.  Sample mode: each record holds
+// x = w c H / p and z = x^2 + y = w (N_d - 1) / p (c H)^2, where y is the
+// second term of the stochastic estimator; then X^2 + Y = (X^2 - Q) + Z with
+// X = sum x, Q = sum x^2, Z = sum z.  For an a reached by one term X^2 - Q
+// is exactly 0, so the estimator does not subtract two nearly equal numbers.
+// FP32 values are summed with TwoSum (hi, lo); x^2 of an FP32 x is exact in
+// FP64.  Terms flagged with the deterministic-threshold bit also enter the
+// *d sums.
+template <typename VT>
+struct SegSum {
+  double X = 0.0, Q = 0.0, Z = 0.0, Xd = 0.0, Qd = 0.0, Zd = 0.0;
+  float xs = 0.f, xc = 0.f, zs = 0.f, zc = 0.f, xds = 0.f, xdc = 0.f, zds = 0.f, zdc = 0.f;
+  SHCI_DEV void add(VT x) {
+    if constexpr (sizeof(VT) == 4)
+      two_sum_f32(xs, xc, (float)x);
+    else
+      X = X + (double)x;
+  }
+  SHCI_DEV void add_sample(VT x, VT z, bool d) {
+    const double xq = (double)x * (double)x;
+    Q = Q + xq;
+    if constexpr (sizeof(VT) == 4) {
+      two_sum_f32(xs, xc, (float)x);
+      two_sum_f32(zs, zc, (float)z);
+      if (d) {
+        two_sum_f32(xds, xdc, (float)x);
+        two_sum_f32(zds, zdc, (float)z);
+        Qd = Qd + xq;
+      }
+    } else {
+      X = X + (double)x;
+      Z = Z + (double)z;
+      if (d) {
+        Xd = Xd + (double)x;
+        Zd = Zd + (double)z;
+        Qd = Qd + xq;
+      }
+    }
+  }
+  SHCI_DEV void finish() {
+    if constexpr (sizeof(VT) == 4) {
+      X = (double)xs + (double)xc;
+      Z = (double)zs + (double)zc;
+      Xd = (double)xds + (double)xdc;
+      Zd = (double)zds + (double)zdc;
+    }
+  }
+  // (X^2 + Y) - (X_d^2 + Y_d)
+  SHCI_DEV double sample_bracket() const { return ((X * X - Q) + Z) - ((Xd * Xd - Qd) + Zd); }
+};
+
 template <int KW>
 SHCI_DEV void load_key(const Recs& r, int64_t idx, uint64_t (&k)[KW]) {
 #pragma unroll
@@ -488,37 +540,16 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
     for (uint32_t s = t; s < nsg; s += 256) {
       const int j0 = R.seg[s], j1 = R.seg[s + 1];
       const int first = R.sb.ia[j0];
-      double X = 0.0, Y = 0.0, Xd = 0.0, Yd = 0.0;
-      if constexpr (sizeof(VT) == 4) {
-        float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sxd = 0.f, cxd = 0.f, syd = 0.f, cyd = 0.f;
-        for (int j = j0; j < j1; ++j) {
-          const int id = R.sb.ia[j];
-          two_sum_f32(sx, cx, (float)R.v[id]);
-          if constexpr (SAMPLE) {
-            two_sum_f32(sy, cy, (float)R.v2[id]);
-            if ((R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
-              two_sum_f32(sxd, cxd, (float)R.v[id]);
-              two_sum_f32(syd, cyd, (float)R.v2[id]);
-            }
-          }
-        }
-        X = (double)sx + (double)cx;
-        Y = (double)sy + (double)cy;
-        Xd = (double)sxd + (double)cxd;
-        Yd = (double)syd + (double)cyd;
-      } else {
-        for (int j = j0; j < j1; ++j) {
-          const int id = R.sb.ia[j];
-          X = X + (double)R.v[id];
-          if constexpr (SAMPLE) {
-            Y = Y + (double)R.v2[id];
-            if ((R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull) {
-              Xd = Xd + (double)R.v[id];
-              Yd = Yd + (double)R.v2[id];
-            }
-          }
-        }
+      SegSum<VT> sum;
+      for (int j = j0; j < j1; ++j) {
+        const int id = R.sb.ia[j];
+        if constexpr (SAMPLE)
+          sum.add_sample(R.v[id], R.v2[id], (R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull);
+        else
+          sum.add(R.v[id]);
       }
+      sum.finish();
+      const double X = sum.X;
       uint64_t k[KW];
 #pragma unroll
       for (int w = 0; w < KW; ++w) k[w] = R.key[w][first];
@@ -536,7 +567,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
         Dd = a.e0 - haa;
         double contrib;
         if constexpr (SAMPLE)
-          contrib = ((X * X + Y) - (Xd * Xd + Yd)) / (Dd * a.nd * (a.nd - 1.0));
+          contrib = sum.sample_bracket() / (Dd * a.nd * (a.nd - 1.0));
         else
           contrib = X * X / Dd;
         e2p += contrib;
@@ -704,6 +735,8 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
       atomicAdd((unsigned long long*)&res->nuniq, (unsigned long long)i3[0]);
       atomicAdd((unsigned long long*)&res->nintr, (unsigned long long)i4[0]);
       atomicAdd((unsigned long long*)&res->nzero, (unsigned long long)i5[0]);
+      // |D| >= 0: the bit patterns of non-negative doubles order like the values
+      atomicMin((unsigned long long*)&res->mind, (unsigned long long)__double_as_longlong(r3[0]));
     } else {
       res->e2 = r1[0];
       res->de0 = r2[0];

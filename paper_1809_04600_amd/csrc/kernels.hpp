@@ -13,6 +13,7 @@ struct Tables {
   double* sD = nullptr;      // [k][p][r] (pr|kk) - (pk|kr)
   double* sJ = nullptr;      // [k][p][r] (pr|kk)
   double* ubound = nullptr;  // [p][r]
+  double* fref = nullptr;    // [2][p][r] singles elements of the reference det (per call)
   double* diag = nullptr;    // packed diagonal table (diag.hpp layout)
   double* hpp = nullptr;     // = diag: h_pp
   double* jtri = nullptr;    // = diag + n: (pp|qq), p <= q, at q(q+1)/2 + p
@@ -24,6 +25,8 @@ struct Tables {
 };
 
 int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st, uint32_t* dflag);
+// T.fref for the reference determinant ref (device, 4 words)
+void singles_ref(const Tables& T, const uint64_t* ref, hipStream_t st);
 
 // Structure-of-arrays record buffer.
 struct Recs {

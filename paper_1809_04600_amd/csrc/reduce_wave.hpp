@@ -190,37 +190,16 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_
       int e1 = e0 + 1;
       while (e1 < M && (W.sk[e1] >> 8) == (W.sk[e0] >> 8)) ++e1;
       const int first = (int)(W.sk[e0] & 0xff);
-      double X = 0.0, Y = 0.0, Xd = 0.0, Yd = 0.0;
-      if constexpr (sizeof(VT) == 4) {
-        float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f, sxd = 0.f, cxd = 0.f, syd = 0.f, cyd = 0.f;
-        for (int e = e0; e < e1; ++e) {
-          const int id = (int)(W.sk[e] & 0xff);
-          two_sum_f32(sx, cx, (float)W.v[id]);
-          if constexpr (SAMPLE) {
-            two_sum_f32(sy, cy, (float)W.v2[id]);
-            if (W.key[aw][id] & am) {
-              two_sum_f32(sxd, cxd, (float)W.v[id]);
-              two_sum_f32(syd, cyd, (float)W.v2[id]);
-            }
-          }
-        }
-        X = (double)sx + (double)cx;
-        Y = (double)sy + (double)cy;
-        Xd = (double)sxd + (double)cxd;
-        Yd = (double)syd + (double)cyd;
-      } else {
-        for (int e = e0; e < e1; ++e) {
-          const int id = (int)(W.sk[e] & 0xff);
-          X = X + (double)W.v[id];
-          if constexpr (SAMPLE) {
-            Y = Y + (double)W.v2[id];
-            if (W.key[aw][id] & am) {
-              Xd = Xd + (double)W.v[id];
-              Yd = Yd + (double)W.v2[id];
-            }
-          }
-        }
+      SegSum<VT> sum;
+      for (int e = e0; e < e1; ++e) {
+        const int id = (int)(W.sk[e] & 0xff);
+        if constexpr (SAMPLE)
+          sum.add_sample(W.v[id], W.v2[id], (W.key[aw][id] & am) != 0ull);
+        else
+          sum.add(W.v[id]);
       }
+      sum.finish();
+      const double X = sum.X;
       uint64_t k[KW];
 #pragma unroll
       for (int w = 0; w < KW; ++w) k[w] = W.key[w][first];
@@ -244,7 +223,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_
         const double rd = 1.0 / Dd;
         double contrib;
         if constexpr (SAMPLE)
-          contrib = ((X * X + Y) - (Xd * Xd + Yd)) * rd / (a.nd * (a.nd - 1.0));
+          contrib = sum.sample_bracket() * rd / (a.nd * (a.nd - 1.0));
         else
           contrib = X * X * rd;
         acc.e2p += contrib;

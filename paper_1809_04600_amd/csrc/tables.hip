@@ -191,6 +191,32 @@ __global__ void k_mag_cum2(double* hist) {
   }
 }
 
+// Singles elements of the reference determinant R for every p, r and spin s:
+// h_pr + sum_{k in R_s, k != p} sD[k][p][r] + sum_{k in R_s'} sJ[k][p][r]
+// (any order; the generator uses them only as a filter with a margin).
+__global__ void k_singles_ref(const uint64_t* ref, const double* h1, const double* sD, const double* sJ,
+                              int n, double* fref) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * n * n) return;
+  const int sp = t / (n * n), p = (t / n) % n, r = t % n;
+  const size_t nn = (size_t)n * n, pr = (size_t)p * n + r;
+  double h = h1[pr];
+  for (int k = 0; k < n; ++k) {
+    const bool in_a = (ref[k >> 6] >> (k & 63)) & 1ull;
+    const bool in_b = (ref[2 + (k >> 6)] >> (k & 63)) & 1ull;
+    const bool same = sp == 0 ? in_a : in_b;
+    const bool other = sp == 0 ? in_b : in_a;
+    if (same && k != p) h += sD[k * nn + pr];
+    if (other) h += sJ[k * nn + pr];
+  }
+  fref[t] = h;
+}
+
+void singles_ref(const Tables& T, const uint64_t* ref, hipStream_t st) {
+  const int m = 2 * T.n * T.n;
+  k_singles_ref<<<(m + 255) / 256, 256, 0, st>>>(ref, T.h1, T.sD, T.sJ, T.n, T.fref);
+}
+
 int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st, uint32_t* dflag) {
   const int n = T.n;
   const int64_t n3 = (int64_t)n * n * n, n4 = n3 * n;

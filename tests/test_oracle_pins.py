@@ -294,3 +294,18 @@ def test_energy_through_cores_matches_pairwise(shape):
         diff += np.array([bin(int(v)).count("1") for v in xo.ravel()]).reshape(xo.shape)
     brute = int(((diff > 0) & (diff <= 4)).sum() // 2)
     assert npairs == npairs6 == brute
+
+
+def test_terms_of_sources_match_full_enumeration():
+    # the per-source term listing used by the large-workload parity tests
+    # finds exactly the kept terms with a outside V
+    x = I.small(10, 3, 3, 150, 3, 5)
+    o = ref.pt2_det(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, 1e-5, terms=True)
+    keys, hv, which = ref.terms_of(10, 3, 3, x.h1, x.eri, x.dets, x.c, 1e-5, np.arange(len(x.c)))
+    assert len(keys) == o.n_terms
+    out_v = [tuple(r) for r in o.keys]
+    assert set(map(tuple, keys)) == set(out_v)
+    cnt = {}
+    for r in map(tuple, keys):
+        cnt[r] = cnt.get(r, 0) + 1
+    assert all(cnt[tuple(k)] == n for k, n in zip(o.keys, o.counts))

@@ -500,19 +500,20 @@ int run_job(Job& J) {
     const bool v2 = SAMPLE;
     const bool pay = J.want_pay;
     auto plan_big = [&](Carver& cv, Recs* A, Recs* B, uint32_t** hist, uint32_t** hoffs, ScanTmp* hsc,
-                        Partials* P, Uniq* U, uint64_t** boff, uint32_t** bidarr, uint64_t** bst,
+                        Partials* P, Uniq* U, uint64_t** boff, uint64_t** bst,
                         uint32_t** slow, Partials* Pq, Partials* Pw) {
       for (int w = 0; w < KW; ++w) A->k[w] = cv.take<uint64_t>(nrec);
       A->v = cv.take<VT>(nrec);
       A->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
       A->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
+      A->bid = cv.take<uint32_t>(nrec);
       if (npass > 0) {
         for (int w = 0; w < KW; ++w) B->k[w] = cv.take<uint64_t>(nrec);
         B->v = cv.take<VT>(nrec);
         B->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
         B->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
+        B->bid = cv.take<uint32_t>(nrec);
       }
-      *bidarr = cv.take<uint32_t>(npass > 0 ? nrec : 1);
       *bst = cv.take<uint64_t>(G.nbucket + 1);
       *slow = cv.take<uint32_t>(G.nbucket + 1);
       *hist = cv.take<uint32_t>((size_t)256 * ntiles);
@@ -562,19 +563,19 @@ int run_job(Job& J) {
     Partials P, Pq, Pw;
     Uniq U;
     uint64_t* boff = nullptr;
-    uint32_t* bidarr = nullptr;
     uint64_t* bst = nullptr;
     uint32_t* slow = nullptr;
     {
       Carver cv(nullptr);
-      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq, &Pw);
+      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bst, &slow, &Pq, &Pw);
       CHK(X->big.ensure(cv.off, X->ws_limit));
       Carver cv2(X->big.p);
-      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bidarr, &bst, &slow, &Pq, &Pw);
+      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bst, &slow, &Pq, &Pw);
     }
     {
       // ---- generation (write pass; repeated after a re-plan, same records) ----
       g.out = A;
+      g.bits_hash = G.bits_hash;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
       HIPCHK(hipEventRecord(X->ev[6], st));
       k_gen<KW, GEN_WRITE, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
@@ -605,7 +606,6 @@ int run_job(Job& J) {
         pa.hist = hist;
         pa.offs = hoffs;
         pa.ntiles = (int)ntiles;
-        pa.bid_out = (pass == npass - 1) ? bidarr : nullptr;
         k_part_hist<KW><<<(int)ntiles, 256, 0, st>>>(pa);
         CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
         if (pay)
@@ -619,7 +619,7 @@ int run_job(Job& J) {
     }
     if (npass > 0) {
       const int64_t m = nrec + 1;
-      k_bucket_bounds<<<(int)std::min<int64_t>(8192, (m + 255) / 256), 256, 0, st>>>(bidarr, nrec, G.nbucket, bst);
+      k_bucket_bounds<<<(int)std::min<int64_t>(8192, (m + 255) / 256), 256, 0, st>>>(cur->bid, nrec, G.nbucket, bst);
     } else {
       const uint64_t hb[2] = {0, (uint64_t)nrec};
       HIPCHK(hipMemcpyAsync(bst, hb, sizeof hb, hipMemcpyHostToDevice, st));
@@ -647,7 +647,7 @@ int run_job(Job& J) {
     uint32_t* slow_count = X->dflag + 3;
     const size_t diag_bytes = (size_t)diag_table_doubles(n) * sizeof(double);
     const bool red_lds = sizeof(RedShared<KW, C, SAMPLE, VT>) + diag_bytes <= 160 * 1024;
-    const bool wave_lds = sizeof(WaveStage<KW, SAMPLE, VT>) * WRED_WAVES + diag_bytes <= 160 * 1024;
+    const bool wave_lds = sizeof(WaveStage) * WRED_WAVES + diag_bytes <= 160 * 1024;
     const int64_t wblocks = std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * 8);
     WaveRedArgs wa;
     wa.r = ra;
@@ -821,6 +821,10 @@ void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
 // takes at `per_rec` bytes per record (two record buffers, bucket ids, the
 // unique store when kept, per-bucket arrays), after a fixed reserve for the
 // per-wavefront partials.
+// Default cap on the records of one pass: larger passes partition more
+// slowly (scattered writes over a larger working set) and gain nothing.
+constexpr int64_t REC_CAP_AUTO = (int64_t)3 << 29;  // 1.61e9
+
 int64_t record_budget(shci_pt2_ctx* X, double per_rec) {
   if (X->rec_limit > 0) return X->rec_limit;
   size_t fr = 0, tt = 0;
@@ -833,7 +837,7 @@ int64_t record_budget(shci_pt2_ctx* X, double per_rec) {
   const size_t reserve = (size_t)(num_cus(X->device) * 8 * WRED_WAVES + 1024) * 64 + (2u << 20);
   avail = avail > reserve ? avail - reserve : 0;
   const int64_t m = (int64_t)(0.75 * (double)avail / per_rec);
-  return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)1 << 31));
+  return std::max<int64_t>(1, std::min<int64_t>(m, REC_CAP_AUTO));
 }
 
 double record_bytes(int kw, int vbytes, bool pay, bool uniq) {
@@ -1165,7 +1169,14 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   Job acc{};
   acc.res.mind = INFINITY;
   int64_t chunks = 0;
-  int32_t k = n_samples;  // first try: every sample in one chunk
+  // chunks hold a power-of-two number of samples (the sample id then fills
+  // its key bits); the first chunk is small and sets the rate
+  auto pow2_floor = [](int64_t v) {
+    int32_t p = 1;
+    while ((int64_t)p * 2 <= v) p *= 2;
+    return p;
+  };
+  int32_t k = std::min<int32_t>(n_samples, 8);
   for (int32_t s0 = 0; s0 < n_samples;) {
     k = std::min<int32_t>(k, n_samples - s0);
     k_sample_compact<<<k, 256, 0, s>>>(t_det + (int64_t)s0 * n_draws, t_w + (int64_t)s0 * n_draws,
@@ -1196,7 +1207,7 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
       if (k == 1) return done(fail(SHCI_ERR_WORKSPACE, "one sample has %lld screened terms; the workspace holds %lld",
                                    (long long)J.nrec, (long long)max_rec));
       const double per = (double)J.nrec / k;
-      k = std::max<int32_t>(1, std::min<int32_t>(k - 1, (int32_t)(0.9 * (double)max_rec / per)));
+      k = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(k - 1, (int64_t)(0.9 * (double)max_rec / per))));
       continue;
     }
     if (r) return done(r);
@@ -1221,7 +1232,7 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
     s0 += k;
     // next chunk: as many samples as the budget allows at this chunk's rate
     const double per = (double)std::max<int64_t>(1, J.nrec) / k;
-    k = std::max<int32_t>(1, (int32_t)std::min<double>(n_samples, 0.9 * (double)max_rec / per));
+    k = pow2_floor(std::max<int64_t>(1, (int64_t)std::min<double>(n_samples, 0.9 * (double)max_rec / per)));
   }
   std::vector<double> ps(n_samples);
   if (hipMemcpyAsync(ps.data(), per_sample, n_samples * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -121,21 +121,46 @@ SHCI_HD void unpack_det(const uint64_t (&k)[KW], int n, uint64_t& a0, uint64_t& 
   b1 = r1 & m1;
 }
 
+// the determinant bits of a key (bits below 2n), other bits cleared
+template <int KW>
+SHCI_HD void mask_det(uint64_t (&k)[KW], int n) {
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int lim = 2 * n - 64 * j;
+    k[j] &= (lim >= 64) ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
+  }
+}
+
+// Hash of the determinant a record key holds (sample id and flag excluded).
+// Buckets, in-bucket order and the V lookup all use it.
+template <int KW>
+SHCI_HD uint64_t det_hash(const uint64_t (&k)[KW], int n) {
+  uint64_t m[KW];
+#pragma unroll
+  for (int j = 0; j < KW; ++j) m[j] = k[j];
+  mask_det<KW>(m, n);
+  return hash_key<KW>(m);
+}
+
 // mask of the grouping bits (everything below the auxiliary flag)
+// (per-word masks selected by value, so the word index never becomes a
+// dynamic index into the key array)
 template <int KW>
 SHCI_HD void clear_aux(uint64_t (&k)[KW], int auxbit) {
+  const int w = auxbit >> 6;
+  const uint64_t m = ~(1ull << (auxbit & 63));
 #pragma unroll
-  for (int j = 0; j < KW; ++j)
-    if (j == (auxbit >> 6)) k[j] &= ~(1ull << (auxbit & 63));
+  for (int j = 0; j < KW; ++j) k[j] &= (j == w) ? m : ~0ull;
 }
 
 template <int KW>
 SHCI_HD bool aux_set(const uint64_t (&k)[KW], int auxbit) {
-  bool r = false;
+  const int w = auxbit >> 6;
+  const uint64_t m = 1ull << (auxbit & 63);
+  uint64_t r = 0;
 #pragma unroll
-  for (int j = 0; j < KW; ++j)
-    if (j == (auxbit >> 6)) r = (k[j] >> (auxbit & 63)) & 1ull;
-  return r;
+  for (int j = 0; j < KW; ++j) r |= (j == w) ? (k[j] & m) : 0ull;
+  return r != 0ull;
 }
 
 // ---------------------------------------------------------------------------

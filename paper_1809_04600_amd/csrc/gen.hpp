@@ -57,6 +57,7 @@ struct GenArgs {
   uint32_t* counter;
   int sbits, auxbit;
   uint32_t bmask, bsel;    // hash batch: keep a only if (hash(a) & bmask) == bsel
+  int bits_hash;           // bucket id = top bits_hash bits of the key hash | sample id above
   // singles prefilter: Fock-like elements of a reference determinant R,
   // Fref[s][p][r] = h_pr + sum_{k in R_s, k != p} sD[k][p][r] + sum_{k in R_s'} sJ[k][p][r]
   const uint64_t* ref;
@@ -194,8 +195,15 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           uint64_t key[KW];
           pack_det<KW>(key, x0, x1, y0, y1, n);
           const uint64_t pos = obase + cursor + (uint64_t)rank_below(bal);
+          {
+            // bucket id: top hash bits of the determinant, sample id above
+            const uint64_t h = hash_key<KW>(key);
+            uint32_t b = a.bits_hash ? (uint32_t)(h >> (64 - a.bits_hash)) : 0u;
+            if constexpr (SAMPLE) b |= sid << a.bits_hash;
+            a.out.bid[pos] = b;
+          }
+          if constexpr (SAMPLE) put_bits<KW>(key, (uint64_t)sid, 0ull, 2 * n);
           if constexpr (SAMPLE) {
-            put_bits<KW>(key, (uint64_t)sid, 0ull, 2 * n);
             if (fabs(H) * absc > a.eps2_d) put_bits<KW>(key, 1ull, 0ull, a.auxbit);
             const double ch = ci * H;
             // x and z = x^2 + y of the stochastic estimator (see SegSum)
@@ -336,13 +344,20 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         if (ndl >= 0 && maybe) {
           const int sp = alpha ? 0 : 1;
           double h = a.Fref[sp * nn + pr_off];
-          for (int t = 0; t < ndl; ++t) {
-            const uint32_t e = s_dl[wv][t];
-            const int k = (int)(e & 127u);
-            const bool same = (int)((e >> 7) & 1u) == sp;
-            if (same && k == p) continue;
-            const double v = (same ? T.sD : T.sJ)[k * nn + pr_off];
-            h = (e >> 8) ? h - v : h + v;
+          // corrections loaded eight at a time
+          for (int t0 = 0; t0 < ndl; t0 += 8) {
+            double v[8];
+            uint32_t e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              e[u] = (t0 + u < ndl) ? (uint32_t)s_dl[wv][t0 + u] : 0xffffu;
+              const int k = (int)(e[u] & 127u);
+              const bool same = (int)((e[u] >> 7) & 1u) == sp;
+              v[u] = 0.0;
+              if (e[u] != 0xffffu && !(same && k == p)) v[u] = (same ? T.sD : T.sJ)[k * nn + pr_off];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) h = ((e[u] >> 8) & 1u) ? h - v[u] : h + v[u];
           }
           maybe = (fabs(h) + a.smarg * ub) * absc * (1.0 + 0x1p-50) > eps2;
         }

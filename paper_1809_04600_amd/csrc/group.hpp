@@ -85,7 +85,7 @@ SHCI_DEV void load_key(const Recs& r, int64_t idx, uint64_t (&k)[KW]) {
 // bucket id of a key (aux bit cleared) and its 64-bit hash
 template <int KW>
 SHCI_DEV uint64_t bucket_id(const uint64_t (&k)[KW], const GroupPlan& G, int n, uint64_t& h) {
-  h = hash_key<KW>(k);
+  h = det_hash<KW>(k, n);
   uint64_t b = G.bits_hash ? (h >> (64 - G.bits_hash)) : 0ull;
   if (G.sbits) {
     uint64_t s0, s1;
@@ -135,6 +135,22 @@ SHCI_DEV uint32_t split_round(SplitScratch& S, bool valid, uint32_t d, int dbits
   return pos;
 }
 
+SHCI_DEV uint32_t block_scan256(uint32_t v, uint32_t* sh, uint32_t* tot) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    uint32_t x = (t >= o) ? sh[t - o] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  *tot = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
 // ---------------------------------------------------------------------------
 // Partition pass kernels
 // ---------------------------------------------------------------------------
@@ -148,7 +164,6 @@ struct PassArgs {
   uint32_t* hist;        // [2^dbits][ntiles]
   const uint32_t* offs;  // exclusive scan of hist
   int ntiles;
-  uint32_t* bid_out;     // last pass: bucket id of every output record (nullable)
 };
 
 template <int KW>
@@ -158,59 +173,88 @@ __global__ void __launch_bounds__(256) k_part_hist(PassArgs a) {
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * PTILE;
   const uint32_t dmask = (1u << a.dbits) - 1u;
+#pragma unroll 4
   for (int j = 0; j < PTILE_ITEMS; ++j) {
     const int64_t idx = base + (int64_t)j * 256 + threadIdx.x;
-    if (idx < a.n) {
-      uint64_t k[KW];
-      load_key<KW>(a.in, idx, k);
-      clear_aux<KW>(k, a.auxbit);
-      uint64_t h;
-      const uint64_t b = bucket_id<KW>(k, a.G, a.nbits_n, h);
-      atomicAdd(&cnt[(uint32_t)(b >> a.shift) & dmask], 1u);
-    }
+    if (idx < a.n) atomicAdd(&cnt[(a.in.bid[idx] >> a.shift) & dmask], 1u);
   }
   __syncthreads();
   if (threadIdx.x < (1 << a.dbits)) a.hist[(int64_t)threadIdx.x * a.ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-template <int KW, typename VT, bool V2, bool PAY>
-__global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
-  __shared__ SplitScratch S;
-  __shared__ uint32_t base_off[256];
+// One stable LSD pass over the bucket id, one tile of PTILE records per
+// block.  Ranks within the tile come from the multisplit; every array is then
+// staged through LDS in digit order and written out so that consecutive
+// threads write consecutive records of one digit run (coalesced stores).
+struct ScatterShared {
+  SplitScratch S;
+  uint32_t lstart[256];  // first local position of each digit
+  uint32_t gbase[256];   // first output position of each digit for this tile
+  uint32_t scan[256];
+  uint8_t sdig[PTILE];   // digit of each local position
+  uint64_t stage[PTILE];
+};
+
+template <typename T>
+SHCI_DEV void stage_copy(ScatterShared& L, const T* in, T* out, int64_t base, int tile_n,
+                         const uint16_t (&lpos)[PTILE_ITEMS]) {
   const int t = threadIdx.x;
-  S.run[t] = 0;
-  S.wcnt[0][t] = S.wcnt[1][t] = S.wcnt[2][t] = S.wcnt[3][t] = 0;
-  base_off[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + blockIdx.x] : 0u;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * PTILE;
-  const uint32_t dmask = (1u << a.dbits) - 1u;
+  T* st = reinterpret_cast<T*>(L.stage);
+#pragma unroll
   for (int j = 0; j < PTILE_ITEMS; ++j) {
-    const int64_t idx = base + (int64_t)j * 256 + t;
-    const bool valid = idx < a.n;
-    uint64_t k[KW];
-    uint32_t d = 0;
-    uint64_t bidv = 0;
-    if (valid) {
-      load_key<KW>(a.in, idx, k);
-      uint64_t kc[KW];
+    const int q = j * 256 + t;
+    if (q < tile_n) st[lpos[j]] = in[base + q];
+  }
+  __syncthreads();
 #pragma unroll
-      for (int w = 0; w < KW; ++w) kc[w] = k[w];
-      clear_aux<KW>(kc, a.auxbit);
-      uint64_t h;
-      bidv = bucket_id<KW>(kc, a.G, a.nbits_n, h);
-      d = (uint32_t)(bidv >> a.shift) & dmask;
-    }
-    const uint32_t r = split_round(S, valid, d, a.dbits);
-    if (valid) {
-      const int64_t pos = (int64_t)base_off[d] + (r);
-#pragma unroll
-      for (int w = 0; w < KW; ++w) a.out.k[w][pos] = k[w];
-      static_cast<VT*>(a.out.v)[pos] = static_cast<const VT*>(a.in.v)[idx];
-      if constexpr (V2) static_cast<VT*>(a.out.v2)[pos] = static_cast<const VT*>(a.in.v2)[idx];
-      if constexpr (PAY) a.out.pay[pos] = a.in.pay[idx];
-      if (a.bid_out) a.bid_out[pos] = (uint32_t)bidv;
+  for (int j = 0; j < PTILE_ITEMS; ++j) {
+    const int q = j * 256 + t;
+    if (q < tile_n) {
+      const uint32_t d = L.sdig[q];
+      out[(int64_t)L.gbase[d] + (q - (int)L.lstart[d])] = st[q];
     }
   }
+  __syncthreads();
+}
+
+template <int KW, typename VT, bool V2, bool PAY>
+__global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
+  __shared__ ScatterShared L;
+  const int t = threadIdx.x;
+  L.S.run[t] = 0;
+  L.S.wcnt[0][t] = L.S.wcnt[1][t] = L.S.wcnt[2][t] = L.S.wcnt[3][t] = 0;
+  L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + blockIdx.x] : 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * PTILE;
+  const int tile_n = (int)((a.n - base < (int64_t)PTILE) ? (a.n - base) : (int64_t)PTILE);
+  const uint32_t dmask = (1u << a.dbits) - 1u;
+  uint16_t lpos[PTILE_ITEMS];
+  uint8_t dig[PTILE_ITEMS];
+#pragma unroll
+  for (int j = 0; j < PTILE_ITEMS; ++j) {
+    const int q = j * 256 + t;
+    const bool valid = q < tile_n;
+    const uint32_t d = valid ? ((a.in.bid[base + q] >> a.shift) & dmask) : 0u;
+    lpos[j] = (uint16_t)split_round(L.S, valid, d, a.dbits);  // rank within digit d
+    dig[j] = (uint8_t)d;
+  }
+  uint32_t tot;
+  L.lstart[t] = block_scan256(L.S.run[t], L.scan, &tot);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PTILE_ITEMS; ++j) {
+    const int q = j * 256 + t;
+    lpos[j] = (uint16_t)(lpos[j] + L.lstart[dig[j]]);
+    if (q < tile_n) L.sdig[lpos[j]] = dig[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < KW; ++w) stage_copy<uint64_t>(L, a.in.k[w], a.out.k[w], base, tile_n, lpos);
+  stage_copy<VT>(L, static_cast<const VT*>(a.in.v), static_cast<VT*>(a.out.v), base, tile_n, lpos);
+  if constexpr (V2)
+    stage_copy<VT>(L, static_cast<const VT*>(a.in.v2), static_cast<VT*>(a.out.v2), base, tile_n, lpos);
+  if constexpr (PAY) stage_copy<uint32_t>(L, a.in.pay, a.out.pay, base, tile_n, lpos);
+  stage_copy<uint32_t>(L, a.in.bid, a.out.bid, base, tile_n, lpos);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,21 +337,6 @@ __global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
 
 // exclusive scan of 256 values held one per thread; returns the prefix,
 // total in *tot (all threads)
-SHCI_DEV uint32_t block_scan256(uint32_t v, uint32_t* sh, uint32_t* tot) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    uint32_t x = (t >= o) ? sh[t - o] : 0u;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
-  }
-  const uint32_t incl = sh[t];
-  *tot = sh[255];
-  __syncthreads();
-  return incl - v;
-}
 
 template <int C>
 struct SortBufs {
@@ -437,7 +466,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       R.v[j] = static_cast<const VT*>(a.in.v)[lo + j];
       if constexpr (SAMPLE) R.v2[j] = static_cast<const VT*>(a.in.v2)[lo + j];
       clear_aux<KW>(k, a.auxbit);
-      R.sb.h2a[j] = sort_hash(hash_key<KW>(k), a.G);
+      R.sb.h2a[j] = sort_hash(det_hash<KW>(k, a.n), a.G);
       R.sb.ia[j] = (uint16_t)j;
     }
     __syncthreads();
@@ -475,7 +504,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
 #pragma unroll
         for (int w = 0; w < KW; ++w) k[w] = R.key[w][j];
         clear_aux<KW>(k, a.auxbit);
-        R.sb.h2a[j] = sort_hash(hash_key<KW>(k), a.G);
+        R.sb.h2a[j] = sort_hash(det_hash<KW>(k, a.n), a.G);
         R.sb.ia[j] = (uint16_t)j;
       }
       __syncthreads();

@@ -34,6 +34,7 @@ struct Recs {
   void* v = nullptr;      // double or float
   void* v2 = nullptr;     // second value (sample mode), same type
   uint32_t* pay = nullptr;  // optional source index
+  uint32_t* bid = nullptr;  // bucket id (written by the generator, moved by the partition)
 };
 
 // Per-bucket partial results written by the reduce kernel.

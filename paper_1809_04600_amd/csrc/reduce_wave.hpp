@@ -1,22 +1,24 @@
 // Bucket reduce, one wavefront per bucket.
 //
-// After the hash partition a bucket holds on average ~128 records (at most
-// WCAP are handled here).  A wavefront stages the bucket in its own LDS slice,
-// sorts 64-bit keys (the hash bits below the bucket id, with the record's
-// position in the low byte) by a bitonic network in registers, so equal
-// determinants become adjacent in record order; segment heads then sum their
-// segment sequentially, look the determinant up in the hash set of V,
-// evaluate H_aa from the LDS diagonal tables and accumulate the contribution.
-// No block-wide barrier is involved.  Buckets that are larger than WCAP, or in
-// which two different determinants share all sorted hash bits, are listed for
-// the block kernel (k_reduce), which sorts by the full key.
+// After the hash partition a bucket holds on average ~100 records (at most
+// WCAP are handled here).  A wavefront loads the bucket's keys, forms 64-bit
+// sort keys (the hash bits below the bucket id, with the record's position in
+// the low byte) and sorts them by a bitonic network in registers, so equal
+// determinants become adjacent in record order.  Only the sorted keys are kept
+// in LDS (2 KB per wavefront): keys and values are read again from global
+// memory (cache-resident) when a segment head sums its segment, looks the
+// determinant up in the hash set of V, evaluates H_aa from the LDS diagonal
+// tables and accumulates the contribution.  No block-wide barrier is involved
+// after the diagonal tables are staged.  Buckets larger than WCAP, or in which
+// two different determinants share all sorted hash bits, are listed for the
+// block kernel (k_reduce), which sorts by the full key.
 #pragma once
 #include "group.hpp"
 
 namespace shci {
 
 constexpr int WCAP = 256;       // records per wavefront bucket
-constexpr int WRED_WAVES = 4;   // wavefronts per block
+constexpr int WRED_WAVES = 8;   // wavefronts per block
 
 SHCI_DEV uint64_t shfl_xor_u64(uint64_t v, int m) {
   const int lo = __shfl_xor((int)(uint32_t)v, m);
@@ -56,13 +58,9 @@ SHCI_DEV void wave_bitonic(uint64_t (&v)[R]) {
   }
 }
 
-template <int KW, bool SAMPLE, typename VT>
+// per-wavefront LDS: the sorted keys of the current bucket
 struct WaveStage {
-  uint64_t key[KW][WCAP];
-  VT v[WCAP];
-  VT v2[SAMPLE ? WCAP : 1];
   uint64_t sk[WCAP];
-  uint64_t h[WCAP];  // hash of each record's key (aux bit clear)
 };
 
 struct WaveRedArgs {
@@ -73,9 +71,10 @@ struct WaveRedArgs {
   Partials Pw;             // per-wavefront partials (deterministic mode)
 };
 
-// stage the bucket in LDS and sort its 64-bit keys (R*64 >= M)
-template <int KW, bool SAMPLE, typename VT, int R>
-SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_t lo, int M) {
+// load the bucket's keys, sort their 64-bit sort keys (R*64 >= M) and leave
+// them in W.sk
+template <int KW, int R>
+SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage& W, int64_t lo, int M) {
   const int lane = lane_id();
   const int bh = a.G.bits_hash;
   uint64_t sk[R];
@@ -86,13 +85,7 @@ SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, in
     if (j < M) {
       uint64_t k[KW];
       load_key<KW>(a.in, lo + j, k);
-#pragma unroll
-      for (int w = 0; w < KW; ++w) W.key[w][j] = k[w];
-      W.v[j] = static_cast<const VT*>(a.in.v)[lo + j];
-      if constexpr (SAMPLE) W.v2[j] = static_cast<const VT*>(a.in.v2)[lo + j];
-      clear_aux<KW>(k, a.auxbit);
-      const uint64_t h = hash_key<KW>(k);
-      W.h[j] = h;
+      const uint64_t h = det_hash<KW>(k, a.n);
       sk[r] = ((h << bh) & ~0xffull) | (uint64_t)j;
     }
   }
@@ -149,32 +142,38 @@ SHCI_DEV void wave_zero_partials(const Partials& P, int64_t b) {
 // accumulate in acc (per lane); in sample mode the caller reduces acc per
 // bucket, otherwise once per wavefront at the end.
 template <int KW, bool SAMPLE, typename VT, bool LDS>
-SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_t b, int64_t lo, int M,
+SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo, int M,
                           const DiagTab<LDS>& DT, const uint64_t (&ref)[4], uint32_t* slow_list,
                           uint32_t* slow_count, SegAcc& acc) {
   const int lane = lane_id();
   const int n = a.n;
+  const int bh = a.G.bits_hash;
   const int aw = a.auxbit >> 6;
   const uint64_t am = 1ull << (a.auxbit & 63);
-  auto key_eq = [&](int x, int y) {
-    bool eq = true;
+  const VT* vin = static_cast<const VT*>(a.in.v);
+  const VT* v2in = static_cast<const VT*>(a.in.v2);
+  const uint64_t* auxw = a.in.k[0];  // key word holding the flag bit
 #pragma unroll
-    for (int w = 0; w < KW; ++w) {
-      uint64_t kx = W.key[w][x], ky = W.key[w][y];
-      if (w == aw) {
-        kx &= ~am;
-        ky &= ~am;
-      }
-      eq = eq && (kx == ky);
-    }
-    return eq;
+  for (int w = 1; w < KW; ++w)
+    if (w == aw) auxw = a.in.k[w];
+  auto key_of = [&](int id, uint64_t (&k)[KW]) {
+    load_key<KW>(a.in, lo + id, k);
+    clear_aux<KW>(k, a.auxbit);
   };
   // equal sort bits must mean equal determinants
   bool clash = false;
 #pragma unroll 1
   for (int e = lane + 1; e < M; e += 64) {
     const uint64_t cur = W.sk[e], prv = W.sk[e - 1];
-    if ((cur >> 8) == (prv >> 8) && !key_eq((int)(cur & 0xff), (int)(prv & 0xff))) clash = true;
+    if ((cur >> 8) == (prv >> 8)) {
+      uint64_t kx[KW], ky[KW];
+      key_of((int)(cur & 0xff), kx);
+      key_of((int)(prv & 0xff), ky);
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < KW; ++w) eq = eq && (kx[w] == ky[w]);
+      clash = clash || !eq;
+    }
   }
   if (ballot(clash)) {
     if (lane == 0) slow_list[atomicAdd(slow_count, 1u)] = (uint32_t)b;
@@ -184,36 +183,36 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_
 #pragma unroll 1
   for (int base = 0; base < M; base += 64) {
     const int e0 = base + lane;
-    const bool head = e0 < M && (e0 == 0 || (W.sk[e0] >> 8) != (W.sk[e0 - 1] >> 8));
+    const uint64_t s0 = (e0 < M) ? W.sk[e0] : 0ull;
+    const bool head = e0 < M && (e0 == 0 || (s0 >> 8) != (W.sk[e0 - 1] >> 8));
     const uint64_t hb = ballot(head);
     if (head) {
       int e1 = e0 + 1;
-      while (e1 < M && (W.sk[e1] >> 8) == (W.sk[e0] >> 8)) ++e1;
-      const int first = (int)(W.sk[e0] & 0xff);
+      while (e1 < M && (W.sk[e1] >> 8) == (s0 >> 8)) ++e1;
+      const int first = (int)(s0 & 0xff);
       SegSum<VT> sum;
       for (int e = e0; e < e1; ++e) {
-        const int id = (int)(W.sk[e] & 0xff);
+        const int id = (e == e0) ? first : (int)(W.sk[e] & 0xff);
         if constexpr (SAMPLE)
-          sum.add_sample(W.v[id], W.v2[id], (W.key[aw][id] & am) != 0ull);
+          sum.add_sample(vin[lo + id], v2in[lo + id], (auxw[lo + id] & am) != 0ull);
         else
-          sum.add(W.v[id]);
+          sum.add(vin[lo + id]);
       }
       sum.finish();
       const double X = sum.X;
       uint64_t k[KW];
-#pragma unroll
-      for (int w = 0; w < KW; ++w) k[w] = W.key[w][first];
-      clear_aux<KW>(k, a.auxbit);
+      key_of(first, k);
       uint64_t a0, a1, b0, b1;
       unpack_det<KW>(k, n, a0, a1, b0, b1);
-      bool inv;
-      if constexpr (SAMPLE) {
-        uint64_t dk[KW];
-        pack_det<KW>(dk, a0, a1, b0, b1, n);
-        inv = vset_contains<KW>(a.V, dk, n);
-      } else {
-        inv = vset_contains_h<KW>(a.V, k, W.h[first], n);  // key holds det bits only
-      }
+      uint64_t dk[KW];
+#pragma unroll
+      for (int w = 0; w < KW; ++w) dk[w] = k[w];
+      mask_det<KW>(dk, n);  // determinant bits only (no sample id)
+      // the determinant hash is the bucket's hash bits above the sorted bits
+      // when those reach the low byte, else recomputed
+      const uint64_t hb_part = (uint64_t)b & ((bh >= 64) ? ~0ull : ((1ull << bh) - 1ull));
+      const uint64_t h = (bh >= 8) ? ((hb_part << (64 - bh)) | ((s0 & ~0xffull) >> bh)) : hash_key<KW>(dk);
+      const bool inv = vset_contains_h<KW>(a.V, dk, h, n);
       const int cntk = e1 - e0;
       acc.ngen += cntk;
       double Dd = 0.0, g = 0.0;
@@ -239,7 +238,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_
         const int64_t o = lo + nbefore + rank_below(hb);
 #pragma unroll
         for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
-        a.U.h2[o] = (uint32_t)(W.sk[e0] >> 32);
+        a.U.h2[o] = (uint32_t)(s0 >> 32);
         a.U.A[o] = X;
         a.U.D[o] = Dd;
         a.U.g[o] = g;
@@ -263,7 +262,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<KW, SAMPLE, VT>& W, int64_
 
 template <int KW, bool SAMPLE, typename VT, bool LDS>
 __global__ void __launch_bounds__(64 * WRED_WAVES) k_reduce_wave(WaveRedArgs A) {
-  __shared__ WaveStage<KW, SAMPLE, VT> WS[WRED_WAVES];
+  __shared__ WaveStage WS[WRED_WAVES];
   const RedArgs& a = A.r;
   const int t = threadIdx.x;
   DiagTab<LDS> DT;
@@ -278,7 +277,7 @@ __global__ void __launch_bounds__(64 * WRED_WAVES) k_reduce_wave(WaveRedArgs A) 
   __syncthreads();
   const int wv = t >> 6;
   const int lane = t & 63;
-  WaveStage<KW, SAMPLE, VT>& W = WS[wv];
+  WaveStage& W = WS[wv];
   const int64_t nwaves = (int64_t)gridDim.x * WRED_WAVES;
   SegAcc acc;
   for (int64_t b = (int64_t)blockIdx.x * WRED_WAVES + wv; b < a.G.nbucket; b += nwaves) {
@@ -289,11 +288,11 @@ __global__ void __launch_bounds__(64 * WRED_WAVES) k_reduce_wave(WaveRedArgs A) 
       continue;
     }
     if (M <= 64)
-      wave_stage_sort<KW, SAMPLE, VT, 1>(a, W, lo, (int)M);
+      wave_stage_sort<KW, 1>(a, W, lo, (int)M);
     else if (M <= 128)
-      wave_stage_sort<KW, SAMPLE, VT, 2>(a, W, lo, (int)M);
+      wave_stage_sort<KW, 2>(a, W, lo, (int)M);
     else
-      wave_stage_sort<KW, SAMPLE, VT, 4>(a, W, lo, (int)M);
+      wave_stage_sort<KW, 4>(a, W, lo, (int)M);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

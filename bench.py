@@ -1,11 +1,14 @@
 """Benchmark: screened PT2 terms/s and E2 wall time on one MI355X.
 
-Workload w1: deterministic screened PT2, (8 alpha, 8 beta) electrons in 40
-orbitals, N_var = 5e4, eps2 = 1e-5, seeded synthetic inputs (the paper's
+Default workload w1: deterministic screened PT2, (8 alpha, 8 beta) electrons in
+40 orbitals, N_var = 5e4, eps2 = 1e-5, seeded synthetic inputs (the paper's
 molecular data are not available).  One step = one shci_pt2_det call on inputs
 already resident in HBM (validation, hash set of V, excitation generation,
-hash partition, bucket sort + segmented reduce + H_aa, E2 reduction).  The
-heat-bath tables are built once per integral set (context) and timed apart.
+hash partition, bucket sort + segmented reduce + H_aa, E2 reduction).
+--workload w3 times the semistochastic 76-orbital, 1e6-determinant workload:
+one step = the deterministic part at eps2^d plus 256 samples of 2000 draws at
+eps2 (shci_pt2_det + shci_pt2_sample).  The heat-bath tables are built once per
+integral set (context) and timed apart.
 
 Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
@@ -53,10 +56,21 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None when
-    missing or taken with other kernel sources."""
+def kernel_names(kind, kw, sampled):
+    """Full FP64 kernel names behind a bench kernel label."""
+    smp = "true" if sampled else "false"
+    return {"k_gen(count)": [f"void shci::k_gen<{kw}, 0, {smp}, double>(shci::GenArgs)"],
+            "k_gen(write)": [f"void shci::k_gen<{kw}, 1, {smp}, double>(shci::GenArgs)"],
+            "partition": [f"void shci::k_part_hist<{kw}>(shci::PassArgs)",
+                          f"void shci::k_part_scatter<{kw}, double, {smp}, false>(shci::PassArgs)"],
+            "k_reduce": [f"void shci::k_reduce_wave<{kw}, {smp}, double, true>(shci::WaveRedArgs)"]}[kind]
+
+
+def measured_traffic(workload, names):
+    """HBM bytes per launch (per pass for the partition) of the named kernels,
+    from the committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy's readings); None when missing or taken with other kernel
+    sources."""
     f = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(f):
         return None
@@ -64,8 +78,10 @@ def measured_traffic(workload, kernel):
         t = json.load(fh)
     if t.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k["hbm_bytes_per_launch"]
+    ks = t.get("kernels", {})
+    if not all(n in ks for n in names):
+        return None
+    return sum(ks[n]["hbm_bytes_per_launch"] for n in names)
 
 
 def copy_probe(mib):
@@ -81,16 +97,38 @@ def copy_probe(mib):
                       "launches": 3}))
 
 
-def timed(ctx, dets, c, e0, eps2, prec, steps):
+SUM_KEYS = ("n_terms", "n_terms_gen", "n_unique", "n_intruder", "n_records", "ms_gen", "ms_sort",
+            "ms_reduce", "ms_total", "ms_k_count", "ms_k_write", "ms_k_reduce")
+
+
+def one_step(ctx, x, dets, c, draws, prec):
+    """One pass of the hot path: the deterministic part (at eps2^d for a
+    semistochastic workload) and, if the workload samples, every sample."""
+    wl = x.wl
+    r = ctx.det(dets, c, x.e0, wl.eps2, prec)
+    st = dict(r.stats)
+    e2 = r.e2
+    if draws is not None:
+        _, mean, sem, ss = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, draws, prec)
+        e2 = e2 + mean
+        st["sem"] = sem
+        st["sample"] = ss
+        for k in SUM_KEYS:
+            st[k] = st[k] + ss[k]
+        st["n_buckets"] = max(st["n_buckets"], ss["n_buckets"])
+        st["min_abs_denom"] = min(st["min_abs_denom"], ss["min_abs_denom"])
+    return e2, st
+
+
+def timed(ctx, x, dets, c, draws, prec, steps):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
     e2 = None
     for _ in range(steps):
-        r = ctx.det(dets, c, e0, eps2, prec)
-        stats.append(r.stats)
-        e2 = r.e2
+        e2, st = one_step(ctx, x, dets, c, draws, prec)
+        stats.append(st)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     avg = {k: sum(s[k] for s in stats) / len(stats) for k in stats[0]
@@ -110,7 +148,7 @@ def cpu_baseline(x, budget_s):
         r = ref.pt2_det(n, na, nb, x.h1, x.eri, x.dets[:m], x.c[:m], x.e0, wl.eps2, unique=False)
         return time.perf_counter() - t0, r
 
-    m = min(2000, len(x.c))
+    m = min(2000 if wl.n_orb <= 50 else 100, len(x.c))
     t, r = run(m)
     if t < budget_s / 3 and m < len(x.c):
         m = min(len(x.c), int(m * budget_s / max(t, 1e-3)))
@@ -150,27 +188,43 @@ def main():
     torch.cuda.synchronize()
     table_ms = (time.perf_counter() - t0) * 1e3
 
+    draws = None
+    if wl.n_samples:
+        # draws proportional to |c_i| (sampling-probability equation), drawn
+        # on the host before timing
+        import numpy as np
+        p = np.abs(x.c) / np.abs(x.c).sum()
+        dr = np.random.default_rng(wl.draw_seed).choice(len(x.c), size=(wl.n_samples, wl.n_draws), p=p)
+        draws = torch.from_numpy(dr.astype(np.uint32).view(np.int32)).to(dev)
     for _ in range(a.warmup):
-        ctx.det(dets, c, x.e0, wl.eps2, "fp64")
-        ctx.det(dets, c, x.e0, wl.eps2, "fp32c")
-    w64, e2_64, s64, avg64 = timed(ctx, dets, c, x.e0, wl.eps2, "fp64", a.steps)
-    w32, e2_32, s32, avg32 = timed(ctx, dets, c, x.e0, wl.eps2, "fp32c", a.steps)
+        one_step(ctx, x, dets, c, draws, "fp64")
+        one_step(ctx, x, dets, c, draws, "fp32c")
+    w64, e2_64, s64, avg64 = timed(ctx, x, dets, c, draws, "fp64", a.steps)
+    w32, e2_32, s32, avg32 = timed(ctx, x, dets, c, draws, "fp32c", a.steps)
 
     n_terms = s64["n_terms"]
     n_rec = s64["n_records"]
-    kw = s64["key_words"]
-    rec64 = 8 * kw + s64["value_bytes"]
-    rec32 = 8 * kw + s32["value_bytes"]
-    npass = math.ceil(math.log2(max(s64["n_buckets"], 1)) / 8) if s64["n_buckets"] > 1 else 0
-    # dominant kernel of the FP64 step, by HIP-event duration
-    kernels = {"k_gen(count)": avg64["ms_k_count"], "k_gen(write)": avg64["ms_k_write"],
-               "partition": avg64["ms_sort"], "k_reduce": avg64["ms_k_reduce"]}
+    # roofline of the part that dominates the step: the samples of a
+    # semistochastic workload, else the deterministic call (HIP-event times)
+    sampled = "sample" in s64
+    src = s64["sample"] if sampled else s64
+    tsrc = src if sampled else avg64
+    kw = src["key_words"]
+    launches = src["n_chunks"] if sampled else 1
+    # record bytes: packed key + value(s) + bucket id
+    rec64 = 8 * kw + src["value_bytes"] + 4
+    rec32 = 8 * kw + (s32["sample"] if sampled else s32)["value_bytes"] + 4
+    nrec_src = src["n_records"]
+    npass = math.ceil(math.log2(max(src["n_buckets"], 1)) / 8) if src["n_buckets"] > 1 else 0
+    kernels = {"k_gen(count)": tsrc["ms_k_count"], "k_gen(write)": tsrc["ms_k_write"],
+               "partition": tsrc["ms_sort"], "k_reduce": tsrc["ms_k_reduce"]}
     dom = max(kernels, key=kernels.get)
-    # algorithmic bytes per launch (per record: packed key + value)
+    # algorithmic bytes over all launches of each kernel
     alg = {"k_gen(count)": 40.0 * len(x.c),             # each source det read once
-           "k_gen(write)": rec64 * n_rec + 40.0 * len(x.c),
-           "partition": 2.0 * rec64 * n_rec * npass,    # read + write per pass
-           "k_reduce": rec64 * n_rec}                    # each record read once
+           "k_gen(write)": rec64 * nrec_src + 40.0 * len(x.c),
+           "partition": (2.0 * rec64 + 4.0) * nrec_src * npass,  # hist reads ids; scatter reads + writes
+           "k_reduce": rec64 * nrec_src}                 # each record read once
+    per_launch = launches * (npass if dom == "partition" else 1)
     achieved = alg[dom] / (kernels[dom] * 1e-3) / 1e9
     reduce_gbs = alg["k_reduce"] / (avg64["ms_k_reduce"] * 1e-3) / 1e9
     sort_gbs = alg["partition"] / (avg64["ms_sort"] * 1e-3) / 1e9 if npass else None
@@ -190,10 +244,15 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.description}", "n_orb": wl.n_orb,
                    "n_alpha": wl.n_alpha, "n_beta": wl.n_beta, "n_var": len(x.c),
                    "eps2": wl.eps2, "n_terms": n_terms, "n_records": n_rec,
-                   "n_unique": s64["n_unique"], "parallelism": "single GPU"},
+                   "n_unique": s64["n_unique"], "parallelism": "single GPU",
+                   **({"eps2_sto": wl.eps2_sto, "n_samples": wl.n_samples, "n_draws": wl.n_draws,
+                       "e2_sem": s64["sem"], "sample_chunks": s64["sample"]["n_chunks"]}
+                      if wl.n_samples else {}),
+                   "min_abs_denom": s64["min_abs_denom"], "n_intruder": s64["n_intruder"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(wl.name, dom), "alg_bytes": alg[dom]},
+                     "traffic": measured_traffic(wl.name, kernel_names(dom, kw, sampled)),
+                     "alg_bytes": alg[dom] / max(1, per_launch), "launches": per_launch},
         "e2_fp64": e2_64,
         "e2_wall_ms_fp64": w64 * 1e3,
         "fp32c": {"e2": e2_32, "e2_wall_ms": w32 * 1e3, "terms_per_s": n_terms / w32,

@@ -355,13 +355,18 @@ int run_job(Job& J) {
   const int64_t nsrc = J.n_items;
   uint64_t vcap = 1024;
   while (vcap < 2 * (uint64_t)J.ndet) vcap <<= 1;
+  int fbits = 10;  // presence filter: ~16 bits per member (false positives ~6%)
+  while (fbits < 32 && ((uint64_t)1 << fbits) < 16 * (uint64_t)J.ndet) ++fbits;
+  const int64_t fwords = ((int64_t)1 << fbits) / 32;
   uint32_t* nsplit;
   uint64_t *soff, *vtab, *total;
+  uint32_t* vfilt;
   ScanTmp sc0;
   auto plan0 = [&](Carver& cv) {
     nsplit = cv.take<uint32_t>(nsrc + 1);
     soff = cv.take<uint64_t>(nsrc + 1);
     vtab = cv.take<uint64_t>(vcap);
+    vfilt = cv.take<uint32_t>(fwords);
     total = cv.take<uint64_t>(4);
     sc0.carve(cv, nsrc + 1);
   };
@@ -382,6 +387,9 @@ int run_job(Job& J) {
   VSet V;
   V.tab = vtab;
   V.mask = vcap - 1;
+  V.filt = vfilt;
+  V.fbits = fbits;
+  k_fill_u32<<<(int)std::min<int64_t>(4096, (fwords + 255) / 256), 256, 0, st>>>(vfilt, fwords, 0u);
   V.dets = J.dets;
   k_fill_u64<<<std::min<int64_t>(4096, (vcap + 255) / 256), 256, 0, st>>>(vtab, (int64_t)vcap, ~0ull);
   k_vset_insert<KW><<<(int)((J.ndet + 255) / 256), 256, 0, st>>>(V, J.ndet, n, dflag);
@@ -606,12 +614,13 @@ int run_job(Job& J) {
         pa.hist = hist;
         pa.offs = hoffs;
         pa.ntiles = (int)ntiles;
-        k_part_hist<KW><<<(int)ntiles, 256, 0, st>>>(pa);
+        const int pgrid = (int)(8 * ((ntiles + 7) / 8));
+        k_part_hist<KW><<<pgrid, 256, 0, st>>>(pa);
         CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
         if (pay)
-          k_part_scatter<KW, VT, SAMPLE, true><<<(int)ntiles, 256, 0, st>>>(pa);
+          k_part_scatter<KW, VT, SAMPLE, true><<<pgrid, 256, 0, st>>>(pa);
         else
-          k_part_scatter<KW, VT, SAMPLE, false><<<(int)ntiles, 256, 0, st>>>(pa);
+          k_part_scatter<KW, VT, SAMPLE, false><<<pgrid, 256, 0, st>>>(pa);
         HIPCHK(hipGetLastError());
         std::swap(cur, oth);
         shift += dbits;

@@ -166,12 +166,23 @@ struct PassArgs {
   int ntiles;
 };
 
+// Tiles are dealt to blocks so that each of the 8 XCDs (blocks are
+// dispatched round-robin over them) takes a contiguous range of tiles: the
+// output runs of neighbouring tiles then meet in one XCD's L2.  The grid has
+// 8 * ceil(ntiles / 8) blocks; blocks past the last tile return at once.
+SHCI_DEV int xcd_tile(int b, int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  return (b & 7) * per + (b >> 3);
+}
+
 template <int KW>
 __global__ void __launch_bounds__(256) k_part_hist(PassArgs a) {
   __shared__ uint32_t cnt[256];
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  if (tile >= a.ntiles) return;
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * PTILE;
+  const int64_t base = (int64_t)tile * PTILE;
   const uint32_t dmask = (1u << a.dbits) - 1u;
 #pragma unroll 4
   for (int j = 0; j < PTILE_ITEMS; ++j) {
@@ -179,35 +190,45 @@ __global__ void __launch_bounds__(256) k_part_hist(PassArgs a) {
     if (idx < a.n) atomicAdd(&cnt[(a.in.bid[idx] >> a.shift) & dmask], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < (1 << a.dbits)) a.hist[(int64_t)threadIdx.x * a.ntiles + blockIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < (1 << a.dbits)) a.hist[(int64_t)threadIdx.x * a.ntiles + tile] = cnt[threadIdx.x];
 }
 
 // One stable LSD pass over the bucket id, one tile of PTILE records per
-// block.  Ranks within the tile come from the multisplit; every array is then
-// staged through LDS in digit order and written out so that consecutive
-// threads write consecutive records of one digit run (coalesced stores).
+// block.  Each wavefront ranks its own contiguous quarter of the tile (ballot
+// match per round, running per-digit counts in its LDS slice, no block
+// barrier), which keeps the order stable; one scan then gives every digit its
+// place in the tile.  Every array is staged through LDS in digit order and
+// written out so that consecutive threads write consecutive records of one
+// digit run (coalesced stores).
+constexpr int PWAVES = 4;                       // wavefronts per partition block
+constexpr int PW_ITEMS = PTILE / PWAVES / 64;   // rounds per wavefront
+
 struct ScatterShared {
-  SplitScratch S;
-  uint32_t lstart[256];  // first local position of each digit
-  uint32_t gbase[256];   // first output position of each digit for this tile
+  uint16_t wc[PWAVES][256];  // per-wavefront count of each digit
+  uint16_t wb[PWAVES][256];  // first local position of each (wavefront, digit)
+  uint32_t lstart[256];      // first local position of each digit
+  uint32_t gbase[256];       // first output position of each digit for this tile
   uint32_t scan[256];
-  uint8_t sdig[PTILE];   // digit of each local position
+  uint8_t sdig[PTILE];       // digit of each local position
   uint64_t stage[PTILE];
 };
 
+// record handled by (wavefront wv, lane, round j) within a tile
+SHCI_DEV int tile_slot(int wv, int lane, int j) { return wv * (PTILE / PWAVES) + j * 64 + lane; }
+
 template <typename T>
 SHCI_DEV void stage_copy(ScatterShared& L, const T* in, T* out, int64_t base, int tile_n,
-                         const uint16_t (&lpos)[PTILE_ITEMS]) {
-  const int t = threadIdx.x;
+                         const uint16_t (&lpos)[PW_ITEMS]) {
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   T* st = reinterpret_cast<T*>(L.stage);
 #pragma unroll
-  for (int j = 0; j < PTILE_ITEMS; ++j) {
-    const int q = j * 256 + t;
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    const int q = tile_slot(wv, lane, j);
     if (q < tile_n) st[lpos[j]] = in[base + q];
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < PTILE_ITEMS; ++j) {
+  for (int j = 0; j < PW_ITEMS; ++j) {
     const int q = j * 256 + t;
     if (q < tile_n) {
       const uint32_t d = L.sdig[q];
@@ -220,31 +241,62 @@ SHCI_DEV void stage_copy(ScatterShared& L, const T* in, T* out, int64_t base, in
 template <int KW, typename VT, bool V2, bool PAY>
 __global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
   __shared__ ScatterShared L;
-  const int t = threadIdx.x;
-  L.S.run[t] = 0;
-  L.S.wcnt[0][t] = L.S.wcnt[1][t] = L.S.wcnt[2][t] = L.S.wcnt[3][t] = 0;
-  L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + blockIdx.x] : 0u;
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  if (tile >= a.ntiles) return;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+#pragma unroll
+  for (int w = 0; w < PWAVES; ++w) L.wc[w][t] = 0;
+  L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + tile] : 0u;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * PTILE;
+  const int64_t base = (int64_t)tile * PTILE;
   const int tile_n = (int)((a.n - base < (int64_t)PTILE) ? (a.n - base) : (int64_t)PTILE);
   const uint32_t dmask = (1u << a.dbits) - 1u;
-  uint16_t lpos[PTILE_ITEMS];
-  uint8_t dig[PTILE_ITEMS];
+  uint16_t lpos[PW_ITEMS];
+  uint8_t dig[PW_ITEMS];
+  uint16_t* wc = L.wc[wv];
 #pragma unroll
-  for (int j = 0; j < PTILE_ITEMS; ++j) {
-    const int q = j * 256 + t;
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    const int q = tile_slot(wv, lane, j);
     const bool valid = q < tile_n;
     const uint32_t d = valid ? ((a.in.bid[base + q] >> a.shift) & dmask) : 0u;
-    lpos[j] = (uint16_t)split_round(L.S, valid, d, a.dbits);  // rank within digit d
+    uint64_t peers = ballot(valid);
+    for (int bb = 0; bb < a.dbits; ++bb) {
+      const bool on = (d >> bb) & 1u;
+      const uint64_t m = ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const int r = rank_below(peers);
+    const uint32_t prior = valid ? wc[d] : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid && r == 0) wc[d] = (uint16_t)(prior + __popcll(peers));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    lpos[j] = (uint16_t)(prior + r);  // rank within digit d among this wavefront's records
     dig[j] = (uint8_t)d;
   }
+  __syncthreads();
   uint32_t tot;
-  L.lstart[t] = block_scan256(L.S.run[t], L.scan, &tot);
+  uint32_t cnt_t = 0;
+#pragma unroll
+  for (int w = 0; w < PWAVES; ++w) cnt_t += L.wc[w][t];
+  const uint32_t ls = block_scan256(cnt_t, L.scan, &tot);
+  L.lstart[t] = ls;
+  {
+    uint32_t acc = ls;
+#pragma unroll
+    for (int w = 0; w < PWAVES; ++w) {
+      L.wb[w][t] = (uint16_t)acc;
+      acc += L.wc[w][t];
+    }
+  }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < PTILE_ITEMS; ++j) {
-    const int q = j * 256 + t;
-    lpos[j] = (uint16_t)(lpos[j] + L.lstart[dig[j]]);
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    const int q = tile_slot(wv, lane, j);
+    lpos[j] = (uint16_t)(lpos[j] + L.wb[wv][dig[j]]);
     if (q < tile_n) L.sdig[lpos[j]] = dig[j];
   }
   __syncthreads();
@@ -283,6 +335,8 @@ struct RedArgs {
 // h is hash_key(k)
 template <int KW>
 SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
+  const uint64_t fb = h >> (64 - V.fbits);
+  if (!((V.filt[fb >> 5] >> (fb & 31)) & 1u)) return false;
   uint64_t slot = h & V.mask;
   const uint32_t fp = (uint32_t)(h >> 32);
   for (uint64_t probe = 0; probe <= V.mask; ++probe) {
@@ -316,6 +370,8 @@ __global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
   const uint64_t h = hash_key<KW>(k);
   const uint32_t fp = (uint32_t)(h >> 32);
   const uint64_t entry = ((uint64_t)fp << 32) | (uint64_t)i;
+  const uint64_t fb = h >> (64 - V.fbits);
+  atomicOr(&V.filt[fb >> 5], 1u << (fb & 31));
   uint64_t slot = h & V.mask;
   for (uint64_t probe = 0; probe <= V.mask; ++probe) {
     const unsigned long long old =

@@ -191,6 +191,25 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
                     const uint32_t* draws, int precision, void* stream, double* per_sample,
                     double* mean, double* sem, shci_pt2_stats* st);
 
+/* Adjoint of the stochastic part: the per-sample estimates of
+ * shci_pt2_sample and the derivatives of their mean with respect to c and
+ * E0, with the draws, p_i and the screening masks held at the forward point
+ * (derivative of the stochastic PT2 equation):
+ *   de2_dc[i] = mean_s sum_{a: (i,a) kept} [ 2 X_a w_i H_ai / p_i
+ *       + 2 (w_i (N_d - 1)/p_i - w_i^2/p_i^2) c_i H_ai^2 - (the same over the
+ *       eps2_d terms, with X_a^d) ] / ((E0 - H_aa) N_d (N_d - 1)),
+ *   X_a = sum_i w_i c_i H_ai / p_i over the sample's kept terms of a.
+ *   de2_dc    device FP64 [n_det], overwritten;
+ *   de2_de0   host, nullable: mean over samples of dS_s/dE0.
+ * The adjoint recomputes each sample's terms (a second generation pass)
+ * and looks its per-a factors up in the sample's unique store.  Other
+ * arguments as shci_pt2_sample; per_sample must be non-NULL. */
+int shci_pt2_sample_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                         double e0, double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
+                         const uint32_t* draws, int precision, void* stream, double* per_sample,
+                         double* mean, double* sem, double* de2_dc, double* de2_de0,
+                         shci_pt2_stats* st);
+
 /* Gradient of the deterministic screened E2 with the screening mask held at
  * the given c:
  *   dE2/dc_i = sum_{a: (i,a) kept, a not in V} 2 H_ai A_a / (E0 - H_aa)

@@ -623,12 +623,20 @@ int64_t oracle_terms_of(int n, int na, int nb, const double* h1, const double* e
 //            + sum_i (w_i (Nd-1)/p_i - w_i^2/p_i^2) c_i^2 H_ai^2 ] / ((E0 - H_aa) Nd (Nd-1)),
 // the inner sums running over the distinct determinants of sample s whose
 // term passes |H_ai c_i| > e.
-int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri,
-                      const uint64_t* dets, const double* c, int64_t nd, double e0, double eps2,
-                      double eps2_d, int32_t ns, int32_t ndraw, const uint32_t* draws, double* out) {
-  System S{n, na, nb, h1, eri};
-  const Det* V = reinterpret_cast<const Det*>(dets);
-  int st = validate(S, V, c, nd);
+//
+// sample_core evaluates it with the sampling probabilities p_i and the
+// screening taken from c_ref and the values from c (c_ref = c is the plain
+// estimator; c != c_ref gives the frozen-mask function used for finite
+// differences).  With grad != NULL it also accumulates the derivative of the
+// mean over samples at frozen draws, p and masks,
+//   d/dc_i = mean_s sum_{a: (i,a) kept} [ 2 X_a w_i H_ai / p_i
+//            + 2 (w_i (Nd-1)/p_i - w_i^2/p_i^2) c_i H_ai^2 - (the same over the
+//            eps2_d terms, with X_a^d) ] / ((E0 - H_aa) Nd (Nd-1)),
+// and per sample de0[s] = dS_s/dE0 = -sum_a [...] / ((E0 - H_aa)^2 Nd (Nd-1)).
+static int sample_core(const System& S, const Det* V, int64_t nd, const double* c, const double* c_ref,
+                       double e0, double eps2, double eps2_d, int32_t ns, int32_t ndraw,
+                       const uint32_t* draws, double* out, double* grad, double* de0) {
+  int st = validate(S, V, c_ref, nd);
   if (st) return st;
   if (ndraw < 2 || ns < 1 || !(eps2 >= 0.0) || !(eps2_d >= eps2)) {
     snprintf(g_err, sizeof g_err, "bad sample arguments");
@@ -641,9 +649,12 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
     }
   std::unordered_set<Det, DetHash> Vset(V, V + nd);
   Neumaier sa;
-  for (int64_t i = 0; i < nd; ++i) sa.add(std::fabs(c[i]));
+  for (int64_t i = 0; i < nd; ++i) sa.add(std::fabs(c_ref[i]));
   const double sum_abs = sa.value();
   const double Nd = (double)ndraw;
+  if (grad)
+    for (int64_t i = 0; i < nd; ++i) grad[i] = 0.0;
+  std::vector<Neumaier> gacc(grad ? nd : 0);
   for (int32_t s = 0; s < ns; ++s) {
     std::vector<uint32_t> dr(draws + (int64_t)s * ndraw, draws + (int64_t)(s + 1) * ndraw);
     std::sort(dr.begin(), dr.end());
@@ -653,7 +664,9 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
     struct T {
       Det a;
       uint32_t i;
-      double x, y;
+      double x, y;  // w c H / p and (w (Nd-1)/p - w^2/p^2) c^2 H^2
+      double wh;    // w H / p
+      double q;     // (w (Nd-1)/p - w^2/p^2) c H^2
       bool d;
     };
     std::vector<T> terms;
@@ -670,14 +683,17 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
     for (size_t u = 0; u < uw.size(); ++u) {
       uint32_t i = uw[u].first;
       double w = uw[u].second;
-      double ci = c[i];
-      double p = std::fabs(ci) / sum_abs;
+      double ci = c[i], cr = c_ref[i];
+      double p = std::fabs(cr) / sum_abs;
+      // screening and H from the reference coefficients' determinant (H does
+      // not depend on c); values with c
       for_each_excitation(S, V[i], [&](const Det& a, double hval) {
-        if (!kept(hval, ci, eps2)) return;
+        if (!kept(hval, cr, eps2)) return;
         double ch = ci * hval;
+        double f = w * (Nd - 1.0) / p - w * w / (p * p);
         double x = w * ch / p;
-        double y = (w * (Nd - 1.0) / p - w * w / (p * p)) * ch * ch;
-        per[u].push_back(T{a, i, x, y, kept(hval, ci, eps2_d)});
+        double y = f * ch * ch;
+        per[u].push_back(T{a, i, x, y, w * hval / p, f * ci * hval * hval, kept(hval, cr, eps2_d)});
       });
     }
     size_t total = 0;
@@ -697,12 +713,18 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
     for (size_t m = 0; m < terms.size(); ++m)
       if (m == 0 || !(terms[m].a == terms[m - 1].a)) heads.push_back(m);
     heads.push_back(terms.size());
+    const int64_t ngroups = (int64_t)heads.size() - 1;
     const int nthr = omp_get_max_threads();
-    std::vector<Neumaier> part(nthr);
+    std::vector<Neumaier> part(nthr), dpart(nthr);
+    // per group: X, X^d and 1 / (D Nd (Nd-1)) (0 for members of V)
+    std::vector<double> gX(grad ? ngroups : 0), gXd(grad ? ngroups : 0), gG(grad ? ngroups : 0);
 #pragma omp parallel for schedule(static)
-    for (int64_t g = 0; g < (int64_t)heads.size() - 1; ++g) {
+    for (int64_t g = 0; g < ngroups; ++g) {
       const size_t k0 = heads[g], j = heads[g + 1];
-      if (Vset.count(terms[k0].a)) continue;
+      if (Vset.count(terms[k0].a)) {
+        if (grad) gG[g] = 0.0;
+        continue;
+      }
       Acc acc;
       for (size_t m = k0; m < j; ++m) {
         acc.X.add(terms[m].x);
@@ -714,16 +736,69 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
       }
       double X = acc.X.value(), Y = acc.Y.value(), Xd = acc.Xd.value(), Yd = acc.Yd.value();
       double Dd = e0 - diag_value(S, terms[k0].a);
-      part[omp_get_thread_num()].add(((X * X + Y) - (Xd * Xd + Yd)) / (Dd * Nd * (Nd - 1.0)));
+      double bracket = (X * X + Y) - (Xd * Xd + Yd);
+      part[omp_get_thread_num()].add(bracket / (Dd * Nd * (Nd - 1.0)));
+      dpart[omp_get_thread_num()].add(-bracket / (Dd * Dd * Nd * (Nd - 1.0)));
+      if (grad) {
+        gX[g] = X;
+        gXd[g] = Xd;
+        gG[g] = 1.0 / (Dd * Nd * (Nd - 1.0));
+      }
     }
-    Neumaier tot;
-    for (auto& q : part) {
-      tot.add(q.s);
-      tot.add(q.c);
+    Neumaier tot, dtot;
+    for (int t = 0; t < nthr; ++t) {
+      tot.add(part[t].s);
+      tot.add(part[t].c);
+      dtot.add(dpart[t].s);
+      dtot.add(dpart[t].c);
     }
     out[s] = tot.value();
+    if (de0) de0[s] = dtot.value();
+    if (grad) {
+      // terms in (a, i) order; per source i the sum runs in that order
+      for (int64_t g = 0; g < ngroups; ++g) {
+        if (gG[g] == 0.0) continue;
+        for (size_t m = heads[g]; m < heads[g + 1]; ++m) {
+          const T& t = terms[m];
+          double v = 2.0 * gX[g] * t.wh + 2.0 * t.q;
+          if (t.d) v -= 2.0 * gXd[g] * t.wh + 2.0 * t.q;
+          gacc[t.i].add(v * gG[g]);
+        }
+      }
+    }
   }
+  if (grad)
+    for (int64_t i = 0; i < nd; ++i) grad[i] = gacc[i].value() / (double)ns;
   return 0;
+}
+
+int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri,
+                      const uint64_t* dets, const double* c, int64_t nd, double e0, double eps2,
+                      double eps2_d, int32_t ns, int32_t ndraw, const uint32_t* draws, double* out) {
+  System S{n, na, nb, h1, eri};
+  return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c, e0, eps2, eps2_d, ns, ndraw, draws,
+                     out, nullptr, nullptr);
+}
+
+// The estimator with p_i and the screening frozen at c_ref and values at c.
+int oracle_pt2_sample_frozen(int n, int na, int nb, const double* h1, const double* eri,
+                             const uint64_t* dets, const double* c, const double* c_ref, int64_t nd,
+                             double e0, double eps2, double eps2_d, int32_t ns, int32_t ndraw,
+                             const uint32_t* draws, double* out) {
+  System S{n, na, nb, h1, eri};
+  return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c_ref, e0, eps2, eps2_d, ns, ndraw, draws,
+                     out, nullptr, nullptr);
+}
+
+// Per-sample estimates, the gradient of their mean with respect to c (draws,
+// p and masks frozen) and per-sample derivatives with respect to E0.
+int oracle_pt2_sample_grad(int n, int na, int nb, const double* h1, const double* eri,
+                           const uint64_t* dets, const double* c, int64_t nd, double e0, double eps2,
+                           double eps2_d, int32_t ns, int32_t ndraw, const uint32_t* draws, double* out,
+                           double* grad, double* de0) {
+  System S{n, na, nb, h1, eri};
+  return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c, e0, eps2, eps2_d, ns, ndraw, draws,
+                     out, grad, de0);
 }
 
 // <c|H|c> over all pairs of V (pairs more than two excitations apart are skipped).

@@ -57,6 +57,12 @@ def lib():
         L.oracle_pt2_sample.restype = _i
         L.oracle_pt2_sample.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d,
                                         C.c_int32, C.c_int32, _p, _p]
+        L.oracle_pt2_sample_frozen.restype = _i
+        L.oracle_pt2_sample_frozen.argtypes = [_i, _i, _i, _p, _p, _p, _p, _p, _i64, _d, _d, _d,
+                                               _i, _i, _p, _p]
+        L.oracle_pt2_sample_grad.restype = _i
+        L.oracle_pt2_sample_grad.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d,
+                                             _i, _i, _p, _p, _p, _p]
         L.oracle_energy.restype = _d
         L.oracle_energy.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64]
         L.oracle_terms_of.restype = _i64
@@ -203,6 +209,44 @@ def pt2_sample(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
     if st:
         raise OracleError(st, L.oracle_last_error().decode())
     return out
+
+
+def pt2_sample_frozen(n, na, nb, h1, eri, dets, c, c_ref, e0, eps2, eps2_d, draws):
+    """Per-sample estimates with p_i and the screening taken from c_ref and
+    the values from c (the function whose derivative the adjoint gives)."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    c_ref = np.ascontiguousarray(c_ref, dtype=np.float64)
+    draws = np.ascontiguousarray(draws, dtype=np.uint32)
+    ns, nd = draws.shape
+    out = np.zeros(ns)
+    L = lib()
+    st = L.oracle_pt2_sample_frozen(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), _ptr(c_ref),
+                                    len(c), float(e0), float(eps2), float(eps2_d), ns, nd,
+                                    _ptr(draws), _ptr(out))
+    if st:
+        raise OracleError(st, L.oracle_last_error().decode())
+    return out
+
+
+def pt2_sample_grad(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
+    """(per-sample estimates, d(mean)/dc at frozen draws/p/masks, per-sample d/dE0)."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    draws = np.ascontiguousarray(draws, dtype=np.uint32)
+    ns, nd = draws.shape
+    out = np.zeros(ns)
+    grad = np.zeros(len(c))
+    de0 = np.zeros(ns)
+    L = lib()
+    st = L.oracle_pt2_sample_grad(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
+                                  float(e0), float(eps2), float(eps2_d), ns, nd, _ptr(draws),
+                                  _ptr(out), _ptr(grad), _ptr(de0))
+    if st:
+        raise OracleError(st, L.oracle_last_error().decode())
+    return out, grad, de0
 
 
 def energy(n, na, nb, h1, eri, dets, c) -> float:

@@ -5,4 +5,5 @@ include/shci_pt2.h); this package is its thin Python binding.
 """
 from .binding import (SHCI_FP32C, SHCI_FP64, Context, ShciError, dets_numpy, dets_tensor,  # noqa: F401
                       lib)
-from .autograd import PT2Function, pt2_energy  # noqa: F401
+from .autograd import (PT2Function, SemistochasticPT2Function, pt2_energy,  # noqa: F401
+                       pt2_semistochastic_energy)

@@ -80,6 +80,9 @@ def lib():
         L.shci_pt2_sample.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, i, p, p,
                                       C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
         L.shci_pt2_sample.restype = i
+        L.shci_pt2_sample_grad.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, i, p, p,
+                                           C.POINTER(d), C.POINTER(d), p, C.POINTER(d), C.POINTER(Stats)]
+        L.shci_pt2_sample_grad.restype = i
         L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), p, C.POINTER(d),
                                     C.POINTER(Stats)]
         L.shci_pt2_grad.restype = i
@@ -218,6 +221,24 @@ class Context:
                                      C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
                                      C.byref(st)))
         return out, mean.value, sem.value, st.as_dict()
+
+    def sample_grad(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64"):
+        """Per-sample estimates and the adjoint of their mean: returns
+        (per_sample, mean, sem, dE/dc tensor, dE/dE0, stats)."""
+        pd, pc, nd = self._inputs(dets, c)
+        ns, ndraw = draws.shape
+        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
+        out = torch.empty(ns, dtype=torch.float64, device=c.device)
+        g = torch.empty(nd, dtype=torch.float64, device=c.device)
+        mean = C.c_double()
+        sem = C.c_double()
+        de0 = C.c_double()
+        st = Stats()
+        _check(lib().shci_pt2_sample_grad(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_d),
+                                          ns, ndraw, pdr, _PREC[precision], _stream(),
+                                          C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
+                                          C.c_void_p(g.data_ptr()), C.byref(de0), C.byref(st)))
+        return out, mean.value, sem.value, g, de0.value, st.as_dict()
 
 
 def dets_tensor(dets_u64, device="cuda"):

@@ -327,6 +327,9 @@ struct Job {
   bool want_u = false;
   bool want_pay = false;
   double* per_sample = nullptr;  // device [nsamp]
+  double* per_sample_de0 = nullptr;  // device [nsamp], nullable: dS_s/dE0
+  const uint64_t* samp_off = nullptr;  // host [nsamp + 1]: item range of each sample of the chunk
+  double grad_scale = 1.0;             // sample mode: weight of this chunk's adjoint
   int64_t max_records = 0;       // > 0: give up after the count pass if exceeded
   uint32_t bmask = 0, bsel = 0;  // hash batch of a (deterministic mode)
   bool grad_accumulate = false;  // add this batch's adjoint to grad
@@ -427,6 +430,7 @@ int run_job(Job& J) {
   uint32_t *w_src, *w_rng, *counts;
   uint64_t *offs, *total1;
   double* gpart = nullptr;
+  double* gitem = nullptr;  // sample mode: adjoint per item before the scatter to determinants
   ScanTmp sc;
   auto plan1 = [&](Carver& cv) {
     w_src = cv.take<uint32_t>(ni + 1);
@@ -435,6 +439,7 @@ int run_job(Job& J) {
     offs = cv.take<uint64_t>(ni + 1);
     total1 = cv.take<uint64_t>(4);
     gpart = J.grad ? cv.take<double>(ni + 1) : nullptr;
+    gitem = (J.grad && SAMPLE) ? cv.take<double>(nsrc + 1) : nullptr;
     sc.carve(cv, ni + 1);
   };
   {
@@ -694,7 +699,7 @@ int run_job(Job& J) {
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
     if (SAMPLE) {
       k_final<<<J.nsamp, 1024, 0, st>>>(P, G.nbucket, 0, J.nsamp, overflow, dflag, X->dres, J.per_sample,
-                                         (int64_t)1 << G.bits_hash);
+                                         (int64_t)1 << G.bits_hash, J.per_sample_de0);
     } else {
       // bucket partials (only the block kernel's buckets are non-zero) and
       // per-wavefront partials, summed in a fixed order
@@ -708,7 +713,7 @@ int run_job(Job& J) {
       Q2.nuniq += fblocks; Q2.nintr += fblocks; Q2.nzero += fblocks; Q2.mind += fblocks;
       k_final_partial<<<(int)fblocks, 256, 0, st>>>(P, G.nbucket, fchunk, Q);
       k_final_partial<<<(int)wfblocks, 256, 0, st>>>(Pw, nwv, wchunk, Q2);
-      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0);
+      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0, nullptr);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(X->ev[3], st));
@@ -751,9 +756,20 @@ int run_job(Job& J) {
       g.L = L;
       g.grad = gpart;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
-      k_gen<KW, GEN_GRAD, false, VT><<<gen_grid, 256, 0, st>>>(g);
-      k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, J.grad,
-                                                              J.grad_accumulate ? 1 : 0);
+      k_gen<KW, GEN_GRAD, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+      if constexpr (SAMPLE) {
+        k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, gitem, 0);
+        for (int32_t smp = 0; smp < J.nsamp; ++smp) {
+          const int64_t o0 = (int64_t)(J.samp_off[smp] - J.samp_off[0]);
+          const int64_t cnt = (int64_t)(J.samp_off[smp + 1] - J.samp_off[smp]);
+          if (cnt > 0)
+            k_grad_scatter<<<(int)((cnt + 255) / 256), 256, 0, st>>>(gitem + o0, J.it_det + o0, cnt,
+                                                                      J.grad_scale, J.grad);
+        }
+      } else {
+        k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, J.grad,
+                                                                J.grad_accumulate ? 1 : 0);
+      }
       HIPCHK(hipGetLastError());
     }
     if (J.want_u && J.ex && J.ex->u_keys) {
@@ -1101,10 +1117,10 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
   return SHCI_OK;
 }
 
-int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
-                    double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
-                    int precision, void* stream, double* per_sample, double* mean, double* sem,
-                    shci_pt2_stats* st) {
+static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                       double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
+                       int precision, void* stream, double* per_sample, double* mean, double* sem,
+                       shci_pt2_stats* st, double* grad, double* de2_de0) {
   CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
   if (!draws || !per_sample) return fail(SHCI_ERR_ARG, "draws or per_sample is NULL");
   if (n_samples < 1 || n_draws < 2) return fail(SHCI_ERR_ARG, "need n_samples >= 1 and n_draws >= 2");
@@ -1127,6 +1143,7 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
     cv.take<uint32_t>(cap);
     cv.take<uint32_t>(cap);
     cv.take<double>(4);
+    cv.take<double>(n_samples + 1);
     ScanTmp tmp;
     tmp.carve(cv, n_samples + 1);
     bytes = cv.off;
@@ -1141,6 +1158,7 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   uint32_t* o_w = cv.take<uint32_t>(cap);
   uint32_t* o_s = cv.take<uint32_t>(cap);
   double* dsum = cv.take<double>(4);
+  double* psde0 = cv.take<double>(n_samples + 1);
   ScanTmp tmp;
   tmp.carve(cv, n_samples + 1);
   auto done = [&](int code) {
@@ -1173,8 +1191,10 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   // the workspace: one generation / partition / reduce launch sequence per
   // chunk covers all its samples (sample id in the key).  The chunk length
   // adapts to the records per sample seen so far.
-  const int64_t max_rec =
-      record_budget(ctx, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false, false));
+  const int64_t max_rec = record_budget(
+      ctx, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false, grad != nullptr));
+  if (grad) k_fill_u64<<<(int)std::min<int64_t>(4096, (n_det + 255) / 256), 256, 0, s>>>(
+      reinterpret_cast<uint64_t*>(grad), n_det, 0ull);
   Job acc{};
   acc.res.mind = INFINITY;
   int64_t chunks = 0;
@@ -1210,7 +1230,14 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
     J.it_s = o_s + hoff[s0];
     J.n_items = (int64_t)(hoff[s0 + k] - hoff[s0]);
     J.per_sample = per_sample + s0;
+    J.per_sample_de0 = psde0 + s0;
     J.max_records = max_rec;
+    J.samp_off = hoff.data() + s0;
+    if (grad) {
+      J.want_u = true;
+      J.grad = grad;
+      J.grad_scale = 1.0 / (double)n_samples;
+    }
     int r = dispatch(J);
     if (r == JOB_TOO_BIG) {
       if (k == 1) return done(fail(SHCI_ERR_WORKSPACE, "one sample has %lld screened terms; the workspace holds %lld",
@@ -1250,6 +1277,15 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   double m = 0.0;
   for (double v : ps) m += v;
   m /= n_samples;
+  if (de2_de0) {
+    std::vector<double> pd(n_samples);
+    if (hipMemcpyAsync(pd.data(), psde0, n_samples * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return done(fail(SHCI_ERR_HIP, "copy of per-sample E0 derivatives failed"));
+    double d = 0.0;
+    for (double v : pd) d += v;
+    *de2_de0 = d / n_samples;
+  }
   double var = 0.0;
   for (double v : ps) var += (v - m) * (v - m);
   if (mean) *mean = m;
@@ -1259,6 +1295,23 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   if (acc.res.nzero) return done(fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
                                       (long long)acc.res.nzero));
   return done(SHCI_OK);
+}
+
+int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                    double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
+                    int precision, void* stream, double* per_sample, double* mean, double* sem,
+                    shci_pt2_stats* st) {
+  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
+                     per_sample, mean, sem, st, nullptr, nullptr);
+}
+
+int shci_pt2_sample_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                         double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
+                         int precision, void* stream, double* per_sample, double* mean, double* sem,
+                         double* de2_dc, double* de2_de0, shci_pt2_stats* st) {
+  if (!de2_dc) return fail(SHCI_ERR_ARG, "de2_dc is NULL");
+  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
+                     per_sample, mean, sem, st, de2_dc, de2_de0);
 }
 
 }  // extern "C"

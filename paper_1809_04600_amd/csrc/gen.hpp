@@ -80,19 +80,20 @@ SHCI_DEV int tri_inv(int u) {
   return y;
 }
 
-// Find g = 2 A_a / D_a of a unique key (aux bit already clear).  Returns 0
-// if the key is not stored (members of V are stored with g = 0).
+// Position of a unique key (flag bit clear; sample id in the key in sample
+// mode) in the unique store, or -1.  Buckets and the in-bucket order use the
+// determinant hash; sid selects the sample's range of buckets.
 template <int KW>
-SHCI_DEV double lookup_g(const uint64_t (&key)[KW], const LookupArgs& L) {
-  uint64_t h = hash_key<KW>(key);
+SHCI_DEV int64_t lookup_u(const uint64_t (&key)[KW], int n, uint32_t sid, const LookupArgs& L) {
+  const uint64_t h = det_hash<KW>(key, n);
   const int bh = L.G.bits_hash;
-  uint64_t b = bh ? (h >> (64 - bh)) : 0ull;
-  uint32_t h2 = (uint32_t)((h << bh) >> 32);
-  uint64_t lo = L.U.start[b];
-  int cnt = L.nseg[b];
+  const uint64_t b = (bh ? (h >> (64 - bh)) : 0ull) | ((uint64_t)sid << bh);
+  const uint32_t h2 = (uint32_t)((h << bh) >> 32);
+  const uint64_t lo = L.U.start[b];
+  const int cnt = L.nseg[b];
   int a = 0, z = cnt;
   while (a < z) {
-    int m = (a + z) >> 1;
+    const int m = (a + z) >> 1;
     if (L.U.h2[lo + m] < h2)
       a = m + 1;
     else
@@ -102,9 +103,9 @@ SHCI_DEV double lookup_g(const uint64_t (&key)[KW], const LookupArgs& L) {
     bool eq = true;
 #pragma unroll
     for (int w = 0; w < KW; ++w) eq = eq && (L.U.k[w][lo + j] == key[w]);
-    if (eq) return L.U.g[lo + j];
+    if (eq) return (int64_t)(lo + j);
   }
-  return 0.0;
+  return -1;
 }
 
 template <int KW, int MODE, bool SAMPLE, typename VT>
@@ -233,7 +234,20 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         if (keep) {
           uint64_t key[KW];
           pack_det<KW>(key, x0, x1, y0, y1, n);
-          gacc += H * lookup_g<KW>(key, a.L);
+          if constexpr (SAMPLE) put_bits<KW>(key, (uint64_t)sid, 0ull, 2 * n);
+          const int64_t o = lookup_u<KW>(key, n, sid, a.L);
+          if (o >= 0) {
+            if constexpr (SAMPLE) {
+              // d/dc_i of the sample bracket over (X^2 + Y) - (X_d^2 + Y_d),
+              // frozen w, p and masks (stored factors: 2 X G, 2 X^d G, G)
+              const double wh = w * H / pr;
+              const double q = 2.0 * (w * (a.nd - 1.0) / pr - w * w / (pr * pr)) * ci * H * H;
+              const bool dflag = fabs(H) * absc > a.eps2_d;
+              gacc += dflag ? (a.L.U.g[o] - a.L.U.A[o]) * wh : a.L.U.g[o] * wh + q * a.L.U.D[o];
+            } else {
+              gacc += H * a.L.U.g[o];
+            }
+          }
         }
       }
     };
@@ -530,6 +544,15 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
 
 // dE2/dc_i = sum of the partial adjoints of the work items of source i, in
 // item order
+// sample mode: add each item's adjoint to its determinant; the items of one
+// sample are distinct determinants, so one launch per sample has no conflicts
+// and the sample order fixes the summation order
+__global__ void k_grad_scatter(const double* gitem, const uint32_t* it_det, int64_t count, double scale,
+                               double* grad) {
+  const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u < count) grad[it_det[u]] += scale * gitem[u];
+}
+
 __global__ void k_grad_sum(const uint32_t* nsplit, const uint64_t* off, const double* part, int64_t n_src,
                            double* grad, int accumulate) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

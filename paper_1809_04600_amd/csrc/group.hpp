@@ -646,18 +646,24 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       const bool inv = vset_contains<KW>(a.V, dk, n);
       const int cntk = j1 - j0;
       ngen += cntk;
-      double Dd = 0.0, g = 0.0;
+      double Dd = 0.0, g = 0.0, gd = 0.0, gG = 0.0;
       if (!inv) {
         const double haa = diag_energy<LDS>(a0, a1, b0, b1, refd, DT, a.ne);
         Dd = a.e0 - haa;
         double contrib;
-        if constexpr (SAMPLE)
-          contrib = sum.sample_bracket() / (Dd * a.nd * (a.nd - 1.0));
-        else
+        if constexpr (SAMPLE) {
+          const double G = 1.0 / (Dd * a.nd * (a.nd - 1.0));
+          contrib = sum.sample_bracket() * G;
+          de0p += -contrib / Dd;
+          g = 2.0 * X * G;
+          gd = 2.0 * sum.Xd * G;
+          gG = G;
+        } else {
           contrib = X * X / Dd;
+          de0p += -(X * X) / (Dd * Dd);
+          g = 2.0 * X / Dd;
+        }
         e2p += contrib;
-        de0p += -(X * X) / (Dd * Dd);
-        g = 2.0 * X / Dd;
         nterm += cntk;
         nuniq += 1;
         nintr += Dd > 0.0;
@@ -669,8 +675,10 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
 #pragma unroll
         for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
         a.U.h2[o] = R.sb.h2a[j0];
-        a.U.A[o] = X;
-        a.U.D[o] = Dd;
+        // deterministic: A_a, D_a, 2 A_a / D_a; sample: 2 X^d G, G, 2 X G with
+        // G = 1 / (D_a Nd (Nd - 1)) (the adjoint's per-a factors)
+        a.U.A[o] = SAMPLE ? gd : X;
+        a.U.D[o] = SAMPLE ? gG : Dd;
         a.U.g[o] = g;
         a.U.cnt[o] = inv ? -cntk : cntk;
       }
@@ -773,7 +781,8 @@ struct DevResult {
 
 __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t seg_lo, int64_t seg_n,
                                                 const uint32_t* overflow, const uint32_t* flags,
-                                                DevResult* res, double* per_sample, int64_t per_seg) {
+                                                DevResult* res, double* per_sample, int64_t per_seg,
+                                                double* per_sample_de0) {
   // sums buckets [seg_lo + s*per_seg, ...) per segment s when per_sample != NULL,
   // or everything into res
   __shared__ double r1[1024], r2[1024], r3[1024];
@@ -814,6 +823,7 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
   if (t == 0) {
     if (per_sample) {
       per_sample[blockIdx.x] = r1[0];
+      if (per_sample_de0) per_sample_de0[blockIdx.x] = r2[0];
       // statistics accumulate over the per-sample blocks
       atomicAdd((unsigned long long*)&res->nterm, (unsigned long long)i1[0]);
       atomicAdd((unsigned long long*)&res->ngen, (unsigned long long)i2[0]);

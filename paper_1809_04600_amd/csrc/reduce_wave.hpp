@@ -215,19 +215,25 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
       const bool inv = vset_contains_h<KW>(a.V, dk, h, n);
       const int cntk = e1 - e0;
       acc.ngen += cntk;
-      double Dd = 0.0, g = 0.0;
+      double Dd = 0.0, g = 0.0, gd = 0.0, gG = 0.0;
       if (!inv) {
         const double haa = diag_energy<LDS>(a0, a1, b0, b1, ref, DT, a.ne);
         Dd = a.e0 - haa;
         const double rd = 1.0 / Dd;
         double contrib;
-        if constexpr (SAMPLE)
-          contrib = sum.sample_bracket() * rd / (a.nd * (a.nd - 1.0));
-        else
+        if constexpr (SAMPLE) {
+          const double G = rd / (a.nd * (a.nd - 1.0));
+          contrib = sum.sample_bracket() * G;
+          acc.de0p += -contrib * rd;
+          g = 2.0 * X * G;
+          gd = 2.0 * sum.Xd * G;
+          gG = G;
+        } else {
           contrib = X * X * rd;
+          acc.de0p += -(X * X) * rd * rd;
+          g = 2.0 * X * rd;
+        }
         acc.e2p += contrib;
-        acc.de0p += -(X * X) * rd * rd;
-        g = 2.0 * X * rd;
         acc.nterm += cntk;
         acc.nuniq += 1;
         acc.nintr += Dd > 0.0;
@@ -239,8 +245,10 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
 #pragma unroll
         for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
         a.U.h2[o] = (uint32_t)(s0 >> 32);
-        a.U.A[o] = X;
-        a.U.D[o] = Dd;
+        // deterministic: A_a, D_a, 2 A_a / D_a; sample: 2 X^d G, G, 2 X G with
+        // G = 1 / (D_a Nd (Nd - 1)) (the adjoint's per-a factors)
+        a.U.A[o] = SAMPLE ? gd : X;
+        a.U.D[o] = SAMPLE ? gG : Dd;
         a.U.g[o] = g;
         a.U.cnt[o] = inv ? -cntk : cntk;
       }

@@ -280,3 +280,54 @@ def test_sample_chunks_match_single_pass():
     scale = max(1.0, np.abs(o).max())
     assert np.abs(outc - out1).max() <= 1e-13 * scale
     assert np.abs(outc - o).max() <= 1e-9 * scale
+
+
+def test_sample_adjoint():
+    # d(mean_s S_s)/dc and dS/dE0 at frozen draws, p and masks, against the
+    # CPU reference; also through several sample chunks and in FP32c
+    x = I.small(10, 3, 3, 200, 3, 13)
+    ctx, dets, c = context(x)
+    rng = np.random.default_rng(17)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    draws = rng.choice(len(x.c), size=(7, 40), p=p).astype(np.uint32)
+    dr = torch.from_numpy(draws.view(np.int32)).cuda()
+    eps2, eps2_d = 1e-6, 1e-4
+    o_out, o_g, o_de0 = ref.pt2_sample_grad(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2, eps2_d, draws)
+    out, mean, sem, g, de0, st = ctx.sample_grad(dets, c, x.e0, eps2, eps2_d, dr, "fp64")
+    g = g.cpu().numpy()
+    scale = max(1.0, np.abs(o_out).max())
+    print("sample adjoint: max |dS|", np.abs(out.cpu().numpy() - o_out).max(),
+          "grad rel", np.linalg.norm(g - o_g) / np.linalg.norm(o_g), "de0", de0, o_de0.mean())
+    assert np.abs(out.cpu().numpy() - o_out).max() <= 1e-9 * scale
+    assert np.linalg.norm(g - o_g) <= 1e-9 * np.linalg.norm(o_g)
+    assert abs(de0 - o_de0.mean()) <= 1e-9 * abs(o_de0.mean())
+    assert abs(np.dot(x.c, g) - 2.0 * mean) <= 1e-9 * abs(mean)
+    ctx.set_record_limit(max(1, st["n_records"] // 5))
+    try:
+        _, _, _, gc, de0c, stc = ctx.sample_grad(dets, c, x.e0, eps2, eps2_d, dr, "fp64")
+    finally:
+        ctx.set_record_limit(0)
+    assert stc["n_chunks"] >= 3
+    assert np.linalg.norm(gc.cpu().numpy() - g) <= 1e-12 * np.linalg.norm(g)
+    _, _, _, g32, _, _ = ctx.sample_grad(dets, c, x.e0, eps2, eps2_d, dr, "fp32c")
+    assert np.linalg.norm(g32.cpu().numpy() - o_g) <= 1e-6 * np.linalg.norm(o_g)
+
+
+def test_semistochastic_autograd():
+    x = I.small(10, 3, 3, 150, 3, 14)
+    ctx, dets, c = context(x)
+    rng = np.random.default_rng(19)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    draws = rng.choice(len(x.c), size=(4, 30), p=p).astype(np.uint32)
+    dr = torch.from_numpy(draws.view(np.int32)).cuda()
+    eps2, eps2_d = 1e-6, 1e-4
+    cc = c.clone().requires_grad_(True)
+    e0 = torch.tensor(x.e0, dtype=torch.float64, device="cuda", requires_grad=True)
+    E = P.pt2_semistochastic_energy(ctx, dets, cc, e0, eps2, eps2_d, dr)
+    E.backward()
+    od = ref.pt2_det(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2_d, grad=True)
+    o_out, o_g, o_de0 = ref.pt2_sample_grad(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2, eps2_d, draws)
+    assert abs(E.item() - (od.e2 + o_out.mean())) <= E2_TOL_FP64
+    want = od.grad + o_g
+    assert np.linalg.norm(cc.grad.cpu().numpy() - want) <= 1e-9 * np.linalg.norm(want)
+    assert abs(e0.grad.item() - (od.de2_de0 + o_de0.mean())) <= 1e-9 * abs(od.de2_de0 + o_de0.mean())

@@ -309,3 +309,38 @@ def test_terms_of_sources_match_full_enumeration():
     for r in map(tuple, keys):
         cnt[r] = cnt.get(r, 0) + 1
     assert all(cnt[tuple(k)] == n for k, n in zip(o.keys, o.counts))
+
+
+def test_stochastic_gradient_pins():
+    # derivative of the mean stochastic estimate at frozen draws, p and masks:
+    # Euler identity (degree-2 homogeneous in c), central differences of the
+    # frozen-mask estimator (exact for a quadratic up to rounding), and the
+    # E0 derivative against Richardson-extrapolated differences
+    x = I.small(8, 3, 2, 120, 3, 21)
+    rng = np.random.default_rng(8)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    draws = rng.choice(len(x.c), size=(5, 30), p=p).astype(np.uint32)
+    eps2, eps2_d = 1e-5, 1e-3
+    args = (8, 3, 2, x.h1, x.eri, x.dets)
+    out, grad, de0 = ref.pt2_sample_grad(*args, x.c, x.e0, eps2, eps2_d, draws)
+    assert np.allclose(out, ref.pt2_sample(*args, x.c, x.e0, eps2, eps2_d, draws), rtol=0, atol=1e-15)
+    mean = out.mean()
+    assert abs(np.dot(x.c, grad) - 2.0 * mean) <= 1e-12 * abs(mean)
+    for i in rng.choice(len(x.c), size=8, replace=False):
+        h = 1e-4 * abs(x.c[i])
+        cp, cm = x.c.copy(), x.c.copy()
+        cp[i] += h
+        cm[i] -= h
+        hp, hm = cp[i] - x.c[i], x.c[i] - cm[i]
+        fp = ref.pt2_sample_frozen(*args, cp, x.c, x.e0, eps2, eps2_d, draws).mean()
+        fm = ref.pt2_sample_frozen(*args, cm, x.c, x.e0, eps2, eps2_d, draws).mean()
+        fd = (fp - fm) / (hp + hm)
+        assert abs(fd - grad[i]) <= 1e-7 * max(np.abs(grad).max(), 1e-300)
+    # dS/dE0: Richardson on central differences
+    def s_at(e0):
+        return ref.pt2_sample(*args, x.c, e0, eps2, eps2_d, draws)
+    d1 = 1e-4
+    c1 = (s_at(x.e0 + d1) - s_at(x.e0 - d1)) / (2 * d1)
+    c2 = (s_at(x.e0 + d1 / 2) - s_at(x.e0 - d1 / 2)) / d1
+    rich = (4 * c2 - c1) / 3
+    assert np.abs(rich - de0).max() <= 1e-6 * np.abs(de0).max()

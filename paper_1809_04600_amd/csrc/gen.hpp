@@ -238,12 +238,20 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           const int64_t o = lookup_u<KW>(key, n, sid, a.L);
           if (o >= 0) {
             if constexpr (SAMPLE) {
-              // d/dc_i of the sample bracket over (X^2 + Y) - (X_d^2 + Y_d),
-              // frozen w, p and masks (stored factors: 2 X G, 2 X^d G, G)
+              // d/dc_i of the sample bracket (X^2 - Q + Z) - (X_d^2 - Q_d + Z_d)
+              // at frozen w, p and masks, in the same cancellation-free form
+              // as the forward: 2 (X - x_i) w H / p + 2 w (N_d - 1) / p c H^2,
+              // minus the same with X_d for terms above eps2_d (stored
+              // factors 2 X G, 2 X_d G and G; x_i rounded as stored)
               const double wh = w * H / pr;
-              const double q = 2.0 * (w * (a.nd - 1.0) / pr - w * w / (pr * pr)) * ci * H * H;
+              const double G = a.L.U.D[o];
               const bool dflag = fabs(H) * absc > a.eps2_d;
-              gacc += dflag ? (a.L.U.g[o] - a.L.U.A[o]) * wh : a.L.U.g[o] * wh + q * a.L.U.D[o];
+              if (dflag) {
+                gacc += (a.L.U.g[o] - a.L.U.A[o]) * wh;
+              } else {
+                const double xi = (double)(VT)(w * (ci * H) / pr);
+                gacc += (a.L.U.g[o] - 2.0 * xi * G) * wh + 2.0 * (w * (a.nd - 1.0) / pr) * ci * H * H * G;
+              }
             } else {
               gacc += H * a.L.U.g[o];
             }

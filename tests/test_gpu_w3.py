@@ -109,3 +109,23 @@ def test_w3_samples(w3):
     print(f"w3 samples fp32c: max |d| per sample {np.abs(out32 - out).max():.3e}, "
           f"|d mean| {abs(mean32 - mean):.3e}", flush=True)
     assert np.abs(out32 - out).max() <= 1e-6
+
+
+def test_w3_sample_adjoint_properties(w3):
+    # the stochastic adjoint at full size on 8 samples: Euler identity
+    # (degree-2 homogeneous at frozen draws, p and masks) and FP32c vs FP64
+    x, ctx, dets, c = w3
+    wl = x.wl
+    draws = _draws(x)[:8]
+    dr = torch.from_numpy(np.ascontiguousarray(draws).view(np.int32)).cuda()
+    out, mean, sem, g, de0, st = ctx.sample_grad(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp64")
+    g = g.cpu().numpy()
+    euler = float(np.dot(x.c, g))
+    print(f"w3 sample adjoint: mean {mean!r}, c.g/2 {euler / 2!r}, dE0 {de0!r}, stats {st}", flush=True)
+    assert abs(euler - 2.0 * mean) <= 1e-8 * max(abs(mean), 1e-12)
+    o8 = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp64")[0].cpu().numpy()
+    assert np.abs(out.cpu().numpy() - o8).max() <= 1e-12 * max(1.0, np.abs(o8).max())
+    _, _, _, g32, _, _ = ctx.sample_grad(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp32c")
+    rel = np.linalg.norm(g32.cpu().numpy() - g) / np.linalg.norm(g)
+    print(f"w3 sample adjoint fp32c rel diff {rel:.3e}", flush=True)
+    assert rel <= 1e-6

@@ -113,7 +113,8 @@ struct shci_pt2_ctx {
 
 namespace {
 
-constexpr int GEN_BLOCKS_PER_CU = 8;
+constexpr int GEN_BLOCKS_PER_CU = 32;  // many more blocks than resident: blocks that finish early are replaced
+constexpr int RED_BLOCKS_PER_CU = 8;
 
 int num_cus(int dev) {
   static int cus = 0;
@@ -542,7 +543,7 @@ int run_job(Job& J) {
       P->nzero = cv.take<int32_t>(nb);
       P->mind = cv.take<double>(nb);
       P->nseg = cv.take<int32_t>(nb);
-      const int64_t nw = (int64_t)cus * 8 * WRED_WAVES;
+      const int64_t nw = (int64_t)cus * RED_BLOCKS_PER_CU * WRED_WAVES;
       Pw->e2 = cv.take<double>(nw);
       Pw->de0 = cv.take<double>(nw);
       Pw->nterm = cv.take<int64_t>(nw);
@@ -662,7 +663,8 @@ int run_job(Job& J) {
     const size_t diag_bytes = (size_t)diag_table_doubles(n) * sizeof(double);
     const bool red_lds = sizeof(RedShared<KW, C, SAMPLE, VT>) + diag_bytes <= 160 * 1024;
     const bool wave_lds = sizeof(WaveStage) * WRED_WAVES + diag_bytes <= 160 * 1024;
-    const int64_t wblocks = std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * 8);
+    const int64_t wblocks =
+        std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * RED_BLOCKS_PER_CU);
     WaveRedArgs wa;
     wa.r = ra;
     wa.bstart = bst;
@@ -859,7 +861,7 @@ int64_t record_budget(shci_pt2_ctx* X, double per_rec) {
   }
   size_t avail = fr + X->big.cap;
   if (X->ws_limit) avail = std::min(avail, X->ws_limit);
-  const size_t reserve = (size_t)(num_cus(X->device) * 8 * WRED_WAVES + 1024) * 64 + (2u << 20);
+  const size_t reserve = (size_t)(num_cus(X->device) * RED_BLOCKS_PER_CU * WRED_WAVES + 1024) * 64 + (2u << 20);
   avail = avail > reserve ? avail - reserve : 0;
   const int64_t m = (int64_t)(0.75 * (double)avail / per_rec);
   return std::max<int64_t>(1, std::min<int64_t>(m, REC_CAP_AUTO));

@@ -300,16 +300,25 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // candidate j -> (spin, p, r); the division by the number of virtual
+      // orbitals goes through a float reciprocal with one integer correction
+      // (exact for j < 2^24)
+      const float inv_va = va ? 1.0f / (float)va : 0.0f, inv_vb = vb ? 1.0f / (float)vb : 0.0f;
       auto cand_of = [&](int j, bool& alpha, int& p, int& r) {
         alpha = j < nsa;
-        if (alpha) {
-          p = occA[j / va];
-          r = virA[j % va];
-        } else {
-          const int jj = j - nsa;
-          p = occB[jj / vb];
-          r = virB[jj % vb];
+        const int jj = alpha ? j : j - nsa;
+        const int d = alpha ? va : vb;
+        int q = (int)((float)jj * (alpha ? inv_va : inv_vb));
+        int rm = jj - q * d;
+        if (rm < 0) {
+          --q;
+          rm += d;
+        } else if (rm >= d) {
+          ++q;
+          rm -= d;
         }
+        p = alpha ? occA[q] : occB[q];
+        r = alpha ? virA[rm] : virB[rm];
       };
       // exact evaluation and emission of queue entries [0, cnt)
       auto process = [&](int cnt) {
@@ -415,6 +424,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     // are probed eight at a time (8 lanes each, first 8 entries); pairs whose
     // first 8 entries all pass are walked afterwards 64 entries at a time.
     const int caa = na * (na - 1) / 2, cbb = nb * (nb - 1) / 2;
+    const float inv_nb = nb ? 1.0f / (float)nb : 0.0f;
     auto decode = [&](int u, int& p, int& q, int& type, int64_t& off, int64_t& len) {
       if (u < caa) {
         const int y = tri_inv(u), x = u - y * (y - 1) / 2;
@@ -429,8 +439,17 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         type = 1;
       } else {
         const int v = u - caa - cbb;
-        p = occA[v / nb];
-        q = occB[v % nb];
+        int qa = (int)((float)v * inv_nb);
+        int rb = v - qa * nb;
+        if (rb < 0) {
+          --qa;
+          rb += nb;
+        } else if (rb >= nb) {
+          ++qa;
+          rb -= nb;
+        }
+        p = occA[qa];
+        q = occB[rb];
         type = 2;
       }
       if (type < 2) {

@@ -191,6 +191,58 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
                     const uint32_t* draws, int precision, void* stream, double* per_sample,
                     double* mean, double* sem, shci_pt2_stats* st);
 
+/* Stochastic part with one batch of P per sample (the stochastic step of the
+ * paper's 3-step method, section IV): sample s keeps only the a whose
+ * determinant hash h has h mod n_batches == sample_batch[s], and its estimate
+ * is multiplied by n_batches (unbiased over a uniform choice of batch).
+ *   n_batches     power of two in [1, 65536];
+ *   sample_batch  device int32 [n_samples], each in [0, n_batches) (random
+ *                 numbers of the method, passed in like the draws).
+ * Other arguments as shci_pt2_sample. */
+int shci_pt2_sample_batched(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                            double e0, double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
+                            const uint32_t* draws, int32_t n_batches, const int32_t* sample_batch,
+                            int precision, void* stream, double* per_sample, double* mean, double* sem,
+                            shci_pt2_stats* st);
+
+/* Per-batch statistics of the deterministic corrections (section IV): for
+ * each listed batch b (h mod n_batches == b, h the determinant hash), over
+ * the a outside V reached by a term with |H_ai c_i| > eps2,
+ *   e_a = (A_a(eps2)^2 - A_a(eps2_hi)^2) / (E0 - H_aa),
+ * A_a(e) the screened sum at threshold e (A_a(INFINITY) = 0, so eps2_hi =
+ * INFINITY gives the plain contributions).  out[k] = {sum e_a, sum e_a^2,
+ * number of a, number of kept terms}.  A batch whose records exceed the
+ * record budget fails with SHCI_ERR_WORKSPACE. */
+typedef struct {
+  double sum, sumsq;
+  int64_t n_unique, n_terms;
+} shci_pt2_batch;
+int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                         double e0, double eps2, double eps2_hi, int32_t n_batches, const int32_t* batches,
+                         int32_t n_list, int precision, void* stream, shci_pt2_batch* out,
+                         shci_pt2_stats* st);
+
+/* The paper's 3-step perturbative correction (3-step equation, section IV):
+ *   E2 = E2_dtm(eps2_dtm)
+ *      + [E2_psto(eps2_psto) - E2_psto(eps2_dtm)]   pseudo-stochastic: batches of
+ *        P (nb_psto) evaluated in order until the standard error of the sum
+ *        over the unevaluated determinants is below 40% of target_error
+ *      + mean_s [S_s(eps2) - S_s(eps2_psto)]        stochastic: one batch of P
+ *        (of nb_sto) per sample, as shci_pt2_sample_batched.
+ * err combines the pseudo-stochastic and stochastic standard errors. */
+typedef struct {
+  double e2, err;
+  double e2_dtm;
+  double e2_psto, err_psto;
+  int32_t psto_batches_used;
+  double e2_sto, err_sto;
+} shci_pt2_3step_result;
+int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
+                        double e0, double eps2_dtm, double eps2_psto, double eps2, double target_error,
+                        int32_t nb_psto, int32_t nb_sto, int32_t n_samples, int32_t n_draws,
+                        const uint32_t* draws, const int32_t* sample_batch, int precision, void* stream,
+                        double* per_sample, shci_pt2_3step_result* res);
+
 /* Adjoint of the stochastic part: the per-sample estimates of
  * shci_pt2_sample and the derivatives of their mean with respect to c and
  * E0, with the draws, p_i and the screening masks held at the forward point

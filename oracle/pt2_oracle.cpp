@@ -321,6 +321,32 @@ struct Result {
   std::vector<double> grad;
 };
 
+// Batch of a determinant for the hash-batch decomposition of P (section IV):
+// h mod n_batches, with h the 64-bit finaliser of MurmurHash3 (its published
+// constants) chained over the ceil(2n/64) words of alpha | beta << n, starting
+// from the first 64 bits of the fractional part of pi.  n_batches is a power
+// of two, so h mod n_batches is h & (n_batches - 1).
+static uint64_t murmur_fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+uint64_t batch_hash(const Det& d, int n) {
+  // bits of alpha | beta << n, word by word
+  uint64_t w[4] = {0, 0, 0, 0};
+  for (int p = 0; p < n; ++p) {
+    if (bit(&d.w[0], p)) w[p >> 6] |= 1ull << (p & 63);
+    if (bit(&d.w[2], p)) w[(n + p) >> 6] |= 1ull << ((n + p) & 63);
+  }
+  uint64_t h = 0x243f6a8885a308d3ull;
+  for (int j = 0; j < (2 * n + 63) / 64; ++j) h = murmur_fmix64(h ^ w[j]);
+  return h;
+}
+
 void collect_terms(const System& S, const Det* dets, const double* c, int64_t nd, double eps2,
                    std::vector<Term>& out) {
   int nt = omp_get_max_threads();
@@ -617,6 +643,51 @@ int64_t oracle_terms_of(int n, int na, int nb, const double* h1, const double* e
   return o;
 }
 
+// Per-batch statistics of e_a = (A_a(eps2)^2 - A_a(eps2_hi)^2) / (E0 - H_aa)
+// over the a outside V of batch `batch` (of n_batches), reached by a term
+// with |H_ai c_i| > eps2; A_a(e) sums the terms above e (none when e is
+// infinite).  out = {sum e_a, sum e_a^2}; counts = {number of a, kept terms}.
+int oracle_det_batch(int n, int na, int nb, const double* h1, const double* eri, const uint64_t* dets,
+                     const double* c, int64_t nd, double e0, double eps2, double eps2_hi, int32_t n_batches,
+                     int32_t batch, double* out, int64_t* counts) {
+  System S{n, na, nb, h1, eri};
+  const Det* V = reinterpret_cast<const Det*>(dets);
+  int st = validate(S, V, c, nd);
+  if (st) return st;
+  std::unordered_set<Det, DetHash> Vset(V, V + nd);
+  std::vector<Term> terms;
+  collect_terms(S, V, c, nd, eps2, terms);
+  Neumaier sum, sq;
+  int64_t nu = 0, nt = 0;
+  size_t k = 0;
+  while (k < terms.size()) {
+    size_t j = k;
+    while (j < terms.size() && terms[j].a == terms[k].a) ++j;
+    const Det& a = terms[k].a;
+    if (!Vset.count(a) && (int64_t)(batch_hash(a, n) & (uint64_t)(n_batches - 1)) == batch) {
+      Neumaier A, Ah;
+      for (size_t m = k; m < j; ++m) {
+        const double t = terms[m].h * c[terms[m].i];
+        A.add(t);
+        if (kept(terms[m].h, c[terms[m].i], eps2_hi)) Ah.add(t);
+      }
+      const double Av = A.value(), Ahv = Ah.value();
+      const double D = e0 - diag_value(S, a);
+      const double e = (Av * Av - Ahv * Ahv) / D;
+      sum.add(e);
+      sq.add(e * e);
+      ++nu;
+      nt += (int64_t)(j - k);
+    }
+    k = j;
+  }
+  out[0] = sum.value();
+  out[1] = sq.value();
+  counts[0] = nu;
+  counts[1] = nt;
+  return 0;
+}
+
 // Stochastic estimator on explicit draws (stochastic PT2 equation).  draws is
 // [ns][ndraw] indices into V; out[s] = S_s(eps2) - S_s(eps2_d), where
 // S_s(e) = sum_{a not in V} [ (sum_i w_i c_i H_ai / p_i)^2
@@ -635,7 +706,8 @@ int64_t oracle_terms_of(int n, int na, int nb, const double* h1, const double* e
 // and per sample de0[s] = dS_s/dE0 = -sum_a [...] / ((E0 - H_aa)^2 Nd (Nd-1)).
 static int sample_core(const System& S, const Det* V, int64_t nd, const double* c, const double* c_ref,
                        double e0, double eps2, double eps2_d, int32_t ns, int32_t ndraw,
-                       const uint32_t* draws, double* out, double* grad, double* de0) {
+                       const uint32_t* draws, double* out, double* grad, double* de0,
+                       int32_t n_batches = 1, const int32_t* sbatch = nullptr) {
   int st = validate(S, V, c_ref, nd);
   if (st) return st;
   if (ndraw < 2 || ns < 1 || !(eps2 >= 0.0) || !(eps2_d >= eps2)) {
@@ -689,6 +761,7 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
       // not depend on c); values with c
       for_each_excitation(S, V[i], [&](const Det& a, double hval) {
         if (!kept(hval, cr, eps2)) return;
+        if (n_batches > 1 && (int64_t)(batch_hash(a, S.n) & (uint64_t)(n_batches - 1)) != sbatch[s]) return;
         double ch = ci * hval;
         double f = w * (Nd - 1.0) / p - w * w / (p * p);
         double x = w * ch / p;
@@ -752,8 +825,9 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
       dtot.add(dpart[t].s);
       dtot.add(dpart[t].c);
     }
-    out[s] = tot.value();
-    if (de0) de0[s] = dtot.value();
+    // one batch of P per sample: the estimate is scaled by the number of batches
+    out[s] = (double)n_batches * tot.value();
+    if (de0) de0[s] = (double)n_batches * dtot.value();
     if (grad) {
       // terms in (a, i) order; per source i the sum runs in that order
       for (int64_t g = 0; g < ngroups; ++g) {
@@ -778,6 +852,18 @@ int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri
   System S{n, na, nb, h1, eri};
   return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c, e0, eps2, eps2_d, ns, ndraw, draws,
                      out, nullptr, nullptr);
+}
+
+// The estimator with one batch of P per sample: sample s keeps the a with
+// batch_hash(a) mod n_batches == sbatch[s]; its estimate is multiplied by
+// n_batches (stochastic step of the 3-step method, section IV).
+int oracle_pt2_sample_batched(int n, int na, int nb, const double* h1, const double* eri,
+                              const uint64_t* dets, const double* c, int64_t nd, double e0, double eps2,
+                              double eps2_d, int32_t ns, int32_t ndraw, const uint32_t* draws,
+                              int32_t n_batches, const int32_t* sbatch, double* out) {
+  System S{n, na, nb, h1, eri};
+  return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c, e0, eps2, eps2_d, ns, ndraw, draws,
+                     out, nullptr, nullptr, n_batches, sbatch);
 }
 
 // The estimator with p_i and the screening frozen at c_ref and values at c.

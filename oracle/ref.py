@@ -57,6 +57,11 @@ def lib():
         L.oracle_pt2_sample.restype = _i
         L.oracle_pt2_sample.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d,
                                         C.c_int32, C.c_int32, _p, _p]
+        L.oracle_det_batch.restype = _i
+        L.oracle_det_batch.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d, _i, _i, _p, _p]
+        L.oracle_pt2_sample_batched.restype = _i
+        L.oracle_pt2_sample_batched.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d, _i, _i,
+                                                _p, _i, _p, _p]
         L.oracle_pt2_sample_frozen.restype = _i
         L.oracle_pt2_sample_frozen.argtypes = [_i, _i, _i, _p, _p, _p, _p, _p, _i64, _d, _d, _d,
                                                _i, _i, _p, _p]
@@ -206,6 +211,40 @@ def pt2_sample(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
     L = lib()
     st = L.oracle_pt2_sample(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
                              float(e0), float(eps2), float(eps2_d), ns, nd, _ptr(draws), _ptr(out))
+    if st:
+        raise OracleError(st, L.oracle_last_error().decode())
+    return out
+
+
+def det_batch(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_hi, n_batches, batch):
+    """(sum e_a, sum e_a^2, number of a, kept terms) over the a of one hash
+    batch, e_a = (A_a(eps2)^2 - A_a(eps2_hi)^2) / D_a."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.zeros(2)
+    cnt = np.zeros(2, dtype=np.int64)
+    L = lib()
+    st = L.oracle_det_batch(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c), float(e0),
+                            float(eps2), float(eps2_hi), int(n_batches), int(batch), _ptr(out), _ptr(cnt))
+    if st:
+        raise OracleError(st, L.oracle_last_error().decode())
+    return out[0], out[1], int(cnt[0]), int(cnt[1])
+
+
+def pt2_sample_batched(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws, n_batches, sample_batch):
+    """Per-sample estimates keeping one hash batch of P per sample, times n_batches."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    draws = np.ascontiguousarray(draws, dtype=np.uint32)
+    sb = np.ascontiguousarray(sample_batch, dtype=np.int32)
+    ns, nd = draws.shape
+    out = np.zeros(ns)
+    L = lib()
+    st = L.oracle_pt2_sample_batched(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
+                                     float(e0), float(eps2), float(eps2_d), ns, nd, _ptr(draws),
+                                     int(n_batches), _ptr(sb), _ptr(out))
     if st:
         raise OracleError(st, L.oracle_last_error().decode())
     return out

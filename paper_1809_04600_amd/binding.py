@@ -53,6 +53,19 @@ class Export(C.Structure):
                 ("t_cap", C.c_int64), ("t_n", C.c_int64)]
 
 
+class Batch(C.Structure):
+    _fields_ = [("sum", C.c_double), ("sumsq", C.c_double), ("n_unique", C.c_int64), ("n_terms", C.c_int64)]
+
+
+class ThreeStep(C.Structure):
+    _fields_ = [("e2", C.c_double), ("err", C.c_double), ("e2_dtm", C.c_double), ("e2_psto", C.c_double),
+                ("err_psto", C.c_double), ("psto_batches_used", C.c_int32), ("e2_sto", C.c_double),
+                ("err_sto", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -83,6 +96,15 @@ def lib():
         L.shci_pt2_sample_grad.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, i, p, p,
                                            C.POINTER(d), C.POINTER(d), p, C.POINTER(d), C.POINTER(Stats)]
         L.shci_pt2_sample_grad.restype = i
+        L.shci_pt2_sample_batched.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, C.c_int32, p,
+                                              i, p, p, C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
+        L.shci_pt2_sample_batched.restype = i
+        L.shci_pt2_det_batches.argtypes = [p, p, p, i64, d, d, d, C.c_int32, p, C.c_int32, i, p, p,
+                                           C.POINTER(Stats)]
+        L.shci_pt2_det_batches.restype = i
+        L.shci_pt2_three_step.argtypes = [p, p, p, i64, d, d, d, d, d, C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_int32, p, p, i, p, p, C.POINTER(ThreeStep)]
+        L.shci_pt2_three_step.restype = i
         L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), p, C.POINTER(d),
                                     C.POINTER(Stats)]
         L.shci_pt2_grad.restype = i
@@ -221,6 +243,49 @@ class Context:
                                      C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
                                      C.byref(st)))
         return out, mean.value, sem.value, st.as_dict()
+
+    def sample_batched(self, dets, c, e0, eps2, eps2_d, draws, n_batches, sample_batch, precision="fp64"):
+        """Stochastic estimates keeping one hash batch of P per sample (times n_batches)."""
+        pd, pc, nd = self._inputs(dets, c)
+        ns, ndraw = draws.shape
+        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
+        psb = _dev(sample_batch, torch.int32, (ns,), "sample_batch")
+        out = torch.empty(ns, dtype=torch.float64, device=c.device)
+        mean = C.c_double()
+        sem = C.c_double()
+        st = Stats()
+        _check(lib().shci_pt2_sample_batched(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_d),
+                                             ns, ndraw, pdr, int(n_batches), psb, _PREC[precision],
+                                             _stream(), C.c_void_p(out.data_ptr()), C.byref(mean),
+                                             C.byref(sem), C.byref(st)))
+        return out, mean.value, sem.value, st.as_dict()
+
+    def det_batches(self, dets, c, e0, eps2, eps2_hi, n_batches, batches, precision="fp64"):
+        """Per-batch (sum, sum of squares, count of a, kept terms) of
+        e_a = (A_a(eps2)^2 - A_a(eps2_hi)^2) / D_a for the listed hash batches."""
+        pd, pc, nd = self._inputs(dets, c)
+        bl = (C.c_int32 * len(batches))(*[int(b) for b in batches])
+        out = (Batch * len(batches))()
+        st = Stats()
+        _check(lib().shci_pt2_det_batches(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_hi),
+                                          int(n_batches), bl, len(batches), _PREC[precision], _stream(), out,
+                                          C.byref(st)))
+        return [(o.sum, o.sumsq, o.n_unique, o.n_terms) for o in out], st.as_dict()
+
+    def three_step(self, dets, c, e0, eps2_dtm, eps2_psto, eps2, target_error, nb_psto, nb_sto, draws,
+                   sample_batch, precision="fp64"):
+        """The 3-step correction; returns (result dict, per-sample tensor)."""
+        pd, pc, nd = self._inputs(dets, c)
+        ns, ndraw = draws.shape
+        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
+        psb = _dev(sample_batch, torch.int32, (ns,), "sample_batch")
+        out = torch.empty(ns, dtype=torch.float64, device=c.device)
+        res = ThreeStep()
+        _check(lib().shci_pt2_three_step(self._ptr, pd, pc, nd, float(e0), float(eps2_dtm), float(eps2_psto),
+                                         float(eps2), float(target_error), int(nb_psto), int(nb_sto), ns, ndraw,
+                                         pdr, psb, _PREC[precision], _stream(), C.c_void_p(out.data_ptr()),
+                                         C.byref(res)))
+        return res.as_dict(), out
 
     def sample_grad(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64"):
         """Per-sample estimates and the adjoint of their mean: returns

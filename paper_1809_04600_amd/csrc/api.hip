@@ -142,6 +142,7 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 __global__ void k_zero_result(DevResult* r) {
   r->e2 = 0.0;
   r->de0 = 0.0;
+  r->e2sq = 0.0;
   r->mind = INFINITY;
   r->nterm = r->ngen = r->nuniq = r->nintr = r->nzero = 0;
   r->overflow = 0;
@@ -332,7 +333,9 @@ struct Job {
   const uint64_t* samp_off = nullptr;  // host [nsamp + 1]: item range of each sample of the chunk
   double grad_scale = 1.0;             // sample mode: weight of this chunk's adjoint
   int64_t max_records = 0;       // > 0: give up after the count pass if exceeded
-  uint32_t bmask = 0, bsel = 0;  // hash batch of a (deterministic mode)
+  uint32_t bmask = 0, bsel = 0;  // hash batch of a
+  const int32_t* sbatch = nullptr;  // device: batch of each sample of the chunk (sample mode)
+  double sample_scale = 1.0;        // factor on every per-sample result (number of batches)
   bool grad_accumulate = false;  // add this batch's adjoint to grad
   double* grad = nullptr;        // device [ndet]
   shci_pt2_export* ex = nullptr;
@@ -476,6 +479,7 @@ int run_job(Job& J) {
   g.auxbit = auxbit;
   g.bmask = J.bmask;
   g.bsel = J.bsel;
+  g.sbatch = J.sbatch;
   g.ref = J.dets;
   g.Fref = T.fref;
   g.smarg = 8.0 * (2 * n + 2 + 2 * DL_CAP) * 0x1p-53;
@@ -536,6 +540,7 @@ int run_job(Job& J) {
       const int64_t nb = G.nbucket;
       P->e2 = cv.take<double>(nb);
       P->de0 = cv.take<double>(nb);
+      P->e2sq = cv.take<double>(nb);
       P->nterm = cv.take<int64_t>(nb);
       P->ngen = cv.take<int64_t>(nb);
       P->nuniq = cv.take<int32_t>(nb);
@@ -546,6 +551,7 @@ int run_job(Job& J) {
       const int64_t nw = (int64_t)cus * RED_BLOCKS_PER_CU * WRED_WAVES;
       Pw->e2 = cv.take<double>(nw);
       Pw->de0 = cv.take<double>(nw);
+      Pw->e2sq = cv.take<double>(nw);
       Pw->nterm = cv.take<int64_t>(nw);
       Pw->ngen = cv.take<int64_t>(nw);
       Pw->nuniq = cv.take<int32_t>(nw);
@@ -554,6 +560,7 @@ int run_job(Job& J) {
       Pw->mind = cv.take<double>(nw);
       Pq->e2 = cv.take<double>(1024);
       Pq->de0 = cv.take<double>(1024);
+      Pq->e2sq = cv.take<double>(1024);
       Pq->nterm = cv.take<int64_t>(1024);
       Pq->ngen = cv.take<int64_t>(1024);
       Pq->nuniq = cv.take<int32_t>(1024);
@@ -701,7 +708,7 @@ int run_job(Job& J) {
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
     if (SAMPLE) {
       k_final<<<J.nsamp, 1024, 0, st>>>(P, G.nbucket, 0, J.nsamp, overflow, dflag, X->dres, J.per_sample,
-                                         (int64_t)1 << G.bits_hash, J.per_sample_de0);
+                                         (int64_t)1 << G.bits_hash, J.per_sample_de0, J.sample_scale);
     } else {
       // bucket partials (only the block kernel's buckets are non-zero) and
       // per-wavefront partials, summed in a fixed order
@@ -711,11 +718,12 @@ int run_job(Job& J) {
       const int64_t wchunk = std::max<int64_t>(256, (nwv + 511) / 512);
       const int64_t wfblocks = (nwv + wchunk - 1) / wchunk;
       Partials Q = Pq, Q2 = Pq;
-      Q2.e2 += fblocks; Q2.de0 += fblocks; Q2.nterm += fblocks; Q2.ngen += fblocks;
+      Q2.e2 += fblocks; Q2.de0 += fblocks; Q2.e2sq += fblocks; Q2.nterm += fblocks; Q2.ngen += fblocks;
       Q2.nuniq += fblocks; Q2.nintr += fblocks; Q2.nzero += fblocks; Q2.mind += fblocks;
       k_final_partial<<<(int)fblocks, 256, 0, st>>>(P, G.nbucket, fchunk, Q);
       k_final_partial<<<(int)wfblocks, 256, 0, st>>>(Pw, nwv, wchunk, Q2);
-      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0, nullptr);
+      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0, nullptr,
+                                   1.0);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(X->ev[3], st));
@@ -1122,12 +1130,23 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
 static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                        double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
                        int precision, void* stream, double* per_sample, double* mean, double* sem,
-                       shci_pt2_stats* st, double* grad, double* de2_de0) {
+                       shci_pt2_stats* st, double* grad, double* de2_de0, int32_t n_batches = 1,
+                       const int32_t* sample_batch = nullptr) {
   CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
   if (!draws || !per_sample) return fail(SHCI_ERR_ARG, "draws or per_sample is NULL");
   if (n_samples < 1 || n_draws < 2) return fail(SHCI_ERR_ARG, "need n_samples >= 1 and n_draws >= 2");
   if (n_draws > MAX_DRAWS) return fail(SHCI_ERR_ARG, "n_draws must be <= %d", MAX_DRAWS);
   if (!(eps2_d >= eps2)) return fail(SHCI_ERR_ARG, "eps2_d must be >= eps2");
+  if (n_batches < 1 || n_batches > 65536 || (n_batches & (n_batches - 1)))
+    return fail(SHCI_ERR_ARG, "n_batches must be a power of two in [1, 65536]");
+  if (n_batches > 1) {
+    if (!sample_batch) return fail(SHCI_ERR_ARG, "sample_batch is NULL");
+    std::vector<int32_t> hb(n_samples);
+    if (hipMemcpy(hb.data(), sample_batch, n_samples * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(SHCI_ERR_HIP, "copy of sample_batch failed");
+    for (int32_t v : hb)
+      if (v < 0 || v >= n_batches) return fail(SHCI_ERR_ARG, "sample_batch entries must lie in [0, n_batches)");
+  }
   const int sbits = std::max(1, ceil_log2((uint64_t)n_samples));
   if (2 * ctx->T.n + sbits + 1 > 256) return fail(SHCI_ERR_NORB, "too many samples for this n_orb");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1235,10 +1254,16 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
     J.per_sample_de0 = psde0 + s0;
     J.max_records = max_rec;
     J.samp_off = hoff.data() + s0;
+    if (n_batches > 1) {
+      // one batch of P per sample, the estimate scaled by the number of batches
+      J.bmask = (uint32_t)(n_batches - 1);
+      J.sbatch = sample_batch + s0;
+      J.sample_scale = (double)n_batches;
+    }
     if (grad) {
       J.want_u = true;
       J.grad = grad;
-      J.grad_scale = 1.0 / (double)n_samples;
+      J.grad_scale = (double)n_batches / (double)n_samples;
     }
     int r = dispatch(J);
     if (r == JOB_TOO_BIG) {
@@ -1314,6 +1339,135 @@ int shci_pt2_sample_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* 
   if (!de2_dc) return fail(SHCI_ERR_ARG, "de2_dc is NULL");
   return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
                      per_sample, mean, sem, st, de2_dc, de2_de0);
+}
+
+int shci_pt2_sample_batched(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                            double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
+                            const uint32_t* draws, int32_t n_batches, const int32_t* sample_batch, int precision,
+                            void* stream, double* per_sample, double* mean, double* sem, shci_pt2_stats* st) {
+  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
+                     per_sample, mean, sem, st, nullptr, nullptr, n_batches, sample_batch);
+}
+
+int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                         double eps2, double eps2_hi, int32_t n_batches, const int32_t* batches, int32_t n_list,
+                         int precision, void* stream, shci_pt2_batch* out, shci_pt2_stats* st) {
+  CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  if (!batches || !out || n_list < 1) return fail(SHCI_ERR_ARG, "batches and out must be non-NULL, n_list >= 1");
+  if (n_batches < 1 || n_batches > 65536 || (n_batches & (n_batches - 1)))
+    return fail(SHCI_ERR_ARG, "n_batches must be a power of two in [1, 65536]");
+  if (!(eps2_hi >= eps2)) return fail(SHCI_ERR_ARG, "eps2_hi must be >= eps2 (INFINITY for one threshold)");
+  for (int32_t k = 0; k < n_list; ++k)
+    if (batches[k] < 0 || batches[k] >= n_batches) return fail(SHCI_ERR_ARG, "batch index out of range");
+  Job proto{};
+  proto.ctx = ctx;
+  proto.st = static_cast<hipStream_t>(stream);
+  proto.dets = dets;
+  proto.c = c;
+  proto.ndet = n_det;
+  proto.e0 = e0;
+  proto.eps2 = eps2;
+  proto.eps2_d = eps2_hi;
+  proto.precision = precision;
+  proto.sample = false;
+  proto.sbits = 0;
+  proto.nsamp = 1;
+  proto.n_items = n_det;
+  const int kw = key_words(ctx->T.n, 0);
+  proto.max_records = record_budget(ctx, record_bytes(kw, precision == SHCI_FP32C ? 4 : 8, false, false));
+  Job acc{};
+  acc.res.mind = INFINITY;
+  for (int32_t k = 0; k < n_list; ++k) {
+    Job J = proto;
+    J.bmask = (uint32_t)(n_batches - 1);
+    J.bsel = (uint32_t)batches[k];
+    const int r = dispatch(J);
+    if (r == JOB_TOO_BIG)
+      return fail(SHCI_ERR_WORKSPACE, "batch %d has %lld terms, above the record budget; use more batches",
+                  batches[k], (long long)J.nrec);
+    if (r) return r;
+    out[k].sum = J.res.e2;
+    out[k].sumsq = J.res.e2sq;
+    out[k].n_unique = J.res.nuniq;
+    out[k].n_terms = J.res.nterm;
+    acc.res.nterm += J.res.nterm;
+    acc.res.ngen += J.res.ngen;
+    acc.res.nuniq += J.res.nuniq;
+    acc.res.nintr += J.res.nintr;
+    acc.res.nzero += J.res.nzero;
+    acc.res.mind = std::min(acc.res.mind, J.res.mind);
+    acc.nbucket = std::max(acc.nbucket, J.nbucket);
+    acc.ms_gen += J.ms_gen;
+    acc.ms_sort += J.ms_sort;
+    acc.ms_reduce += J.ms_reduce;
+    acc.ms_k_count += J.ms_k_count;
+    acc.ms_k_write += J.ms_k_write;
+    acc.ms_k_reduce += J.ms_k_reduce;
+    acc.nrec += J.nrec;
+    acc.kw = J.kw;
+    acc.vbytes = J.vbytes;
+  }
+  acc.nbatch = n_list;
+  fill_stats(st, acc, acc.ms_gen + acc.ms_sort + acc.ms_reduce);
+  if (acc.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                                 (long long)acc.res.nzero);
+  return SHCI_OK;
+}
+
+int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                        double eps2_dtm, double eps2_psto, double eps2, double target_error, int32_t nb_psto,
+                        int32_t nb_sto, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
+                        const int32_t* sample_batch, int precision, void* stream, double* per_sample,
+                        shci_pt2_3step_result* res) {
+  if (!res || !per_sample) return fail(SHCI_ERR_ARG, "res and per_sample must be non-NULL");
+  if (!(eps2 <= eps2_psto && eps2_psto <= eps2_dtm)) return fail(SHCI_ERR_ARG, "need eps2 <= eps2_psto <= eps2_dtm");
+  if (!(target_error > 0.0)) return fail(SHCI_ERR_ARG, "target_error must be > 0");
+  *res = shci_pt2_3step_result{};
+  // 1. deterministic step at eps2_dtm, every batch of P (hash batches when
+  //    the records do not fit)
+  CHK(shci_pt2_det(ctx, dets, c, n_det, e0, eps2_dtm, precision, stream, &res->e2_dtm, nullptr, nullptr));
+  // 2. pseudo-stochastic step: batches of P in order; per batch the
+  //    corrections (A(eps2_psto)^2 - A(eps2_dtm)^2) / D of its unique a.  The
+  //    total is estimated from the evaluated a; its standard error is that of
+  //    the sum over the a not yet evaluated.  Stop below 40% of the target.
+  double S = 0.0, SS = 0.0;
+  int64_t nev = 0;
+  int32_t b = 0;
+  double est = 0.0, sig = 0.0;
+  for (; b < nb_psto;) {
+    shci_pt2_batch o{};
+    const int32_t idx = b;
+    CHK(shci_pt2_det_batches(ctx, dets, c, n_det, e0, eps2_psto, eps2_dtm, nb_psto, &idx, 1, precision, stream,
+                             &o, nullptr));
+    ++b;
+    S += o.sum;
+    SS += o.sumsq;
+    nev += o.n_unique;
+    if (b == nb_psto || nev == 0) {
+      est = S * (double)nb_psto / (double)b;
+      sig = 0.0;
+      if (b == nb_psto) break;
+      continue;
+    }
+    const double mean = S / (double)nev;
+    const double var = std::max(0.0, SS / (double)nev - mean * mean);
+    const double nrest = (double)nev * ((double)nb_psto / (double)b - 1.0);
+    est = S + nrest * mean;
+    sig = std::sqrt(nrest * var);
+    if (sig < 0.4 * target_error) break;
+  }
+  res->e2_psto = est;
+  res->err_psto = sig;
+  res->psto_batches_used = b;
+  // 3. stochastic step: samples of V, one random batch of P per sample
+  double mean = 0.0, sem = 0.0;
+  CHK(shci_pt2_sample_batched(ctx, dets, c, n_det, e0, eps2, eps2_psto, n_samples, n_draws, draws, nb_sto,
+                              sample_batch, precision, stream, per_sample, &mean, &sem, nullptr));
+  res->e2_sto = mean;
+  res->err_sto = sem;
+  res->e2 = res->e2_dtm + res->e2_psto + res->e2_sto;
+  res->err = std::sqrt(res->err_psto * res->err_psto + res->err_sto * res->err_sto);
+  return SHCI_OK;
 }
 
 }  // extern "C"

@@ -131,15 +131,21 @@ SHCI_HD void mask_det(uint64_t (&k)[KW], int n) {
   }
 }
 
-// Hash of the determinant a record key holds (sample id and flag excluded).
-// Buckets, in-bucket order and the V lookup all use it.
+// Hash of the determinant a key holds: the chained finaliser over the
+// ceil(2n/64) words of alpha | beta << n (sample id and flag excluded), so the
+// value depends on the determinant and n only, not on the key width.
+// Buckets, in-bucket order, the V lookup and the hash batches of P all use it.
 template <int KW>
 SHCI_HD uint64_t det_hash(const uint64_t (&k)[KW], int n) {
   uint64_t m[KW];
 #pragma unroll
   for (int j = 0; j < KW; ++j) m[j] = k[j];
   mask_det<KW>(m, n);
-  return hash_key<KW>(m);
+  const int dw = (2 * n + 63) >> 6;
+  uint64_t h = 0x243f6a8885a308d3ull;
+#pragma unroll
+  for (int j = 0; j < KW; ++j) h = (j < dw) ? fmix64(h ^ m[j]) : h;
+  return h;
 }
 
 // mask of the grouping bits (everything below the auxiliary flag)

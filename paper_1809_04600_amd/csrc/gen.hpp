@@ -62,6 +62,7 @@ struct GenArgs {
   uint32_t* counter;
   int sbits, auxbit;
   uint32_t bmask, bsel;    // hash batch: keep a only if (hash(a) & bmask) == bsel
+  const int32_t* sbatch;   // sample mode, nullable: batch of each sample (replaces bsel)
   int bits_hash;           // bucket id = top bits_hash bits of the key hash | sample id above
   // singles prefilter: Fock-like elements of a reference determinant R,
   // Fref[s][p][r] = h_pr + sum_{k in R_s, k != p} sD[k][p][r] + sum_{k in R_s'} sJ[k][p][r]
@@ -190,7 +191,8 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         if (keep) {
           uint64_t hk[KW];
           pack_det<KW>(hk, x0, x1, y0, y1, n);
-          keep = ((uint32_t)hash_key<KW>(hk) & a.bmask) == a.bsel;
+          const uint32_t want = (SAMPLE && a.sbatch) ? (uint32_t)a.sbatch[sid] : a.bsel;
+          keep = ((uint32_t)det_hash<KW>(hk, n) & a.bmask) == want;
         }
       }
       const uint64_t bal = ballot(keep);
@@ -203,7 +205,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           const uint64_t pos = obase + cursor + (uint64_t)rank_below(bal);
           {
             // bucket id: top hash bits of the determinant, sample id above
-            const uint64_t h = hash_key<KW>(key);
+            const uint64_t h = det_hash<KW>(key, n);
             uint32_t b = a.bits_hash ? (uint32_t)(h >> (64 - a.bits_hash)) : 0u;
             if constexpr (SAMPLE) b |= sid << a.bits_hash;
             a.out.bid[pos] = b;
@@ -218,6 +220,9 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
             static_cast<VT*>(a.out.v)[pos] = (VT)xv;
             static_cast<VT*>(a.out.v2)[pos] = (VT)zv;
           } else {
+            // flag: the term also passes the upper threshold of a
+            // two-threshold evaluation (eps2_d is infinite otherwise)
+            if (fabs(H) * absc > a.eps2_d) put_bits<KW>(key, 1ull, 0ull, a.auxbit);
             VT t;
             if constexpr (sizeof(VT) == 4)
               t = (float)H * (float)ci;

@@ -37,11 +37,16 @@ template <typename VT>
 struct SegSum {
   double X = 0.0, Q = 0.0, Z = 0.0, Xd = 0.0, Qd = 0.0, Zd = 0.0;
   float xs = 0.f, xc = 0.f, zs = 0.f, zc = 0.f, xds = 0.f, xdc = 0.f, zds = 0.f, zdc = 0.f;
-  SHCI_DEV void add(VT x) {
-    if constexpr (sizeof(VT) == 4)
+  // deterministic term; d: the term also passes the upper threshold of a
+  // two-threshold evaluation (its sum is X_d)
+  SHCI_DEV void add(VT x, bool d) {
+    if constexpr (sizeof(VT) == 4) {
       two_sum_f32(xs, xc, (float)x);
-    else
+      if (d) two_sum_f32(xds, xdc, (float)x);
+    } else {
       X = X + (double)x;
+      if (d) Xd = Xd + (double)x;
+    }
   }
   SHCI_DEV void add_sample(VT x, VT z, bool d) {
     const double xq = (double)x * (double)x;
@@ -358,7 +363,7 @@ SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h
 
 template <int KW>
 SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
-  return vset_contains_h<KW>(V, k, hash_key<KW>(k), n);
+  return vset_contains_h<KW>(V, k, det_hash<KW>(k, n), n);
 }
 
 template <int KW>
@@ -367,7 +372,7 @@ __global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
   if (i >= nd) return;
   uint64_t k[KW];
   pack_det<KW>(k, V.dets[4 * i], V.dets[4 * i + 1], V.dets[4 * i + 2], V.dets[4 * i + 3], n);
-  const uint64_t h = hash_key<KW>(k);
+  const uint64_t h = det_hash<KW>(k, n);
   const uint32_t fp = (uint32_t)(h >> 32);
   const uint64_t entry = ((uint64_t)fp << 32) | (uint64_t)i;
   const uint64_t fb = h >> (64 - V.fbits);
@@ -438,6 +443,7 @@ struct RedShared {
   uint32_t scan[256];
   double red[256];
   double red2[256];
+  double red3[256];
   int64_t ired[256];
   int64_t ired2[256];
   int32_t ired3[256];
@@ -501,6 +507,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
         atomicOr(a.overflow, 1u);
         a.P.e2[b] = 0.0;
         a.P.de0[b] = 0.0;
+        a.P.e2sq[b] = 0.0;
         a.P.nterm[b] = 0;
         a.P.ngen[b] = 0;
         a.P.nuniq[b] = 0;
@@ -619,7 +626,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
     if (t == 0) R.seg[nsg] = (uint16_t)M;
     __syncthreads();
 
-    double e2p = 0.0, de0p = 0.0, dmn = INFINITY;
+    double e2p = 0.0, de0p = 0.0, e2sq = 0.0, dmn = INFINITY;
     int64_t nterm = 0, ngen = 0;
     int32_t nuniq = 0, nintr = 0, nzero = 0;
     for (uint32_t s = t; s < nsg; s += 256) {
@@ -628,10 +635,11 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       SegSum<VT> sum;
       for (int j = j0; j < j1; ++j) {
         const int id = R.sb.ia[j];
+        const bool dflag = (R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull;
         if constexpr (SAMPLE)
-          sum.add_sample(R.v[id], R.v2[id], (R.key[a.auxbit >> 6][id] >> (a.auxbit & 63)) & 1ull);
+          sum.add_sample(R.v[id], R.v2[id], dflag);
         else
-          sum.add(R.v[id]);
+          sum.add(R.v[id], dflag);
       }
       sum.finish();
       const double X = sum.X;
@@ -659,11 +667,13 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
           gd = 2.0 * sum.Xd * G;
           gG = G;
         } else {
-          contrib = X * X / Dd;
-          de0p += -(X * X) / (Dd * Dd);
+          const double a2 = X * X - sum.Xd * sum.Xd;  // see k_reduce_wave
+          contrib = a2 / Dd;
+          de0p += -a2 / (Dd * Dd);
           g = 2.0 * X / Dd;
         }
         e2p += contrib;
+        e2sq += contrib * contrib;
         nterm += cntk;
         nuniq += 1;
         nintr += Dd > 0.0;
@@ -686,6 +696,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
     // fixed-shape block reductions
     R.red[t] = e2p;
     R.red2[t] = de0p;
+    R.red3[t] = e2sq;
     R.ired[t] = nterm;
     R.ired2[t] = ngen;
     R.ired3[t] = nuniq;
@@ -697,6 +708,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       if (t < o) {
         R.red[t] += R.red[t + o];
         R.red2[t] += R.red2[t + o];
+        R.red3[t] += R.red3[t + o];
         R.ired[t] += R.ired[t + o];
         R.ired2[t] += R.ired2[t + o];
         R.ired3[t] += R.ired3[t + o];
@@ -709,6 +721,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
     if (t == 0) {
       a.P.e2[b] = R.red[0];
       a.P.de0[b] = R.red2[0];
+      a.P.e2sq[b] = R.red3[0];
       a.P.nterm[b] = R.ired[0];
       a.P.ngen[b] = R.ired2[0];
       a.P.nuniq[b] = R.ired3[0];
@@ -728,15 +741,16 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
 // first level of the final reduction: block b sums buckets [b*chunk, ...)
 // into slot b of Q (same layout as Partials); fixed order
 __global__ void __launch_bounds__(256) k_final_partial(Partials P, int64_t nb, int64_t chunk, Partials Q) {
-  __shared__ double r1[256], r2[256], r3[256];
+  __shared__ double r1[256], r2[256], r3[256], r4[256];
   __shared__ int64_t i1[256], i2[256], i3[256], i4[256], i5[256];
   const int t = threadIdx.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(nb, lo + chunk);
-  double e = 0.0, d = 0.0, mn = INFINITY;
+  double e = 0.0, d = 0.0, q = 0.0, mn = INFINITY;
   int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
   for (int64_t b = lo + t; b < hi; b += 256) {
     e += P.e2[b];
     d += P.de0[b];
+    q += P.e2sq[b];
     mn = fmin(mn, P.mind[b]);
     nt += P.nterm[b];
     ng += P.ngen[b];
@@ -744,13 +758,14 @@ __global__ void __launch_bounds__(256) k_final_partial(Partials P, int64_t nb, i
     ni += P.nintr[b];
     nz += P.nzero[b];
   }
-  r1[t] = e; r2[t] = d; r3[t] = mn;
+  r1[t] = e; r2[t] = d; r3[t] = mn; r4[t] = q;
   i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (t < o) {
       r1[t] += r1[t + o];
       r2[t] += r2[t + o];
+      r4[t] += r4[t + o];
       r3[t] = fmin(r3[t], r3[t + o]);
       i1[t] += i1[t + o];
       i2[t] += i2[t + o];
@@ -764,6 +779,7 @@ __global__ void __launch_bounds__(256) k_final_partial(Partials P, int64_t nb, i
     const int b = blockIdx.x;
     Q.e2[b] = r1[0];
     Q.de0[b] = r2[0];
+    Q.e2sq[b] = r4[0];
     Q.mind[b] = r3[0];
     Q.nterm[b] = i1[0];
     Q.ngen[b] = i2[0];
@@ -774,7 +790,7 @@ __global__ void __launch_bounds__(256) k_final_partial(Partials P, int64_t nb, i
 }
 
 struct DevResult {
-  double e2, de0, mind;
+  double e2, de0, mind, e2sq;
   int64_t nterm, ngen, nuniq, nintr, nzero;
   uint32_t overflow, flags;
 };
@@ -782,21 +798,22 @@ struct DevResult {
 __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t seg_lo, int64_t seg_n,
                                                 const uint32_t* overflow, const uint32_t* flags,
                                                 DevResult* res, double* per_sample, int64_t per_seg,
-                                                double* per_sample_de0) {
+                                                double* per_sample_de0, double sample_scale) {
   // sums buckets [seg_lo + s*per_seg, ...) per segment s when per_sample != NULL,
   // or everything into res
-  __shared__ double r1[1024], r2[1024], r3[1024];
+  __shared__ double r1[1024], r2[1024], r3[1024], r4[1024];
   __shared__ int64_t i1[1024], i2[1024], i3[1024], i4[1024], i5[1024];
   const int t = threadIdx.x;
   const int64_t lo = per_sample ? seg_lo + (int64_t)blockIdx.x * per_seg : 0;
   const int64_t cnt = per_sample ? per_seg : nb;
   const int64_t chunk = (cnt + 1023) / 1024;
   const int64_t b0 = lo + t * chunk, b1 = min(lo + cnt, b0 + chunk);
-  double e = 0.0, d = 0.0, mn = INFINITY;
+  double e = 0.0, d = 0.0, q = 0.0, mn = INFINITY;
   int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
   for (int64_t b = b0; b < b1; ++b) {
     e += P.e2[b];
     d += P.de0[b];
+    q += P.e2sq[b];
     mn = fmin(mn, P.mind[b]);
     nt += P.nterm[b];
     ng += P.ngen[b];
@@ -804,13 +821,14 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
     ni += P.nintr[b];
     nz += P.nzero[b];
   }
-  r1[t] = e; r2[t] = d; r3[t] = mn;
+  r1[t] = e; r2[t] = d; r3[t] = mn; r4[t] = q;
   i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
   __syncthreads();
   for (int o = 512; o > 0; o >>= 1) {
     if (t < o) {
       r1[t] += r1[t + o];
       r2[t] += r2[t + o];
+      r4[t] += r4[t + o];
       r3[t] = fmin(r3[t], r3[t + o]);
       i1[t] += i1[t + o];
       i2[t] += i2[t + o];
@@ -822,8 +840,8 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
   }
   if (t == 0) {
     if (per_sample) {
-      per_sample[blockIdx.x] = r1[0];
-      if (per_sample_de0) per_sample_de0[blockIdx.x] = r2[0];
+      per_sample[blockIdx.x] = sample_scale * r1[0];
+      if (per_sample_de0) per_sample_de0[blockIdx.x] = sample_scale * r2[0];
       // statistics accumulate over the per-sample blocks
       atomicAdd((unsigned long long*)&res->nterm, (unsigned long long)i1[0]);
       atomicAdd((unsigned long long*)&res->ngen, (unsigned long long)i2[0]);
@@ -835,6 +853,7 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
     } else {
       res->e2 = r1[0];
       res->de0 = r2[0];
+      res->e2sq = r4[0];
       res->mind = r3[0];
       res->nterm = i1[0];
       res->ngen = i2[0];

@@ -41,6 +41,7 @@ struct Recs {
 struct Partials {
   double* e2 = nullptr;      // [nbucket] sum of contributions
   double* de0 = nullptr;     // [nbucket] sum of -A^2/D^2
+  double* e2sq = nullptr;    // [nbucket] sum of squared contributions (per unique a)
   int64_t* nterm = nullptr;  // [nbucket] kept terms with a outside V
   int64_t* ngen = nullptr;   // [nbucket] all kept terms
   int32_t* nuniq = nullptr;  // [nbucket] unique a outside V

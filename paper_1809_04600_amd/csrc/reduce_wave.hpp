@@ -95,19 +95,20 @@ SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage& W, int64_t lo, int M)
 }
 
 struct SegAcc {
-  double e2p = 0.0, de0p = 0.0, dmn = INFINITY;
+  double e2p = 0.0, de0p = 0.0, e2sq = 0.0, dmn = INFINITY;
   int64_t nterm = 0, ngen = 0;
   int32_t nuniq = 0, nintr = 0, nzero = 0;
 };
 
 SHCI_DEV void wave_write_partials(const Partials& P, int64_t b, SegAcc acc) {
-  double e2p = acc.e2p, de0p = acc.de0p, dmn = acc.dmn;
+  double e2p = acc.e2p, de0p = acc.de0p, e2sq = acc.e2sq, dmn = acc.dmn;
   int64_t nterm = acc.nterm, ngen = acc.ngen;
   int32_t nuniq = acc.nuniq, nintr = acc.nintr, nzero = acc.nzero;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     e2p += __shfl_xor(e2p, o);
     de0p += __shfl_xor(de0p, o);
+    e2sq += __shfl_xor(e2sq, o);
     dmn = fmin(dmn, __shfl_xor(dmn, o));
     nterm += __shfl_xor(nterm, o);
     ngen += __shfl_xor(ngen, o);
@@ -118,6 +119,7 @@ SHCI_DEV void wave_write_partials(const Partials& P, int64_t b, SegAcc acc) {
   if (lane_id() == 0) {
     P.e2[b] = e2p;
     P.de0[b] = de0p;
+    P.e2sq[b] = e2sq;
     P.nterm[b] = nterm;
     P.ngen[b] = ngen;
     P.nuniq[b] = nuniq;
@@ -130,6 +132,7 @@ SHCI_DEV void wave_write_partials(const Partials& P, int64_t b, SegAcc acc) {
 SHCI_DEV void wave_zero_partials(const Partials& P, int64_t b) {
   P.e2[b] = 0.0;
   P.de0[b] = 0.0;
+  P.e2sq[b] = 0.0;
   P.nterm[b] = 0;
   P.ngen[b] = 0;
   P.nuniq[b] = 0;
@@ -196,7 +199,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
         if constexpr (SAMPLE)
           sum.add_sample(vin[lo + id], v2in[lo + id], (auxw[lo + id] & am) != 0ull);
         else
-          sum.add(vin[lo + id]);
+          sum.add(vin[lo + id], (auxw[lo + id] & am) != 0ull);
       }
       sum.finish();
       const double X = sum.X;
@@ -211,7 +214,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
       // the determinant hash is the bucket's hash bits above the sorted bits
       // when those reach the low byte, else recomputed
       const uint64_t hb_part = (uint64_t)b & ((bh >= 64) ? ~0ull : ((1ull << bh) - 1ull));
-      const uint64_t h = (bh >= 8) ? ((hb_part << (64 - bh)) | ((s0 & ~0xffull) >> bh)) : hash_key<KW>(dk);
+      const uint64_t h = (bh >= 8) ? ((hb_part << (64 - bh)) | ((s0 & ~0xffull) >> bh)) : det_hash<KW>(dk, n);
       const bool inv = vset_contains_h<KW>(a.V, dk, h, n);
       const int cntk = e1 - e0;
       acc.ngen += cntk;
@@ -229,11 +232,15 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
           gd = 2.0 * sum.Xd * G;
           gG = G;
         } else {
-          contrib = X * X * rd;
-          acc.de0p += -(X * X) * rd * rd;
+          // (A^2 - A_hi^2) / D; A_hi (terms above the upper threshold) is 0
+          // unless a two-threshold evaluation was asked for
+          const double a2 = X * X - sum.Xd * sum.Xd;
+          contrib = a2 * rd;
+          acc.de0p += -a2 * rd * rd;
           g = 2.0 * X * rd;
         }
         acc.e2p += contrib;
+        acc.e2sq += contrib * contrib;
         acc.nterm += cntk;
         acc.nuniq += 1;
         acc.nintr += Dd > 0.0;

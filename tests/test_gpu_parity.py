@@ -331,3 +331,48 @@ def test_semistochastic_autograd():
     want = od.grad + o_g
     assert np.linalg.norm(cc.grad.cpu().numpy() - want) <= 1e-9 * np.linalg.norm(want)
     assert abs(e0.grad.item() - (od.de2_de0 + o_de0.mean())) <= 1e-9 * abs(od.de2_de0 + o_de0.mean())
+
+
+def test_hash_batches_three_step():
+    # per-batch statistics (one and two thresholds), one batch of P per
+    # sample, and the 3-step composition, against the CPU reference
+    x = I.small(12, 3, 3, 300, 3, 31)
+    ctx, dets, c = context(x)
+    args = (12, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0)
+    eps_dtm, eps_psto, eps2 = 1e-4, 1e-6, 1e-7
+    nbat = 4
+    rows, _ = ctx.det_batches(dets, c, x.e0, eps_psto, eps_dtm, nbat, list(range(nbat)), "fp64")
+    for b, r in enumerate(rows):
+        o = ref.det_batch(*args, eps_psto, eps_dtm, nbat, b)
+        assert r[2] == o[2] and r[3] == o[3]
+        assert abs(r[0] - o[0]) <= 1e-12 * max(1e-300, abs(o[0])) + 1e-15
+        assert abs(r[1] - o[1]) <= 1e-10 * abs(o[1]) + 1e-300
+    rows1, _ = ctx.det_batches(dets, c, x.e0, eps_psto, float("inf"), nbat, [0, 3], "fp32c")
+    for r, b in zip(rows1, [0, 3]):
+        o = ref.det_batch(*args, eps_psto, np.inf, nbat, b)
+        assert r[2] == o[2] and abs(r[0] - o[0]) <= E2_TOL_FP32C
+    rng = np.random.default_rng(37)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    draws = rng.choice(len(x.c), size=(6, 40), p=p).astype(np.uint32)
+    sb = rng.integers(0, 8, size=6).astype(np.int32)
+    dr = torch.from_numpy(draws.view(np.int32)).cuda()
+    sbt = torch.from_numpy(sb).cuda()
+    out, mean, sem, st = ctx.sample_batched(dets, c, x.e0, eps2, eps_psto, dr, 8, sbt, "fp64")
+    o = ref.pt2_sample_batched(*args, eps2, eps_psto, draws, 8, sb)
+    assert np.abs(out.cpu().numpy() - o).max() <= 1e-9 * max(1.0, np.abs(o).max())
+    # 3-step: a tiny target evaluates every pseudo-stochastic batch, which
+    # then equals E2(psto) - E2(dtm) exactly
+    res, per = ctx.three_step(dets, c, x.e0, eps_dtm, eps_psto, eps2, 1e-30, nbat, 8, dr, sbt, "fp64")
+    o_dtm = ref.pt2_det(*args, eps_dtm, unique=False).e2
+    o_psto = ref.pt2_det(*args, eps_psto, unique=False).e2
+    print("3-step:", res)
+    assert res["psto_batches_used"] == nbat and res["err_psto"] == 0.0
+    assert abs(res["e2_dtm"] - o_dtm) <= E2_TOL_FP64
+    assert abs(res["e2_psto"] - (o_psto - o_dtm)) <= E2_TOL_FP64
+    assert abs(res["e2_sto"] - o.mean()) <= 1e-9
+    assert abs(res["e2"] - (o_dtm + (o_psto - o_dtm) + o.mean())) <= 2 * E2_TOL_FP64
+    # a loose target stops after the first batch with an estimate and error
+    res1, _ = ctx.three_step(dets, c, x.e0, eps_dtm, eps_psto, eps2, 1.0, nbat, 8, dr, sbt, "fp64")
+    assert res1["psto_batches_used"] == 1 and res1["err_psto"] > 0.0
+    r0 = ref.det_batch(*args, eps_psto, eps_dtm, nbat, 0)
+    assert abs(res1["e2_psto"] - r0[0] * nbat) <= 1e-12 * abs(r0[0] * nbat) + 1e-15

@@ -344,3 +344,30 @@ def test_stochastic_gradient_pins():
     c2 = (s_at(x.e0 + d1 / 2) - s_at(x.e0 - d1 / 2)) / d1
     rich = (4 * c2 - c1) / 3
     assert np.abs(rich - de0).max() <= 1e-6 * np.abs(de0).max()
+
+
+def test_hash_batches_partition_p():
+    # the hash batches partition P: batch sums add up to E2 (and, with an
+    # upper threshold, to E2(eps2) - E2(eps2_hi)); counts add up; batches are
+    # evenly filled
+    x = I.small(10, 3, 3, 200, 3, 23)
+    args = (10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0)
+    nbat = 8
+    o = ref.pt2_det(*args, 1e-6, unique=False)
+    oh = ref.pt2_det(*args, 1e-4, unique=False)
+    rows = [ref.det_batch(*args, 1e-6, np.inf, nbat, b) for b in range(nbat)]
+    assert abs(sum(r[0] for r in rows) - o.e2) <= 1e-12 * abs(o.e2)
+    assert sum(r[2] for r in rows) == o.n_unique and sum(r[3] for r in rows) == o.n_terms
+    cnt = np.array([r[2] for r in rows], dtype=float)
+    assert np.all(np.abs(cnt - cnt.mean()) <= 5 * np.sqrt(cnt.mean()) + 1)
+    rows2 = [ref.det_batch(*args, 1e-6, 1e-4, nbat, b) for b in range(nbat)]
+    assert abs(sum(r[0] for r in rows2) - (o.e2 - oh.e2)) <= 1e-12 * abs(o.e2)
+    # one batch of P per sample: averaged over the batch choice, the estimate
+    # is the unbatched one
+    rng = np.random.default_rng(29)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    draws = rng.choice(len(x.c), size=(3, 25), p=p).astype(np.uint32)
+    full = ref.pt2_sample(*args, 1e-6, 1e-4, draws)
+    per_b = np.array([ref.pt2_sample_batched(*args, 1e-6, 1e-4, draws, nbat, np.full(3, b, np.int32))
+                      for b in range(nbat)])
+    assert np.abs(per_b.mean(axis=0) - full).max() <= 1e-12 * max(1.0, np.abs(full).max())

@@ -243,6 +243,22 @@ int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c
                         const uint32_t* draws, const int32_t* sample_batch, int precision, void* stream,
                         double* per_sample, shci_pt2_3step_result* res);
 
+/* Selection of new variational determinants from the same pass (variational
+ * stage, section II.A): one deterministic pass with generation threshold
+ * eps_gen, then among its perturbative determinants a outside V
+ *   SHCI_SELECT_HCI:   every a, i.e. max_i |H_ai c_i| > eps_gen (the
+ *                      heat-bath criterion with eps1 = eps_gen); value = A_a;
+ *   SHCI_SELECT_CIPSI: |A_a^2 / (E0 - H_aa)| > threshold (the CIPSI energy
+ *                      criterion, preselected at eps_gen); value = A_a^2 / D_a.
+ *   out_keys  device uint64 [cap][4] (input layout), out_val device FP64 [cap];
+ *   n_out     host: number selected.  SHCI_ERR_WORKSPACE if the pass has more
+ *             than cap perturbative determinants.  Order unspecified but
+ *             deterministic. */
+enum { SHCI_SELECT_HCI = 0, SHCI_SELECT_CIPSI = 1 };
+int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                double eps_gen, int mode, double threshold, int precision, void* stream, uint64_t* out_keys,
+                double* out_val, int64_t cap, int64_t* n_out, shci_pt2_stats* st);
+
 /* Adjoint of the stochastic part: the per-sample estimates of
  * shci_pt2_sample and the derivatives of their mean with respect to c and
  * E0, with the draws, p_i and the screening masks held at the forward point

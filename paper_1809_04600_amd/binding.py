@@ -105,6 +105,9 @@ def lib():
         L.shci_pt2_three_step.argtypes = [p, p, p, i64, d, d, d, d, d, C.c_int32, C.c_int32, C.c_int32,
                                           C.c_int32, p, p, i, p, p, C.POINTER(ThreeStep)]
         L.shci_pt2_three_step.restype = i
+        L.shci_pt2_select.argtypes = [p, p, p, i64, d, d, i, d, i, p, p, p, i64, C.POINTER(i64),
+                                      C.POINTER(Stats)]
+        L.shci_pt2_select.restype = i
         L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), p, C.POINTER(d),
                                     C.POINTER(Stats)]
         L.shci_pt2_grad.restype = i
@@ -271,6 +274,24 @@ class Context:
                                           int(n_batches), bl, len(batches), _PREC[precision], _stream(), out,
                                           C.byref(st)))
         return [(o.sum, o.sumsq, o.n_unique, o.n_terms) for o in out], st.as_dict()
+
+    def select(self, dets, c, e0, eps_gen, mode="hci", threshold=0.0, cap=1 << 20, precision="fp64"):
+        """New determinants from one pass: mode "hci" (every a reached with
+        |H_ai c_i| > eps_gen; value A_a) or "cipsi" (|A_a^2/D_a| > threshold
+        after preselection at eps_gen; value A_a^2/D_a).  Returns (keys
+        int64 [m, 4], values [m])."""
+        pd, pc, nd = self._inputs(dets, c)
+        dev = c.device
+        keys = torch.zeros((cap, 4), dtype=torch.int64, device=dev)
+        vals = torch.zeros(cap, dtype=torch.float64, device=dev)
+        n_out = C.c_int64()
+        st = Stats()
+        m = {"hci": 0, "cipsi": 1}[mode]
+        _check(lib().shci_pt2_select(self._ptr, pd, pc, nd, float(e0), float(eps_gen), m, float(threshold),
+                                     _PREC[precision], _stream(), C.c_void_p(keys.data_ptr()),
+                                     C.c_void_p(vals.data_ptr()), cap, C.byref(n_out), C.byref(st)))
+        k = n_out.value
+        return keys[:k], vals[:k]
 
     def three_step(self, dets, c, e0, eps2_dtm, eps2_psto, eps2, target_error, nb_psto, nb_sto, draws,
                    sample_batch, precision="fp64"):

@@ -241,6 +241,29 @@ __global__ void k_sample_compact(const uint32_t* it_det, const uint32_t* it_w, c
   }
 }
 
+// Selection of new determinants: flag[i] = 1 if exported unique i meets the
+// criterion (HCI: every a reached at the generation threshold; CIPSI:
+// |A_a^2 / D_a| > threshold), value[i] = A_a (HCI) or A_a^2 / D_a (CIPSI).
+__global__ void k_select_flags(const double* A, const double* D, int64_t n, int mode, double thr, uint32_t* flag,
+                               double* value) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double e = A[i] * A[i] / D[i];
+    const bool keep = (mode == SHCI_SELECT_HCI) ? true : fabs(e) > thr;
+    flag[i] = keep ? 1u : 0u;
+    value[i] = (mode == SHCI_SELECT_HCI) ? A[i] : e;
+  }
+}
+
+__global__ void k_select_compact(const uint64_t* keys, const double* value, const uint32_t* flag,
+                                 const uint64_t* pos, int64_t n, uint64_t* out_keys, double* out_val) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[i]) continue;
+    const uint64_t o = pos[i];
+    for (int w = 0; w < 4; ++w) out_keys[4 * o + w] = keys[4 * i + w];
+    out_val[o] = value[i];
+  }
+}
+
 // Unique export: copy the non-V uniques of every bucket to dense arrays.
 template <int KW>
 __global__ void k_export_uniq(Uniq U, const int32_t* nseg, const uint64_t* boff, int64_t nb, int n,
@@ -1468,6 +1491,71 @@ int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c
   res->e2 = res->e2_dtm + res->e2_psto + res->e2_sto;
   res->err = std::sqrt(res->err_psto * res->err_psto + res->err_sto * res->err_sto);
   return SHCI_OK;
+}
+
+int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                double eps_gen, int mode, double threshold, int precision, void* stream, uint64_t* out_keys,
+                double* out_val, int64_t cap, int64_t* n_out, shci_pt2_stats* st) {
+  if (mode != SHCI_SELECT_HCI && mode != SHCI_SELECT_CIPSI) return fail(SHCI_ERR_ARG, "unknown selection mode");
+  if (!out_keys || !out_val || !n_out || cap < 1) return fail(SHCI_ERR_ARG, "out_keys, out_val, n_out, cap >= 1");
+  if (mode == SHCI_SELECT_CIPSI && !(threshold >= 0.0)) return fail(SHCI_ERR_ARG, "threshold must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every unique a of the pass, exported into work arrays of the caller's capacity
+  DevBuf tmp;
+  auto plan = [&](Carver& cv, uint64_t** k, double** A, double** D, int32_t** cnt, uint32_t** flag, double** val,
+                  uint64_t** pos, ScanTmp* sc) {
+    *k = cv.take<uint64_t>(4 * cap);
+    *A = cv.take<double>(cap);
+    *D = cv.take<double>(cap);
+    *cnt = cv.take<int32_t>(cap);
+    *flag = cv.take<uint32_t>(cap + 1);
+    *val = cv.take<double>(cap);
+    *pos = cv.take<uint64_t>(cap + 1);
+    sc->carve(cv, cap + 1);
+  };
+  uint64_t *k, *pos;
+  double *A, *D, *val;
+  int32_t* cnt;
+  uint32_t* flag;
+  ScanTmp sc;
+  {
+    Carver cv(nullptr);
+    plan(cv, &k, &A, &D, &cnt, &flag, &val, &pos, &sc);
+    CHK(tmp.ensure(cv.off, ctx->ws_limit));
+    Carver cv2(tmp.p);
+    plan(cv2, &k, &A, &D, &cnt, &flag, &val, &pos, &sc);
+  }
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return code;
+  };
+  shci_pt2_export ex{};
+  ex.u_keys = k;
+  ex.u_A = A;
+  ex.u_D = D;
+  ex.u_cnt = cnt;
+  ex.u_cap = cap;
+  double e2 = 0.0;
+  int r = shci_pt2_det(ctx, dets, c, n_det, e0, eps_gen, precision, stream, &e2, st, &ex);
+  if (r) return done(r);
+  if (ex.u_n > cap)
+    return done(fail(SHCI_ERR_WORKSPACE, "%lld perturbative determinants exceed cap = %lld",
+                     (long long)ex.u_n, (long long)cap));
+  const int64_t nu = ex.u_n;
+  *n_out = 0;
+  if (nu == 0) return done(SHCI_OK);
+  const int grid = (int)std::min<int64_t>(4096, (nu + 255) / 256);
+  k_select_flags<<<grid, 256, 0, s>>>(A, D, nu, mode, threshold, flag, val);
+  r = scan_exclusive<uint32_t, uint64_t>(flag, pos, nu, sc, pos + nu, s);
+  if (r) return done(r);
+  k_select_compact<<<grid, 256, 0, s>>>(k, val, flag, pos, nu, out_keys, out_val);
+  uint64_t h = 0;
+  if (hipMemcpyAsync(&h, pos + nu, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(fail(SHCI_ERR_HIP, "selection count copy failed"));
+  *n_out = (int64_t)h;
+  return done(SHCI_OK);
 }
 
 }  // extern "C"

@@ -376,3 +376,29 @@ def test_hash_batches_three_step():
     assert res1["psto_batches_used"] == 1 and res1["err_psto"] > 0.0
     r0 = ref.det_batch(*args, eps_psto, eps_dtm, nbat, 0)
     assert abs(res1["e2_psto"] - r0[0] * nbat) <= 1e-12 * abs(r0[0] * nbat) + 1e-15
+
+
+def test_selection_criteria():
+    # HCI: every a outside V with max_i |H_ai c_i| > eps1; CIPSI: |A^2/D| >
+    # threshold after preselection -- sets bit-exact, values to the bar
+    x = I.small(10, 3, 3, 150, 3, 41)
+    ctx, dets, c = context(x)
+    eps1 = 1e-4
+    keys, vals = ctx.select(dets, c, x.e0, eps1, "hci", cap=100000)
+    o = _oracle(x, eps1)
+    gk = keys_np(keys)
+    assert len(gk) == o.n_unique
+    go, oo = sort_keys(gk), sort_keys(o.keys)
+    assert np.array_equal(gk[go], o.keys[oo])
+    assert np.abs(vals.cpu().numpy()[go] - o.A[oo]).max() <= 1e-13
+    pre, thr = 1e-6, 1e-6
+    keys, vals = ctx.select(dets, c, x.e0, pre, "cipsi", thr, cap=100000)
+    o = _oracle(x, pre)
+    e = o.A ** 2 / o.D
+    want = o.keys[np.abs(e) > thr]
+    gk = keys_np(keys)
+    assert len(gk) == len(want) > 0
+    assert np.array_equal(gk[sort_keys(gk)], want[sort_keys(want)])
+    ge = vals.cpu().numpy()[sort_keys(gk)]
+    we = e[np.abs(e) > thr][sort_keys(want)]
+    assert np.abs(ge - we).max() <= 1e-12 * np.abs(we).max()

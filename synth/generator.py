@@ -175,8 +175,10 @@ def _excite_spin(rng, rows: int, n: int, nsig: int, lev: np.ndarray) -> np.ndarr
     return (base & ~hole_bits) | part_bits
 
 
-def make_dets(n: int, na: int, nb: int, n_var: int, max_level: int, rng: np.random.Generator):
-    """Return (dets uint64 [n_var,4], level int8 [n_var]); HF first."""
+def make_dets(n: int, na: int, nb: int, n_var: int, max_level: int, rng: np.random.Generator,
+              progress=None):
+    """Return (dets uint64 [n_var,4], level int8 [n_var]); HF first.
+    progress(have, n_var), if given, is called after each batch of draws."""
     va, vb = n - na, n - nb
     ma, mb = min(na, va), min(nb, vb)
     hf = hf_det(na, nb)
@@ -207,6 +209,8 @@ def make_dets(n: int, na: int, nb: int, n_var: int, max_level: int, rng: np.rand
             have += 1
             if have == n_var:
                 break
+        if progress is not None:
+            progress(have, n_var)
     return np.ascontiguousarray(np.concatenate(dets)), np.concatenate(levels)
 
 
@@ -253,14 +257,14 @@ class Inputs:
     extra: dict = field(default_factory=dict)
 
 
-def make_raw(wl: Workload | str, n_var: int | None = None) -> Inputs:
+def make_raw(wl: Workload | str, n_var: int | None = None, progress=None) -> Inputs:
     """Draw integrals, determinants and noise for a workload (no c, no E0)."""
     if isinstance(wl, str):
         wl = WORKLOADS[wl]
     rng = np.random.default_rng(wl.seed)
     h1, eri = make_integrals(wl.n_orb, rng)
     nv = wl.n_var if n_var is None else n_var
-    dets, levels = make_dets(wl.n_orb, wl.n_alpha, wl.n_beta, nv, wl.max_level, rng)
+    dets, levels = make_dets(wl.n_orb, wl.n_alpha, wl.n_beta, nv, wl.max_level, rng, progress)
     noise = noise_values(nv, rng)
     return Inputs(wl, h1, eri, dets, levels, noise)
 

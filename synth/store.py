@@ -21,9 +21,9 @@ def fingerprint(a: np.ndarray) -> np.ndarray:
     return np.frombuffer(h, dtype=np.uint8).copy()
 
 
-def load(name: str, check: bool = True) -> G.Inputs:
+def load(name: str, check: bool = True, progress=None) -> G.Inputs:
     """Regenerate workload `name` and attach its stored c and E0."""
-    x = G.make_raw(name)
+    x = G.make_raw(name, progress=progress)
     with np.load(data_path(name), allow_pickle=False) as z:
         amp = z["mp1"]
         x.e0 = float(z["e0"])

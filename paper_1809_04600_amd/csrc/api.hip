@@ -548,12 +548,14 @@ int run_job(Job& J) {
       A->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
       A->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
       A->bid = cv.take<uint32_t>(nrec);
+      A->haa = cv.take<double>(nrec);
       if (npass > 0) {
         for (int w = 0; w < KW; ++w) B->k[w] = cv.take<uint64_t>(nrec);
         B->v = cv.take<VT>(nrec);
         B->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
         B->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
         B->bid = cv.take<uint32_t>(nrec);
+        B->haa = cv.take<double>(nrec);
       }
       *bst = cv.take<uint64_t>(G.nbucket + 1);
       *slow = cv.take<uint32_t>(G.nbucket + 1);
@@ -654,9 +656,9 @@ int run_job(Job& J) {
         k_part_hist<KW><<<pgrid, 256, 0, st>>>(pa);
         CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
         if (pay)
-          k_part_scatter<KW, VT, SAMPLE, true><<<pgrid, 256, 0, st>>>(pa);
+          k_part_scatter<KW, VT, SAMPLE, true><<<pgrid, PTHREADS, 0, st>>>(pa);
         else
-          k_part_scatter<KW, VT, SAMPLE, false><<<pgrid, 256, 0, st>>>(pa);
+          k_part_scatter<KW, VT, SAMPLE, false><<<pgrid, PTHREADS, 0, st>>>(pa);
         HIPCHK(hipGetLastError());
         std::swap(cur, oth);
         shift += dbits;
@@ -679,20 +681,13 @@ int run_job(Job& J) {
     ra.auxbit = auxbit;
     ra.e0 = J.e0;
     ra.nd = J.nd;
-    ra.diag = T.diag;
     ra.V = V;
     ra.P = P;
     ra.U = U;
     ra.overflow = overflow;
     ra.want_u = J.want_u ? 1 : 0;
     ra.bstart = bst;
-    ra.ref_det = J.dets;
-    ra.ne = T.na + T.nb;
-    k_diag_ref<<<1, 256, 0, st>>>(J.dets, n, T.na + T.nb, T.diag);
     uint32_t* slow_count = X->dflag + 3;
-    const size_t diag_bytes = (size_t)diag_table_doubles(n) * sizeof(double);
-    const bool red_lds = sizeof(RedShared<KW, C, SAMPLE, VT>) + diag_bytes <= 160 * 1024;
-    const bool wave_lds = sizeof(WaveStage) * WRED_WAVES + diag_bytes <= 160 * 1024;
     const int64_t wblocks =
         std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * RED_BLOCKS_PER_CU);
     WaveRedArgs wa;
@@ -704,27 +699,13 @@ int run_job(Job& J) {
     k_fill_u32<<<1, 64, 0, st>>>(overflow, 1, 0u);
     k_fill_u32<<<1, 64, 0, st>>>(slow_count, 1, 0u);
     HIPCHK(hipEventRecord(X->ev[8], st));
-    {
-      if (wave_lds) {
-        HIPCHK(hipFuncSetAttribute((const void*)k_reduce_wave<KW, SAMPLE, VT, true>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_bytes));
-        k_reduce_wave<KW, SAMPLE, VT, true><<<(int)wblocks, 64 * WRED_WAVES, diag_bytes, st>>>(wa);
-      } else {
-        k_reduce_wave<KW, SAMPLE, VT, false><<<(int)wblocks, 64 * WRED_WAVES, 0, st>>>(wa);
-      }
-    }
+    k_reduce_wave<KW, SAMPLE, VT><<<(int)wblocks, 64 * WRED_WAVES, 0, st>>>(wa);
     // buckets the wavefront kernel could not take: block kernel with a full-key sort
     ra.blist = slow;
     ra.nlist = slow_count;
     {
       const int rgrid = (int)std::min<int64_t>(G.nbucket, (int64_t)cus * 2);
-      if (red_lds) {
-        HIPCHK(hipFuncSetAttribute((const void*)k_reduce<KW, C, SAMPLE, VT, true>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_bytes));
-        k_reduce<KW, C, SAMPLE, VT, true><<<rgrid, 256, diag_bytes, st>>>(ra);
-      } else {
-        k_reduce<KW, C, SAMPLE, VT, false><<<rgrid, 256, 0, st>>>(ra);
-      }
+      k_reduce<KW, C, SAMPLE, VT><<<rgrid, 256, 0, st>>>(ra);
     }
     HIPCHK(hipEventRecord(X->ev[9], st));
     HIPCHK(hipGetLastError());
@@ -899,7 +880,9 @@ int64_t record_budget(shci_pt2_ctx* X, double per_rec) {
 }
 
 double record_bytes(int kw, int vbytes, bool pay, bool uniq) {
-  return 2.0 * (8.0 * kw + vbytes + (pay ? 4.0 : 0.0)) + 4.0 + 2.0 + (uniq ? 8.0 * kw + 40.0 : 0.0);
+  // two record buffers (keys, values, payload, bucket id, H_aa), then slack
+  // for the bucket tables and the per-unique output
+  return 2.0 * (8.0 * kw + vbytes + (pay ? 4.0 : 0.0) + 4.0 + 8.0) + 2.0 + (uniq ? 8.0 * kw + 40.0 : 0.0);
 }
 
 // Deterministic evaluation within the record budget.  When the screened

@@ -16,6 +16,7 @@
 // Lane-parallel emission uses ballot + mbcnt compaction, so the record order
 // is fixed by (source index, generation order) and the run is deterministic.
 #pragma once
+#include "diag.hpp"
 #include "kernels.hpp"
 
 namespace shci {
@@ -116,6 +117,9 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
   __shared__ uint16_t s_sq[4][128];      // queue of singles candidates
   __shared__ uint8_t s_plist[4][64];
   __shared__ uint8_t s_llist[4][64];
+  __shared__ double s_F[4][256];         // Fock-like diagonal of the source, alpha | beta << 7
+  __shared__ uint32_t s_dq[4][128];      // queue of kept doubles: excitation code
+  __shared__ double s_dv[4][128];        //   and table value
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   uint8_t* occA = s_lists[wv][0];
@@ -181,12 +185,37 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    // H_aa of every written term is an update of the source's H_ii by the
+    // Fock-like diagonal F of the source (both spins, one orbital per lane)
+    double hii = 0.0;
+    double* Fw = s_F[wv];
+    const DiagLayout DL = DiagLayout::make(n);
+    if constexpr (MODE == GEN_WRITE) {
+      double part = 0.0;
+      for (int x = lane; x < n; x += 64) {
+        double fa, fb;
+        fock_diag2(T.diag, DL, x, occA, na, occB, nb, fa, fb);
+        Fw[x] = fa;
+        Fw[128 + x] = fb;
+        const double hx = T.diag[x];
+        if (occ(A0, A1, x)) part += hx + fa;
+        if (occ(B0, B1, x)) part += hx + fb;
+      }
+      // butterfly: every lane ends with the same (commutative) sum
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+      hii = 0.5 * part;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
     uint64_t obase = 0;
     if constexpr (MODE == GEN_WRITE) obase = a.offs[item];
     uint64_t cursor = 0;  // uniform
     double gacc = 0.0;
 
-    auto emit = [&](bool keep, uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, double H) {
+    auto emit = [&](bool keep, uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, double H, double haa) {
       if (a.bmask) {  // uniform
         if (keep) {
           uint64_t hk[KW];
@@ -232,6 +261,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           }
 #pragma unroll
           for (int q = 0; q < KW; ++q) a.out.k[q][pos] = key[q];
+          a.out.haa[pos] = haa;
           if (a.out.pay) a.out.pay[pos] = (uint32_t)i;
         }
         cursor += (uint64_t)__popcll(bal);
@@ -371,7 +401,11 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
           flip(y0, y1, p);
           flip(y0, y1, r);
         }
-        emit(keep, x0, x1, y0, y1, H);
+        double haa = 0.0;
+        if constexpr (MODE == GEN_WRITE) {
+          if (keep) haa = hii + en_single(Fw + (alpha ? 0 : 128), T.diag, DL, p, r);
+        }
+        emit(keep, x0, x1, y0, y1, H, haa);
       };
       for (int j0 = 0; j0 < nsing; j0 += 64) {
         const int j = j0 + lane;
@@ -465,14 +499,23 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         len = T.los;
       }
     };
-    // one heat-bath entry (value v, target rs) of pair (p, q, type)
-    auto dbl = [&](bool pass, int type, int p, int q, double v, uint16_t rs) {
-      const int r = rs & 0xff, s2 = rs >> 8;
-      bool keep = pass;
+    // Kept doubles are queued (type << 28 | p << 21 | q << 14 | r << 7 | s,
+    // and the table value) and written 64 at a time, so the key, hash, H_aa
+    // and stores of a write run on full wavefronts.  Plain counting needs
+    // no queue.
+    const bool dqueue = MODE != GEN_COUNT || a.bmask != 0u;  // uniform
+    uint32_t* dq = s_dq[wv];
+    double* dv = s_dv[wv];
+    int dqn = 0;  // uniform
+    auto dflush = [&](int cnt) {
+      const bool valid = lane < cnt;
+      const uint32_t cd = valid ? dq[lane] : 0u;
+      const double v = valid ? dv[lane] : 0.0;
+      const int type = (int)(cd >> 28), p = (int)((cd >> 21) & 127u), q = (int)((cd >> 14) & 127u),
+                r = (int)((cd >> 7) & 127u), s2 = (int)(cd & 127u);
       uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
       int par = 0;
       if (type == 0) {
-        keep = keep && !occ(A0, A1, r) && !occ(A0, A1, s2);
         par = between(x0, x1, p, r);
         flip(x0, x1, p);
         flip(x0, x1, r);
@@ -480,7 +523,6 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         flip(x0, x1, q);
         flip(x0, x1, s2);
       } else if (type == 1) {
-        keep = keep && !occ(B0, B1, r) && !occ(B0, B1, s2);
         par = between(y0, y1, p, r);
         flip(y0, y1, p);
         flip(y0, y1, r);
@@ -488,14 +530,62 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
         flip(y0, y1, q);
         flip(y0, y1, s2);
       } else {
-        keep = keep && !occ(A0, A1, r) && !occ(B0, B1, s2);
         par = between(A0, A1, p, r) + between(B0, B1, q, s2);
         flip(x0, x1, p);
         flip(x0, x1, r);
         flip(y0, y1, q);
         flip(y0, y1, s2);
       }
-      emit(keep, x0, x1, y0, y1, (par & 1) ? -v : v);
+      double haa = 0.0;
+      if constexpr (MODE == GEN_WRITE) {
+        if (valid)
+          haa = hii + en_double(Fw + (type == 1 ? 128 : 0), Fw + (type == 0 ? 0 : 128), T.diag, DL, p, q,
+                                r, s2, type < 2);
+      }
+      emit(valid, x0, x1, y0, y1, (par & 1) ? -v : v, haa);
+    };
+    // one heat-bath entry (value v, target rs) of pair (p, q, type)
+    auto dbl = [&](bool pass, int type, int p, int q, double v, uint16_t rs) {
+      const int r = rs & 0xff, s2 = rs >> 8;
+      bool keep = pass;
+      if (type == 0)
+        keep = keep && !occ(A0, A1, r) && !occ(A0, A1, s2);
+      else if (type == 1)
+        keep = keep && !occ(B0, B1, r) && !occ(B0, B1, s2);
+      else
+        keep = keep && !occ(A0, A1, r) && !occ(B0, B1, s2);
+      const uint64_t bal = ballot(keep);
+      if (!dqueue) {
+        cursor += (uint64_t)__popcll(bal);
+        return;
+      }
+      if (keep) {
+        const int o = dqn + rank_below(bal);
+        dq[o] = ((uint32_t)type << 28) | ((uint32_t)p << 21) | ((uint32_t)q << 14) | ((uint32_t)r << 7) |
+                (uint32_t)s2;
+        dv[o] = v;
+      }
+      dqn += __popcll(bal);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (dqn >= 64) {
+        dflush(64);
+        const bool mv = lane + 64 < dqn;
+        const uint32_t rc = mv ? dq[lane + 64] : 0u;
+        const double rv = mv ? dv[lane + 64] : 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (mv) {
+          dq[lane] = rc;
+          dv[lane] = rv;
+        }
+        dqn -= 64;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
     };
     uint8_t* plist = s_plist[wv];
     uint8_t* llist = s_llist[wv];
@@ -562,6 +652,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
       }
     }
 
+    if (dqn > 0) dflush(dqn);
     if constexpr (MODE == GEN_COUNT) {
       if (lane == 0) a.counts[item] = (uint32_t)cursor;
     }

@@ -205,8 +205,27 @@ __global__ void __launch_bounds__(256) k_part_hist(PassArgs a) {
 // place in the tile.  Every array is staged through LDS in digit order and
 // written out so that consecutive threads write consecutive records of one
 // digit run (coalesced stores).
-constexpr int PWAVES = 4;                       // wavefronts per partition block
+constexpr int PWAVES = 16;                      // wavefronts per partition block
+constexpr int PTHREADS = 64 * PWAVES;
 constexpr int PW_ITEMS = PTILE / PWAVES / 64;   // rounds per wavefront
+
+// exclusive scan of 256 per-digit values held by threads [0, 256) of a block
+// of PTHREADS threads (the others take part in the barriers only)
+SHCI_DEV uint32_t digit_scan(uint32_t v, uint32_t* sh) {
+  const int t = threadIdx.x;
+  if (t < 256) sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    uint32_t x = 0;
+    if (t < 256 && t >= o) x = sh[t - o];
+    __syncthreads();
+    if (t < 256) sh[t] += x;
+    __syncthreads();
+  }
+  const uint32_t incl = (t < 256) ? sh[t] : 0u;
+  __syncthreads();
+  return incl - v;
+}
 
 struct ScatterShared {
   uint16_t wc[PWAVES][256];  // per-wavefront count of each digit
@@ -234,7 +253,7 @@ SHCI_DEV void stage_copy(ScatterShared& L, const T* in, T* out, int64_t base, in
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < PW_ITEMS; ++j) {
-    const int q = j * 256 + t;
+    const int q = j * PTHREADS + t;
     if (q < tile_n) {
       const uint32_t d = L.sdig[q];
       out[(int64_t)L.gbase[d] + (q - (int)L.lstart[d])] = st[q];
@@ -244,14 +263,16 @@ SHCI_DEV void stage_copy(ScatterShared& L, const T* in, T* out, int64_t base, in
 }
 
 template <int KW, typename VT, bool V2, bool PAY>
-__global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
+__global__ void __launch_bounds__(PTHREADS) k_part_scatter(PassArgs a) {
   __shared__ ScatterShared L;
   const int tile = xcd_tile(blockIdx.x, a.ntiles);
   if (tile >= a.ntiles) return;
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  if (t < 256) {
 #pragma unroll
-  for (int w = 0; w < PWAVES; ++w) L.wc[w][t] = 0;
-  L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + tile] : 0u;
+    for (int w = 0; w < PWAVES; ++w) L.wc[w][t] = 0;
+    L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + tile] : 0u;
+  }
   __syncthreads();
   const int64_t base = (int64_t)tile * PTILE;
   const int tile_n = (int)((a.n - base < (int64_t)PTILE) ? (a.n - base) : (int64_t)PTILE);
@@ -283,13 +304,14 @@ __global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
     dig[j] = (uint8_t)d;
   }
   __syncthreads();
-  uint32_t tot;
   uint32_t cnt_t = 0;
+  if (t < 256) {
 #pragma unroll
-  for (int w = 0; w < PWAVES; ++w) cnt_t += L.wc[w][t];
-  const uint32_t ls = block_scan256(cnt_t, L.scan, &tot);
-  L.lstart[t] = ls;
-  {
+    for (int w = 0; w < PWAVES; ++w) cnt_t += L.wc[w][t];
+  }
+  const uint32_t ls = digit_scan(cnt_t, L.scan);
+  if (t < 256) {
+    L.lstart[t] = ls;
     uint32_t acc = ls;
 #pragma unroll
     for (int w = 0; w < PWAVES; ++w) {
@@ -311,6 +333,7 @@ __global__ void __launch_bounds__(256) k_part_scatter(PassArgs a) {
   if constexpr (V2)
     stage_copy<VT>(L, static_cast<const VT*>(a.in.v2), static_cast<VT*>(a.out.v2), base, tile_n, lpos);
   if constexpr (PAY) stage_copy<uint32_t>(L, a.in.pay, a.out.pay, base, tile_n, lpos);
+  stage_copy<double>(L, a.in.haa, a.out.haa, base, tile_n, lpos);
   stage_copy<uint32_t>(L, a.in.bid, a.out.bid, base, tile_n, lpos);
 }
 
@@ -323,14 +346,11 @@ struct RedArgs {
   GroupPlan G;
   int n, auxbit;
   double e0, nd;
-  const double* diag;  // packed diagonal table (diag.hpp layout, reference part filled)
   VSet V;
   Partials P;
   Uniq U;
   uint32_t* overflow;
   int want_u;
-  const uint64_t* ref_det;  // reference determinant for H_aa (first det of V)
-  int ne;                   // electrons
   const uint64_t* bstart;   // [nbucket + 1] bucket start offsets (nullable: binary search)
   const uint32_t* blist;    // buckets to process (nullable: all)
   const uint32_t* nlist;    // device count of blist
@@ -455,21 +475,13 @@ struct RedShared {
   uint32_t nseg;
 };
 
-template <int KW, int C, bool SAMPLE, typename VT, bool LDS>
+template <int KW, int C, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
   __shared__ RedShared<KW, C, SAMPLE, VT> R;
   if (a.blist && (int64_t)*a.nlist <= (int64_t)blockIdx.x) return;
   const int t = threadIdx.x;
   const int n = a.n;
   R.S.wcnt[0][t] = R.S.wcnt[1][t] = R.S.wcnt[2][t] = R.S.wcnt[3][t] = 0;
-  DiagTab<LDS> DT;
-  DT.g = a.diag;
-  DT.L = DiagLayout::make(n);
-  if constexpr (LDS) {
-    for (int x = t; x < DT.L.total; x += 256) g_lds_tab[x] = a.diag[x];
-  }
-  uint64_t refd[4];
-  for (int w = 0; w < 4; ++w) refd[w] = a.ref_det[w];
   __syncthreads();
 
   const int64_t nb = a.blist ? (int64_t)*a.nlist : a.G.nbucket;
@@ -656,7 +668,7 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
       ngen += cntk;
       double Dd = 0.0, g = 0.0, gd = 0.0, gG = 0.0;
       if (!inv) {
-        const double haa = diag_energy<LDS>(a0, a1, b0, b1, refd, DT, a.ne);
+        const double haa = a.in.haa[lo + first];
         Dd = a.e0 - haa;
         double contrib;
         if constexpr (SAMPLE) {

@@ -35,6 +35,7 @@ struct Recs {
   void* v2 = nullptr;     // second value (sample mode), same type
   uint32_t* pay = nullptr;  // optional source index
   uint32_t* bid = nullptr;  // bucket id (written by the generator, moved by the partition)
+  double* haa = nullptr;    // H_aa of the term's determinant (written by the generator)
 };
 
 // Per-bucket partial results written by the reduce kernel.

@@ -144,10 +144,9 @@ SHCI_DEV void wave_zero_partials(const Partials& P, int64_t b) {
 // Returns false if the bucket was handed to the block kernel.  Contributions
 // accumulate in acc (per lane); in sample mode the caller reduces acc per
 // bucket, otherwise once per wavefront at the end.
-template <int KW, bool SAMPLE, typename VT, bool LDS>
+template <int KW, bool SAMPLE, typename VT>
 SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo, int M,
-                          const DiagTab<LDS>& DT, const uint64_t (&ref)[4], uint32_t* slow_list,
-                          uint32_t* slow_count, SegAcc& acc) {
+                          uint32_t* slow_list, uint32_t* slow_count, SegAcc& acc) {
   const int lane = lane_id();
   const int n = a.n;
   const int bh = a.G.bits_hash;
@@ -220,7 +219,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
       acc.ngen += cntk;
       double Dd = 0.0, g = 0.0, gd = 0.0, gG = 0.0;
       if (!inv) {
-        const double haa = diag_energy<LDS>(a0, a1, b0, b1, ref, DT, a.ne);
+        const double haa = a.in.haa[lo + first];
         Dd = a.e0 - haa;
         const double rd = 1.0 / Dd;
         double contrib;
@@ -275,21 +274,11 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
   return true;
 }
 
-template <int KW, bool SAMPLE, typename VT, bool LDS>
+template <int KW, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8))) k_reduce_wave(WaveRedArgs A) {
   __shared__ WaveStage WS[WRED_WAVES];
   const RedArgs& a = A.r;
   const int t = threadIdx.x;
-  DiagTab<LDS> DT;
-  DT.g = a.diag;
-  DT.L = DiagLayout::make(a.n);
-  if constexpr (LDS) {
-    for (int x = t; x < DT.L.total; x += blockDim.x) g_lds_tab[x] = a.diag[x];
-  }
-  uint64_t ref[4];
-#pragma unroll
-  for (int w = 0; w < 4; ++w) ref[w] = a.ref_det[w];
-  __syncthreads();
   const int wv = t >> 6;
   const int lane = t & 63;
   WaveStage& W = WS[wv];
@@ -311,7 +300,7 @@ __global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_p
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    wave_bucket<KW, SAMPLE, VT, LDS>(a, W, b, lo, (int)M, DT, ref, A.slow_list, A.slow_count, acc);
+    wave_bucket<KW, SAMPLE, VT>(a, W, b, lo, (int)M, A.slow_list, A.slow_count, acc);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -89,36 +89,82 @@ static int check_diag(int n, int na, int nb, unsigned seed) {
       }
     }
   };
-  // reference det R: lowest orbitals, then F_p(sigma) and E(R) as on the device
-  uint64_t ra[2] = {0, 0}, rb[2] = {0, 0};
-  for (int p = 0; p < na; ++p) ra[p >> 6] |= 1ull << (p & 63);
-  for (int p = 0; p < nb; ++p) rb[p >> 6] |= 1ull << (p & 63);
-  for (int t = 0; t < 2 * n; ++t) {
-    const int p = t % n, sp = t / n;
-    const uint64_t* same = sp ? rb : ra;
-    const uint64_t* oth = sp ? ra : rb;
-    double v = h[p];
-    for (int q = 0; q < n; ++q) {
-      if (bit(same, q) && q != p) v += J[p * n + q] - K[p * n + q];
-      if (bit(oth, q)) v += J[p * n + q];
+  // random source i: F of both spins and H_ii as in the generator, then the
+  // H_aa of random singles and doubles (all three spin cases) by the update
+  auto occ_list = [&](const uint64_t* s, uint8_t* out) {
+    int c = 0;
+    for (int p = 0; p < n; ++p)
+      if (bit(s, p)) out[c++] = (uint8_t)p;
+    return c;
+  };
+  auto pick = [&](const uint64_t* s, bool occupied) {
+    for (;;) {
+      const int p = (int)(g() % n);
+      if ((bit(s, p) != 0) == occupied) return p;
     }
-    tab[L.of + t] = v;
-  }
-  tab[L.oe] = diag_plain(ra[0], ra[1], rb[0], rb[1], tab.data(), L);
-  double maxerr = std::fabs(tab[L.oe] - direct(ra, rb));
-  DiagTab<false> T;
-  T.g = tab.data();
-  T.L = L;
-  const uint64_t r[4] = {ra[0], ra[1], rb[0], rb[1]};
-  for (int it = 0; it < 5000; ++it) {
+  };
+  double maxerr = 0.0;
+  int nchk = 0;
+  for (int it = 0; it < 400; ++it) {
     uint64_t a[2], b[2];
     rand_string(na, a);
     rand_string(nb, b);
-    const double e0 = direct(a, b);
-    maxerr = std::fmax(maxerr, std::fabs(diag_energy<false>(a[0], a[1], b[0], b[1], r, T, na + nb) - e0));
-    if (n <= 64) maxerr = std::fmax(maxerr, std::fabs(diag_energy1<false>(a[0], b[0], r[0], r[2], T, 0) - e0));
+    uint8_t oa[128], ob[128];
+    const int ca = occ_list(a, oa), cb = occ_list(b, ob);
+    std::vector<double> F(256, 0.0);
+    double part = 0.0;
+    for (int x = 0; x < n; ++x) {
+      fock_diag2(tab.data(), L, x, oa, ca, ob, cb, F[x], F[128 + x]);
+      if (bit(a, x)) part += h[x] + F[x];
+      if (bit(b, x)) part += h[x] + F[128 + x];
+    }
+    const double hii = 0.5 * part;
+    maxerr = std::fmax(maxerr, std::fabs(hii - direct(a, b)));
+    for (int rep = 0; rep < 8; ++rep) {
+      uint64_t xa[2] = {a[0], a[1]}, xb[2] = {b[0], b[1]};
+      auto flip2 = [](uint64_t* s, int p) { s[p >> 6] ^= 1ull << (p & 63); };
+      double d = 0.0;
+      const int kind = (int)(g() % 5);  // singles alpha/beta, doubles aa/bb/ab
+      if (kind < 2) {
+        const uint64_t* s = kind ? b : a;
+        if ((kind ? nb : na) == 0 || (kind ? nb : na) == n) continue;
+        const int p = pick(s, true), r = pick(s, false);
+        d = en_single(F.data() + (kind ? 128 : 0), tab.data(), L, p, r);
+        flip2(kind ? xb : xa, p);
+        flip2(kind ? xb : xa, r);
+      } else if (kind < 4) {
+        const bool beta = kind == 3;
+        const int ne_s = beta ? nb : na;
+        if (ne_s < 2 || n - ne_s < 2) continue;
+        const uint64_t* s = beta ? b : a;
+        const int p = pick(s, true);
+        int q = pick(s, true);
+        while (q == p) q = pick(s, true);
+        const int r = pick(s, false);
+        int t = pick(s, false);
+        while (t == r) t = pick(s, false);
+        const double* Fs = F.data() + (beta ? 128 : 0);
+        d = en_double(Fs, Fs, tab.data(), L, p, q, r, t, true);
+        uint64_t* xs = beta ? xb : xa;
+        flip2(xs, p);
+        flip2(xs, q);
+        flip2(xs, r);
+        flip2(xs, t);
+      } else {
+        if (na == 0 || nb == 0 || na == n || nb == n) continue;
+        const int p = pick(a, true), r = pick(a, false);
+        const int q = pick(b, true), t = pick(b, false);
+        d = en_double(F.data(), F.data() + 128, tab.data(), L, p, q, r, t, false);
+        flip2(xa, p);
+        flip2(xa, r);
+        flip2(xb, q);
+        flip2(xb, t);
+      }
+      maxerr = std::fmax(maxerr, std::fabs((hii + d) - direct(xa, xb)));
+      ++nchk;
+    }
   }
-  printf("H_aa n=%d na=%d nb=%d: max |error| %.3g\n", n, na, nb, maxerr);
+  printf("H_aa update n=%d na=%d nb=%d (%d excitations): max |error| %.3g\n", n, na, nb, nchk, maxerr);
   return maxerr > 1e-11;
 }
 

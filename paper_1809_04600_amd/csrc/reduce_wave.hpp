@@ -1,17 +1,17 @@
 // Bucket reduce, one wavefront per bucket.
 //
 // After the hash partition a bucket holds on average ~100 records (at most
-// WCAP are handled here).  A wavefront loads the bucket's keys, forms 64-bit
-// sort keys (the hash bits below the bucket id, with the record's position in
+// WCAP are handled here).  A wavefront loads the bucket's keys, forms 32-bit
+// sort keys (24 hash bits below the bucket id, with the record's position in
 // the low byte) and sorts them by a bitonic network in registers, so equal
-// determinants become adjacent in record order.  Only the sorted keys are kept
-// in LDS (2 KB per wavefront): keys and values are read again from global
-// memory (cache-resident) when a segment head sums its segment, looks the
-// determinant up in the hash set of V, evaluates H_aa from the LDS diagonal
-// tables and accumulates the contribution.  No block-wide barrier is involved
-// after the diagonal tables are staged.  Buckets larger than WCAP, or in which
-// two different determinants share all sorted hash bits, are listed for the
-// block kernel (k_reduce), which sorts by the full key.
+// determinants become adjacent in record order.  The sorted keys and the full
+// hash of every record are kept in LDS (3 KB per wavefront): keys and values
+// are read again from global memory (cache-resident) when a segment head sums
+// its segment, looks the determinant up in the hash set of V, takes H_aa from
+// the record and accumulates the contribution.  No block-wide barrier is
+// involved.  Buckets larger than WCAP, or in which two different determinants
+// share all sorted hash bits, are listed for the block kernel (k_reduce),
+// which sorts by the full key.
 #pragma once
 #include "group.hpp"
 
@@ -20,15 +20,9 @@ namespace shci {
 constexpr int WCAP = 256;       // records per wavefront bucket
 constexpr int WRED_WAVES = 8;   // wavefronts per block
 
-SHCI_DEV uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const int lo = __shfl_xor((int)(uint32_t)v, m);
-  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
 // ascending bitonic sort of R*64 keys held as v[r] at element r*64 + lane
 template <int R>
-SHCI_DEV void wave_bitonic(uint64_t (&v)[R]) {
+SHCI_DEV void wave_bitonic(uint32_t (&v)[R]) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 2; k <= 64 * R; k <<= 1) {
@@ -41,16 +35,16 @@ SHCI_DEV void wave_bitonic(uint64_t (&v)[R]) {
         if (j >= 64) {
           const int rp = r ^ (j >> 6);
           if (rp > r) {
-            const uint64_t x = v[r], y = v[rp];
+            const uint32_t x = v[r], y = v[rp];
             const bool sw = up ? (x > y) : (x < y);
             v[r] = sw ? y : x;
             v[rp] = sw ? x : y;
           }
         } else {
-          const uint64_t p = shfl_xor_u64(v[r], j);
+          const uint32_t p = (uint32_t)__shfl_xor((int)v[r], j);
           const bool lower = (lane & j) == 0;
-          const uint64_t mn = v[r] < p ? v[r] : p;
-          const uint64_t mx = v[r] < p ? p : v[r];
+          const uint32_t mn = v[r] < p ? v[r] : p;
+          const uint32_t mx = v[r] < p ? p : v[r];
           v[r] = (lower == up) ? mn : mx;
         }
       }
@@ -58,9 +52,11 @@ SHCI_DEV void wave_bitonic(uint64_t (&v)[R]) {
   }
 }
 
-// per-wavefront LDS: the sorted keys of the current bucket
+// per-wavefront LDS: the sorted keys of the current bucket and the
+// determinant hash of each record (by position)
 struct WaveStage {
-  uint64_t sk[WCAP];
+  uint32_t sk[WCAP];
+  uint64_t h[WCAP];
 };
 
 struct WaveRedArgs {
@@ -71,22 +67,23 @@ struct WaveRedArgs {
   Partials Pw;             // per-wavefront partials (deterministic mode)
 };
 
-// load the bucket's keys, sort their 64-bit sort keys (R*64 >= M) and leave
-// them in W.sk
+// load the bucket's keys, sort their 32-bit sort keys (R*64 >= M) and leave
+// them in W.sk, the hashes in W.h
 template <int KW, int R>
 SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage& W, int64_t lo, int M) {
   const int lane = lane_id();
   const int bh = a.G.bits_hash;
-  uint64_t sk[R];
+  uint32_t sk[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = r * 64 + lane;
-    sk[r] = ~0ull;
+    sk[r] = ~0u;
     if (j < M) {
       uint64_t k[KW];
       load_key<KW>(a.in, lo + j, k);
       const uint64_t h = det_hash<KW>(k, a.n);
-      sk[r] = ((h << bh) & ~0xffull) | (uint64_t)j;
+      W.h[j] = h;
+      sk[r] = ((uint32_t)((h << bh) >> 32) & ~0xffu) | (uint32_t)j;
     }
   }
   wave_bitonic<R>(sk);
@@ -166,7 +163,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
   bool clash = false;
 #pragma unroll 1
   for (int e = lane + 1; e < M; e += 64) {
-    const uint64_t cur = W.sk[e], prv = W.sk[e - 1];
+    const uint32_t cur = W.sk[e], prv = W.sk[e - 1];
     if ((cur >> 8) == (prv >> 8)) {
       uint64_t kx[KW], ky[KW];
       key_of((int)(cur & 0xff), kx);
@@ -185,7 +182,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
 #pragma unroll 1
   for (int base = 0; base < M; base += 64) {
     const int e0 = base + lane;
-    const uint64_t s0 = (e0 < M) ? W.sk[e0] : 0ull;
+    const uint32_t s0 = (e0 < M) ? W.sk[e0] : 0u;
     const bool head = e0 < M && (e0 == 0 || (s0 >> 8) != (W.sk[e0 - 1] >> 8));
     const uint64_t hb = ballot(head);
     if (head) {
@@ -210,10 +207,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
 #pragma unroll
       for (int w = 0; w < KW; ++w) dk[w] = k[w];
       mask_det<KW>(dk, n);  // determinant bits only (no sample id)
-      // the determinant hash is the bucket's hash bits above the sorted bits
-      // when those reach the low byte, else recomputed
-      const uint64_t hb_part = (uint64_t)b & ((bh >= 64) ? ~0ull : ((1ull << bh) - 1ull));
-      const uint64_t h = (bh >= 8) ? ((hb_part << (64 - bh)) | ((s0 & ~0xffull) >> bh)) : det_hash<KW>(dk, n);
+      const uint64_t h = W.h[first];
       const bool inv = vset_contains_h<KW>(a.V, dk, h, n);
       const int cntk = e1 - e0;
       acc.ngen += cntk;
@@ -250,7 +244,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
         const int64_t o = lo + nbefore + rank_below(hb);
 #pragma unroll
         for (int w = 0; w < KW; ++w) a.U.k[w][o] = k[w];
-        a.U.h2[o] = (uint32_t)(s0 >> 32);
+        a.U.h2[o] = (uint32_t)((h << bh) >> 32);
         // deterministic: A_a, D_a, 2 A_a / D_a; sample: 2 X^d G, G, 2 X G with
         // G = 1 / (D_a Nd (Nd - 1)) (the adjoint's per-a factors)
         a.U.A[o] = SAMPLE ? gd : X;
@@ -261,12 +255,9 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
     }
     nbefore += __popcll(hb);
   }
-  if constexpr (SAMPLE) {
-    wave_write_partials(a.P, b, acc);
-    acc = SegAcc();
-  } else if (lane == 0) {
-    wave_zero_partials(a.P, b);
-  }
+  // the contributions stay in acc; the caller writes them once per run of
+  // buckets (sample mode) or once per wavefront
+  if (lane == 0) wave_zero_partials(a.P, b);
   if (lane == 0) {
     a.P.nseg[b] = nbefore;
     if (a.want_u) a.U.start[b] = (uint64_t)lo;
@@ -283,8 +274,20 @@ __global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_p
   const int lane = t & 63;
   WaveStage& W = WS[wv];
   const int64_t nwaves = (int64_t)gridDim.x * WRED_WAVES;
+  const int bh = a.G.bits_hash;
   SegAcc acc;
+  // sample mode: the buckets of one sample that this wavefront reduced add
+  // up in acc and are written into the partials of the last of them (the
+  // others hold zeros), so the cross-lane reduction runs once per sample
+  int64_t last_ok = -1;
   for (int64_t b = (int64_t)blockIdx.x * WRED_WAVES + wv; b < a.G.nbucket; b += nwaves) {
+    if constexpr (SAMPLE) {
+      if (last_ok >= 0 && (b >> bh) != (last_ok >> bh)) {
+        wave_write_partials(a.P, last_ok, acc);
+        acc = SegAcc();
+        last_ok = -1;
+      }
+    }
     const int64_t lo = (int64_t)A.bstart[b];
     const int64_t M = (int64_t)A.bstart[b + 1] - lo;
     if (M > WCAP) {
@@ -300,12 +303,16 @@ __global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_p
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    wave_bucket<KW, SAMPLE, VT>(a, W, b, lo, (int)M, A.slow_list, A.slow_count, acc);
+    if (wave_bucket<KW, SAMPLE, VT>(a, W, b, lo, (int)M, A.slow_list, A.slow_count, acc)) last_ok = b;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if constexpr (!SAMPLE) wave_write_partials(A.Pw, (int64_t)blockIdx.x * WRED_WAVES + wv, acc);
+  if constexpr (SAMPLE) {
+    if (last_ok >= 0) wave_write_partials(a.P, last_ok, acc);
+  } else {
+    wave_write_partials(A.Pw, (int64_t)blockIdx.x * WRED_WAVES + wv, acc);
+  }
 }
 
 // bucket start offsets from the bucket id of every record (records are

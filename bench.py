@@ -211,9 +211,9 @@ def main():
     tsrc = src if sampled else avg64
     kw = src["key_words"]
     launches = src["n_chunks"] if sampled else 1
-    # record bytes: packed key + value(s) + bucket id
-    rec64 = 8 * kw + src["value_bytes"] + 4
-    rec32 = 8 * kw + (s32["sample"] if sampled else s32)["value_bytes"] + 4
+    # record bytes: packed key + value(s) + H_aa (FP64) + bucket id
+    rec64 = 8 * kw + src["value_bytes"] + 8 + 4
+    rec32 = 8 * kw + (s32["sample"] if sampled else s32)["value_bytes"] + 8 + 4
     nrec_src = src["n_records"]
     npass = math.ceil(math.log2(max(src["n_buckets"], 1)) / 8) if src["n_buckets"] > 1 else 0
     kernels = {"k_gen(count)": tsrc["ms_k_count"], "k_gen(write)": tsrc["ms_k_write"],

@@ -240,25 +240,72 @@ struct ScatterShared {
 // record handled by (wavefront wv, lane, round j) within a tile
 SHCI_DEV int tile_slot(int wv, int lane, int j) { return wv * (PTILE / PWAVES) + j * 64 + lane; }
 
+// bit pattern of a 4- or 8-byte value in a 64-bit register, and back
 template <typename T>
-SHCI_DEV void stage_copy(ScatterShared& L, const T* in, T* out, int64_t base, int tile_n,
-                         const uint16_t (&lpos)[PW_ITEMS]) {
+SHCI_DEV uint64_t to_bits(T v) {
+  if constexpr (sizeof(T) == 8) {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    return u;
+  } else {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    return u;
+  }
+}
+template <typename T>
+SHCI_DEV T from_bits(uint64_t u) {
+  T v;
+  if constexpr (sizeof(T) == 8) {
+    __builtin_memcpy(&v, &u, 8);
+  } else {
+    const uint32_t w = (uint32_t)u;
+    __builtin_memcpy(&v, &w, 4);
+  }
+  return v;
+}
+
+// One record array of a tile: values of this thread's records (held in
+// 64-bit registers, 4-byte arrays zero-extended) are placed at their local
+// positions in LDS, then written out as contiguous digit runs.
+template <typename T>
+SHCI_DEV void tile_load(const T* in, int64_t base, int tile_n, uint64_t (&r)[PW_ITEMS]) {
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  // every load is issued (slots past the tile re-read its first record), so
+  // the loads of a thread are in flight together
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    const int q = tile_slot(wv, lane, j);
+    r[j] = to_bits<T>(in[base + (q < tile_n ? q : 0)]);
+  }
+}
+
+template <typename T>
+SHCI_DEV void tile_scatter(ScatterShared& L, const uint64_t (&r)[PW_ITEMS], T* out, int tile_n,
+                           const uint16_t (&lpos)[PW_ITEMS]) {
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   T* st = reinterpret_cast<T*>(L.stage);
 #pragma unroll
   for (int j = 0; j < PW_ITEMS; ++j) {
     const int q = tile_slot(wv, lane, j);
-    if (q < tile_n) st[lpos[j]] = in[base + q];
+    if (q < tile_n) st[lpos[j]] = from_bits<T>(r[j]);
   }
   __syncthreads();
+  // all LDS reads first, then the stores (distinct registers, so the stores
+  // issue back to back)
+  T val[PW_ITEMS];
+  int64_t dst[PW_ITEMS];
 #pragma unroll
   for (int j = 0; j < PW_ITEMS; ++j) {
     const int q = j * PTHREADS + t;
-    if (q < tile_n) {
-      const uint32_t d = L.sdig[q];
-      out[(int64_t)L.gbase[d] + (q - (int)L.lstart[d])] = st[q];
-    }
+    const int qq = q < tile_n ? q : 0;
+    const uint32_t d = L.sdig[qq];
+    dst[j] = (int64_t)L.gbase[d] + (qq - (int)L.lstart[d]);
+    val[j] = st[qq];
   }
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j)
+    if (j * PTHREADS + t < tile_n) out[dst[j]] = val[j];
   __syncthreads();
 }
 
@@ -280,11 +327,16 @@ __global__ void __launch_bounds__(PTHREADS) k_part_scatter(PassArgs a) {
   uint16_t lpos[PW_ITEMS];
   uint8_t dig[PW_ITEMS];
   uint16_t* wc = L.wc[wv];
+  // bucket ids of this thread's records, then (in flight during the ranking)
+  // the first key word
+  uint64_t ids[PW_ITEMS], cur[PW_ITEMS], nxt[PW_ITEMS];
+  tile_load<uint32_t>(a.in.bid, base, tile_n, ids);
+  tile_load<uint64_t>(a.in.k[0], base, tile_n, cur);
 #pragma unroll
   for (int j = 0; j < PW_ITEMS; ++j) {
     const int q = tile_slot(wv, lane, j);
     const bool valid = q < tile_n;
-    const uint32_t d = valid ? ((a.in.bid[base + q] >> a.shift) & dmask) : 0u;
+    const uint32_t d = valid ? (((uint32_t)ids[j] >> a.shift) & dmask) : 0u;
     uint64_t peers = ballot(valid);
     for (int bb = 0; bb < a.dbits; ++bb) {
       const bool on = (d >> bb) & 1u;
@@ -327,14 +379,56 @@ __global__ void __launch_bounds__(PTHREADS) k_part_scatter(PassArgs a) {
     if (q < tile_n) L.sdig[lpos[j]] = dig[j];
   }
   __syncthreads();
+  // arrays in order: key words, v, [v2], H_aa, [payload], bucket id; the
+  // next array's loads are issued before the current one is written
+  constexpr int NA = KW + 3 + (V2 ? 1 : 0) + (PAY ? 1 : 0);
+  auto load_arr = [&](int x, uint64_t (&r)[PW_ITEMS]) {
+    if (x < KW) {
 #pragma unroll
-  for (int w = 0; w < KW; ++w) stage_copy<uint64_t>(L, a.in.k[w], a.out.k[w], base, tile_n, lpos);
-  stage_copy<VT>(L, static_cast<const VT*>(a.in.v), static_cast<VT*>(a.out.v), base, tile_n, lpos);
-  if constexpr (V2)
-    stage_copy<VT>(L, static_cast<const VT*>(a.in.v2), static_cast<VT*>(a.out.v2), base, tile_n, lpos);
-  if constexpr (PAY) stage_copy<uint32_t>(L, a.in.pay, a.out.pay, base, tile_n, lpos);
-  stage_copy<double>(L, a.in.haa, a.out.haa, base, tile_n, lpos);
-  stage_copy<uint32_t>(L, a.in.bid, a.out.bid, base, tile_n, lpos);
+      for (int w = 0; w < KW; ++w)
+        if (w == x) tile_load<uint64_t>(a.in.k[w], base, tile_n, r);
+      return;
+    }
+    x -= KW;
+    if (x == 0) return tile_load<VT>(static_cast<const VT*>(a.in.v), base, tile_n, r);
+    if constexpr (V2) {
+      if (x == 1) return tile_load<VT>(static_cast<const VT*>(a.in.v2), base, tile_n, r);
+      x -= 1;
+    }
+    if (x == 1) return tile_load<double>(a.in.haa, base, tile_n, r);
+    if constexpr (PAY) {
+      if (x == 2) return tile_load<uint32_t>(a.in.pay, base, tile_n, r);
+      x -= 1;
+    }
+    tile_load<uint32_t>(a.in.bid, base, tile_n, r);
+  };
+  auto store_arr = [&](int x, const uint64_t (&r)[PW_ITEMS]) {
+    if (x < KW) {
+#pragma unroll
+      for (int w = 0; w < KW; ++w)
+        if (w == x) tile_scatter<uint64_t>(L, r, a.out.k[w], tile_n, lpos);
+      return;
+    }
+    x -= KW;
+    if (x == 0) return tile_scatter<VT>(L, r, static_cast<VT*>(a.out.v), tile_n, lpos);
+    if constexpr (V2) {
+      if (x == 1) return tile_scatter<VT>(L, r, static_cast<VT*>(a.out.v2), tile_n, lpos);
+      x -= 1;
+    }
+    if (x == 1) return tile_scatter<double>(L, r, a.out.haa, tile_n, lpos);
+    if constexpr (PAY) {
+      if (x == 2) return tile_scatter<uint32_t>(L, r, a.out.pay, tile_n, lpos);
+      x -= 1;
+    }
+    tile_scatter<uint32_t>(L, r, a.out.bid, tile_n, lpos);
+  };
+#pragma unroll
+  for (int x = 0; x < NA; ++x) {
+    if (x + 1 < NA) load_arr(x + 1, nxt);
+    store_arr(x, cur);
+#pragma unroll
+    for (int j = 0; j < PW_ITEMS; ++j) cur[j] = nxt[j];
+  }
 }
 
 // ---------------------------------------------------------------------------

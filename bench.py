@@ -59,11 +59,12 @@ def kernel_sources_sha256():
 def kernel_names(kind, kw, sampled):
     """Full FP64 kernel names behind a bench kernel label."""
     smp = "true" if sampled else "false"
-    return {"k_gen(count)": [f"void shci::k_gen<{kw}, 0, {smp}, double>(shci::GenArgs)"],
-            "k_gen(write)": [f"void shci::k_gen<{kw}, 1, {smp}, double>(shci::GenArgs)"],
+    return {"k_gen(count)": [f"void shci::k_gen_count<{kw}, {smp}, double>(shci::GenArgs)"],
+            "k_gen(write)": [f"void shci::k_gen_write_sample<{kw}, double>(shci::GenArgs)" if sampled
+                             else f"void shci::k_gen_write<{kw}, double>(shci::GenArgs)"],
             "partition": [f"void shci::k_part_hist<{kw}>(shci::PassArgs)",
                           f"void shci::k_part_scatter<{kw}, double, {smp}, false>(shci::PassArgs)"],
-            "k_reduce": [f"void shci::k_reduce_wave<{kw}, {smp}, double, true>(shci::WaveRedArgs)"]}[kind]
+            "k_reduce": [f"void shci::k_reduce_wave<{kw}, {smp}, double>(shci::WaveRedArgs)"]}[kind]
 
 
 def measured_traffic(workload, names):

@@ -510,7 +510,7 @@ int run_job(Job& J) {
   const int gen_grid = cus * GEN_BLOCKS_PER_CU;
   k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
   HIPCHK(hipEventRecord(X->ev[4], st));
-  k_gen<KW, GEN_COUNT, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+  k_gen_count<KW, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
   HIPCHK(hipEventRecord(X->ev[5], st));
   HIPCHK(hipGetLastError());
   CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, total1, st));
@@ -624,7 +624,10 @@ int run_job(Job& J) {
       g.bits_hash = G.bits_hash;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
       HIPCHK(hipEventRecord(X->ev[6], st));
-      k_gen<KW, GEN_WRITE, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+      if constexpr (SAMPLE)
+        k_gen_write_sample<KW, VT><<<gen_grid, 256, 0, st>>>(g);
+      else
+        k_gen_write<KW, VT><<<gen_grid, 256, 0, st>>>(g);
       HIPCHK(hipEventRecord(X->ev[7], st));
       HIPCHK(hipGetLastError());
       if (J.ex && J.ex->t_keys && J.ex->t_cap > 0 && pay) {
@@ -770,7 +773,7 @@ int run_job(Job& J) {
       g.L = L;
       g.grad = gpart;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
-      k_gen<KW, GEN_GRAD, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+      k_gen_grad<KW, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
       if constexpr (SAMPLE) {
         k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, gitem, 0);
         for (int32_t smp = 0; smp < J.nsamp; ++smp) {

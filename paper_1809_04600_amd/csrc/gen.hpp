@@ -111,7 +111,7 @@ SHCI_DEV int64_t lookup_u(const uint64_t (&key)[KW], int n, uint32_t sid, const 
 }
 
 template <int KW, int MODE, bool SAMPLE, typename VT>
-__global__ void __launch_bounds__(256) k_gen(GenArgs a) {
+SHCI_DEV void gen_body(const GenArgs& a) {
   __shared__ uint8_t s_lists[4][4][128];
   __shared__ uint16_t s_dl[4][DL_CAP];   // differences of the source from R
   __shared__ uint16_t s_sq[4][128];      // queue of singles candidates
@@ -663,6 +663,27 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     }
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+// The walks of the generator.  The count walk carries the least state and
+// gains from six wavefronts per SIMD, the deterministic write walk from five;
+// the sample write walk and the adjoint walk keep the compiler's choice (all
+// measured).
+template <int KW, bool SAMPLE, typename VT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_gen_count(GenArgs a) {
+  gen_body<KW, GEN_COUNT, SAMPLE, VT>(a);
+}
+template <int KW, typename VT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_gen_write(GenArgs a) {
+  gen_body<KW, GEN_WRITE, false, VT>(a);
+}
+template <int KW, typename VT>
+__global__ void __launch_bounds__(256) k_gen_write_sample(GenArgs a) {
+  gen_body<KW, GEN_WRITE, true, VT>(a);
+}
+template <int KW, bool SAMPLE, typename VT>
+__global__ void __launch_bounds__(256) k_gen_grad(GenArgs a) {
+  gen_body<KW, GEN_GRAD, SAMPLE, VT>(a);
 }
 
 // dE2/dc_i = sum of the partial adjoints of the work items of source i, in

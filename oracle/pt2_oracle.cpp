@@ -18,7 +18,9 @@
 //   * the gradient dE2/dc_i = sum_a 2 H_ai A_a / D_a and dE2/dE0 =
 //     -sum_a A_a^2 / D_a^2 at a frozen screening mask;
 //   * helpers that build workload inputs: <c|H|c> and the MP1-like amplitudes
-//     H_i0 / (E_HF - H_ii) of the doubles of the Hartree-Fock determinant.
+//     H_i0 / (E_HF - H_ii) of the doubles of the Hartree-Fock determinant;
+//   * H c on the variational space, row by row over every pair (the product
+//     that section III evaluates through alpha/beta string lists).
 //
 // Method: every single and double excitation of every variational determinant
 // is enumerated by brute force (no heat-bath table, no early exit); matrix
@@ -909,6 +911,41 @@ double oracle_energy(int n, int na, int nb, const double* h1, const double* eri,
   Neumaier e;
   for (int64_t i = 0; i < nd; ++i) e.add(row[i]);
   return e.value();
+}
+
+// H c on the variational space, row by row (the fast evaluation through alpha
+// and beta string lists is the subject of section III and Algorithms 1-2; the
+// oracle takes every pair): for each requested row i,
+//   y_i = sum_j <i|H|j> c_j over all j of V in index order (Neumaier sum,
+//         <i|H|j> evaluated from the source j),
+// and the number of j != i that differ from i by one or two excitations.
+int oracle_hc_rows(int n, int na, int nb, const double* h1, const double* eri, const uint64_t* dets,
+                   const double* c, int64_t nd, const int64_t* rows, int64_t nrows, double* y,
+                   int64_t* nconn) {
+  System S{n, na, nb, h1, eri};
+  const Det* V = reinterpret_cast<const Det*>(dets);
+  if (int st = validate(S, V, c, nd)) return st;
+  for (int64_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] >= nd) {
+      snprintf(g_err, sizeof g_err, "row %lld outside [0, %lld)", (long long)rows[r], (long long)nd);
+      return -6;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    Neumaier acc;
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < nd; ++j) {
+      int diff = 0;
+      for (int w = 0; w < 4; ++w) diff += __builtin_popcountll(V[i].w[w] ^ V[j].w[w]);
+      if (diff > 4) continue;
+      if (j != i) ++cnt;
+      acc.add(hij(S, V[i], V[j]) * c[j]);
+    }
+    y[r] = acc.value();
+    nconn[r] = cnt;
+  }
+  return 0;
 }
 
 // <c|H|c> for large V without visiting every pair.  Two distinct

@@ -75,6 +75,8 @@ def lib():
         L.oracle_energy_cores.restype = _d
         L.oracle_energy_cores.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _i, _i, _p]
         L.oracle_mp1.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _p, _p]
+        L.oracle_hc_rows.restype = _i
+        L.oracle_hc_rows.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _p, _i64, _p, _p]
         L.oracle_max_threads.restype = _i
         _lib = L
     return _lib
@@ -294,6 +296,24 @@ def energy(n, na, nb, h1, eri, dets, c) -> float:
     dets = np.ascontiguousarray(dets, dtype=np.uint64)
     c = np.ascontiguousarray(c, dtype=np.float64)
     return lib().oracle_energy(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c))
+
+
+def hc_rows(n, na, nb, h1, eri, dets, c, rows=None):
+    """Rows of H c on V by every pair: (y [m], connections [m]) for the given
+    row indices (all rows when None); connections counts the j != i within
+    two excitations."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    rows = np.arange(len(c), dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.zeros(len(rows))
+    cnt = np.zeros(len(rows), dtype=np.int64)
+    L = lib()
+    st = L.oracle_hc_rows(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c), _ptr(rows), len(rows),
+                          _ptr(y), _ptr(cnt))
+    if st:
+        raise OracleError(st, L.oracle_last_error().decode())
+    return y, cnt
 
 
 def terms_of(n, na, nb, h1, eri, dets, c, eps2, sources):

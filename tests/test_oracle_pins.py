@@ -371,3 +371,31 @@ def test_hash_batches_partition_p():
     per_b = np.array([ref.pt2_sample_batched(*args, 1e-6, 1e-4, draws, nbat, np.full(3, b, np.int32))
                       for b in range(nbat)])
     assert np.abs(per_b.mean(axis=0) - full).max() <= 1e-12 * max(1.0, np.abs(full).max())
+
+
+def test_hc_rows_match_dense_linear_algebra(space_227, space_226):
+    """H c on V against the second-quantised Hamiltonian restricted to V, and
+    the connection counts against the excitation degree counted on the bit
+    strings."""
+    for (x, dets, index, H, W), (n, na, nb) in ((space_227, (7, 3, 2)), (space_226, (6, 2, 2))):
+        rng = np.random.default_rng(17)
+        v = _random_v(rng, len(dets), min(len(dets), 90))
+        c = rng.standard_normal(len(v))
+        y, cnt = ref.hc_rows(n, na, nb, x.h1, x.eri, W[v], c)
+        want = H[np.ix_(v, v)] @ c
+        assert np.abs(y - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+        # degree: half the number of differing spin orbitals
+        deg = np.array([[bin(dets[i] ^ dets[j]).count("1") // 2 for j in v] for i in v])
+        assert np.array_equal(cnt, ((deg >= 1) & (deg <= 2)).sum(axis=1))
+        # a subset of rows gives the same values
+        rows = np.array([3, 0, len(v) - 1])
+        y2, cnt2 = ref.hc_rows(n, na, nb, x.h1, x.eri, W[v], c, rows)
+        assert np.array_equal(y2, y[rows]) and np.array_equal(cnt2, cnt[rows])
+        # c^T H c of the rows is the variational energy
+        assert abs(c @ y - c @ want) <= 1e-12 * max(1.0, abs(c @ want))
+
+
+def test_hc_rows_rejects_bad_rows(space_227):
+    x, dets, index, H, W = space_227
+    with pytest.raises(ref.OracleError):
+        ref.hc_rows(7, 3, 2, x.h1, x.eri, W[:5], np.ones(5), np.array([5]))

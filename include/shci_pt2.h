@@ -290,6 +290,26 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
                   double e0, double eps2, int precision, void* stream, double* e2,
                   double* de2_dc, double* de2_de0, shci_pt2_stats* st);
 
+/* y = H c on the variational space (section III: the alpha/beta string lists
+ * of Table I and the connection loops of Algorithms 1-2), and the
+ * variational energy <c|H|c>/<c|c>.  Determinants are grouped by their alpha
+ * and by their beta string; row i visits its beta group (alpha singles and
+ * doubles), its alpha group (beta singles and doubles) and, through the
+ * alpha-singles lists, the determinants one alpha and one beta single away.
+ *   dets   device uint64 [n_det][4] (input layout), unique; c device FP64 [n_det]
+ *   y      device FP64 [n_det], out: sum_j H_ij c_j (H_ii c_i included)
+ *   n_conn device uint32 [n_det] or NULL, out: the j != i one or two
+ *          excitations from i
+ *   e_var  host or NULL, out: <c|H|c> / <c|c>
+ *   st     host or NULL: n_terms = sum of n_conn, n_records = length of the
+ *          alpha-singles lists, ms_gen (lists), ms_reduce (rows), ms_total
+ * FP64 throughout; rows are summed in a fixed order, so y is deterministic.
+ * Errors: SHCI_ERR_ARG (NULL, n_det outside [1, 2^31 - 1)), SHCI_ERR_DET,
+ * SHCI_ERR_DUP, SHCI_ERR_NONFINITE (c), SHCI_ERR_WORKSPACE, SHCI_ERR_HIP.
+ * The library allocates and frees its workspace inside the call. */
+int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, void* stream,
+                double* y, uint32_t* n_conn, double* e_var, shci_pt2_stats* st);
+
 /* Message for the last non-OK status returned to the calling thread. */
 const char* shci_pt2_last_error(void);
 

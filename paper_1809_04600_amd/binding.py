@@ -111,6 +111,8 @@ def lib():
         L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), p, C.POINTER(d),
                                     C.POINTER(Stats)]
         L.shci_pt2_grad.restype = i
+        L.shci_pt2_hc.argtypes = [p, p, p, i64, p, p, p, C.POINTER(d), C.POINTER(Stats)]
+        L.shci_pt2_hc.restype = i
         _lib = L
     return _lib
 
@@ -292,6 +294,19 @@ class Context:
                                      C.c_void_p(vals.data_ptr()), cap, C.byref(n_out), C.byref(st)))
         k = n_out.value
         return keys[:k], vals[:k]
+
+    def hc(self, dets, c):
+        """y = H c on the variational space and <c|H|c>/<c|c>: returns
+        (y tensor, connections per row tensor (int32 view of uint32), e_var,
+        stats)."""
+        pd, pc, nd = self._inputs(dets, c)
+        y = torch.empty(nd, dtype=torch.float64, device=c.device)
+        conn = torch.empty(nd, dtype=torch.int32, device=c.device)
+        ev = C.c_double()
+        st = Stats()
+        _check(lib().shci_pt2_hc(self._ptr, pd, pc, nd, _stream(), C.c_void_p(y.data_ptr()),
+                                 C.c_void_p(conn.data_ptr()), C.byref(ev), C.byref(st)))
+        return y, conn, ev.value, st.as_dict()
 
     def three_step(self, dets, c, e0, eps2_dtm, eps2_psto, eps2, target_error, nb_psto, nb_sto, draws,
                    sample_batch, precision="fp64"):

@@ -11,6 +11,7 @@
 
 #include "../../include/shci_pt2.h"
 #include "group.hpp"
+#include "hc.hpp"
 #include "reduce_wave.hpp"
 #include "scan.hpp"
 
@@ -1022,6 +1023,10 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     T.hb_rs = cv.take<uint16_t>(nhb);
     T.hb_max = cv.take<double>(T.nss + n2);
     T.mag_cum = cv.take<double>(144);
+    {
+      const int64_t npair = (int64_t)n * (n + 1) / 2;
+      T.g8 = cv.take<double>(npair * (npair + 1) / 2);
+    }
     X->dflag = cv.take<uint32_t>(16);
     X->dres = cv.take<DevResult>(1);
 
@@ -1541,6 +1546,154 @@ int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
       hipStreamSynchronize(s) != hipSuccess)
     return done(fail(SHCI_ERR_HIP, "selection count copy failed"));
   *n_out = (int64_t)h;
+  return done(SHCI_OK);
+}
+
+int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, void* stream,
+                double* y, uint32_t* n_conn, double* e_var, shci_pt2_stats* st) {
+  if (!ctx || !dets || !c || !y) return fail(SHCI_ERR_ARG, "ctx, dets, c and y must be non-NULL");
+  if (n_det < 1 || n_det >= (int64_t)0x7fffffff) return fail(SHCI_ERR_ARG, "n_det must be in [1, 2^31 - 1)");
+  if (st) *st = shci_pt2_stats{};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Tables& T = ctx->T;
+  const int64_t n = n_det;
+  const uint64_t cap = 1ull << ceil_log2((uint64_t)(2 * n));
+  const int64_t ntiles = (n + PAIR_TILE - 1) / PAIR_TILE;
+  int passes = 0;
+  while (passes < 4 && ((uint64_t)(n - 1) >> (8 * passes)) != 0) ++passes;
+  if (passes == 0) passes = 1;
+  // workspace: string tables, groups, two pair-sort buffer sets per spin,
+  // histograms, group starts, singles counts and offsets
+  DevBuf ws, wl;
+  struct Plan {
+    uint32_t *slot[2], *grp[2], *k0[2], *v0[2], *k1[2], *v1[2], *hist, *hoffs, *scnt, *cnt_tmp;
+    uint64_t *start[2], *soff, *tot;
+    double* dots;
+    ScanTmp sh, ss;
+  } P{};
+  auto plan = [&](Carver& cv) {
+    for (int sp = 0; sp < 2; ++sp) {
+      P.slot[sp] = cv.take<uint32_t>(cap);
+      P.grp[sp] = cv.take<uint32_t>(n);
+      P.k0[sp] = cv.take<uint32_t>(n);
+      P.v0[sp] = cv.take<uint32_t>(n);
+      P.k1[sp] = cv.take<uint32_t>(n);
+      P.v1[sp] = cv.take<uint32_t>(n);
+      P.start[sp] = cv.take<uint64_t>(n + 1);
+    }
+    P.hist = cv.take<uint32_t>(256 * ntiles);
+    P.hoffs = cv.take<uint32_t>(256 * ntiles);
+    P.scnt = cv.take<uint32_t>(n + 1);
+    P.cnt_tmp = cv.take<uint32_t>(n);
+    P.soff = cv.take<uint64_t>(n + 1);
+    P.tot = cv.take<uint64_t>(2);
+    P.dots = cv.take<double>(2);
+    P.sh.carve(cv, 256 * ntiles);
+    P.ss.carve(cv, n + 1);
+  };
+  {
+    Carver cv(nullptr);
+    plan(cv);
+    CHK(ws.ensure(cv.off, ctx->ws_limit));
+    Carver cv2(ws.p);
+    plan(cv2);
+  }
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    ws.release();
+    wl.release();
+    return code;
+  };
+  const int g1 = (int)((n + 255) / 256);
+  const int gw = (int)std::min<int64_t>((n + 3) / 4, (int64_t)num_cus(ctx->device) * 16);
+  HIPCHK(hipEventRecord(ctx->ev[0], s));
+  k_fill_u32<<<1, 64, 0, s>>>(ctx->dflag, 4, 0u);
+  k_validate<<<g1, 256, 0, s>>>(dets, c, n, T.n, T.na, T.nb, ctx->dflag);
+  for (int sp = 0; sp < 2; ++sp) {
+    StrTab tab{P.slot[sp], cap - 1};
+    k_fill_u32<<<(int)std::min<uint64_t>(4096, (cap + 255) / 256), 256, 0, s>>>(P.slot[sp], (int64_t)cap, STR_EMPTY);
+    k_str_insert<<<g1, 256, 0, s>>>(dets, n, sp, tab);
+    k_str_group<<<g1, 256, 0, s>>>(dets, n, sp, tab, P.grp[sp]);
+    // members of each group in index order: stable sort of (group, index)
+    k_pair_init<<<g1, 256, 0, s>>>(P.grp[sp], n, P.k0[sp], P.v0[sp]);
+    uint32_t *kin = P.k0[sp], *vin = P.v0[sp], *kout = P.k1[sp], *vout = P.v1[sp];
+    const int pg = (int)((ntiles + 3) / 4);
+    for (int pass = 0; pass < passes; ++pass) {
+      k_pair_count<<<pg, 256, 0, s>>>(kin, n, 8 * pass, ntiles, P.hist);
+      int r = scan_exclusive<uint32_t, uint32_t>(P.hist, P.hoffs, 256 * ntiles, P.sh, nullptr, s);
+      if (r) return done(r);
+      k_pair_place<<<pg, 256, 0, s>>>(kin, vin, n, 8 * pass, ntiles, P.hoffs, kout, vout);
+      std::swap(kin, kout);
+      std::swap(vin, vout);
+    }
+    // kin: sorted groups, vin: members
+    P.k0[sp] = kin;
+    P.v0[sp] = vin;
+    k_bucket_bounds<<<(int)std::min<int64_t>(8192, (n + 256) / 256), 256, 0, s>>>(kin, n, n, P.start[sp]);
+  }
+  // alpha-singles lists of the alpha groups
+  StrTab ta{P.slot[0], cap - 1};
+  SinglesArgs sa{dets, n, T.n, T.na, ta, P.grp[0], P.scnt, P.soff, nullptr};
+  k_fill_u32<<<g1 + 1, 256, 0, s>>>(P.scnt, n + 1, 0u);
+  k_str_singles<false><<<gw, 256, 0, s>>>(sa);
+  {
+    int r = scan_exclusive<uint32_t, uint64_t>(P.scnt, P.soff, n + 1, P.ss, nullptr, s);
+    if (r) return done(r);
+  }
+  uint64_t nsl = 0;
+  uint32_t hf = 0;
+  if (hipMemcpyAsync(&nsl, P.soff + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(fail(SHCI_ERR_HIP, "string list preparation failed"));
+  if (hf & 1u) return done(fail(SHCI_ERR_DET, "a determinant has a wrong electron count or an orbital >= n_orb"));
+  if (hf & 2u) return done(fail(SHCI_ERR_NONFINITE, "c holds a NaN or Inf"));
+  CHK(wl.ensure(std::max<uint64_t>(1, nsl) * sizeof(uint32_t), ctx->ws_limit));
+  sa.list = static_cast<uint32_t*>(wl.p);
+  if (nsl) k_str_singles<true><<<gw, 256, 0, s>>>(sa);
+  HcArgs ha{};
+  ha.T = T;
+  ha.dets = dets;
+  ha.c = c;
+  ha.nd = n;
+  ha.grpA = P.grp[0];
+  ha.grpB = P.grp[1];
+  ha.memA = P.v0[0];
+  ha.memB = P.v0[1];
+  ha.startA = P.start[0];
+  ha.startB = P.start[1];
+  ha.soff = P.soff;
+  ha.slist = sa.list;
+  ha.y = y;
+  ha.nconn = n_conn ? n_conn : P.cnt_tmp;
+  ha.flag = ctx->dflag;
+  HIPCHK(hipEventRecord(ctx->ev[1], s));
+  k_hc_rows<<<gw, 256, 0, s>>>(ha);
+  HIPCHK(hipEventRecord(ctx->ev[2], s));
+  k_sum_u32<<<1, 1024, 0, s>>>(ha.nconn, n, P.tot);
+  k_dot2<<<1, 1024, 0, s>>>(c, y, n, P.dots);
+  HIPCHK(hipEventRecord(ctx->ev[3], s));
+  HIPCHK(hipGetLastError());
+  double dots[2] = {0.0, 0.0};
+  uint64_t nconn_tot = 0;
+  if (hipMemcpyAsync(dots, P.dots, sizeof dots, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&nconn_tot, P.tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(fail(SHCI_ERR_HIP, "H c failed: %s", hipGetErrorString(hipGetLastError())));
+  if (hf & 4u) return done(fail(SHCI_ERR_DUP, "the variational space contains a duplicate determinant"));
+  if (e_var) *e_var = dots[0] / dots[1];
+  if (st) {
+    float a = 0.f, b = 0.f, t = 0.f;
+    (void)hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]);
+    (void)hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]);
+    (void)hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]);
+    st->n_terms = (int64_t)nconn_tot;
+    st->n_records = (int64_t)nsl;
+    st->ms_gen = a;
+    st->ms_reduce = b;
+    st->ms_total = t;
+  }
   return done(SHCI_OK);
 }
 

@@ -22,6 +22,8 @@ struct Tables {
   uint16_t* hb_rs = nullptr; // r | s << 8
   double* hb_max = nullptr;  // per key, largest |value| (0 if empty)
   double* mag_cum = nullptr; // [2][72] entries with |value| >= 2^e, e = -64..7, per table kind
+  double* g8 = nullptr;      // (pq|rs) folded by its 8-fold symmetry: pair indices P = pq, Q = rs
+                             // (x(x+1)/2 + y, x >= y), entry max(P,Q)(max+1)/2 + min(P,Q)
 };
 
 int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st, uint32_t* dflag);

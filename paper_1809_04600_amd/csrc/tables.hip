@@ -217,6 +217,28 @@ void singles_ref(const Tables& T, const uint64_t* ref, hipStream_t st) {
   k_singles_ref<<<(m + 255) / 256, 256, 0, st>>>(ref, T.h1, T.sD, T.sJ, T.n, T.fref);
 }
 
+// (pq|rs) folded by the 8-fold symmetry: entry k of the (P, Q) triangle with
+// P = pq and Q = rs pair indices (the integrals are symmetric bit for bit, so
+// any representative is exact)
+__global__ void k_eri8(const double* eri, int n, int64_t npair, double* g8) {
+  const int64_t tot = npair * (npair + 1) / 2;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t P = (int64_t)floor((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+    while (P * (P + 1) / 2 > k) --P;
+    while ((P + 1) * (P + 2) / 2 <= k) ++P;
+    const int64_t Q = k - P * (P + 1) / 2;
+    int p = (int)floor((sqrt(8.0 * (double)P + 1.0) - 1.0) * 0.5);
+    while ((int64_t)p * (p + 1) / 2 > P) --p;
+    while ((int64_t)(p + 1) * (p + 2) / 2 <= P) ++p;
+    const int q = (int)(P - (int64_t)p * (p + 1) / 2);
+    int r = (int)floor((sqrt(8.0 * (double)Q + 1.0) - 1.0) * 0.5);
+    while ((int64_t)r * (r + 1) / 2 > Q) --r;
+    while ((int64_t)(r + 1) * (r + 2) / 2 <= Q) ++r;
+    const int s = (int)(Q - (int64_t)r * (r + 1) / 2);
+    g8[k] = eri_at(eri, n, p, q, r, s);
+  }
+}
+
 int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st, uint32_t* dflag) {
   const int n = T.n;
   const int64_t n3 = (int64_t)n * n * n, n4 = n3 * n;
@@ -237,6 +259,8 @@ int build_tables(Tables& T, const double* h1, const double* eri, hipStream_t st,
   const int64_t nss_e = (int64_t)T.nss * T.lss, ntot = nss_e + (int64_t)n * n * T.los;
   k_mag_hist2<<<2048, 256, 0, st>>>(T.hb_val, nss_e, ntot, T.mag_cum);
   k_mag_cum2<<<1, 64, 0, st>>>(T.mag_cum);
+  const int64_t npair = (int64_t)n * (n + 1) / 2;
+  k_eri8<<<4096, 256, 0, st>>>(eri, n, npair, T.g8);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -1564,10 +1564,10 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   if (passes == 0) passes = 1;
   // workspace: string tables, groups, two pair-sort buffer sets per spin,
   // histograms, group starts, singles counts and offsets
-  DevBuf ws, wl;
+  DevBuf ws, wl[2];
   struct Plan {
-    uint32_t *slot[2], *grp[2], *k0[2], *v0[2], *k1[2], *v1[2], *hist, *hoffs, *scnt, *cnt_tmp;
-    uint64_t *start[2], *soff, *tot;
+    uint32_t *slot[2], *grp[2], *k0[2], *v0[2], *k1[2], *v1[2], *hist, *hoffs, *scnt[2], *cnt_tmp, *pval;
+    uint64_t *start[2], *soff[2], *tot, *oth0[2], *oth1[2], *pkey;
     double* dots;
     ScanTmp sh, ss;
   } P{};
@@ -1580,12 +1580,16 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
       P.k1[sp] = cv.take<uint32_t>(n);
       P.v1[sp] = cv.take<uint32_t>(n);
       P.start[sp] = cv.take<uint64_t>(n + 1);
+      P.scnt[sp] = cv.take<uint32_t>(n + 1);
+      P.soff[sp] = cv.take<uint64_t>(n + 1);
+      P.oth0[sp] = cv.take<uint64_t>(n);
+      P.oth1[sp] = cv.take<uint64_t>(n);
     }
+    P.pkey = cv.take<uint64_t>(cap);
+    P.pval = cv.take<uint32_t>(cap);
     P.hist = cv.take<uint32_t>(256 * ntiles);
     P.hoffs = cv.take<uint32_t>(256 * ntiles);
-    P.scnt = cv.take<uint32_t>(n + 1);
     P.cnt_tmp = cv.take<uint32_t>(n);
-    P.soff = cv.take<uint64_t>(n + 1);
     P.tot = cv.take<uint64_t>(2);
     P.dots = cv.take<double>(2);
     P.sh.carve(cv, 256 * ntiles);
@@ -1601,7 +1605,8 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   auto done = [&](int code) {
     (void)hipStreamSynchronize(s);
     ws.release();
-    wl.release();
+    wl[0].release();
+    wl[1].release();
     return code;
   };
   const int g1 = (int)((n + 255) / 256);
@@ -1630,27 +1635,38 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
     P.k0[sp] = kin;
     P.v0[sp] = vin;
     k_bucket_bounds<<<(int)std::min<int64_t>(8192, (n + 256) / 256), 256, 0, s>>>(kin, n, n, P.start[sp]);
+    // the other-spin string of each member, in member order
+    k_pack_other<<<g1, 256, 0, s>>>(vin, dets, n, 1 - sp, P.oth0[sp], P.oth1[sp]);
   }
-  // alpha-singles lists of the alpha groups
-  StrTab ta{P.slot[0], cap - 1};
-  SinglesArgs sa{dets, n, T.n, T.na, ta, P.grp[0], P.scnt, P.soff, nullptr};
-  k_fill_u32<<<g1 + 1, 256, 0, s>>>(P.scnt, n + 1, 0u);
-  k_str_singles<false><<<gw, 256, 0, s>>>(sa);
-  {
-    int r = scan_exclusive<uint32_t, uint64_t>(P.scnt, P.soff, n + 1, P.ss, nullptr, s);
+  // (alpha group, beta group) -> determinant
+  PairTab pt{P.pkey, P.pval, cap - 1};
+  k_fill_u64<<<(int)std::min<uint64_t>(4096, (cap + 255) / 256), 256, 0, s>>>(P.pkey, (int64_t)cap, PAIR_EMPTY);
+  k_fill_u32<<<(int)std::min<uint64_t>(4096, (cap + 255) / 256), 256, 0, s>>>(P.pval, (int64_t)cap, STR_EMPTY);
+  k_pairtab_insert<<<g1, 256, 0, s>>>(P.grp[0], P.grp[1], n, pt);
+  // alpha- and beta-singles lists of the groups
+  SinglesArgs sa[2];
+  uint64_t nsl[2] = {0, 0};
+  for (int sp = 0; sp < 2; ++sp) {
+    sa[sp] = SinglesArgs{dets, n, T.n, sp ? T.nb : T.na, sp, StrTab{P.slot[sp], cap - 1}, P.grp[sp], P.scnt[sp],
+                         P.soff[sp], nullptr};
+    k_fill_u32<<<g1 + 1, 256, 0, s>>>(P.scnt[sp], n + 1, 0u);
+    k_str_singles<false><<<gw, 256, 0, s>>>(sa[sp]);
+    int r = scan_exclusive<uint32_t, uint64_t>(P.scnt[sp], P.soff[sp], n + 1, P.ss, nullptr, s);
     if (r) return done(r);
   }
-  uint64_t nsl = 0;
   uint32_t hf = 0;
-  if (hipMemcpyAsync(&nsl, P.soff + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(&nsl[0], P.soff[0] + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&nsl[1], P.soff[1] + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return done(fail(SHCI_ERR_HIP, "string list preparation failed"));
   if (hf & 1u) return done(fail(SHCI_ERR_DET, "a determinant has a wrong electron count or an orbital >= n_orb"));
   if (hf & 2u) return done(fail(SHCI_ERR_NONFINITE, "c holds a NaN or Inf"));
-  CHK(wl.ensure(std::max<uint64_t>(1, nsl) * sizeof(uint32_t), ctx->ws_limit));
-  sa.list = static_cast<uint32_t*>(wl.p);
-  if (nsl) k_str_singles<true><<<gw, 256, 0, s>>>(sa);
+  for (int sp = 0; sp < 2; ++sp) {
+    if (int r = wl[sp].ensure(std::max<uint64_t>(1, nsl[sp]) * sizeof(uint32_t), ctx->ws_limit)) return done(r);
+    sa[sp].list = static_cast<uint32_t*>(wl[sp].p);
+    if (nsl[sp]) k_str_singles<true><<<gw, 256, 0, s>>>(sa[sp]);
+  }
   HcArgs ha{};
   ha.T = T;
   ha.dets = dets;
@@ -1662,8 +1678,15 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   ha.memB = P.v0[1];
   ha.startA = P.start[0];
   ha.startB = P.start[1];
-  ha.soff = P.soff;
-  ha.slist = sa.list;
+  ha.soff = P.soff[0];
+  ha.slist = sa[0].list;
+  ha.soffB = P.soff[1];
+  ha.slistB = sa[1].list;
+  ha.bOfA0 = P.oth0[0];
+  ha.bOfA1 = P.oth1[0];
+  ha.aOfB0 = P.oth0[1];
+  ha.aOfB1 = P.oth1[1];
+  ha.pt = pt;
   ha.y = y;
   ha.nconn = n_conn ? n_conn : P.cnt_tmp;
   ha.flag = ctx->dflag;
@@ -1689,7 +1712,7 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
     (void)hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]);
     (void)hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[3]);
     st->n_terms = (int64_t)nconn_tot;
-    st->n_records = (int64_t)nsl;
+    st->n_records = (int64_t)(nsl[0] + nsl[1]);
     st->ms_gen = a;
     st->ms_reduce = b;
     st->ms_total = t;

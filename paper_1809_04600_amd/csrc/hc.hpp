@@ -12,8 +12,12 @@
 //   * the members of its alpha group (same alpha string: beta singles and
 //     doubles),
 //   * for each alpha group one alpha single away, its members whose beta
-//     string is one beta single away (opposite-spin doubles),
-// and adds H_ii c_i.  Elements are evaluated from the row's determinant as
+//     string is one beta single away (opposite-spin doubles): a small group
+//     is scanned, a large one is probed with the beta groups one single away
+//     from the row's beta string through a table of (alpha group, beta
+//     group) pairs, whichever visits fewer entries,
+// and adds H_ii c_i.  The other-spin strings of each group's members are
+// packed in member order, so scans stream them.  Elements are evaluated from the row's determinant as
 // the source, with the phases and the canonical single-element sum of the
 // excitation generator.  One wavefront per row; lanes take the members, and
 // the row sum is a fixed butterfly, so y is deterministic.
@@ -147,22 +151,24 @@ __global__ void __launch_bounds__(256) k_pair_place(const uint32_t* kin, const u
 }
 
 // ---------------------------------------------------------------------------
-// Alpha groups one single excitation away (Table I: the alpha-singles lists)
+// Groups one single excitation away (Table I: the alpha- and beta-singles
+// lists)
 // ---------------------------------------------------------------------------
 struct SinglesArgs {
   const uint64_t* dets;
   int64_t nd;
-  int n, ne;  // orbitals, alpha electrons
+  int n, ne;  // orbitals, electrons of the spin
+  int spin;
   StrTab t;
-  const uint32_t* grp;  // alpha group of each determinant
+  const uint32_t* grp;  // group of each determinant for that spin
   uint32_t* cnt;        // per representative: number of neighbours
   const uint64_t* off;  // per representative: first list position (WRITE)
   uint32_t* list;       // neighbour groups (WRITE)
 };
 
 // One wavefront per representative determinant (the smallest index of its
-// alpha group); candidates r -> s (r occupied, s empty, both ascending) in
-// order, found strings appended in that order.
+// group); candidates r -> s (r occupied, s empty, both ascending) in order,
+// found strings appended in that order.
 template <bool WRITE>
 __global__ void __launch_bounds__(256) k_str_singles(SinglesArgs a) {
   __shared__ uint8_t s_occ[4][128], s_vir[4][128];
@@ -173,7 +179,7 @@ __global__ void __launch_bounds__(256) k_str_singles(SinglesArgs a) {
   uint8_t* virl = s_vir[wv];
   for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < a.nd; i += nwaves) {
     if (a.grp[i] != (uint32_t)i) continue;  // uniform
-    const uint64_t w0 = a.dets[4 * i], w1 = a.dets[4 * i + 1];
+    const uint64_t w0 = a.dets[4 * i + 2 * a.spin], w1 = a.dets[4 * i + 2 * a.spin + 1];
     {
       int co = 0, cv = 0;
       for (int h = 0; h < 2; ++h) {
@@ -199,7 +205,7 @@ __global__ void __launch_bounds__(256) k_str_singles(SinglesArgs a) {
         uint64_t x0 = w0, x1 = w1;
         flip(x0, x1, r);
         flip(x0, x1, s);
-        g = str_find(a.dets, 0, a.t, x0, x1);
+        g = str_find(a.dets, a.spin, a.t, x0, x1);
       }
       const bool hit = g != STR_EMPTY;
       const uint64_t hb = ballot(hit);
@@ -213,6 +219,56 @@ __global__ void __launch_bounds__(256) k_str_singles(SinglesArgs a) {
     }
     wave_sync();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Table of (alpha group, beta group) -> determinant, open addressing on the
+// 64-bit key gA << 32 | gB (capacity a power of two >= 2 N)
+// ---------------------------------------------------------------------------
+constexpr uint64_t PAIR_EMPTY = ~0ull;
+
+struct PairTab {
+  uint64_t* key;
+  uint32_t* val;
+  uint64_t mask;
+};
+
+__global__ void k_pairtab_insert(const uint32_t* grpA, const uint32_t* grpB, int64_t nd, PairTab t) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nd) return;
+  const uint64_t k = ((uint64_t)grpA[i] << 32) | grpB[i];
+  uint64_t s = fmix64(k) & t.mask;
+  for (;;) {
+    const unsigned long long cur = atomicCAS((unsigned long long*)&t.key[s], (unsigned long long)PAIR_EMPTY,
+                                             (unsigned long long)k);
+    if (cur == PAIR_EMPTY || cur == k) {
+      // equal keys only for a repeated determinant (reported by the rows)
+      atomicMin(&t.val[s], (uint32_t)i);
+      return;
+    }
+    s = (s + 1) & t.mask;
+  }
+}
+
+SHCI_DEV uint32_t pairtab_find(const PairTab& t, uint32_t ga, uint32_t gb) {
+  const uint64_t k = ((uint64_t)ga << 32) | gb;
+  uint64_t s = fmix64(k) & t.mask;
+  for (;;) {
+    const uint64_t cur = t.key[s];
+    if (cur == PAIR_EMPTY) return STR_EMPTY;
+    if (cur == k) return t.val[s];
+    s = (s + 1) & t.mask;
+  }
+}
+
+// the other-spin string of each member, in member order
+__global__ void k_pack_other(const uint32_t* mem, const uint64_t* dets, int64_t nd, int other, uint64_t* o0,
+                             uint64_t* o1) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nd) return;
+  const int64_t j = mem[e];
+  o0[e] = dets[4 * j + 2 * other];
+  o1[e] = dets[4 * j + 2 * other + 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -231,6 +287,13 @@ struct HcArgs {
   const uint64_t* startB;
   const uint64_t* soff;   // [nd + 1] alpha-singles list of group g: [soff[g], soff[g + 1])
   const uint32_t* slist;
+  const uint64_t* soffB;  // beta-singles lists
+  const uint32_t* slistB;
+  const uint64_t* bOfA0;  // beta string of alpha-group member e (words 0, 1)
+  const uint64_t* bOfA1;
+  const uint64_t* aOfB0;  // alpha string of beta-group member e
+  const uint64_t* aOfB1;
+  PairTab pt;
   double* y;
   uint32_t* nconn;        // optional
   uint32_t* flag;         // |= 4: a determinant occurs twice
@@ -311,7 +374,7 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
       for (uint64_t e = a.startB[g] + lane; e < a.startB[g + 1]; e += 64) {
         const uint32_t j = a.memB[e];
         if (j == (uint32_t)i) continue;
-        const uint64_t x0 = a.dets[4 * (int64_t)j], x1 = a.dets[4 * (int64_t)j + 1];
+        const uint64_t x0 = a.aOfB0[e], x1 = a.aOfB1[e];
         const uint64_t h0 = A0 & ~x0, h1 = A1 & ~x1, q0 = x0 & ~A0, q1 = x1 & ~A1;
         const int d = __popcll(h0) + __popcll(h1);
         dup = dup || d == 0;
@@ -342,7 +405,7 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
       for (uint64_t e = a.startA[g] + lane; e < a.startA[g + 1]; e += 64) {
         const uint32_t j = a.memA[e];
         if (j == (uint32_t)i) continue;
-        const uint64_t x0 = a.dets[4 * (int64_t)j + 2], x1 = a.dets[4 * (int64_t)j + 3];
+        const uint64_t x0 = a.bOfA0[e], x1 = a.bOfA1[e];
         const uint64_t h0 = B0 & ~x0, h1 = B1 & ~x1, q0 = x0 & ~B0, q1 = x1 & ~B1;
         const int d = __popcll(h0) + __popcll(h1);
         double H = 0.0;
@@ -369,22 +432,39 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
     // alpha single and beta single: alpha groups one alpha single away, their
     // members one beta single away
     {
-      const uint32_t ga = a.grpA[i];
+      const uint32_t ga = a.grpA[i], gb = a.grpB[i];
+      const uint64_t sb0 = a.soffB[gb], nsb = a.soffB[gb + 1] - sb0;
       for (uint64_t sidx = a.soff[ga]; sidx < a.soff[ga + 1]; ++sidx) {  // uniform
         const uint32_t g2 = a.slist[sidx];
         const uint64_t z0 = a.dets[4 * (int64_t)g2], z1 = a.dets[4 * (int64_t)g2 + 1];
         const int p = lowest(A0 & ~z0, A1 & ~z1), r = lowest(z0 & ~A0, z1 & ~A1);
         const int para = between(A0, A1, p, r);
-        for (uint64_t e = a.startA[g2] + lane; e < a.startA[g2 + 1]; e += 64) {
-          const uint32_t j = a.memA[e];
-          const uint64_t x0 = a.dets[4 * (int64_t)j + 2], x1 = a.dets[4 * (int64_t)j + 3];
-          const uint64_t h0 = B0 & ~x0, h1 = B1 & ~x1;
-          if (__popcll(h0) + __popcll(h1) != 1) continue;
-          const int q = lowest(h0, h1), s = lowest(x0 & ~B0, x1 & ~B1);
-          double H = eri_g8(T.g8, p, r, q, s);
-          if ((para + between(B0, B1, q, s)) & 1) H = -H;
-          cnt += 1;
-          acc += H * a.c[j];
+        const uint64_t m0 = a.startA[g2], m1 = a.startA[g2 + 1];
+        if (m1 - m0 <= nsb) {
+          // scan the members of the alpha group
+          for (uint64_t e = m0 + lane; e < m1; e += 64) {
+            const uint64_t x0 = a.bOfA0[e], x1 = a.bOfA1[e];
+            const uint64_t h0 = B0 & ~x0, h1 = B1 & ~x1;
+            if (__popcll(h0) + __popcll(h1) != 1) continue;
+            const int q = lowest(h0, h1), s = lowest(x0 & ~B0, x1 & ~B1);
+            double H = eri_g8(T.g8, p, r, q, s);
+            if ((para + between(B0, B1, q, s)) & 1) H = -H;
+            cnt += 1;
+            acc += H * a.c[a.memA[e]];
+          }
+        } else {
+          // probe (alpha group, beta group one single away) pairs
+          for (uint64_t k = lane; k < nsb; k += 64) {
+            const uint32_t gb2 = a.slistB[sb0 + k];
+            const uint32_t j = pairtab_find(a.pt, g2, gb2);
+            if (j == STR_EMPTY) continue;
+            const uint64_t x0 = a.dets[4 * (int64_t)gb2 + 2], x1 = a.dets[4 * (int64_t)gb2 + 3];
+            const int q = lowest(B0 & ~x0, B1 & ~x1), s = lowest(x0 & ~B0, x1 & ~B1);
+            double H = eri_g8(T.g8, p, r, q, s);
+            if ((para + between(B0, B1, q, s)) & 1) H = -H;
+            cnt += 1;
+            acc += H * a.c[j];
+          }
         }
       }
     }

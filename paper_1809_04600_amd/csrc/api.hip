@@ -1568,6 +1568,7 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   struct Plan {
     uint32_t *slot[2], *grp[2], *k0[2], *v0[2], *k1[2], *v1[2], *hist, *hoffs, *scnt[2], *cnt_tmp, *pval;
     uint64_t *start[2], *soff[2], *tot, *oth0[2], *oth1[2], *pkey;
+    uint32_t* othf[2];
     double* dots;
     ScanTmp sh, ss;
   } P{};
@@ -1584,6 +1585,7 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
       P.soff[sp] = cv.take<uint64_t>(n + 1);
       P.oth0[sp] = cv.take<uint64_t>(n);
       P.oth1[sp] = cv.take<uint64_t>(n);
+      P.othf[sp] = cv.take<uint32_t>(n);
     }
     P.pkey = cv.take<uint64_t>(cap);
     P.pval = cv.take<uint32_t>(cap);
@@ -1636,7 +1638,7 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
     P.v0[sp] = vin;
     k_bucket_bounds<<<(int)std::min<int64_t>(8192, (n + 256) / 256), 256, 0, s>>>(kin, n, n, P.start[sp]);
     // the other-spin string of each member, in member order
-    k_pack_other<<<g1, 256, 0, s>>>(vin, dets, n, 1 - sp, P.oth0[sp], P.oth1[sp]);
+    k_pack_other<<<g1, 256, 0, s>>>(vin, dets, n, 1 - sp, P.oth0[sp], P.oth1[sp], P.othf[sp]);
   }
   // (alpha group, beta group) -> determinant
   PairTab pt{P.pkey, P.pval, cap - 1};
@@ -1686,6 +1688,8 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   ha.bOfA1 = P.oth1[0];
   ha.aOfB0 = P.oth0[1];
   ha.aOfB1 = P.oth1[1];
+  ha.bOfAf = P.othf[0];
+  ha.aOfBf = P.othf[1];
   ha.pt = pt;
   ha.y = y;
   ha.nconn = n_conn ? n_conn : P.cnt_tmp;

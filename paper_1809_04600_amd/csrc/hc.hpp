@@ -17,7 +17,11 @@
 //     from the row's beta string through a table of (alpha group, beta
 //     group) pairs, whichever visits fewer entries,
 // and adds H_ii c_i.  The other-spin strings of each group's members are
-// packed in member order, so scans stream them.  Elements are evaluated from the row's determinant as
+// packed in member order, so scans stream them, together with a 32-bit fold
+// of each (the XOR of its 32-bit quarters): two strings k excitations apart
+// differ in 2k bits, and folding can only cancel differing bits, so a fold
+// difference of more than 2k bits rules the pair out before the full strings
+// are read.  Elements are evaluated from the row's determinant as
 // the source, with the phases and the canonical single-element sum of the
 // excitation generator.  One wavefront per row; lanes take the members, and
 // the row sum is a fixed butterfly, so y is deterministic.
@@ -261,14 +265,20 @@ SHCI_DEV uint32_t pairtab_find(const PairTab& t, uint32_t ga, uint32_t gb) {
   }
 }
 
-// the other-spin string of each member, in member order
+SHCI_HD uint32_t fold32(uint64_t w0, uint64_t w1) {
+  return (uint32_t)w0 ^ (uint32_t)(w0 >> 32) ^ (uint32_t)w1 ^ (uint32_t)(w1 >> 32);
+}
+
+// the other-spin string of each member, in member order, and its fold
 __global__ void k_pack_other(const uint32_t* mem, const uint64_t* dets, int64_t nd, int other, uint64_t* o0,
-                             uint64_t* o1) {
+                             uint64_t* o1, uint32_t* of) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= nd) return;
   const int64_t j = mem[e];
-  o0[e] = dets[4 * j + 2 * other];
-  o1[e] = dets[4 * j + 2 * other + 1];
+  const uint64_t w0 = dets[4 * j + 2 * other], w1 = dets[4 * j + 2 * other + 1];
+  o0[e] = w0;
+  o1[e] = w1;
+  of[e] = fold32(w0, w1);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,6 +303,8 @@ struct HcArgs {
   const uint64_t* bOfA1;
   const uint64_t* aOfB0;  // alpha string of beta-group member e
   const uint64_t* aOfB1;
+  const uint32_t* bOfAf;  // folds of the packed strings
+  const uint32_t* aOfBf;
   PairTab pt;
   double* y;
   uint32_t* nconn;        // optional
@@ -371,7 +383,9 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
     // same beta string: alpha singles and doubles
     {
       const uint32_t g = a.grpB[i];
+      const uint32_t fi = fold32(A0, A1);
       for (uint64_t e = a.startB[g] + lane; e < a.startB[g + 1]; e += 64) {
+        if (__popc(a.aOfBf[e] ^ fi) > 4) continue;
         const uint32_t j = a.memB[e];
         if (j == (uint32_t)i) continue;
         const uint64_t x0 = a.aOfB0[e], x1 = a.aOfB1[e];
@@ -402,7 +416,9 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
     // same alpha string: beta singles and doubles
     {
       const uint32_t g = a.grpA[i];
+      const uint32_t fi = fold32(B0, B1);
       for (uint64_t e = a.startA[g] + lane; e < a.startA[g + 1]; e += 64) {
+        if (__popc(a.bOfAf[e] ^ fi) > 4) continue;
         const uint32_t j = a.memA[e];
         if (j == (uint32_t)i) continue;
         const uint64_t x0 = a.bOfA0[e], x1 = a.bOfA1[e];
@@ -433,6 +449,7 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
     // members one beta single away
     {
       const uint32_t ga = a.grpA[i], gb = a.grpB[i];
+      const uint32_t fb = fold32(B0, B1);
       const uint64_t sb0 = a.soffB[gb], nsb = a.soffB[gb + 1] - sb0;
       for (uint64_t sidx = a.soff[ga]; sidx < a.soff[ga + 1]; ++sidx) {  // uniform
         const uint32_t g2 = a.slist[sidx];
@@ -443,6 +460,7 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
         if (m1 - m0 <= nsb) {
           // scan the members of the alpha group
           for (uint64_t e = m0 + lane; e < m1; e += 64) {
+            if (__popc(a.bOfAf[e] ^ fb) > 2) continue;
             const uint64_t x0 = a.bOfA0[e], x1 = a.bOfA1[e];
             const uint64_t h0 = B0 & ~x0, h1 = B1 & ~x1;
             if (__popcll(h0) + __popcll(h1) != 1) continue;

@@ -8,7 +8,9 @@ hash partition, bucket sort + segmented reduce + H_aa, E2 reduction).
 --workload w3 times the semistochastic 76-orbital, 1e6-determinant workload:
 one step = the deterministic part at eps2^d plus 256 samples of 2000 draws at
 eps2 (shci_pt2_det + shci_pt2_sample).  The heat-bath tables are built once per
-integral set (context) and timed apart.
+integral set (context) and timed apart.  H c on the same variational space
+(shci_pt2_hc, string lists + rows) is timed after the steps and reported
+under "hc"; it is not part of the step.
 
 Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
@@ -161,6 +163,18 @@ def cpu_baseline(x, budget_s):
             "e2_sample": r.e2, "seconds": t}
 
 
+def hc_timing(ctx, x, dets, c, reps=3):
+    """H c on the same V (string lists and rows), outside the PT2 step:
+    device time of the last of `reps` calls, connections per second, and the
+    variational energy against the stored E0."""
+    ctx.hc(dets, c)
+    for _ in range(reps):
+        _, _, ev, st = ctx.hc(dets, c)
+    return {"ms_total": st["ms_total"], "ms_lists": st["ms_gen"], "ms_rows": st["ms_reduce"],
+            "connections": st["n_terms"], "connections_per_s": st["n_terms"] / (st["ms_total"] * 1e-3),
+            "e_var_minus_e0": ev - x.e0}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -266,6 +280,7 @@ def main():
         "reduce_gbs_fp64": reduce_gbs,
         "record_bytes": {"fp64": rec64, "fp32c": rec32},
         "table_build_ms": table_ms,
+        "hc": hc_timing(ctx, x, dets, c),
     }
     if not a.no_cpu:
         cb = cpu_baseline(x, a.cpu_seconds)

@@ -64,7 +64,7 @@ def test_terms_bit_exact_small(small_sys, eps2):
     # H_ai c_i bit for bit
     assert np.array_equal(gv[go], (o.term_h * x.c[o.term_i])[oo])
     A, D, oA, oD = _check_unique(r.unique, o)
-    # H_aa is summed in another order on the GPU (relative to a reference det)
+    # H_aa is summed in another order on the GPU (an update of the source diagonal)
     assert np.abs(D - oD).max() <= 1e-12 * max(1.0, np.abs(oD).max())
     assert np.abs(A - oA).max() <= 1e-13
     assert abs(r.e2 - o.e2) <= E2_TOL_FP64

@@ -169,6 +169,16 @@ SHCI_HD bool aux_set(const uint64_t (&k)[KW], int auxbit) {
   return r != 0ull;
 }
 
+// k -> (hi, lo) with k = hi (hi + 1) / 2 + lo, 0 <= lo <= hi (the triangle
+// with its diagonal); the square root only seeds hi, integer steps make it exact
+SHCI_HD void tri_split(int64_t k, int64_t& hi, int64_t& lo) {
+  int64_t h = (int64_t)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+  while (h * (h + 1) / 2 > k) --h;
+  while ((h + 1) * (h + 2) / 2 <= k) ++h;
+  hi = h;
+  lo = k - h * (h + 1) / 2;
+}
+
 // ---------------------------------------------------------------------------
 // Spin strings (2 words) and fermion signs.
 // ---------------------------------------------------------------------------

@@ -223,19 +223,11 @@ void singles_ref(const Tables& T, const uint64_t* ref, hipStream_t st) {
 __global__ void k_eri8(const double* eri, int n, int64_t npair, double* g8) {
   const int64_t tot = npair * (npair + 1) / 2;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.x * blockDim.x) {
-    int64_t P = (int64_t)floor((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
-    while (P * (P + 1) / 2 > k) --P;
-    while ((P + 1) * (P + 2) / 2 <= k) ++P;
-    const int64_t Q = k - P * (P + 1) / 2;
-    int p = (int)floor((sqrt(8.0 * (double)P + 1.0) - 1.0) * 0.5);
-    while ((int64_t)p * (p + 1) / 2 > P) --p;
-    while ((int64_t)(p + 1) * (p + 2) / 2 <= P) ++p;
-    const int q = (int)(P - (int64_t)p * (p + 1) / 2);
-    int r = (int)floor((sqrt(8.0 * (double)Q + 1.0) - 1.0) * 0.5);
-    while ((int64_t)r * (r + 1) / 2 > Q) --r;
-    while ((int64_t)(r + 1) * (r + 2) / 2 <= Q) ++r;
-    const int s = (int)(Q - (int64_t)r * (r + 1) / 2);
-    g8[k] = eri_at(eri, n, p, q, r, s);
+    int64_t P, Q, p, q, r, s;
+    tri_split(k, P, Q);
+    tri_split(P, p, q);
+    tri_split(Q, r, s);
+    g8[k] = eri_at(eri, n, (int)p, (int)q, (int)r, (int)s);
   }
 }
 

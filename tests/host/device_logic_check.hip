@@ -5,6 +5,7 @@
 // Exit status 0 on success.
 #define SHCI_DEV __host__ __device__ inline
 #include "../../paper_1809_04600_amd/csrc/diag.hpp"
+#include "../../paper_1809_04600_amd/csrc/hc.hpp"
 
 #include <cmath>
 #include <cstdio>
@@ -168,8 +169,56 @@ static int check_diag(int n, int na, int nb, unsigned seed) {
   return maxerr > 1e-11;
 }
 
+// triangle split, the folded integral table of the H c kernels, and the fold
+// prefilter's bound
+static int check_hc_helpers() {
+  int bad = 0;
+  for (int64_t k = 0; k < 40000000; k += (k < 100000 ? 1 : 7)) {
+    int64_t hi, lo;
+    tri_split(k, hi, lo);
+    bad += !(lo >= 0 && lo <= hi && hi * (hi + 1) / 2 + lo == k);
+  }
+  const int n = 9;
+  std::mt19937_64 g(5);
+  std::normal_distribution<double> N(0, 1);
+  std::vector<double> eri((size_t)n * n * n * n);
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q <= p; ++q)
+      for (int r = 0; r < n; ++r)
+        for (int s = 0; s <= r; ++s) {
+          if (p * (p + 1) / 2 + q < r * (r + 1) / 2 + s) continue;
+          const double v = N(g);
+          const int idx[8][4] = {{p, q, r, s}, {q, p, r, s}, {p, q, s, r}, {q, p, s, r},
+                                 {r, s, p, q}, {s, r, p, q}, {r, s, q, p}, {s, r, q, p}};
+          for (auto& t : idx) eri[((size_t)(t[0] * n + t[1]) * n + t[2]) * n + t[3]] = v;
+        }
+  const int64_t npair = n * (n + 1) / 2, tot = npair * (npair + 1) / 2;
+  std::vector<double> g8(tot);
+  for (int64_t k = 0; k < tot; ++k) {
+    int64_t P, Q, p, q, r, s;
+    tri_split(k, P, Q);
+    tri_split(P, p, q);
+    tri_split(Q, r, s);
+    g8[k] = eri[((size_t)(p * n + q) * n + r) * n + s];
+  }
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      for (int r = 0; r < n; ++r)
+        for (int s = 0; s < n; ++s)
+          bad += eri_g8(g8.data(), p, q, r, s) != eri[((size_t)(p * n + q) * n + r) * n + s];
+  for (int it = 0; it < 100000; ++it) {
+    const uint64_t a0 = g(), a1 = g() & 0xfff, b0 = a0 ^ (1ull << (g() % 64)) ^ (1ull << (g() % 64)),
+                   b1 = a1 ^ ((g() & 1) ? (1ull << (g() % 12)) : 0);
+    const int full = __builtin_popcountll(a0 ^ b0) + __builtin_popcountll(a1 ^ b1);
+    bad += __builtin_popcount(fold32(a0, a1) ^ fold32(b0, b1)) > full;
+  }
+  printf("H c helpers: %d mismatches\n", bad);
+  return bad;
+}
+
 int main() {
   int bad = check_pack();
+  bad += check_hc_helpers();
   bad += check_diag(10, 3, 3, 1);
   bad += check_diag(40, 8, 8, 2);
   bad += check_diag(76, 14, 14, 3);

@@ -343,6 +343,7 @@ SHCI_DEV int lowest(uint64_t x0, uint64_t x1) {
 
 __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
   __shared__ uint8_t s_occ[4][2][128];
+  __shared__ uint32_t s_q[4][128];  // queue of same-string members that pass the fold
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   const Tables& T = a.T;
@@ -380,70 +381,70 @@ __global__ void __launch_bounds__(256) k_hc_rows(HcArgs a) {
     double acc = 0.0;
     uint32_t cnt = 0;
     bool dup = false;
-    // same beta string: alpha singles and doubles
-    {
-      const uint32_t g = a.grpB[i];
-      const uint32_t fi = fold32(A0, A1);
-      for (uint64_t e = a.startB[g] + lane; e < a.startB[g + 1]; e += 64) {
-        if (__popc(a.aOfBf[e] ^ fi) > 4) continue;
-        const uint32_t j = a.memB[e];
-        if (j == (uint32_t)i) continue;
-        const uint64_t x0 = a.aOfB0[e], x1 = a.aOfB1[e];
-        const uint64_t h0 = A0 & ~x0, h1 = A1 & ~x1, q0 = x0 & ~A0, q1 = x1 & ~A1;
-        const int d = __popcll(h0) + __popcll(h1);
+    // Same-string groups: members whose fold passes are queued (member
+    // position in the low 31 bits, bit 31 set for the alpha group) and
+    // evaluated 64 at a time on full wavefronts.
+    uint32_t* qu = s_q[wv];
+    int qn = 0;  // uniform
+    auto process = [&](int m) {
+      const bool valid = lane < m;
+      const uint32_t code = valid ? qu[lane] : 0u;
+      const bool inA = (code >> 31) != 0;  // member of the row's alpha group: beta excitation
+      const uint64_t e = code & 0x7fffffffu;
+      double H = 0.0;
+      int d = 0;
+      uint32_t j = 0;
+      if (valid) {
+        j = inA ? a.memA[e] : a.memB[e];
+        const uint64_t S0 = inA ? B0 : A0, S1 = inA ? B1 : A1;
+        const uint64_t x0 = inA ? a.bOfA0[e] : a.aOfB0[e], x1 = inA ? a.bOfA1[e] : a.aOfB1[e];
+        const uint64_t h0 = S0 & ~x0, h1 = S1 & ~x1, q0 = x0 & ~S0, q1 = x1 & ~S1;
+        d = __popcll(h0) + __popcll(h1);
+        if (d == 1) {
+          const int p = lowest(h0, h1), r = lowest(q0, q1);
+          H = single_elem(T, occA, na, occB, nb, !inA, p, r);
+          if (between(S0, S1, p, r) & 1) H = -H;
+        } else if (d == 2) {
+          const int p = lowest(h0, h1), r = lowest(q0, q1);
+          const int qq = lowest(h0 & (h0 - 1), h0 ? h1 : (h1 & (h1 - 1)));
+          const int ss = lowest(q0 & (q0 - 1), q0 ? q1 : (q1 & (q1 - 1)));
+          uint64_t y0 = S0, y1 = S1;
+          int par = between(y0, y1, p, r);
+          flip(y0, y1, p);
+          flip(y0, y1, r);
+          par += between(y0, y1, qq, ss);
+          H = eri_g8(T.g8, p, r, qq, ss) - eri_g8(T.g8, p, ss, qq, r);
+          if (par & 1) H = -H;
+        }
         dup = dup || d == 0;
-        double H = 0.0;
-        if (d == 1) {
-          const int p = lowest(h0, h1), r = lowest(q0, q1);
-          H = single_elem(T, occA, na, occB, nb, true, p, r);
-          if (between(A0, A1, p, r) & 1) H = -H;
-        } else if (d == 2) {
-          const int p = lowest(h0, h1), r = lowest(q0, q1);
-          const int q = lowest(h0 & (h0 - 1), h0 ? h1 : (h1 & (h1 - 1)));
-          const int s = lowest(q0 & (q0 - 1), q0 ? q1 : (q1 & (q1 - 1)));
-          uint64_t y0 = A0, y1 = A1;
-          int par = between(y0, y1, p, r);
-          flip(y0, y1, p);
-          flip(y0, y1, r);
-          par += between(y0, y1, q, s);
-          H = eri_g8(T.g8, p, r, q, s) - eri_g8(T.g8, p, s, q, r);
-          if (par & 1) H = -H;
-        }
         cnt += (d == 1 || d == 2);
         acc += H * a.c[j];
       }
-    }
-    // same alpha string: beta singles and doubles
+    };
+    auto scan = [&](uint64_t lo, uint64_t hi, const uint32_t* fo, const uint32_t* mem, uint32_t fi, uint32_t tag) {
+      for (uint64_t e0 = lo; e0 < hi; e0 += 64) {  // uniform
+        const uint64_t e = e0 + lane;
+        const bool pass = e < hi && __popc(fo[e] ^ fi) <= 4 && mem[e] != (uint32_t)i;
+        const uint64_t pb = ballot(pass);
+        if (pass) qu[qn + rank_below(pb)] = (uint32_t)e | tag;
+        qn += __popcll(pb);
+        wave_sync();
+        if (qn >= 64) {
+          process(64);
+          const uint32_t rest = (lane + 64 < qn) ? qu[lane + 64] : 0u;
+          wave_sync();
+          if (lane + 64 < qn) qu[lane] = rest;
+          qn -= 64;
+          wave_sync();
+        }
+      }
+    };
     {
-      const uint32_t g = a.grpA[i];
-      const uint32_t fi = fold32(B0, B1);
-      for (uint64_t e = a.startA[g] + lane; e < a.startA[g + 1]; e += 64) {
-        if (__popc(a.bOfAf[e] ^ fi) > 4) continue;
-        const uint32_t j = a.memA[e];
-        if (j == (uint32_t)i) continue;
-        const uint64_t x0 = a.bOfA0[e], x1 = a.bOfA1[e];
-        const uint64_t h0 = B0 & ~x0, h1 = B1 & ~x1, q0 = x0 & ~B0, q1 = x1 & ~B1;
-        const int d = __popcll(h0) + __popcll(h1);
-        double H = 0.0;
-        if (d == 1) {
-          const int p = lowest(h0, h1), r = lowest(q0, q1);
-          H = single_elem(T, occA, na, occB, nb, false, p, r);
-          if (between(B0, B1, p, r) & 1) H = -H;
-        } else if (d == 2) {
-          const int p = lowest(h0, h1), r = lowest(q0, q1);
-          const int q = lowest(h0 & (h0 - 1), h0 ? h1 : (h1 & (h1 - 1)));
-          const int s = lowest(q0 & (q0 - 1), q0 ? q1 : (q1 & (q1 - 1)));
-          uint64_t y0 = B0, y1 = B1;
-          int par = between(y0, y1, p, r);
-          flip(y0, y1, p);
-          flip(y0, y1, r);
-          par += between(y0, y1, q, s);
-          H = eri_g8(T.g8, p, r, q, s) - eri_g8(T.g8, p, s, q, r);
-          if (par & 1) H = -H;
-        }
-        cnt += (d == 1 || d == 2);
-        acc += H * a.c[j];
-      }
+      const uint32_t gB = a.grpB[i], gA = a.grpA[i];
+      scan(a.startB[gB], a.startB[gB + 1], a.aOfBf, a.memB, fold32(A0, A1), 0u);
+      scan(a.startA[gA], a.startA[gA + 1], a.bOfAf, a.memA, fold32(B0, B1), 0x80000000u);
+      if (qn > 0) process(qn);
+      wave_sync();
     }
     // alpha single and beta single: alpha groups one alpha single away, their
     // members one beta single away

@@ -266,7 +266,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
 }
 
 template <int KW, bool SAMPLE, typename VT>
-__global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8))) k_reduce_wave(WaveRedArgs A) {
+__global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_per_eu(6, 8))) k_reduce_wave(WaveRedArgs A) {
   __shared__ WaveStage WS[WRED_WAVES];
   const RedArgs& a = A.r;
   const int t = threadIdx.x;

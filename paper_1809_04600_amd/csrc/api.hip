@@ -456,7 +456,7 @@ int run_job(Job& J) {
 
   // ---- phase 1: work items, count pass ----
   uint32_t *w_src, *w_rng, *counts;
-  uint64_t *offs, *total1;
+  uint64_t* offs;
   double* gpart = nullptr;
   double* gitem = nullptr;  // sample mode: adjoint per item before the scatter to determinants
   ScanTmp sc;
@@ -465,7 +465,6 @@ int run_job(Job& J) {
     w_rng = cv.take<uint32_t>(ni + 1);
     counts = cv.take<uint32_t>(ni + 1);
     offs = cv.take<uint64_t>(ni + 1);
-    total1 = cv.take<uint64_t>(4);
     gpart = J.grad ? cv.take<double>(ni + 1) : nullptr;
     gitem = (J.grad && SAMPLE) ? cv.take<double>(nsrc + 1) : nullptr;
     sc.carve(cv, ni + 1);
@@ -498,6 +497,7 @@ int run_job(Job& J) {
   g.T = T;
   g.counts = counts;
   g.offs = offs;
+  g.flag = dflag;
   g.counter = counter;
   g.sbits = J.sbits;
   g.auxbit = auxbit;
@@ -514,8 +514,9 @@ int run_job(Job& J) {
   k_gen_count<KW, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
   HIPCHK(hipEventRecord(X->ev[5], st));
   HIPCHK(hipGetLastError());
-  CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, total1, st));
-  HIPCHK(hipMemcpyAsync(hostv, total1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  // offs[ni] = total: the write walk checks every item's end against it
+  CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, offs + ni, st));
+  HIPCHK(hipMemcpyAsync(hostv, offs + ni, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const int64_t nrec = (int64_t)hostv[0];
   if (J.max_records > 0 && nrec > J.max_records) {
@@ -739,6 +740,8 @@ int run_job(Job& J) {
     HIPCHK(hipMemcpyAsync(&J.res, X->dres, sizeof(DevResult), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&hov, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (J.res.flags & 32u)
+      return fail(SHCI_ERR_HIP, "internal error: the write walk kept a different number of terms than the count walk");
     if (hov) {
       // a bucket held more records than fit in LDS: plan again with one more
       // hash bit; the write pass regenerates the same records

@@ -57,6 +57,7 @@ struct GenArgs {
   double nd;
   double eps2, eps2_d;
   Tables T;
+  uint32_t* flag;  // |= 32: a write walk kept a different number of terms than its count walk
   uint32_t* counts;
   const uint64_t* offs;
   Recs out;
@@ -210,8 +211,11 @@ SHCI_DEV void gen_body(const GenArgs& a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    uint64_t obase = 0;
-    if constexpr (MODE == GEN_WRITE) obase = a.offs[item];
+    uint64_t obase = 0, oend = 0;
+    if constexpr (MODE == GEN_WRITE) {
+      obase = a.offs[item];
+      oend = a.offs[item + 1];
+    }
     uint64_t cursor = 0;  // uniform
     double gacc = 0.0;
 
@@ -228,10 +232,10 @@ SHCI_DEV void gen_body(const GenArgs& a) {
       if constexpr (MODE == GEN_COUNT) {
         cursor += (uint64_t)__popcll(bal);
       } else if constexpr (MODE == GEN_WRITE) {
-        if (keep) {
+        const uint64_t pos = obase + cursor + (uint64_t)rank_below(bal);
+        if (keep && pos < oend) {  // the count walk sized [obase, oend)
           uint64_t key[KW];
           pack_det<KW>(key, x0, x1, y0, y1, n);
-          const uint64_t pos = obase + cursor + (uint64_t)rank_below(bal);
           {
             // bucket id: top hash bits of the determinant, sample id above
             const uint64_t h = det_hash<KW>(key, n);
@@ -416,6 +420,7 @@ SHCI_DEV void gen_body(const GenArgs& a) {
         const size_t pr_off = (size_t)p * n + r;
         const double ub = valid ? T.ubound[pr_off] : 0.0;
         bool maybe = valid && (ub * absc > eps2);
+        bool sure = false;  // kept for certain (count walk without batch filter)
         if (ndl >= 0 && maybe) {
           const int sp = alpha ? 0 : 1;
           double h = a.Fref[sp * nn + pr_off];
@@ -435,6 +440,15 @@ SHCI_DEV void gen_body(const GenArgs& a) {
             for (int u = 0; u < 8; ++u) h = ((e[u] >> 8) & 1u) ? h - v[u] : h + v[u];
           }
           maybe = (fabs(h) + a.smarg * ub) * absc * (1.0 + 0x1p-50) > eps2;
+          // the margin bounds |H - h| several times over, so this implies the
+          // exact element passes; only counting needs no value
+          if constexpr (MODE == GEN_COUNT) sure = (fabs(h) - a.smarg * ub) * absc * (1.0 - 0x1p-50) > eps2;
+        }
+        if constexpr (MODE == GEN_COUNT) {
+          if (a.bmask == 0u) {  // uniform
+            cursor += (uint64_t)__popcll(ballot(sure));
+            maybe = maybe && !sure;
+          }
         }
         const uint64_t mb = ballot(maybe);
         if (maybe) sq[qn + rank_below(mb)] = (uint16_t)j;
@@ -655,6 +669,9 @@ SHCI_DEV void gen_body(const GenArgs& a) {
     if (dqn > 0) dflush(dqn);
     if constexpr (MODE == GEN_COUNT) {
       if (lane == 0) a.counts[item] = (uint32_t)cursor;
+    }
+    if constexpr (MODE == GEN_WRITE) {
+      if (lane == 0 && obase + cursor != oend) atomicOr(a.flag, 32u);
     }
     if constexpr (MODE == GEN_GRAD) {
 #pragma unroll

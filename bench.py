@@ -12,7 +12,7 @@ integral set (context) and timed apart.  H c on the same variational space
 (shci_pt2_hc, string lists + rows) is timed after the steps and reported
 under "hc"; it is not part of the step.
 
-Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is rejected: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -178,8 +178,8 @@ def hc_timing(ctx, x, dets, c, reps=3):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the multi-GPU sharding is a design in DESIGN.md, not implemented)",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {a.gpus} is not supported "
+              "(sharding across GPUs is designed but not implemented)",
               file=sys.stderr)
         sys.exit(2)
     if a.copy_probe:

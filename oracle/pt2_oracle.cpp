@@ -103,11 +103,14 @@ inline bool bit(const uint64_t* s, int p) { return (s[p >> 6] >> (p & 63)) & 1ul
 inline void flip(uint64_t* s, int p) { s[p >> 6] ^= (1ull << (p & 63)); }
 
 // number of occupied orbitals of spin string s strictly between p and r
+// (population count of the string masked to the orbitals lo+1 .. hi-1)
 inline int between(const uint64_t* s, int p, int r) {
   int lo = std::min(p, r), hi = std::max(p, r);
-  int cnt = 0;
-  for (int k = lo + 1; k < hi; ++k) cnt += bit(s, k);
-  return cnt;
+  if (hi - lo < 2) return 0;
+  unsigned __int128 str = ((unsigned __int128)s[1] << 64) | s[0];
+  unsigned __int128 mask = (((unsigned __int128)1 << hi) - 1) & ~((((unsigned __int128)1 << lo) << 1) - 1);
+  unsigned __int128 v = str & mask;
+  return __builtin_popcountll((uint64_t)v) + __builtin_popcountll((uint64_t)(v >> 64));
 }
 
 inline double sign_of(int parity) { return (parity & 1) ? -1.0 : 1.0; }

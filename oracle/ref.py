@@ -78,6 +78,13 @@ def lib():
         L.oracle_hc_rows.restype = _i
         L.oracle_hc_rows.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _p, _i64, _p, _p]
         L.oracle_max_threads.restype = _i
+        L.oracle_alias_last_error.restype = C.c_char_p
+        L.oracle_splitmix64.restype = C.c_uint64
+        L.oracle_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.oracle_alias_table.restype = _i
+        L.oracle_alias_table.argtypes = [_p, _i64, _p, _p, _p, _p, _p, _p, _p]
+        L.oracle_alias_draws.restype = _i
+        L.oracle_alias_draws.argtypes = [_p, _i64, C.c_uint64, C.c_int32, C.c_int32, _p]
         _lib = L
     return _lib
 
@@ -366,3 +373,49 @@ def mp1(n, na, nb, h1, eri, dets, mask, ref) -> np.ndarray:
 
 def max_threads() -> int:
     return lib().oracle_max_threads()
+
+
+def splitmix64(seed: int, m: int) -> int:
+    """Output number m (m >= 1) of SplitMix64 seeded with `seed`."""
+    return int(lib().oracle_splitmix64(seed & (2**64 - 1), m & (2**64 - 1)))
+
+
+@dataclass
+class AliasTable:
+    threshold: np.ndarray   # [n] uint64: bucket k keeps k when v < threshold[k]
+    alias: np.ndarray       # [n] uint32
+    mass: list              # [n] exact integer masses N W_i (Python ints)
+    own: list               # [n] exact own mass of each bucket
+    capacity: int           # T = sum W_i
+
+
+def alias_table(c) -> AliasTable:
+    """Alias table of p_i = |c_i| / sum_j |c_j| (integer masses, Vose's sweep)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    n = len(c)
+    P = np.zeros(n, dtype=np.uint64)
+    al = np.zeros(n, dtype=np.uint32)
+    mlo = np.zeros(n, dtype=np.uint64)
+    mhi = np.zeros(n, dtype=np.uint64)
+    olo = np.zeros(n, dtype=np.uint64)
+    ohi = np.zeros(n, dtype=np.uint64)
+    t = np.zeros(2, dtype=np.uint64)
+    L = lib()
+    st = L.oracle_alias_table(_ptr(c), n, _ptr(P), _ptr(al), _ptr(mlo), _ptr(mhi), _ptr(olo), _ptr(ohi),
+                              _ptr(t))
+    if st:
+        raise OracleError(st, L.oracle_alias_last_error().decode())
+    mass = [int(h) << 64 | int(l) for l, h in zip(mlo, mhi)]
+    own = [int(h) << 64 | int(l) for l, h in zip(olo, ohi)]
+    return AliasTable(P, al, mass, own, int(t[1]) << 64 | int(t[0]))
+
+
+def alias_draws(c, n_samples: int, n_draws: int, seed: int) -> np.ndarray:
+    """Draws [n_samples, n_draws] (uint32) of the stochastic samples from the seed."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.zeros((n_samples, n_draws), dtype=np.uint32)
+    L = lib()
+    st = L.oracle_alias_draws(_ptr(c), len(c), seed & (2**64 - 1), n_samples, n_draws, _ptr(out))
+    if st:
+        raise OracleError(st, L.oracle_alias_last_error().decode())
+    return out

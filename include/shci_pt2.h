@@ -29,8 +29,17 @@
  *
  * Memory: every pointer marked "device" must be device memory of the current
  * HIP device; "host" pointers are host memory.  All input and output buffers
- * are owned by the caller.  The context owns the integral-derived tables and a
- * grow-only device workspace, both freed by shci_pt2_ctx_destroy.
+ * are owned by the caller.  The context owns the integral-derived tables.
+ * Device scratch memory: the PT2 calls take a workspace (ws, ws_bytes), a
+ * device region owned by the caller (for instance from torch's caching
+ * allocator), aligned to 256 bytes.  With a workspace the call allocates
+ * nothing and frees nothing; when the screened terms do not fit it, the
+ * deterministic calls split the perturbative space into hash batches and the
+ * sampling calls evaluate fewer samples per chunk (shci_pt2_workspace_size
+ * gives the bytes for a given number of records per pass).  With ws = NULL
+ * the context's own grow-only buffers are used instead: they are allocated
+ * (hipMalloc) when a call needs more than they hold, after a synchronisation
+ * of the call's stream, and freed by shci_pt2_ctx_destroy.
  *
  * Streams: all work is enqueued on `stream` (a hipStream_t, NULL = default
  * stream).  Calls that return host scalars synchronise that stream before
@@ -40,8 +49,9 @@
  * the ABI.  shci_pt2_last_error() returns a thread-local message for the last
  * non-OK status of the calling thread.  Inputs are never modified.
  *
- * Concurrency: a context may be used by one call at a time (its workspace is
- * shared by all calls on it).
+ * Concurrency: a context may be used by one call at a time (its grow-only
+ * buffers, flags and timing events are shared by all calls on it); a
+ * workspace may be used by one call at a time.
  */
 #ifndef SHCI_PT2_H
 #define SHCI_PT2_H
@@ -61,6 +71,23 @@ typedef struct shci_pt2_ctx shci_pt2_ctx;
  * reduction stay binary64.  Screening decisions are binary64 in both modes,
  * so both produce the same connection set. */
 enum shci_precision { SHCI_FP64 = 0, SHCI_FP32C = 1 };
+
+/* Operations sized by shci_pt2_workspace_size. */
+enum shci_op {
+  SHCI_OP_DET = 0,          /* shci_pt2_det, shci_pt2_det_batches */
+  SHCI_OP_GRAD = 1,         /* shci_pt2_grad, recompute mode */
+  SHCI_OP_GRAD_KEEP = 2,    /* shci_pt2_grad, keep mode */
+  SHCI_OP_SAMPLE = 3,       /* shci_pt2_sample, shci_pt2_sample_batched (seed path included) */
+  SHCI_OP_SAMPLE_GRAD = 4,  /* shci_pt2_sample_grad */
+  SHCI_OP_DRAWS = 5         /* shci_pt2_draws */
+};
+
+/* Adjoint modes of shci_pt2_grad. */
+enum shci_grad_mode {
+  SHCI_GRAD_AUTO = 0,       /* keep when one pass holds every record, else recompute */
+  SHCI_GRAD_KEEP = 1,       /* records carry their position; no second generation pass */
+  SHCI_GRAD_RECOMPUTE = 2   /* the adjoint walks the connections again (hash batches allowed) */
+};
 
 enum shci_status {
   SHCI_OK = 0,
@@ -138,12 +165,26 @@ typedef struct {
 int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, const double* eri,
                         void* stream, shci_pt2_ctx** out);
 
-/* Frees the context, its tables and its workspace.  NULL is ignored. */
+/* Frees the context, its tables and its grow-only buffers.  NULL is ignored. */
 void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx);
 
-/* Caps the context's device workspace (bytes; 0 = no cap).  Calls whose
- * working set would exceed the cap fail with SHCI_ERR_WORKSPACE. */
+/* Caps the context's own grow-only buffers (bytes; 0 = no cap; calls with
+ * ws = NULL).  A region that would exceed the cap fails with
+ * SHCI_ERR_WORKSPACE. */
 int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes);
+
+/* Workspace bytes for `op` (enum shci_op) on n_det variational determinants
+ * when one pass materialises up to n_records screened terms (values below
+ * 1024 count as 1024; the records of a previous call are in
+ * shci_pt2_stats.n_records).  Sampling ops also take n_samples and n_draws
+ * (the seed path's draws and alias table are included).  A workspace of this
+ * size holds one pass of that many records; a smaller one makes the call use
+ * more hash batches or smaller sample chunks.  The figure assumes at most
+ * 2 n_det work items (heavy determinants split over their occupied pairs);
+ * more items take their room from the records.
+ *   bytes  host, out.  Errors: SHCI_ERR_ARG. */
+int shci_pt2_workspace_size(const shci_pt2_ctx* ctx, int op, int64_t n_det, int64_t n_records, int32_t n_samples,
+                            int32_t n_draws, int precision, size_t* bytes);
 
 /* Caps the screened-term records one generation pass materialises
  * (0 = automatic: what free device memory, or the workspace cap, holds).
@@ -161,13 +202,14 @@ int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records);
  *   c     device FP64 [n_det];
  *   e0    E0 of every denominator; eps2 >= 0 the screening threshold;
  *   precision  SHCI_FP64 or SHCI_FP32C;
+ *   ws, ws_bytes  device workspace or NULL (see Memory above);
  *   e2    host, receives E2; st host, nullable; ex host struct, nullable.
  * The result is deterministic: repeated calls give identical bits.
  * SHCI_ERR_SINGULAR is returned (with e2 = +-inf or nan) if a kept a has
  * E0 - H_aa == 0 exactly; intruders with E0 - H_aa > 0 are counted, not
  * rejected. */
 int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
-                 double e0, double eps2, int precision, void* stream, double* e2,
+                 double e0, double eps2, int precision, void* ws, size_t ws_bytes, void* stream, double* e2,
                  shci_pt2_stats* st, shci_pt2_export* ex);
 
 /* Stochastic part of the semistochastic PT2 (semistochastic and stochastic
@@ -181,15 +223,40 @@ int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64
  * |H_ai c_i| > e, and per_sample[s] = S_s(eps2) - S_s(eps2_d), both
  * thresholds evaluated on the same samples in one pass.  The semistochastic
  * estimate is E2 = E2_det(eps2_d) + mean_s per_sample[s].
- *   draws   device uint32 [n_samples][n_draws], each < n_det;
- *   eps2 <= eps2_d; n_draws >= 2; n_samples >= 1;
+ *   draws   device uint32 [n_samples][n_draws], each < n_det, or NULL: the
+ *           seed path draws them on the device with p_i = |c_i| / sum_j |c_j|
+ *           by the alias method (sampling-probability equation; the paper
+ *           cites Walker and Kronmal-Peterson): an alias table built by
+ *           Vose's method on exact 128-bit integer masses (weights
+ *           floor(|c_i| 2^(K-E)), 2^(E-1) <= max|c| < 2^E, K = 127 -
+ *           2 ceil(log2 n_det)), and draw k of sample s taken from SplitMix64
+ *           outputs 2(s n_draws + k) + 1 (bucket, multiply-shift) and + 2
+ *           (64-bit threshold); shci_pt2_draws returns the same draws;
+ *   seed    the SplitMix64 seed of the seed path (ignored with draws);
+ *   eps2 <= eps2_d; n_draws in [2, 4096]; n_samples >= 1;
+ *   n_samples * n_draws < 2^31;
+ *   ws, ws_bytes  device workspace or NULL;
  *   per_sample  device FP64 [n_samples];
  *   mean, sem   host, nullable: mean and standard error (sd / sqrt(n_samples))
  *               of per_sample (sem = 0 when n_samples == 1). */
 int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
                     double e0, double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
-                    const uint32_t* draws, int precision, void* stream, double* per_sample,
-                    double* mean, double* sem, shci_pt2_stats* st);
+                    const uint32_t* draws, uint64_t seed, int precision, void* ws, size_t ws_bytes,
+                    void* stream, double* per_sample, double* mean, double* sem, shci_pt2_stats* st);
+
+/* The seed path's draws alone: draws [n_samples][n_draws] (device, out) as
+ * shci_pt2_sample makes them from c and seed.  ws, ws_bytes: workspace or
+ * NULL.  Errors: SHCI_ERR_ARG, SHCI_ERR_NONFINITE (c not finite or all
+ * zero). */
+int shci_pt2_draws(shci_pt2_ctx* ctx, const double* c, int64_t n_det, uint64_t seed, int32_t n_samples,
+                   int32_t n_draws, void* ws, size_t ws_bytes, void* stream, uint32_t* draws);
+
+/* The alias table of p_i = |c_i| / sum_j |c_j| that the seed path draws
+ * from: bucket k keeps k when a uniform 64-bit value is below threshold[k],
+ * else it gives alias[k].  threshold device uint64 [n_det], alias device
+ * uint32 [n_det] (out).  Errors as shci_pt2_draws. */
+int shci_pt2_alias_table(shci_pt2_ctx* ctx, const double* c, int64_t n_det, void* ws, size_t ws_bytes,
+                         void* stream, uint64_t* threshold, uint32_t* alias);
 
 /* Stochastic part with one batch of P per sample (the stochastic step of the
  * paper's 3-step method, section IV): sample s keeps only the a whose
@@ -197,13 +264,15 @@ int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
  * is multiplied by n_batches (unbiased over a uniform choice of batch).
  *   n_batches     power of two in [1, 65536];
  *   sample_batch  device int32 [n_samples], each in [0, n_batches) (random
- *                 numbers of the method, passed in like the draws).
+ *                 numbers of the method, passed in like the draws), or NULL:
+ *                 sample s takes the top log2(n_batches) bits of SplitMix64
+ *                 output 2 n_samples n_draws + s + 1 of `seed`.
  * Other arguments as shci_pt2_sample. */
 int shci_pt2_sample_batched(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
                             double e0, double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
                             const uint32_t* draws, int32_t n_batches, const int32_t* sample_batch,
-                            int precision, void* stream, double* per_sample, double* mean, double* sem,
-                            shci_pt2_stats* st);
+                            uint64_t seed, int precision, void* ws, size_t ws_bytes, void* stream,
+                            double* per_sample, double* mean, double* sem, shci_pt2_stats* st);
 
 /* Per-batch statistics of the deterministic corrections (section IV): for
  * each listed batch b (h mod n_batches == b, h the determinant hash), over
@@ -212,15 +281,15 @@ int shci_pt2_sample_batched(shci_pt2_ctx* ctx, const uint64_t* dets, const doubl
  * A_a(e) the screened sum at threshold e (A_a(INFINITY) = 0, so eps2_hi =
  * INFINITY gives the plain contributions).  out[k] = {sum e_a, sum e_a^2,
  * number of a, number of kept terms}.  A batch whose records exceed the
- * record budget fails with SHCI_ERR_WORKSPACE. */
+ * record budget (or the workspace) fails with SHCI_ERR_WORKSPACE. */
 typedef struct {
   double sum, sumsq;
   int64_t n_unique, n_terms;
 } shci_pt2_batch;
 int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
                          double e0, double eps2, double eps2_hi, int32_t n_batches, const int32_t* batches,
-                         int32_t n_list, int precision, void* stream, shci_pt2_batch* out,
-                         shci_pt2_stats* st);
+                         int32_t n_list, int precision, void* ws, size_t ws_bytes, void* stream,
+                         shci_pt2_batch* out, shci_pt2_stats* st);
 
 /* The paper's 3-step perturbative correction (3-step equation, section IV):
  *   E2 = E2_dtm(eps2_dtm)
@@ -229,7 +298,11 @@ int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* 
  *        over the unevaluated determinants is below 40% of target_error
  *      + mean_s [S_s(eps2) - S_s(eps2_psto)]        stochastic: one batch of P
  *        (of nb_sto) per sample, as shci_pt2_sample_batched.
- * err combines the pseudo-stochastic and stochastic standard errors. */
+ * err combines the pseudo-stochastic and stochastic standard errors.
+ * draws and sample_batch may be NULL (seed path, as shci_pt2_sample and
+ * shci_pt2_sample_batched).  The paper asks for at least 16
+ * pseudo-stochastic batches and at least 10 samples; the call accepts
+ * smaller values (small tests) and leaves that choice to the caller. */
 typedef struct {
   double e2, err;
   double e2_dtm;
@@ -240,8 +313,8 @@ typedef struct {
 int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
                         double e0, double eps2_dtm, double eps2_psto, double eps2, double target_error,
                         int32_t nb_psto, int32_t nb_sto, int32_t n_samples, int32_t n_draws,
-                        const uint32_t* draws, const int32_t* sample_batch, int precision, void* stream,
-                        double* per_sample, shci_pt2_3step_result* res);
+                        const uint32_t* draws, const int32_t* sample_batch, uint64_t seed, int precision,
+                        void* ws, size_t ws_bytes, void* stream, double* per_sample, shci_pt2_3step_result* res);
 
 /* Selection of new variational determinants from the same pass (variational
  * stage, section II.A): one deterministic pass with generation threshold
@@ -253,7 +326,8 @@ int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c
  *   out_keys  device uint64 [cap][4] (input layout), out_val device FP64 [cap];
  *   n_out     host: number selected.  SHCI_ERR_WORKSPACE if the pass has more
  *             than cap perturbative determinants.  Order unspecified but
- *             deterministic. */
+ *             deterministic.  Scratch memory comes from the context's
+ *             grow-only buffers. */
 enum { SHCI_SELECT_HCI = 0, SHCI_SELECT_CIPSI = 1 };
 int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                 double eps_gen, int mode, double threshold, int precision, void* stream, uint64_t* out_keys,
@@ -274,21 +348,29 @@ int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
  * arguments as shci_pt2_sample; per_sample must be non-NULL. */
 int shci_pt2_sample_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
                          double e0, double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
-                         const uint32_t* draws, int precision, void* stream, double* per_sample,
-                         double* mean, double* sem, double* de2_dc, double* de2_de0,
-                         shci_pt2_stats* st);
+                         const uint32_t* draws, uint64_t seed, int precision, void* ws, size_t ws_bytes,
+                         void* stream, double* per_sample, double* mean, double* sem, double* de2_dc,
+                         double* de2_de0, shci_pt2_stats* st);
 
 /* Gradient of the deterministic screened E2 with the screening mask held at
  * the given c:
  *   dE2/dc_i = sum_{a: (i,a) kept, a not in V} 2 H_ai A_a / (E0 - H_aa)
  *   dE2/dE0  = -sum_a A_a^2 / (E0 - H_aa)^2.
- * The forward pass runs first (precision as in shci_pt2_det); the adjoint
- * regenerates the connections of every i and looks up 2 A_a / D_a, so no
- * per-term storage is kept.  de2_dc: device FP64 [n_det]; e2, de2_de0: host,
- * nullable. */
+ * The forward pass runs first (precision as in shci_pt2_det).  mode
+ * (enum shci_grad_mode):
+ *   SHCI_GRAD_KEEP: every record carries its position; the reduce writes
+ *     t * 2 A_a / D_a per record (t = H_ai c_i, 0 for a in V) and the sums
+ *     over each source's records, divided by c_i, give dE2/dc_i (fixed
+ *     order, deterministic); 12 more bytes per record;
+ *   SHCI_GRAD_RECOMPUTE: the unique a are kept with 2 A_a / D_a and the
+ *     adjoint regenerates the connections of every i and looks them up, so
+ *     no per-term storage is kept (hash batches allowed);
+ *   SHCI_GRAD_AUTO: keep when one pass holds every record, else recompute.
+ * de2_dc: device FP64 [n_det]; e2, de2_de0: host, nullable; ws, ws_bytes:
+ * workspace or NULL. */
 int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det,
-                  double e0, double eps2, int precision, void* stream, double* e2,
-                  double* de2_dc, double* de2_de0, shci_pt2_stats* st);
+                  double e0, double eps2, int precision, int mode, void* ws, size_t ws_bytes, void* stream,
+                  double* e2, double* de2_dc, double* de2_de0, shci_pt2_stats* st);
 
 /* y = H c on the variational space (section III: the alpha/beta string lists
  * of Table I and the connection loops of Algorithms 1-2), and the
@@ -306,7 +388,7 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
  * FP64 throughout; rows are summed in a fixed order, so y is deterministic.
  * Errors: SHCI_ERR_ARG (NULL, n_det outside [1, 2^31 - 1)), SHCI_ERR_DET,
  * SHCI_ERR_DUP, SHCI_ERR_NONFINITE (c), SHCI_ERR_WORKSPACE, SHCI_ERR_HIP.
- * The library allocates and frees its workspace inside the call. */
+ * Scratch memory comes from the context's grow-only buffers. */
 int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, void* stream,
                 double* y, uint32_t* n_conn, double* e_var, shci_pt2_stats* st);
 

@@ -10,12 +10,13 @@
 // construction details; the readings used here:
 //
 //  1. Integer masses.  With m = max_i |c_i| = f 2^E (f in [0.5, 1)), b the
-//     number of bits of N - 1 (0 for N = 1) and K = 126 - b, the weight of i is
-//     the exact integer W_i = floor(|c_i| 2^(K - E)) (an exact scaling of the
-//     binary64 value, truncated below 2^(E - K)).  Bucket capacity T = sum W_i;
-//     item mass a_i = N W_i; sum a_i = N T.  All of it is exact in 128-bit
-//     unsigned arithmetic (a_i, T < 2^126), so the table does not depend on
-//     the order of any sum.
+//     number of bits of N - 1 (0 for N = 1) and K = 127 - 2b, the weight of i
+//     is the exact integer W_i = floor(|c_i| 2^(K - E)) (an exact scaling of
+//     the binary64 value, truncated below 2^(E - K)).  Bucket capacity
+//     T = sum W_i; item mass a_i = N W_i; sum a_i = N T.  All of it is exact in
+//     128-bit unsigned arithmetic, and so is every sum of masses or of bucket
+//     deficits (at most N T < 2^127), so the table does not depend on the
+//     order of any sum.
 //  2. Table (Vose's method, sweep order).  Items with a_i < T are light, the
 //     others heavy; both in increasing index order.  The current heavy covers
 //     the lights one after the other; whenever its remaining mass r is no
@@ -94,7 +95,7 @@ int build(const double* c, int64_t n, Table& t) {
   }
   int E;
   std::frexp(m, &E);
-  const int K = 126 - bits_of(n);
+  const int K = 127 - 2 * bits_of(n);
   t.a.assign(n, 0);
   t.T = 0;
   for (int64_t i = 0; i < n; ++i) {

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libshci_pt2.so")
 SHCI_FP64 = 0
 SHCI_FP32C = 1
 _PREC = {"fp64": SHCI_FP64, "fp32c": SHCI_FP32C, SHCI_FP64: SHCI_FP64, SHCI_FP32C: SHCI_FP32C}
+OPS = {"det": 0, "grad": 1, "grad_keep": 2, "sample": 3, "sample_grad": 4, "draws": 5}
+GRAD_MODES = {"auto": 0, "keep": 1, "recompute": 2}
 
 STATUS = {0: "SHCI_OK", -1: "SHCI_ERR_ARG", -2: "SHCI_ERR_NORB", -3: "SHCI_ERR_DET",
           -4: "SHCI_ERR_DUP", -5: "SHCI_ERR_NONFINITE", -6: "SHCI_ERR_WORKSPACE",
@@ -87,28 +89,35 @@ def lib():
         L.shci_pt2_ctx_set_workspace_limit.restype = i
         L.shci_pt2_ctx_set_record_limit.argtypes = [p, C.c_int64]
         L.shci_pt2_ctx_set_record_limit.restype = i
-        L.shci_pt2_det.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), C.POINTER(Stats),
+        u64, sz, i32 = C.c_uint64, C.c_size_t, C.c_int32
+        L.shci_pt2_workspace_size.argtypes = [p, i, i64, i64, i32, i32, i, C.POINTER(sz)]
+        L.shci_pt2_workspace_size.restype = i
+        L.shci_pt2_det.argtypes = [p, p, p, i64, d, d, i, p, sz, p, C.POINTER(d), C.POINTER(Stats),
                                    C.POINTER(Export)]
         L.shci_pt2_det.restype = i
-        L.shci_pt2_sample.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, i, p, p,
+        L.shci_pt2_sample.argtypes = [p, p, p, i64, d, d, d, i32, i32, p, u64, i, p, sz, p, p,
                                       C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
         L.shci_pt2_sample.restype = i
-        L.shci_pt2_sample_grad.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, i, p, p,
+        L.shci_pt2_draws.argtypes = [p, p, i64, u64, i32, i32, p, sz, p, p]
+        L.shci_pt2_draws.restype = i
+        L.shci_pt2_alias_table.argtypes = [p, p, i64, p, sz, p, p, p]
+        L.shci_pt2_alias_table.restype = i
+        L.shci_pt2_sample_grad.argtypes = [p, p, p, i64, d, d, d, i32, i32, p, u64, i, p, sz, p, p,
                                            C.POINTER(d), C.POINTER(d), p, C.POINTER(d), C.POINTER(Stats)]
         L.shci_pt2_sample_grad.restype = i
-        L.shci_pt2_sample_batched.argtypes = [p, p, p, i64, d, d, d, C.c_int32, C.c_int32, p, C.c_int32, p,
-                                              i, p, p, C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
+        L.shci_pt2_sample_batched.argtypes = [p, p, p, i64, d, d, d, i32, i32, p, i32, p, u64,
+                                              i, p, sz, p, p, C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
         L.shci_pt2_sample_batched.restype = i
-        L.shci_pt2_det_batches.argtypes = [p, p, p, i64, d, d, d, C.c_int32, p, C.c_int32, i, p, p,
+        L.shci_pt2_det_batches.argtypes = [p, p, p, i64, d, d, d, i32, p, i32, i, p, sz, p, p,
                                            C.POINTER(Stats)]
         L.shci_pt2_det_batches.restype = i
-        L.shci_pt2_three_step.argtypes = [p, p, p, i64, d, d, d, d, d, C.c_int32, C.c_int32, C.c_int32,
-                                          C.c_int32, p, p, i, p, p, C.POINTER(ThreeStep)]
+        L.shci_pt2_three_step.argtypes = [p, p, p, i64, d, d, d, d, d, i32, i32, i32,
+                                          i32, p, p, u64, i, p, sz, p, p, C.POINTER(ThreeStep)]
         L.shci_pt2_three_step.restype = i
         L.shci_pt2_select.argtypes = [p, p, p, i64, d, d, i, d, i, p, p, p, i64, C.POINTER(i64),
                                       C.POINTER(Stats)]
         L.shci_pt2_select.restype = i
-        L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), p, C.POINTER(d),
+        L.shci_pt2_grad.argtypes = [p, p, p, i64, d, d, i, i, p, sz, p, C.POINTER(d), p, C.POINTER(d),
                                     C.POINTER(Stats)]
         L.shci_pt2_grad.restype = i
         L.shci_pt2_hc.argtypes = [p, p, p, i64, p, p, p, C.POINTER(d), C.POINTER(Stats)]
@@ -160,6 +169,31 @@ class Context:
                                          C.byref(ptr)))
         self._ptr = ptr
 
+    _ws = None
+
+    def set_workspace(self, ws):
+        """Device workspace passed to every PT2 call: a uint8 device tensor,
+        a size in bytes (allocated through torch), or None (the library's own
+        grow-only buffers)."""
+        if ws is None or isinstance(ws, torch.Tensor):
+            self._ws = ws
+        else:
+            self._ws = torch.empty(int(ws), dtype=torch.uint8, device="cuda")
+
+    def workspace_size(self, op, n_det, n_records=0, n_samples=0, n_draws=0, precision="fp64") -> int:
+        out = C.c_size_t()
+        _check(lib().shci_pt2_workspace_size(self._ptr, OPS[op], int(n_det), int(n_records), int(n_samples),
+                                             int(n_draws), _PREC[precision], C.byref(out)))
+        return out.value
+
+    def _wsarg(self, ws):
+        w = self._ws if ws is None else ws
+        if w is False or w is None:
+            return C.c_void_p(None), 0
+        if not (w.is_cuda and w.dtype == torch.uint8 and w.is_contiguous()):
+            raise ValueError("workspace must be a contiguous uint8 device tensor")
+        return C.c_void_p(w.data_ptr()), w.numel()
+
     def close(self):
         if getattr(self, "_ptr", None):
             lib().shci_pt2_ctx_destroy(self._ptr)
@@ -183,8 +217,11 @@ class Context:
         nd = c.shape[0]
         return _dev(dets, torch.int64, (nd, 4), "dets"), _dev(c, torch.float64, (nd,), "c"), nd
 
-    def det(self, dets, c, e0, eps2, precision="fp64", unique_cap=0, terms_cap=0) -> DetResult:
+    def det(self, dets, c, e0, eps2, precision="fp64", unique_cap=0, terms_cap=0, ws=None) -> DetResult:
+        """Deterministic screened PT2.  ws: workspace tensor for this call
+        (False: none, None: the context's set_workspace)."""
         pd, pc, nd = self._inputs(dets, c)
+        pw, nw = self._wsarg(ws)
         e2 = C.c_double()
         st = Stats()
         ex = None
@@ -211,7 +248,7 @@ class Context:
                 ex.t_val = bufs["t_val"].data_ptr()
                 ex.t_cap = terms_cap
         _check(lib().shci_pt2_det(self._ptr, pd, pc, nd, float(e0), float(eps2), _PREC[precision],
-                                  _stream(), C.byref(e2), C.byref(st),
+                                  pw, nw, _stream(), C.byref(e2), C.byref(st),
                                   C.byref(ex) if ex is not None else None))
         r = DetResult(e2.value, st.as_dict())
         if ex is not None and unique_cap:
@@ -224,57 +261,96 @@ class Context:
                        "val": bufs["t_val"][:m]}
         return r
 
-    def grad(self, dets, c, e0, eps2, precision="fp64"):
+    def grad(self, dets, c, e0, eps2, precision="fp64", mode="auto", ws=None):
+        """E2, dE2/dc (device tensor), dE2/dE0, stats.  mode: "auto", "keep"
+        or "recompute" (the adjoint's source of the connections)."""
         pd, pc, nd = self._inputs(dets, c)
+        pw, nw = self._wsarg(ws)
         g = torch.empty(nd, dtype=torch.float64, device=c.device)
         e2 = C.c_double()
         de0 = C.c_double()
         st = Stats()
         _check(lib().shci_pt2_grad(self._ptr, pd, pc, nd, float(e0), float(eps2), _PREC[precision],
-                                   _stream(), C.byref(e2), C.c_void_p(g.data_ptr()), C.byref(de0),
-                                   C.byref(st)))
+                                   GRAD_MODES[mode], pw, nw, _stream(), C.byref(e2),
+                                   C.c_void_p(g.data_ptr()), C.byref(de0), C.byref(st)))
         return e2.value, g, de0.value, st.as_dict()
 
-    def sample(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64"):
-        pd, pc, nd = self._inputs(dets, c)
+    def _draws_arg(self, draws, n_samples, n_draws):
+        if draws is None:
+            if not n_samples or not n_draws:
+                raise ValueError("the seed path needs n_samples and n_draws")
+            return C.c_void_p(None), int(n_samples), int(n_draws)
         ns, ndraw = draws.shape
-        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
+        return _dev(draws, torch.int32, (ns, ndraw), "draws"), ns, ndraw
+
+    def sample(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64", *, seed=0, n_samples=None,
+               n_draws=None, ws=None):
+        """Per-sample S_s(eps2) - S_s(eps2_d).  draws: int32 [ns, nd] device
+        tensor, or None with n_samples, n_draws and seed (draws made on the
+        device by the alias method)."""
+        pd, pc, nd = self._inputs(dets, c)
+        pdr, ns, ndraw = self._draws_arg(draws, n_samples, n_draws)
+        pw, nw = self._wsarg(ws)
         out = torch.empty(ns, dtype=torch.float64, device=c.device)
         mean = C.c_double()
         sem = C.c_double()
         st = Stats()
         _check(lib().shci_pt2_sample(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_d),
-                                     ns, ndraw, pdr, _PREC[precision], _stream(),
-                                     C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
+                                     ns, ndraw, pdr, int(seed) & (2**64 - 1), _PREC[precision], pw, nw,
+                                     _stream(), C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
                                      C.byref(st)))
         return out, mean.value, sem.value, st.as_dict()
 
-    def sample_batched(self, dets, c, e0, eps2, eps2_d, draws, n_batches, sample_batch, precision="fp64"):
-        """Stochastic estimates keeping one hash batch of P per sample (times n_batches)."""
+    def draws(self, c, n_samples, n_draws, seed, ws=None):
+        """Draws of the seed path: int32 device tensor [n_samples, n_draws]."""
+        nd = c.shape[0]
+        pc = _dev(c, torch.float64, (nd,), "c")
+        pw, nw = self._wsarg(ws)
+        out = torch.empty((n_samples, n_draws), dtype=torch.int32, device=c.device)
+        _check(lib().shci_pt2_draws(self._ptr, pc, nd, int(seed) & (2**64 - 1), int(n_samples), int(n_draws),
+                                    pw, nw, _stream(), C.c_void_p(out.data_ptr())))
+        return out
+
+    def alias_table(self, c, ws=None):
+        """(thresholds as int64 tensor with the uint64 bits, aliases int32) of the seed path."""
+        nd = c.shape[0]
+        pc = _dev(c, torch.float64, (nd,), "c")
+        pw, nw = self._wsarg(ws)
+        thr = torch.empty(nd, dtype=torch.int64, device=c.device)
+        al = torch.empty(nd, dtype=torch.int32, device=c.device)
+        _check(lib().shci_pt2_alias_table(self._ptr, pc, nd, pw, nw, _stream(), C.c_void_p(thr.data_ptr()),
+                                          C.c_void_p(al.data_ptr())))
+        return thr, al
+
+    def sample_batched(self, dets, c, e0, eps2, eps2_d, draws, n_batches, sample_batch, precision="fp64", *,
+                       seed=0, n_samples=None, n_draws=None, ws=None):
+        """Stochastic estimates keeping one hash batch of P per sample (times
+        n_batches); sample_batch None: batches from the seed."""
         pd, pc, nd = self._inputs(dets, c)
-        ns, ndraw = draws.shape
-        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
-        psb = _dev(sample_batch, torch.int32, (ns,), "sample_batch")
+        pdr, ns, ndraw = self._draws_arg(draws, n_samples, n_draws)
+        psb = C.c_void_p(None) if sample_batch is None else _dev(sample_batch, torch.int32, (ns,), "sample_batch")
+        pw, nw = self._wsarg(ws)
         out = torch.empty(ns, dtype=torch.float64, device=c.device)
         mean = C.c_double()
         sem = C.c_double()
         st = Stats()
         _check(lib().shci_pt2_sample_batched(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_d),
-                                             ns, ndraw, pdr, int(n_batches), psb, _PREC[precision],
-                                             _stream(), C.c_void_p(out.data_ptr()), C.byref(mean),
-                                             C.byref(sem), C.byref(st)))
+                                             ns, ndraw, pdr, int(n_batches), psb, int(seed) & (2**64 - 1),
+                                             _PREC[precision], pw, nw, _stream(), C.c_void_p(out.data_ptr()),
+                                             C.byref(mean), C.byref(sem), C.byref(st)))
         return out, mean.value, sem.value, st.as_dict()
 
-    def det_batches(self, dets, c, e0, eps2, eps2_hi, n_batches, batches, precision="fp64"):
+    def det_batches(self, dets, c, e0, eps2, eps2_hi, n_batches, batches, precision="fp64", ws=None):
         """Per-batch (sum, sum of squares, count of a, kept terms) of
         e_a = (A_a(eps2)^2 - A_a(eps2_hi)^2) / D_a for the listed hash batches."""
         pd, pc, nd = self._inputs(dets, c)
+        pw, nw = self._wsarg(ws)
         bl = (C.c_int32 * len(batches))(*[int(b) for b in batches])
         out = (Batch * len(batches))()
         st = Stats()
         _check(lib().shci_pt2_det_batches(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_hi),
-                                          int(n_batches), bl, len(batches), _PREC[precision], _stream(), out,
-                                          C.byref(st)))
+                                          int(n_batches), bl, len(batches), _PREC[precision], pw, nw, _stream(),
+                                          out, C.byref(st)))
         return [(o.sum, o.sumsq, o.n_unique, o.n_terms) for o in out], st.as_dict()
 
     def select(self, dets, c, e0, eps_gen, mode="hci", threshold=0.0, cap=1 << 20, precision="fp64"):
@@ -309,26 +385,28 @@ class Context:
         return y, conn, ev.value, st.as_dict()
 
     def three_step(self, dets, c, e0, eps2_dtm, eps2_psto, eps2, target_error, nb_psto, nb_sto, draws,
-                   sample_batch, precision="fp64"):
-        """The 3-step correction; returns (result dict, per-sample tensor)."""
+                   sample_batch, precision="fp64", *, seed=0, n_samples=None, n_draws=None, ws=None):
+        """The 3-step correction; returns (result dict, per-sample tensor).
+        draws / sample_batch None: made from the seed on the device."""
         pd, pc, nd = self._inputs(dets, c)
-        ns, ndraw = draws.shape
-        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
-        psb = _dev(sample_batch, torch.int32, (ns,), "sample_batch")
+        pdr, ns, ndraw = self._draws_arg(draws, n_samples, n_draws)
+        psb = C.c_void_p(None) if sample_batch is None else _dev(sample_batch, torch.int32, (ns,), "sample_batch")
+        pw, nw = self._wsarg(ws)
         out = torch.empty(ns, dtype=torch.float64, device=c.device)
         res = ThreeStep()
         _check(lib().shci_pt2_three_step(self._ptr, pd, pc, nd, float(e0), float(eps2_dtm), float(eps2_psto),
                                          float(eps2), float(target_error), int(nb_psto), int(nb_sto), ns, ndraw,
-                                         pdr, psb, _PREC[precision], _stream(), C.c_void_p(out.data_ptr()),
-                                         C.byref(res)))
+                                         pdr, psb, int(seed) & (2**64 - 1), _PREC[precision], pw, nw, _stream(),
+                                         C.c_void_p(out.data_ptr()), C.byref(res)))
         return res.as_dict(), out
 
-    def sample_grad(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64"):
+    def sample_grad(self, dets, c, e0, eps2, eps2_d, draws, precision="fp64", *, seed=0, n_samples=None,
+                    n_draws=None, ws=None):
         """Per-sample estimates and the adjoint of their mean: returns
         (per_sample, mean, sem, dE/dc tensor, dE/dE0, stats)."""
         pd, pc, nd = self._inputs(dets, c)
-        ns, ndraw = draws.shape
-        pdr = _dev(draws, torch.int32, (ns, ndraw), "draws")
+        pdr, ns, ndraw = self._draws_arg(draws, n_samples, n_draws)
+        pw, nw = self._wsarg(ws)
         out = torch.empty(ns, dtype=torch.float64, device=c.device)
         g = torch.empty(nd, dtype=torch.float64, device=c.device)
         mean = C.c_double()
@@ -336,7 +414,8 @@ class Context:
         de0 = C.c_double()
         st = Stats()
         _check(lib().shci_pt2_sample_grad(self._ptr, pd, pc, nd, float(e0), float(eps2), float(eps2_d),
-                                          ns, ndraw, pdr, _PREC[precision], _stream(),
+                                          ns, ndraw, pdr, int(seed) & (2**64 - 1), _PREC[precision], pw, nw,
+                                          _stream(),
                                           C.c_void_p(out.data_ptr()), C.byref(mean), C.byref(sem),
                                           C.c_void_p(g.data_ptr()), C.byref(de0), C.byref(st)))
         return out, mean.value, sem.value, g, de0.value, st.as_dict()

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/shci_pt2.h"
+#include "alias.hpp"
 #include "group.hpp"
 #include "hc.hpp"
 #include "reduce_wave.hpp"
@@ -43,17 +44,18 @@ int fail(int code, const char* fmt, ...) {
     if (s_ != SHCI_OK) return s_;   \
   } while (0)
 
-// grow-only device buffer
+// grow-only device buffer (the context's memory when the caller passes no
+// workspace); growing waits for the calling stream, then reallocates
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
-  int ensure(size_t bytes, size_t limit) {
+  int ensure(size_t bytes, size_t limit, hipStream_t st) {
     if (bytes <= cap) return SHCI_OK;
     if (limit && bytes > limit)
       return fail(SHCI_ERR_WORKSPACE, "workspace of %zu bytes exceeds the limit of %zu", bytes, limit);
     if (p) {
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess) return fail(SHCI_ERR_HIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return fail(SHCI_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
       (void)hipFree(p);
       p = nullptr;
       cap = 0;
@@ -79,7 +81,7 @@ struct DevBuf {
   }
 };
 
-// bump allocator over a DevBuf (two passes: size, then carve)
+// bump allocator over a region (two passes: size, then carve)
 struct Carver {
   char* base;
   size_t off = 0;
@@ -93,6 +95,14 @@ struct Carver {
   }
 };
 
+// Regions of device memory a call uses, by purpose.  With a caller
+// workspace every region is carved from it in call order (stack discipline:
+// mark / reset), and the call allocates nothing; without one, each region is
+// the context's grow-only buffer of that purpose.
+enum Slot { SL_V, SL_ITEMS, SL_REC, SL_SAMPLE, SL_DRAWS, SL_ALIAS, SL_TABLE, SL_SEL, SL_HC, SL_HCL0, SL_HCL1, NSLOT };
+
+constexpr size_t WS_ALIGN = 256;
+
 int ceil_log2(uint64_t x) {
   int b = 0;
   while ((1ull << b) < x) ++b;
@@ -104,7 +114,8 @@ int ceil_log2(uint64_t x) {
 struct shci_pt2_ctx {
   int device = 0;
   Tables T;
-  DevBuf tables, small, small1, big;
+  DevBuf tables;
+  DevBuf slot[NSLOT];
   size_t ws_limit = 0;
   int64_t rec_limit = 0;  // records per pass (0: from device memory)
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
@@ -113,6 +124,50 @@ struct shci_pt2_ctx {
 };
 
 namespace {
+
+struct Arena {
+  shci_pt2_ctx* X = nullptr;
+  hipStream_t st = nullptr;
+  char* base = nullptr;  // caller workspace, or nullptr: the context's buffers
+  size_t cap = 0, off = 0;
+  Arena(shci_pt2_ctx* x, hipStream_t s, void* ws, size_t bytes)
+      : X(x), st(s), base(static_cast<char*>(ws)), cap(ws ? bytes : 0) {}
+  bool caller() const { return base != nullptr; }
+  size_t mark() const { return off; }
+  void reset(size_t m) { off = m; }
+  // bytes still free in the caller workspace
+  size_t remaining() const {
+    const size_t o = (off + WS_ALIGN - 1) & ~(WS_ALIGN - 1);
+    return cap > o ? cap - o : 0;
+  }
+  int take(int slot, size_t bytes, void** p) {
+    if (caller()) {
+      const size_t o = (off + WS_ALIGN - 1) & ~(WS_ALIGN - 1);
+      if (o + bytes > cap)
+        return fail(SHCI_ERR_WORKSPACE, "the workspace of %zu bytes is too small (%zu more needed)", cap,
+                    o + bytes - cap);
+      *p = base + o;
+      off = o + bytes;
+      return SHCI_OK;
+    }
+    CHK(X->slot[slot].ensure(bytes, X->ws_limit, st));
+    *p = X->slot[slot].p;
+    return SHCI_OK;
+  }
+};
+
+// carve a planned layout from a region of the arena: plan(cv) runs once to
+// size it and once on the region
+template <class Plan>
+int carve_region(Arena& A, int slot, Plan&& plan) {
+  Carver cv(nullptr);
+  plan(cv);
+  void* p = nullptr;
+  CHK(A.take(slot, std::max<size_t>(cv.off, 1), &p));
+  Carver cv2(p);
+  plan(cv2);
+  return SHCI_OK;
+}
 
 constexpr int GEN_BLOCKS_PER_CU = 32;  // many more blocks than resident: blocks that finish early are replaced
 constexpr int RED_BLOCKS_PER_CU = 8;
@@ -356,7 +411,11 @@ struct Job {
   double* per_sample_de0 = nullptr;  // device [nsamp], nullable: dS_s/dE0
   const uint64_t* samp_off = nullptr;  // host [nsamp + 1]: item range of each sample of the chunk
   double grad_scale = 1.0;             // sample mode: weight of this chunk's adjoint
+  Arena* ar = nullptr;           // device memory of the call
   int64_t max_records = 0;       // > 0: give up after the count pass if exceeded
+  int64_t max_records_eff = 0;   // on JOB_TOO_BIG: the records that would have fit
+  bool keep = false;             // adjoint from the forward records (record positions carried)
+  double* contrib = nullptr;     // keep mode: per record t * 2 A_a / D_a (records' generation order)
   uint32_t bmask = 0, bsel = 0;  // hash batch of a
   const int32_t* sbatch = nullptr;  // device: batch of each sample of the chunk (sample mode)
   double sample_scale = 1.0;        // factor on every per-sample result (number of batches)
@@ -372,6 +431,120 @@ struct Job {
   int32_t nbatch = 1;
 };
 
+// Layout of the record region of one pass.
+struct BigDims {
+  int kw = 0, vsize = 8;
+  bool v2 = false, pay = false, want_u = false, keep = false;
+  int64_t nrec = 0, nbucket = 1, ntiles = 1;
+  int64_t npart = 1;  // per-wavefront partial slots (waves, times the sample slots in sample mode)
+  int npass = 0;
+};
+struct BigPlan {
+  Recs A, B;
+  uint32_t *hist = nullptr, *hoffs = nullptr;
+  ScanTmp hsc;
+  Partials P, Pq, Pw;
+  Uniq U;
+  uint64_t *boff = nullptr, *bst = nullptr;
+  uint32_t* slow = nullptr;
+  uint32_t* slow_bits = nullptr;  // bitmap of the block kernel's buckets
+  double* contrib = nullptr;      // keep mode: per-record adjoint terms
+};
+
+template <class CV>
+void plan_partials(CV& cv, Partials& P, int64_t m, bool nseg) {
+  P.e2 = cv.template take<double>(m);
+  P.de0 = cv.template take<double>(m);
+  P.e2sq = cv.template take<double>(m);
+  P.nterm = cv.template take<int64_t>(m);
+  P.ngen = cv.template take<int64_t>(m);
+  P.nuniq = cv.template take<int32_t>(m);
+  P.nintr = cv.template take<int32_t>(m);
+  P.nzero = cv.template take<int32_t>(m);
+  P.mind = cv.template take<double>(m);
+  P.nseg = nseg ? cv.template take<int32_t>(m) : nullptr;
+}
+
+template <class CV>
+void plan_recs(CV& cv, Recs& R, const BigDims& d) {
+  const int64_t m = d.nrec;
+  for (int w = 0; w < d.kw; ++w) R.k[w] = cv.template take<uint64_t>(m);
+  R.v = d.vsize == 4 ? (void*)cv.template take<float>(m) : (void*)cv.template take<double>(m);
+  R.v2 = d.v2 ? (d.vsize == 4 ? (void*)cv.template take<float>(m) : (void*)cv.template take<double>(m)) : nullptr;
+  R.pay = d.pay ? cv.template take<uint32_t>(m) : nullptr;
+  R.bid = cv.template take<uint32_t>(m);
+  R.haa = cv.template take<double>(m);
+}
+
+template <class CV>
+void plan_big(CV& cv, const BigDims& d, BigPlan& o) {
+  const int64_t nb = d.nbucket;
+  plan_recs(cv, o.A, d);
+  if (d.npass > 0) plan_recs(cv, o.B, d);
+  o.bst = cv.template take<uint64_t>(nb + 1);
+  o.slow = cv.template take<uint32_t>(nb + 1);
+  o.slow_bits = cv.template take<uint32_t>(nb / 32 + 1);
+  o.hist = cv.template take<uint32_t>((size_t)256 * d.ntiles);
+  o.hoffs = cv.template take<uint32_t>((size_t)256 * d.ntiles + 1);
+  o.hsc.carve(cv, std::max<int64_t>((int64_t)256 * d.ntiles, nb + 1));
+  plan_partials(cv, o.P, nb, true);
+  plan_partials(cv, o.Pw, d.npart, false);
+  plan_partials(cv, o.Pq, 1024, false);
+  if (d.want_u) {
+    for (int w = 0; w < d.kw; ++w) o.U.k[w] = cv.template take<uint64_t>(d.nrec);
+    o.U.h2 = cv.template take<uint32_t>(d.nrec);
+    o.U.A = cv.template take<double>(d.nrec);
+    o.U.D = cv.template take<double>(d.nrec);
+    o.U.g = cv.template take<double>(d.nrec);
+    o.U.cnt = cv.template take<int32_t>(d.nrec);
+    o.U.start = cv.template take<uint64_t>(nb + 1);
+    o.boff = cv.template take<uint64_t>(nb + 1);
+  }
+  o.contrib = d.keep ? cv.template take<double>(d.nrec) : nullptr;
+}
+
+// hash set of V: 2^ceil(log2 2N) slots, presence filter of ~16 bits per member
+void vset_dims(int64_t ndet, uint64_t& vcap, int& fbits, int64_t& fwords) {
+  vcap = 1024;
+  while (vcap < 2 * (uint64_t)ndet) vcap <<= 1;
+  fbits = 10;  // false positives ~6%
+  while (fbits < 32 && ((uint64_t)1 << fbits) < 16 * (uint64_t)ndet) ++fbits;
+  fwords = ((int64_t)1 << fbits) / 32;
+}
+
+struct Phase0 {  // per source: work split; hash set of V
+  uint32_t* nsplit = nullptr;
+  uint64_t *soff = nullptr, *vtab = nullptr, *total = nullptr;
+  uint32_t* vfilt = nullptr;
+  ScanTmp sc0;
+};
+template <class CV>
+void plan_phase0(CV& cv, Phase0& p, int64_t nsrc, uint64_t vcap, int64_t fwords) {
+  p.nsplit = cv.template take<uint32_t>(nsrc + 1);
+  p.soff = cv.template take<uint64_t>(nsrc + 1);
+  p.vtab = cv.template take<uint64_t>(vcap);
+  p.vfilt = cv.template take<uint32_t>(fwords);
+  p.total = cv.template take<uint64_t>(4);
+  p.sc0.carve(cv, nsrc + 1);
+}
+
+struct Phase1 {  // per work item: source, pair range, count, offset, adjoint parts
+  uint32_t *w_src = nullptr, *w_rng = nullptr, *counts = nullptr;
+  uint64_t* offs = nullptr;
+  double *gpart = nullptr, *gitem = nullptr;
+  ScanTmp sc;
+};
+template <class CV>
+void plan_phase1(CV& cv, Phase1& p, int64_t ni, int64_t nsrc, bool grad, bool sample) {
+  p.w_src = cv.template take<uint32_t>(ni + 1);
+  p.w_rng = cv.template take<uint32_t>(ni + 1);
+  p.counts = cv.template take<uint32_t>(ni + 1);
+  p.offs = cv.template take<uint64_t>(ni + 1);
+  p.gpart = grad ? cv.template take<double>(ni + 1) : nullptr;
+  p.gitem = (grad && sample) ? cv.template take<double>(nsrc + 1) : nullptr;
+  p.sc.carve(cv, ni + 1);
+}
+
 template <int KW, typename VT, bool SAMPLE>
 int run_job(Job& J) {
   shci_pt2_ctx* X = J.ctx;
@@ -384,30 +557,18 @@ int run_job(Job& J) {
 
   // ---- phase 0: validation, hash set of V, work split per source ----
   const int64_t nsrc = J.n_items;
-  uint64_t vcap = 1024;
-  while (vcap < 2 * (uint64_t)J.ndet) vcap <<= 1;
-  int fbits = 10;  // presence filter: ~16 bits per member (false positives ~6%)
-  while (fbits < 32 && ((uint64_t)1 << fbits) < 16 * (uint64_t)J.ndet) ++fbits;
-  const int64_t fwords = ((int64_t)1 << fbits) / 32;
-  uint32_t* nsplit;
-  uint64_t *soff, *vtab, *total;
-  uint32_t* vfilt;
-  ScanTmp sc0;
-  auto plan0 = [&](Carver& cv) {
-    nsplit = cv.take<uint32_t>(nsrc + 1);
-    soff = cv.take<uint64_t>(nsrc + 1);
-    vtab = cv.take<uint64_t>(vcap);
-    vfilt = cv.take<uint32_t>(fwords);
-    total = cv.take<uint64_t>(4);
-    sc0.carve(cv, nsrc + 1);
-  };
-  {
-    Carver cv(nullptr);
-    plan0(cv);
-    CHK(X->small.ensure(cv.off, X->ws_limit));
-    Carver cv2(X->small.p);
-    plan0(cv2);
-  }
+  uint64_t vcap;
+  int fbits;
+  int64_t fwords;
+  vset_dims(J.ndet, vcap, fbits, fwords);
+  Phase0 p0;
+  Arena& AR = *J.ar;
+  const size_t job_mark = AR.mark();
+  CHK(carve_region(AR, SL_V, [&](Carver& cv) { plan_phase0(cv, p0, nsrc, vcap, fwords); }));
+  uint32_t* nsplit = p0.nsplit;
+  uint64_t *soff = p0.soff, *vtab = p0.vtab, *total = p0.total;
+  uint32_t* vfilt = p0.vfilt;
+  ScanTmp& sc0 = p0.sc0;
   uint32_t* dflag = X->dflag;
   uint32_t* counter = X->dflag + 1;
   uint32_t* overflow = X->dflag + 2;
@@ -455,27 +616,13 @@ int run_job(Job& J) {
   if (ni >= (int64_t)0xffffffffll) return fail(SHCI_ERR_WORKSPACE, "too many work items");
 
   // ---- phase 1: work items, count pass ----
-  uint32_t *w_src, *w_rng, *counts;
-  uint64_t* offs;
-  double* gpart = nullptr;
-  double* gitem = nullptr;  // sample mode: adjoint per item before the scatter to determinants
-  ScanTmp sc;
-  auto plan1 = [&](Carver& cv) {
-    w_src = cv.take<uint32_t>(ni + 1);
-    w_rng = cv.take<uint32_t>(ni + 1);
-    counts = cv.take<uint32_t>(ni + 1);
-    offs = cv.take<uint64_t>(ni + 1);
-    gpart = J.grad ? cv.take<double>(ni + 1) : nullptr;
-    gitem = (J.grad && SAMPLE) ? cv.take<double>(nsrc + 1) : nullptr;
-    sc.carve(cv, ni + 1);
-  };
-  {
-    Carver cv(nullptr);
-    plan1(cv);
-    CHK(X->small1.ensure(cv.off, X->ws_limit));
-    Carver cv2(X->small1.p);
-    plan1(cv2);
-  }
+  Phase1 p1;
+  CHK(carve_region(AR, SL_ITEMS, [&](Carver& cv) { plan_phase1(cv, p1, ni, nsrc, J.grad != nullptr, SAMPLE); }));
+  uint32_t *w_src = p1.w_src, *w_rng = p1.w_rng, *counts = p1.counts;
+  uint64_t* offs = p1.offs;
+  double* gpart = p1.gpart;
+  double* gitem = p1.gitem;  // sample mode: adjoint per item before the scatter to determinants
+  ScanTmp& sc = p1.sc;
   k_split_fill<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, nsrc, npairs, w_src, w_rng);
 
   GenArgs g{};
@@ -507,6 +654,7 @@ int run_job(Job& J) {
   g.ref = J.dets;
   g.Fref = T.fref;
   g.smarg = 8.0 * (2 * n + 2 + 2 * DL_CAP) * 0x1p-53;
+  g.pay_pos = J.keep ? 1 : 0;
   singles_ref(T, J.dets, st);
   const int gen_grid = cus * GEN_BLOCKS_PER_CU;
   k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
@@ -521,6 +669,8 @@ int run_job(Job& J) {
   const int64_t nrec = (int64_t)hostv[0];
   if (J.max_records > 0 && nrec > J.max_records) {
     J.nrec = nrec;
+    J.max_records_eff = J.max_records;
+    AR.reset(job_mark);
     return JOB_TOO_BIG;
   }
   if (nrec >= (int64_t)0xffffffffll)
@@ -531,95 +681,69 @@ int run_job(Job& J) {
   GroupPlan G;
   G.sbits = J.sbits;
   {
+    // buckets of 64-128 records on average; one more hash bit (32-64) when
+    // it costs no extra partition pass: smaller buckets sort in fewer
+    // register slots in the reduce
     const int64_t per_sample_rec = SAMPLE ? std::max<int64_t>(1, nrec / std::max(1, J.nsamp)) : nrec;
     G.bits_hash = std::min(26, std::max(0, ceil_log2((uint64_t)((per_sample_rec + 127) / 128))));
+    const int nb0 = G.bits_hash + G.sbits;
+    if (G.bits_hash < 26 && per_sample_rec >= ((int64_t)64 << G.bits_hash) && (nb0 + 1 + 7) / 8 == (nb0 + 7) / 8)
+      G.bits_hash += 1;
   }
 
+  const size_t big_mark = AR.mark();
   for (int attempt = 0;; ++attempt) {
+    AR.reset(big_mark);
     G.nbits = G.bits_hash + G.sbits;
     G.nbucket = (int64_t)1 << G.nbits;
     const int npass = (G.nbits + 7) / 8;
     const int64_t ntiles = std::max<int64_t>(1, (nrec + PTILE - 1) / PTILE);
     const bool v2 = SAMPLE;
-    const bool pay = J.want_pay;
-    auto plan_big = [&](Carver& cv, Recs* A, Recs* B, uint32_t** hist, uint32_t** hoffs, ScanTmp* hsc,
-                        Partials* P, Uniq* U, uint64_t** boff, uint64_t** bst,
-                        uint32_t** slow, Partials* Pq, Partials* Pw) {
-      for (int w = 0; w < KW; ++w) A->k[w] = cv.take<uint64_t>(nrec);
-      A->v = cv.take<VT>(nrec);
-      A->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
-      A->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
-      A->bid = cv.take<uint32_t>(nrec);
-      A->haa = cv.take<double>(nrec);
-      if (npass > 0) {
-        for (int w = 0; w < KW; ++w) B->k[w] = cv.take<uint64_t>(nrec);
-        B->v = cv.take<VT>(nrec);
-        B->v2 = v2 ? cv.take<VT>(nrec) : nullptr;
-        B->pay = pay ? cv.take<uint32_t>(nrec) : nullptr;
-        B->bid = cv.take<uint32_t>(nrec);
-        B->haa = cv.take<double>(nrec);
-      }
-      *bst = cv.take<uint64_t>(G.nbucket + 1);
-      *slow = cv.take<uint32_t>(G.nbucket + 1);
-      *hist = cv.take<uint32_t>((size_t)256 * ntiles);
-      *hoffs = cv.take<uint32_t>((size_t)256 * ntiles + 1);
-      hsc->carve(cv, std::max<int64_t>((int64_t)256 * ntiles, G.nbucket + 1));
-      const int64_t nb = G.nbucket;
-      P->e2 = cv.take<double>(nb);
-      P->de0 = cv.take<double>(nb);
-      P->e2sq = cv.take<double>(nb);
-      P->nterm = cv.take<int64_t>(nb);
-      P->ngen = cv.take<int64_t>(nb);
-      P->nuniq = cv.take<int32_t>(nb);
-      P->nintr = cv.take<int32_t>(nb);
-      P->nzero = cv.take<int32_t>(nb);
-      P->mind = cv.take<double>(nb);
-      P->nseg = cv.take<int32_t>(nb);
-      const int64_t nw = (int64_t)cus * RED_BLOCKS_PER_CU * WRED_WAVES;
-      Pw->e2 = cv.take<double>(nw);
-      Pw->de0 = cv.take<double>(nw);
-      Pw->e2sq = cv.take<double>(nw);
-      Pw->nterm = cv.take<int64_t>(nw);
-      Pw->ngen = cv.take<int64_t>(nw);
-      Pw->nuniq = cv.take<int32_t>(nw);
-      Pw->nintr = cv.take<int32_t>(nw);
-      Pw->nzero = cv.take<int32_t>(nw);
-      Pw->mind = cv.take<double>(nw);
-      Pq->e2 = cv.take<double>(1024);
-      Pq->de0 = cv.take<double>(1024);
-      Pq->e2sq = cv.take<double>(1024);
-      Pq->nterm = cv.take<int64_t>(1024);
-      Pq->ngen = cv.take<int64_t>(1024);
-      Pq->nuniq = cv.take<int32_t>(1024);
-      Pq->nintr = cv.take<int32_t>(1024);
-      Pq->nzero = cv.take<int32_t>(1024);
-      Pq->mind = cv.take<double>(1024);
-      if (J.want_u) {
-        for (int w = 0; w < KW; ++w) U->k[w] = cv.take<uint64_t>(nrec);
-        U->h2 = cv.take<uint32_t>(nrec);
-        U->A = cv.take<double>(nrec);
-        U->D = cv.take<double>(nrec);
-        U->g = cv.take<double>(nrec);
-        U->cnt = cv.take<int32_t>(nrec);
-        U->start = cv.take<uint64_t>(nb + 1);
-        *boff = cv.take<uint64_t>(nb + 1);
-      }
-    };
-    Recs A, B;
-    uint32_t *hist, *hoffs;
-    ScanTmp hsc;
-    Partials P, Pq, Pw;
-    Uniq U;
-    uint64_t* boff = nullptr;
-    uint64_t* bst = nullptr;
-    uint32_t* slow = nullptr;
-    {
+    const bool pay = J.want_pay || J.keep;
+    BigDims bd;
+    bd.kw = KW;
+    bd.vsize = (int)sizeof(VT);
+    bd.v2 = v2;
+    bd.pay = pay;
+    bd.want_u = J.want_u;
+    bd.keep = J.keep;
+    bd.nrec = nrec;
+    bd.nbucket = G.nbucket;
+    bd.ntiles = ntiles;
+    bd.npass = npass;
+    // reduce launch: wavefronts, and the sample slots of the chunk's key bits
+    const int64_t wblocks =
+        std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * RED_BLOCKS_PER_CU);
+    const int64_t nwv = wblocks * WRED_WAVES;
+    const int64_t nslots = SAMPLE ? ((int64_t)1 << G.sbits) : 1;
+    bd.npart = nwv * nslots;
+    BigPlan BP;
+    if (AR.caller()) {
+      // the records must fit what the workspace has left; otherwise report
+      // how many would have fit (hash batches / smaller sample chunks)
       Carver cv(nullptr);
-      plan_big(cv, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bst, &slow, &Pq, &Pw);
-      CHK(X->big.ensure(cv.off, X->ws_limit));
-      Carver cv2(X->big.p);
-      plan_big(cv2, &A, &B, &hist, &hoffs, &hsc, &P, &U, &boff, &bst, &slow, &Pq, &Pw);
+      plan_big(cv, bd, BP);
+      if (cv.off > AR.remaining()) {
+        J.nrec = nrec;
+        J.max_records_eff = std::max<int64_t>(
+            1, (int64_t)(0.95 * (double)nrec * (double)AR.remaining() / (double)cv.off));
+        AR.reset(job_mark);
+        return JOB_TOO_BIG;
+      }
     }
+    CHK(carve_region(AR, SL_REC, [&](Carver& cv) { plan_big(cv, bd, BP); }));
+    Recs& A = BP.A;
+    Recs& B = BP.B;
+    uint32_t* hist = BP.hist;
+    uint32_t* hoffs = BP.hoffs;
+    ScanTmp& hsc = BP.hsc;
+    Partials& P = BP.P;
+    Partials& Pq = BP.Pq;
+    Partials& Pw = BP.Pw;
+    Uniq& U = BP.U;
+    uint64_t* boff = BP.boff;
+    uint64_t* bst = BP.bst;
+    uint32_t* slow = BP.slow;
     {
       // ---- generation (write pass; repeated after a re-plan, same records) ----
       g.out = A;
@@ -692,17 +816,23 @@ int run_job(Job& J) {
     ra.overflow = overflow;
     ra.want_u = J.want_u ? 1 : 0;
     ra.bstart = bst;
+    ra.contrib = (J.keep && !SAMPLE) ? BP.contrib : nullptr;
     uint32_t* slow_count = X->dflag + 3;
-    const int64_t wblocks =
-        std::min<int64_t>((G.nbucket + WRED_WAVES - 1) / WRED_WAVES, (int64_t)cus * RED_BLOCKS_PER_CU);
     WaveRedArgs wa;
     wa.r = ra;
     wa.bstart = bst;
     wa.slow_list = slow;
     wa.slow_count = slow_count;
+    wa.slow_bits = BP.slow_bits;
     wa.Pw = Pw;
+    wa.nwaves = nwv;
+    wa.nsamp = (int32_t)nslots;
     k_fill_u32<<<1, 64, 0, st>>>(overflow, 1, 0u);
     k_fill_u32<<<1, 64, 0, st>>>(slow_count, 1, 0u);
+    {
+      const int64_t nw = G.nbucket / 32 + 1;
+      k_fill_u32<<<(int)std::min<int64_t>(4096, (nw + 255) / 256), 256, 0, st>>>(BP.slow_bits, nw, 0u);
+    }
     HIPCHK(hipEventRecord(X->ev[8], st));
     k_reduce_wave<KW, SAMPLE, VT><<<(int)wblocks, 64 * WRED_WAVES, 0, st>>>(wa);
     // buckets the wavefront kernel could not take: block kernel with a full-key sort
@@ -716,20 +846,19 @@ int run_job(Job& J) {
     HIPCHK(hipGetLastError());
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
     if (SAMPLE) {
-      k_final<<<J.nsamp, 1024, 0, st>>>(P, G.nbucket, 0, J.nsamp, overflow, dflag, X->dres, J.per_sample,
-                                         (int64_t)1 << G.bits_hash, J.per_sample_de0, J.sample_scale);
+      k_final_sample<<<J.nsamp, 1024, 0, st>>>(Pw, nwv, P, BP.slow_bits, G.bits_hash, X->dres, J.per_sample,
+                                                J.per_sample_de0, J.sample_scale);
     } else {
-      // bucket partials (only the block kernel's buckets are non-zero) and
-      // per-wavefront partials, summed in a fixed order
-      const int64_t fchunk = std::max<int64_t>(256, (G.nbucket + 511) / 512);
+      // the block kernel's bucket partials (through the bitmap, in bucket
+      // order) and the per-wavefront partials, summed in a fixed order
+      const int64_t fchunk = std::max<int64_t>(8192, ((G.nbucket + 511) / 512 + 31) / 32 * 32);
       const int64_t fblocks = (G.nbucket + fchunk - 1) / fchunk;
-      const int64_t nwv = wblocks * WRED_WAVES;
       const int64_t wchunk = std::max<int64_t>(256, (nwv + 511) / 512);
       const int64_t wfblocks = (nwv + wchunk - 1) / wchunk;
       Partials Q = Pq, Q2 = Pq;
       Q2.e2 += fblocks; Q2.de0 += fblocks; Q2.e2sq += fblocks; Q2.nterm += fblocks; Q2.ngen += fblocks;
       Q2.nuniq += fblocks; Q2.nintr += fblocks; Q2.nzero += fblocks; Q2.mind += fblocks;
-      k_final_partial<<<(int)fblocks, 256, 0, st>>>(P, G.nbucket, fchunk, Q);
+      k_final_partial_marked<<<(int)fblocks, 256, 0, st>>>(P, BP.slow_bits, G.nbucket, fchunk, Q);
       k_final_partial<<<(int)wfblocks, 256, 0, st>>>(Pw, nwv, wchunk, Q2);
       k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0, nullptr,
                                    1.0);
@@ -769,7 +898,14 @@ int run_job(Job& J) {
     J.vbytes = (int)sizeof(VT) * (SAMPLE ? 2 : 1);
     J.nbucket = (int32_t)G.nbucket;
 
-    if (J.want_u && J.grad) {
+    if (J.keep && J.grad && !SAMPLE) {
+      // adjoint from the forward records: per work item, the sum of its
+      // records' t * 2 A_a / D_a; per source, divided by c_i
+      k_keep_item_sum<<<(int)((ni + 3) / 4), 256, 0, st>>>(offs, ni, BP.contrib, gpart);
+      k_grad_sum<<<(int)((nsrc + 255) / 256), 256, 0, st>>>(nsplit, soff, gpart, nsrc, J.grad,
+                                                              J.grad_accumulate ? 1 : 0, J.c);
+      HIPCHK(hipGetLastError());
+    } else if (J.want_u && J.grad) {
       LookupArgs L;
       L.U = U;
       L.nseg = P.nseg;
@@ -805,6 +941,7 @@ int run_job(Job& J) {
       J.ex->t_n = nrec;
     }
     HIPCHK(hipStreamSynchronize(st));
+    AR.reset(job_mark);
     return SHCI_OK;
   }
 }
@@ -871,25 +1008,36 @@ void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
 // slowly (scattered writes over a larger working set) and gain nothing.
 constexpr int64_t REC_CAP_AUTO = (int64_t)3 << 29;  // 1.61e9
 
-int64_t record_budget(shci_pt2_ctx* X, double per_rec) {
+int64_t record_budget(const Arena& A, double per_rec) {
+  shci_pt2_ctx* X = A.X;
   if (X->rec_limit > 0) return X->rec_limit;
-  size_t fr = 0, tt = 0;
-  if (hipMemGetInfo(&fr, &tt) != hipSuccess) {
-    (void)hipGetLastError();
-    fr = 0;
+  size_t avail;
+  if (A.caller()) {
+    // an estimate for sizing; run_job checks the exact layout against the
+    // workspace after its count pass
+    avail = A.remaining();
+  } else {
+    size_t fr = 0, tt = 0;
+    if (hipMemGetInfo(&fr, &tt) != hipSuccess) {
+      (void)hipGetLastError();
+      fr = 0;
+    }
+    avail = fr + X->slot[SL_REC].cap;
+    if (X->ws_limit) avail = std::min(avail, X->ws_limit);
   }
-  size_t avail = fr + X->big.cap;
-  if (X->ws_limit) avail = std::min(avail, X->ws_limit);
   const size_t reserve = (size_t)(num_cus(X->device) * RED_BLOCKS_PER_CU * WRED_WAVES + 1024) * 64 + (2u << 20);
   avail = avail > reserve ? avail - reserve : 0;
-  const int64_t m = (int64_t)(0.75 * (double)avail / per_rec);
+  const int64_t m = (int64_t)((A.caller() ? 0.9 : 0.75) * (double)avail / per_rec);
   return std::max<int64_t>(1, std::min<int64_t>(m, REC_CAP_AUTO));
 }
 
-double record_bytes(int kw, int vbytes, bool pay, bool uniq) {
+double record_bytes(int kw, int vbytes, bool pay, bool uniq, bool keep = false) {
   // two record buffers (keys, values, payload, bucket id, H_aa), then slack
-  // for the bucket tables and the per-unique output
-  return 2.0 * (8.0 * kw + vbytes + (pay ? 4.0 : 0.0) + 4.0 + 8.0) + 2.0 + (uniq ? 8.0 * kw + 40.0 : 0.0);
+  // for the bucket tables and the per-unique output (and the keep-mode
+  // per-record adjoint terms)
+  pay = pay || keep;
+  return 2.0 * (8.0 * kw + vbytes + (pay ? 4.0 : 0.0) + 4.0 + 8.0) + 2.0 + (uniq ? 8.0 * kw + 40.0 : 0.0) +
+         (keep ? 8.0 : 0.0);
 }
 
 // Deterministic evaluation within the record budget.  When the screened
@@ -901,7 +1049,7 @@ int run_det_batched(const Job& proto, Job& acc) {
   shci_pt2_ctx* X = proto.ctx;
   const int kw = key_words(X->T.n, 0);
   const int vb = proto.precision == SHCI_FP32C ? 4 : 8;
-  const int64_t max_rec = record_budget(X, record_bytes(kw, vb, proto.want_pay, proto.want_u));
+  const int64_t max_rec = record_budget(*proto.ar, record_bytes(kw, vb, proto.want_pay, proto.want_u, proto.keep));
   uint32_t nb = 1;
   for (;;) {
     acc = Job{};
@@ -911,7 +1059,9 @@ int run_det_batched(const Job& proto, Job& acc) {
       Job J = proto;
       J.bmask = nb - 1;
       J.bsel = b;
-      J.max_records = max_rec;
+      // with a caller workspace the job checks its exact layout against what
+      // is left of it after its count pass
+      J.max_records = (proto.ar->caller() && X->rec_limit == 0) ? REC_CAP_AUTO : max_rec;
       J.grad_accumulate = b > 0;
       shci_pt2_export exb{};
       if (proto.ex) {
@@ -936,13 +1086,13 @@ int run_det_batched(const Job& proto, Job& acc) {
       const int r = dispatch(J);
       if (r == JOB_TOO_BIG) {
         // batches needed at this batch's size, with a margin for unevenness
-        const double need = 1.3 * (double)J.nrec * nb / (double)max_rec;
+        const double need = 1.3 * (double)J.nrec * nb / (double)std::max<int64_t>(1, J.max_records_eff);
         uint32_t nn = nb;
         while (nn < need) nn <<= 1;
         if (nn == nb) nn <<= 1;
         if (nn > 256)
           return fail(SHCI_ERR_WORKSPACE, "%lld screened terms need more than 256 hash batches of %lld records",
-                      (long long)((double)J.nrec * nb), (long long)max_rec);
+                      (long long)((double)J.nrec * nb), (long long)J.max_records_eff);
         nb = nn;
         again = true;
         break;
@@ -980,11 +1130,154 @@ int run_det_batched(const Job& proto, Job& acc) {
 
 }  // namespace
 
+namespace {
+
+int ws_check(const void* ws, size_t ws_bytes) {
+  if (ws && ((uintptr_t)ws & (WS_ALIGN - 1)))
+    return fail(SHCI_ERR_ARG, "ws must be aligned to %zu bytes", WS_ALIGN);
+  if (ws && ws_bytes == 0) return fail(SHCI_ERR_ARG, "ws_bytes must be > 0 when ws is given");
+  return SHCI_OK;
+}
+
+// Alias table of p_i = |c_i| / sum_j |c_j| (thresholds and aliases, device
+// arrays of n); temporaries from the arena, released on return.
+struct AliasTmp {
+  AliasArgs a;
+  ScanTmp s1, s2, s3;
+};
+template <class CV>
+void plan_alias(CV& cv, AliasTmp& t, int64_t n) {
+  const int64_t nblk = (n + 4095) / 4096;
+  t.a.maxbits = cv.template take<uint64_t>(2);
+  t.a.w = cv.template take<u128>(n);
+  t.a.tsum = cv.template take<u128>(nblk);
+  t.a.tot = cv.template take<u128>(1);
+  t.a.isl = cv.template take<uint32_t>(n);
+  t.a.lpos = cv.template take<uint64_t>(n + 1);
+  t.a.hidx = cv.template take<uint32_t>(n);
+  t.a.dl = cv.template take<u128>(n + 1);
+  t.a.xh = cv.template take<u128>(n + 1);
+  t.s1.carve(cv, n + 1);
+  t.s2.carve(cv, n + 1, 2);
+  t.s3.carve(cv, n + 1, 2);
+}
+
+int build_alias(Arena& A, const double* c, int64_t n, uint64_t* thr, uint32_t* alias, hipStream_t st) {
+  AliasTmp t;
+  const size_t m = A.mark();
+  CHK(carve_region(A, SL_ALIAS, [&](Carver& cv) { plan_alias(cv, t, n); }));
+  AliasArgs& a = t.a;
+  a.c = c;
+  a.n = n;
+  a.K = 127 - 2 * ceil_log2((uint64_t)n);
+  a.thr = thr;
+  a.alias = alias;
+  a.flag = A.X->dflag;
+  const int64_t nblk = (n + 4095) / 4096;
+  const int grid = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  k_fill_u64<<<1, 64, 0, st>>>(a.maxbits, 1, 0ull);
+  k_alias_max<<<grid, 256, 0, st>>>(c, n, a.maxbits, a.flag);
+  k_alias_weights<<<(int)nblk, 256, 0, st>>>(a);
+  k_alias_total<<<1, 256, 0, st>>>(a, nblk);
+  k_alias_classify<<<grid, 256, 0, st>>>(a);
+  CHK(scan_exclusive<uint32_t, uint64_t>(a.isl, a.lpos, n, t.s1, a.lpos + n, st));
+  k_alias_heavies<<<grid, 256, 0, st>>>(a);
+  CHK(scan_exclusive<u128, u128>(a.dl, a.dl, n, t.s2, a.dl + n, st));
+  CHK(scan_exclusive<u128, u128>(a.xh, a.xh, n, t.s3, a.xh + n, st));
+  k_alias_assemble<<<grid, 256, 0, st>>>(a);
+  HIPCHK(hipGetLastError());
+  // later regions may reuse the temporaries: they run after these kernels
+  // on the same stream
+  A.reset(m);
+  return SHCI_OK;
+}
+
+// batch of P of each sample on the seed path: the top log2(n_batches) bits
+// of SplitMix64 output 2 N_s N_d + s + 1 (after the outputs of the draws)
+__global__ void k_seed_batches(uint64_t seed, int32_t ns, int32_t nd, int32_t n_batches, int32_t* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  const uint64_t r = splitmix64_out(seed, 2 * (uint64_t)ns * (uint64_t)nd + (uint64_t)s + 1);
+  out[s] = (int32_t)__umul64hi(r, (uint64_t)n_batches);
+}
+
+__global__ void k_check_batches(const int32_t* sb, int32_t ns, int32_t n_batches, uint32_t* flag) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < ns && (sb[s] < 0 || sb[s] >= n_batches)) atomicOr(flag, 128u);
+}
+
+// draws [ns][nd] of the stochastic samples from the seed
+int seed_draws(Arena& A, const double* c, int64_t n, uint64_t seed, int32_t ns, int32_t nd, uint32_t* draws,
+               hipStream_t st) {
+  uint64_t* thr = nullptr;
+  uint32_t* al = nullptr;
+  const size_t m = A.mark();
+  CHK(carve_region(A, SL_TABLE, [&](Carver& cv) {
+    thr = cv.take<uint64_t>(n);
+    al = cv.take<uint32_t>(n);
+  }));
+  CHK(build_alias(A, c, n, thr, al, st));
+  const int64_t tot = (int64_t)ns * nd;
+  k_alias_draw<<<(int)std::min<int64_t>(16384, (tot + 255) / 256), 256, 0, st>>>(thr, al, n, seed, ns, nd, draws);
+  HIPCHK(hipGetLastError());
+  A.reset(m);
+  return SHCI_OK;
+}
+
+// bytes of the job regions (validation / V set, work items, records)
+size_t job_bytes(int kw, int vsize, bool sample, bool grad, bool keep, bool want_u, int64_t ndet, int64_t nsrc,
+                 int64_t ni, int64_t nrec, int32_t nsamp, int cus) {
+  uint64_t vcap;
+  int fbits;
+  int64_t fwords;
+  vset_dims(ndet, vcap, fbits, fwords);
+  size_t tot = 0;
+  {
+    Carver cv(nullptr);
+    Phase0 p;
+    plan_phase0(cv, p, nsrc, vcap, fwords);
+    tot += cv.off + WS_ALIGN;
+  }
+  {
+    Carver cv(nullptr);
+    Phase1 p;
+    plan_phase1(cv, p, ni, nsrc, grad, sample);
+    tot += cv.off + WS_ALIGN;
+  }
+  {
+    GroupPlan G;
+    G.sbits = sample ? std::max(1, ceil_log2((uint64_t)std::max(1, nsamp))) : 0;
+    const int64_t per = sample ? std::max<int64_t>(1, nrec / std::max(1, nsamp)) : nrec;
+    G.bits_hash = std::min(26, std::max(0, ceil_log2((uint64_t)((per + 127) / 128))));
+    G.nbits = G.bits_hash + G.sbits;
+    BigDims d;
+    d.kw = kw;
+    d.vsize = vsize;
+    d.v2 = sample;
+    d.pay = keep;
+    d.want_u = want_u;
+    d.keep = keep;
+    d.nrec = nrec;
+    // one re-plan with an extra hash bit is allowed for
+    d.nbucket = (int64_t)1 << (G.nbits + 1);
+    d.ntiles = std::max<int64_t>(1, (nrec + PTILE - 1) / PTILE);
+    d.npass = (G.nbits + 1 + 7) / 8;
+    d.npart = (int64_t)cus * RED_BLOCKS_PER_CU * WRED_WAVES * (sample ? ((int64_t)1 << G.sbits) : 1);
+    Carver cv(nullptr);
+    BigPlan o;
+    plan_big(cv, d, o);
+    tot += cv.off + WS_ALIGN;
+  }
+  return tot;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* shci_pt2_last_error(void) { return g_msg; }
 
-const char* shci_pt2_version(void) { return "shci_pt2 0.1 (gfx950)"; }
+const char* shci_pt2_version(void) { return "shci_pt2 0.2 (gfx950)"; }
 
 int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, const double* eri, void* stream,
                         shci_pt2_ctx** out) {
@@ -1037,7 +1330,7 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
   {
     Carver cv(nullptr);
     plan(cv);
-    int s = X->tables.ensure(cv.off, 0);
+    int s = X->tables.ensure(cv.off, 0, st);
     if (s) return bail(s);
     Carver cv2(X->tables.p);
     plan(cv2);
@@ -1064,9 +1357,7 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   ctx->tables.release();
-  ctx->small.release();
-  ctx->small1.release();
-  ctx->big.release();
+  for (auto& b : ctx->slot) b.release();
   delete ctx;
 }
 
@@ -1083,13 +1374,74 @@ int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes) {
   return SHCI_OK;
 }
 
+int shci_pt2_workspace_size(const shci_pt2_ctx* ctx, int op, int64_t n_det, int64_t n_records, int32_t n_samples,
+                            int32_t n_draws, int precision, size_t* bytes) {
+  if (!ctx || !bytes) return fail(SHCI_ERR_ARG, "ctx and bytes must be non-NULL");
+  if (n_det < 1 || n_det >= (int64_t)0xffffffffll) return fail(SHCI_ERR_ARG, "n_det must be in [1, 2^32 - 1)");
+  if (n_records < 0) return fail(SHCI_ERR_ARG, "n_records must be >= 0");
+  if (precision != SHCI_FP64 && precision != SHCI_FP32C) return fail(SHCI_ERR_ARG, "unknown precision");
+  const bool sample = op == SHCI_OP_SAMPLE || op == SHCI_OP_SAMPLE_GRAD;
+  if (op < SHCI_OP_DET || op > SHCI_OP_DRAWS) return fail(SHCI_ERR_ARG, "unknown op");
+  if ((sample || op == SHCI_OP_DRAWS) && (n_samples < 1 || n_draws < 1))
+    return fail(SHCI_ERR_ARG, "sample ops need n_samples >= 1 and n_draws >= 1");
+  const int vsize = precision == SHCI_FP32C ? 4 : 8;
+  const int cus = num_cus(ctx->device);
+  const int64_t nrec = std::max<int64_t>(n_records, 1024);
+  const int64_t cap = sample || op == SHCI_OP_DRAWS ? (int64_t)n_samples * n_draws : 0;
+  size_t tot = 0;
+  // seed path: draws and sample batches, then the alias table and its
+  // temporaries (released before the samples are evaluated)
+  size_t draws_b = 0, alias_b = 0;
+  if (cap) {
+    Carver cv(nullptr);
+    cv.take<uint32_t>(cap);
+    cv.take<int32_t>(n_samples);
+    draws_b = cv.off + WS_ALIGN;
+    Carver ca(nullptr);
+    ca.take<uint64_t>(n_det);
+    ca.take<uint32_t>(n_det);
+    AliasTmp t;
+    plan_alias(ca, t, n_det);
+    alias_b = ca.off + 2 * WS_ALIGN;
+  }
+  if (op == SHCI_OP_DRAWS) {
+    *bytes = draws_b + alias_b;
+    return SHCI_OK;
+  }
+  if (sample) {
+    Carver cv(nullptr);
+    for (int k = 0; k < 5; ++k) cv.take<uint32_t>(cap);
+    cv.take<uint32_t>(n_samples + 1);
+    cv.take<uint64_t>(n_samples + 1);
+    cv.take<double>(4);
+    cv.take<double>(n_samples + 1);
+    ScanTmp tmp;
+    tmp.carve(cv, n_samples + 1);
+    const size_t items_b = cv.off + WS_ALIGN;
+    const int kw = key_words(ctx->T.n, std::max(1, ceil_log2((uint64_t)n_samples)));
+    const size_t job = job_bytes(kw, vsize, true, op == SHCI_OP_SAMPLE_GRAD, false, op == SHCI_OP_SAMPLE_GRAD,
+                                 n_det, cap, cap + cap / 2, nrec, n_samples, cus);
+    tot = draws_b + std::max(alias_b, items_b + job);
+  } else {
+    const int kw = key_words(ctx->T.n, 0);
+    const bool keep = op == SHCI_OP_GRAD_KEEP;
+    const bool grad = op == SHCI_OP_GRAD || keep;
+    tot = job_bytes(kw, vsize, false, grad, keep, op == SHCI_OP_GRAD, n_det, n_det, 2 * n_det, nrec, 1, cus);
+  }
+  *bytes = tot;
+  return SHCI_OK;
+}
+
 int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
-                 double eps2, int precision, void* stream, double* e2, shci_pt2_stats* st,
-                 shci_pt2_export* ex) {
+                 double eps2, int precision, void* ws, size_t ws_bytes, void* stream, double* e2,
+                 shci_pt2_stats* st, shci_pt2_export* ex) {
   CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  CHK(ws_check(ws, ws_bytes));
   if (!e2) return fail(SHCI_ERR_ARG, "e2 is NULL");
+  Arena AR(ctx, static_cast<hipStream_t>(stream), ws, ws_bytes);
   Job J{};
   J.ctx = ctx;
+  J.ar = &AR;
   J.st = static_cast<hipStream_t>(stream);
   J.dets = dets;
   J.c = c;
@@ -1116,12 +1468,17 @@ int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64
 }
 
 int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
-                  double eps2, int precision, void* stream, double* e2, double* de2_dc, double* de2_de0,
-                  shci_pt2_stats* st) {
+                  double eps2, int precision, int mode, void* ws, size_t ws_bytes, void* stream, double* e2,
+                  double* de2_dc, double* de2_de0, shci_pt2_stats* st) {
   CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  CHK(ws_check(ws, ws_bytes));
   if (!de2_dc) return fail(SHCI_ERR_ARG, "de2_dc is NULL");
+  if (mode != SHCI_GRAD_AUTO && mode != SHCI_GRAD_KEEP && mode != SHCI_GRAD_RECOMPUTE)
+    return fail(SHCI_ERR_ARG, "unknown adjoint mode");
+  Arena AR(ctx, static_cast<hipStream_t>(stream), ws, ws_bytes);
   Job J{};
   J.ctx = ctx;
+  J.ar = &AR;
   J.st = static_cast<hipStream_t>(stream);
   J.dets = dets;
   J.c = c;
@@ -1132,8 +1489,36 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
   J.precision = precision;
   J.nsamp = 1;
   J.n_items = n_det;
-  J.want_u = true;
   J.grad = de2_dc;
+  // keep: records carry their position, the reduce writes each record's
+  // adjoint term (no second generation pass); recompute: the unique store
+  // is kept and the adjoint walks the connections again.  auto takes keep
+  // when one pass holds every record, recompute when hash batches are needed.
+  bool keep = mode == SHCI_GRAD_KEEP;
+  if (mode == SHCI_GRAD_AUTO) {
+    J.keep = true;
+    J.want_u = false;
+    J.max_records = 0;
+    Job probe = J;
+    // one keep-mode pass if it fits; otherwise recompute over hash batches
+    const int kw = key_words(ctx->T.n, 0);
+    probe.max_records = record_budget(AR, record_bytes(kw, precision == SHCI_FP32C ? 4 : 8, false, false, true));
+    if (AR.caller() && ctx->rec_limit == 0) probe.max_records = REC_CAP_AUTO;
+    const int r = dispatch(probe);
+    if (r == SHCI_OK) {
+      probe.nbatch = 1;
+      if (e2) *e2 = probe.res.e2;
+      if (de2_de0) *de2_de0 = probe.res.de0;
+      fill_stats(st, probe, probe.ms_gen + probe.ms_sort + probe.ms_reduce);
+      if (probe.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
+                                       (long long)probe.res.nzero);
+      return SHCI_OK;
+    }
+    if (r != JOB_TOO_BIG) return r;
+    keep = false;
+  }
+  J.keep = keep;
+  J.want_u = !keep;
   Job R;
   CHK(run_det_batched(J, R));
   if (e2) *e2 = R.res.e2;
@@ -1146,71 +1531,72 @@ int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int6
 
 static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                        double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
-                       int precision, void* stream, double* per_sample, double* mean, double* sem,
-                       shci_pt2_stats* st, double* grad, double* de2_de0, int32_t n_batches = 1,
-                       const int32_t* sample_batch = nullptr) {
+                       uint64_t seed, int precision, void* ws, size_t ws_bytes, void* stream, double* per_sample,
+                       double* mean, double* sem, shci_pt2_stats* st, double* grad, double* de2_de0,
+                       int32_t n_batches = 1, const int32_t* sample_batch = nullptr) {
   CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
-  if (!draws || !per_sample) return fail(SHCI_ERR_ARG, "draws or per_sample is NULL");
+  CHK(ws_check(ws, ws_bytes));
+  if (!per_sample) return fail(SHCI_ERR_ARG, "per_sample is NULL");
   if (n_samples < 1 || n_draws < 2) return fail(SHCI_ERR_ARG, "need n_samples >= 1 and n_draws >= 2");
   if (n_draws > MAX_DRAWS) return fail(SHCI_ERR_ARG, "n_draws must be <= %d", MAX_DRAWS);
+  if ((int64_t)n_samples * n_draws >= ((int64_t)1 << 31))
+    return fail(SHCI_ERR_ARG, "n_samples * n_draws must be < 2^31");
   if (!(eps2_d >= eps2)) return fail(SHCI_ERR_ARG, "eps2_d must be >= eps2");
   if (n_batches < 1 || n_batches > 65536 || (n_batches & (n_batches - 1)))
     return fail(SHCI_ERR_ARG, "n_batches must be a power of two in [1, 65536]");
-  if (n_batches > 1) {
-    if (!sample_batch) return fail(SHCI_ERR_ARG, "sample_batch is NULL");
-    std::vector<int32_t> hb(n_samples);
-    if (hipMemcpy(hb.data(), sample_batch, n_samples * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(SHCI_ERR_HIP, "copy of sample_batch failed");
-    for (int32_t v : hb)
-      if (v < 0 || v >= n_batches) return fail(SHCI_ERR_ARG, "sample_batch entries must lie in [0, n_batches)");
-  }
   const int sbits = std::max(1, ceil_log2((uint64_t)n_samples));
   if (2 * ctx->T.n + sbits + 1 > 256) return fail(SHCI_ERR_NORB, "too many samples for this n_orb");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // items: distinct dets per sample
-  DevBuf items;
-  const int64_t cap = (int64_t)n_samples * n_draws;
-  {
-    size_t bytes = 0;
-    Carver cv(nullptr);
-    cv.take<uint32_t>(cap);
-    cv.take<uint32_t>(cap);
-    cv.take<uint32_t>(n_samples + 1);
-    cv.take<uint64_t>(n_samples + 1);
-    cv.take<uint32_t>(cap);
-    cv.take<uint32_t>(cap);
-    cv.take<uint32_t>(cap);
-    cv.take<double>(4);
-    cv.take<double>(n_samples + 1);
-    ScanTmp tmp;
-    tmp.carve(cv, n_samples + 1);
-    bytes = cv.off;
-    CHK(items.ensure(bytes, 0));
+  Arena AR(ctx, s, ws, ws_bytes);
+  k_fill_u32<<<1, 64, 0, s>>>(ctx->dflag, 4, 0u);
+  // seed path: draws (and sample batches) made on the device
+  const uint32_t* dr = draws;
+  const int32_t* sbatch = sample_batch;
+  if (!draws || (n_batches > 1 && !sample_batch)) {
+    uint32_t* own_d = nullptr;
+    int32_t* own_b = nullptr;
+    CHK(carve_region(AR, SL_DRAWS, [&](Carver& cv) {
+      own_d = cv.take<uint32_t>((int64_t)n_samples * n_draws);
+      own_b = cv.take<int32_t>(n_samples);
+    }));
+    if (!draws) {
+      CHK(seed_draws(AR, c, n_det, seed, n_samples, n_draws, own_d, s));
+      dr = own_d;
+    }
+    if (n_batches > 1 && !sample_batch) {
+      k_seed_batches<<<(n_samples + 255) / 256, 256, 0, s>>>(seed, n_samples, n_draws, n_batches, own_b);
+      sbatch = own_b;
+    }
   }
-  Carver cv(items.p);
-  uint32_t* t_det = cv.take<uint32_t>(cap);
-  uint32_t* t_w = cv.take<uint32_t>(cap);
-  uint32_t* ucount = cv.take<uint32_t>(n_samples + 1);
-  uint64_t* uoff = cv.take<uint64_t>(n_samples + 1);
-  uint32_t* o_det = cv.take<uint32_t>(cap);
-  uint32_t* o_w = cv.take<uint32_t>(cap);
-  uint32_t* o_s = cv.take<uint32_t>(cap);
-  double* dsum = cv.take<double>(4);
-  double* psde0 = cv.take<double>(n_samples + 1);
+  if (n_batches > 1 && sample_batch)
+    k_check_batches<<<(n_samples + 255) / 256, 256, 0, s>>>(sample_batch, n_samples, n_batches, ctx->dflag);
+  // items: distinct dets per sample
+  const int64_t cap = (int64_t)n_samples * n_draws;
+  uint32_t *t_det, *t_w, *ucount, *o_det, *o_w, *o_s;
+  uint64_t* uoff;
+  double *dsum, *psde0;
   ScanTmp tmp;
-  tmp.carve(cv, n_samples + 1);
+  CHK(carve_region(AR, SL_SAMPLE, [&](Carver& cv) {
+    t_det = cv.take<uint32_t>(cap);
+    t_w = cv.take<uint32_t>(cap);
+    ucount = cv.take<uint32_t>(n_samples + 1);
+    uoff = cv.take<uint64_t>(n_samples + 1);
+    o_det = cv.take<uint32_t>(cap);
+    o_w = cv.take<uint32_t>(cap);
+    o_s = cv.take<uint32_t>(cap);
+    dsum = cv.take<double>(4);
+    psde0 = cv.take<double>(n_samples + 1);
+    tmp.carve(cv, n_samples + 1);
+  }));
   auto done = [&](int code) {
     (void)hipStreamSynchronize(s);
-    items.release();
     return code;
   };
-  k_fill_u32<<<1, 64, 0, s>>>(ctx->dflag, 4, 0u);
-  k_sample_items<<<n_samples, 256, 0, s>>>(draws, n_draws, n_det, t_det, t_w, ucount, ctx->dflag);
+  k_sample_items<<<n_samples, 256, 0, s>>>(dr, n_draws, n_det, t_det, t_w, ucount, ctx->dflag);
   k_sum_abs<<<1, 1024, 0, s>>>(c, n_det, dsum);
   uint64_t* tot = uoff + n_samples;
   int sc = scan_exclusive<uint32_t, uint64_t>(ucount, uoff, n_samples, tmp, tot, s);
   if (sc) return done(sc);
-  uint64_t hn = 0;
   double hsum = 0.0;
   uint32_t hf = 0;
   std::vector<uint64_t> hoff(n_samples + 1);
@@ -1220,9 +1606,10 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
       hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return done(fail(SHCI_ERR_HIP, "sample preparation failed"));
-  hn = hoff[n_samples];
-  (void)hn;
+  if (hf & 2u) return done(fail(SHCI_ERR_NONFINITE, "c contains a non-finite value"));
+  if (hf & 64u) return done(fail(SHCI_ERR_NONFINITE, "every coefficient is zero"));
   if (hf & 16u) return done(fail(SHCI_ERR_ARG, "a draw is >= n_det"));
+  if (hf & 128u) return done(fail(SHCI_ERR_ARG, "sample_batch entries must lie in [0, n_batches)"));
   if (!(hsum > 0.0) || !std::isfinite(hsum)) return done(fail(SHCI_ERR_NONFINITE, "sum |c| is not positive and finite"));
 
   // Samples are evaluated in chunks of consecutive samples whose records fit
@@ -1230,7 +1617,7 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
   // chunk covers all its samples (sample id in the key).  The chunk length
   // adapts to the records per sample seen so far.
   const int64_t max_rec = record_budget(
-      ctx, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false, grad != nullptr));
+      AR, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false, grad != nullptr));
   if (grad) k_fill_u64<<<(int)std::min<int64_t>(4096, (n_det + 255) / 256), 256, 0, s>>>(
       reinterpret_cast<uint64_t*>(grad), n_det, 0ull);
   Job acc{};
@@ -1250,6 +1637,7 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
                                          ucount + s0, uoff + s0, n_draws, 0, o_det, o_w, o_s);
     Job J{};
     J.ctx = ctx;
+    J.ar = &AR;
     J.st = s;
     J.dets = dets;
     J.c = c;
@@ -1269,12 +1657,12 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
     J.n_items = (int64_t)(hoff[s0 + k] - hoff[s0]);
     J.per_sample = per_sample + s0;
     J.per_sample_de0 = psde0 + s0;
-    J.max_records = max_rec;
+    J.max_records = (AR.caller() && ctx->rec_limit == 0) ? REC_CAP_AUTO : max_rec;
     J.samp_off = hoff.data() + s0;
     if (n_batches > 1) {
       // one batch of P per sample, the estimate scaled by the number of batches
       J.bmask = (uint32_t)(n_batches - 1);
-      J.sbatch = sample_batch + s0;
+      J.sbatch = sbatch + s0;
       J.sample_scale = (double)n_batches;
     }
     if (grad) {
@@ -1285,9 +1673,9 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
     int r = dispatch(J);
     if (r == JOB_TOO_BIG) {
       if (k == 1) return done(fail(SHCI_ERR_WORKSPACE, "one sample has %lld screened terms; the workspace holds %lld",
-                                   (long long)J.nrec, (long long)max_rec));
+                                   (long long)J.nrec, (long long)J.max_records_eff));
       const double per = (double)J.nrec / k;
-      k = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(k - 1, (int64_t)(0.9 * (double)max_rec / per))));
+      k = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(k - 1, (int64_t)(0.9 * (double)J.max_records_eff / per))));
       continue;
     }
     if (r) return done(r);
@@ -1343,41 +1731,46 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
 
 int shci_pt2_sample(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                     double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
-                    int precision, void* stream, double* per_sample, double* mean, double* sem,
-                    shci_pt2_stats* st) {
-  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
-                     per_sample, mean, sem, st, nullptr, nullptr);
+                    uint64_t seed, int precision, void* ws, size_t ws_bytes, void* stream, double* per_sample,
+                    double* mean, double* sem, shci_pt2_stats* st) {
+  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, seed, precision, ws,
+                     ws_bytes, stream, per_sample, mean, sem, st, nullptr, nullptr);
 }
 
 int shci_pt2_sample_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                          double eps2, double eps2_d, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
-                         int precision, void* stream, double* per_sample, double* mean, double* sem,
-                         double* de2_dc, double* de2_de0, shci_pt2_stats* st) {
+                         uint64_t seed, int precision, void* ws, size_t ws_bytes, void* stream, double* per_sample,
+                         double* mean, double* sem, double* de2_dc, double* de2_de0, shci_pt2_stats* st) {
   if (!de2_dc) return fail(SHCI_ERR_ARG, "de2_dc is NULL");
-  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
-                     per_sample, mean, sem, st, de2_dc, de2_de0);
+  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, seed, precision, ws,
+                     ws_bytes, stream, per_sample, mean, sem, st, de2_dc, de2_de0);
 }
 
 int shci_pt2_sample_batched(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                             double eps2, double eps2_d, int32_t n_samples, int32_t n_draws,
-                            const uint32_t* draws, int32_t n_batches, const int32_t* sample_batch, int precision,
-                            void* stream, double* per_sample, double* mean, double* sem, shci_pt2_stats* st) {
-  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, precision, stream,
-                     per_sample, mean, sem, st, nullptr, nullptr, n_batches, sample_batch);
+                            const uint32_t* draws, int32_t n_batches, const int32_t* sample_batch, uint64_t seed,
+                            int precision, void* ws, size_t ws_bytes, void* stream, double* per_sample,
+                            double* mean, double* sem, shci_pt2_stats* st) {
+  return sample_impl(ctx, dets, c, n_det, e0, eps2, eps2_d, n_samples, n_draws, draws, seed, precision, ws,
+                     ws_bytes, stream, per_sample, mean, sem, st, nullptr, nullptr, n_batches, sample_batch);
 }
 
 int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                          double eps2, double eps2_hi, int32_t n_batches, const int32_t* batches, int32_t n_list,
-                         int precision, void* stream, shci_pt2_batch* out, shci_pt2_stats* st) {
+                         int precision, void* ws, size_t ws_bytes, void* stream, shci_pt2_batch* out,
+                         shci_pt2_stats* st) {
   CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  CHK(ws_check(ws, ws_bytes));
   if (!batches || !out || n_list < 1) return fail(SHCI_ERR_ARG, "batches and out must be non-NULL, n_list >= 1");
   if (n_batches < 1 || n_batches > 65536 || (n_batches & (n_batches - 1)))
     return fail(SHCI_ERR_ARG, "n_batches must be a power of two in [1, 65536]");
   if (!(eps2_hi >= eps2)) return fail(SHCI_ERR_ARG, "eps2_hi must be >= eps2 (INFINITY for one threshold)");
   for (int32_t k = 0; k < n_list; ++k)
     if (batches[k] < 0 || batches[k] >= n_batches) return fail(SHCI_ERR_ARG, "batch index out of range");
+  Arena AR(ctx, static_cast<hipStream_t>(stream), ws, ws_bytes);
   Job proto{};
   proto.ctx = ctx;
+  proto.ar = &AR;
   proto.st = static_cast<hipStream_t>(stream);
   proto.dets = dets;
   proto.c = c;
@@ -1391,7 +1784,9 @@ int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* 
   proto.nsamp = 1;
   proto.n_items = n_det;
   const int kw = key_words(ctx->T.n, 0);
-  proto.max_records = record_budget(ctx, record_bytes(kw, precision == SHCI_FP32C ? 4 : 8, false, false));
+  proto.max_records = (AR.caller() && ctx->rec_limit == 0)
+                          ? REC_CAP_AUTO
+                          : record_budget(AR, record_bytes(kw, precision == SHCI_FP32C ? 4 : 8, false, false));
   Job acc{};
   acc.res.mind = INFINITY;
   for (int32_t k = 0; k < n_list; ++k) {
@@ -1400,8 +1795,8 @@ int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* 
     J.bsel = (uint32_t)batches[k];
     const int r = dispatch(J);
     if (r == JOB_TOO_BIG)
-      return fail(SHCI_ERR_WORKSPACE, "batch %d has %lld terms, above the record budget; use more batches",
-                  batches[k], (long long)J.nrec);
+      return fail(SHCI_ERR_WORKSPACE, "batch %d has %lld terms, above the %lld records that fit; use more batches",
+                  batches[k], (long long)J.nrec, (long long)J.max_records_eff);
     if (r) return r;
     out[k].sum = J.res.e2;
     out[k].sumsq = J.res.e2sq;
@@ -1434,15 +1829,17 @@ int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* 
 int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                         double eps2_dtm, double eps2_psto, double eps2, double target_error, int32_t nb_psto,
                         int32_t nb_sto, int32_t n_samples, int32_t n_draws, const uint32_t* draws,
-                        const int32_t* sample_batch, int precision, void* stream, double* per_sample,
-                        shci_pt2_3step_result* res) {
+                        const int32_t* sample_batch, uint64_t seed, int precision, void* ws, size_t ws_bytes,
+                        void* stream, double* per_sample, shci_pt2_3step_result* res) {
   if (!res || !per_sample) return fail(SHCI_ERR_ARG, "res and per_sample must be non-NULL");
   if (!(eps2 <= eps2_psto && eps2_psto <= eps2_dtm)) return fail(SHCI_ERR_ARG, "need eps2 <= eps2_psto <= eps2_dtm");
   if (!(target_error > 0.0)) return fail(SHCI_ERR_ARG, "target_error must be > 0");
+  if (nb_psto < 1 || nb_sto < 1) return fail(SHCI_ERR_ARG, "nb_psto and nb_sto must be >= 1");
   *res = shci_pt2_3step_result{};
   // 1. deterministic step at eps2_dtm, every batch of P (hash batches when
   //    the records do not fit)
-  CHK(shci_pt2_det(ctx, dets, c, n_det, e0, eps2_dtm, precision, stream, &res->e2_dtm, nullptr, nullptr));
+  CHK(shci_pt2_det(ctx, dets, c, n_det, e0, eps2_dtm, precision, ws, ws_bytes, stream, &res->e2_dtm, nullptr,
+                   nullptr));
   // 2. pseudo-stochastic step: batches of P in order; per batch the
   //    corrections (A(eps2_psto)^2 - A(eps2_dtm)^2) / D of its unique a.  The
   //    total is estimated from the evaluated a; its standard error is that of
@@ -1454,8 +1851,8 @@ int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c
   for (; b < nb_psto;) {
     shci_pt2_batch o{};
     const int32_t idx = b;
-    CHK(shci_pt2_det_batches(ctx, dets, c, n_det, e0, eps2_psto, eps2_dtm, nb_psto, &idx, 1, precision, stream,
-                             &o, nullptr));
+    CHK(shci_pt2_det_batches(ctx, dets, c, n_det, e0, eps2_psto, eps2_dtm, nb_psto, &idx, 1, precision, ws,
+                             ws_bytes, stream, &o, nullptr));
     ++b;
     S += o.sum;
     SS += o.sumsq;
@@ -1479,7 +1876,8 @@ int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c
   // 3. stochastic step: samples of V, one random batch of P per sample
   double mean = 0.0, sem = 0.0;
   CHK(shci_pt2_sample_batched(ctx, dets, c, n_det, e0, eps2, eps2_psto, n_samples, n_draws, draws, nb_sto,
-                              sample_batch, precision, stream, per_sample, &mean, &sem, nullptr));
+                              sample_batch, seed, precision, ws, ws_bytes, stream, per_sample, &mean, &sem,
+                              nullptr));
   res->e2_sto = mean;
   res->err_sto = sem;
   res->e2 = res->e2_dtm + res->e2_psto + res->e2_sto;
@@ -1490,40 +1888,28 @@ int shci_pt2_three_step(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c
 int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
                 double eps_gen, int mode, double threshold, int precision, void* stream, uint64_t* out_keys,
                 double* out_val, int64_t cap, int64_t* n_out, shci_pt2_stats* st) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
   if (mode != SHCI_SELECT_HCI && mode != SHCI_SELECT_CIPSI) return fail(SHCI_ERR_ARG, "unknown selection mode");
   if (!out_keys || !out_val || !n_out || cap < 1) return fail(SHCI_ERR_ARG, "out_keys, out_val, n_out, cap >= 1");
   if (mode == SHCI_SELECT_CIPSI && !(threshold >= 0.0)) return fail(SHCI_ERR_ARG, "threshold must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // every unique a of the pass, exported into work arrays of the caller's capacity
-  DevBuf tmp;
-  auto plan = [&](Carver& cv, uint64_t** k, double** A, double** D, int32_t** cnt, uint32_t** flag, double** val,
-                  uint64_t** pos, ScanTmp* sc) {
-    *k = cv.take<uint64_t>(4 * cap);
-    *A = cv.take<double>(cap);
-    *D = cv.take<double>(cap);
-    *cnt = cv.take<int32_t>(cap);
-    *flag = cv.take<uint32_t>(cap + 1);
-    *val = cv.take<double>(cap);
-    *pos = cv.take<uint64_t>(cap + 1);
-    sc->carve(cv, cap + 1);
-  };
+  // every unique a of the pass, exported into the context's selection buffer
   uint64_t *k, *pos;
   double *A, *D, *val;
   int32_t* cnt;
   uint32_t* flag;
   ScanTmp sc;
-  {
-    Carver cv(nullptr);
-    plan(cv, &k, &A, &D, &cnt, &flag, &val, &pos, &sc);
-    CHK(tmp.ensure(cv.off, ctx->ws_limit));
-    Carver cv2(tmp.p);
-    plan(cv2, &k, &A, &D, &cnt, &flag, &val, &pos, &sc);
-  }
-  auto done = [&](int code) {
-    (void)hipStreamSynchronize(s);
-    tmp.release();
-    return code;
-  };
+  Arena AR(ctx, s, nullptr, 0);
+  CHK(carve_region(AR, SL_SEL, [&](Carver& cv) {
+    k = cv.take<uint64_t>(4 * cap);
+    A = cv.take<double>(cap);
+    D = cv.take<double>(cap);
+    cnt = cv.take<int32_t>(cap);
+    flag = cv.take<uint32_t>(cap + 1);
+    val = cv.take<double>(cap);
+    pos = cv.take<uint64_t>(cap + 1);
+    sc.carve(cv, cap + 1);
+  }));
   shci_pt2_export ex{};
   ex.u_keys = k;
   ex.u_A = A;
@@ -1531,25 +1917,64 @@ int shci_pt2_select(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, in
   ex.u_cnt = cnt;
   ex.u_cap = cap;
   double e2 = 0.0;
-  int r = shci_pt2_det(ctx, dets, c, n_det, e0, eps_gen, precision, stream, &e2, st, &ex);
-  if (r) return done(r);
+  int r = shci_pt2_det(ctx, dets, c, n_det, e0, eps_gen, precision, nullptr, 0, stream, &e2, st, &ex);
+  if (r) return r;
   if (ex.u_n > cap)
-    return done(fail(SHCI_ERR_WORKSPACE, "%lld perturbative determinants exceed cap = %lld",
-                     (long long)ex.u_n, (long long)cap));
+    return fail(SHCI_ERR_WORKSPACE, "%lld perturbative determinants exceed cap = %lld", (long long)ex.u_n,
+                (long long)cap);
   const int64_t nu = ex.u_n;
   *n_out = 0;
-  if (nu == 0) return done(SHCI_OK);
+  if (nu == 0) return SHCI_OK;
   const int grid = (int)std::min<int64_t>(4096, (nu + 255) / 256);
   k_select_flags<<<grid, 256, 0, s>>>(A, D, nu, mode, threshold, flag, val);
   r = scan_exclusive<uint32_t, uint64_t>(flag, pos, nu, sc, pos + nu, s);
-  if (r) return done(r);
+  if (r) return r;
   k_select_compact<<<grid, 256, 0, s>>>(k, val, flag, pos, nu, out_keys, out_val);
   uint64_t h = 0;
   if (hipMemcpyAsync(&h, pos + nu, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
-    return done(fail(SHCI_ERR_HIP, "selection count copy failed"));
+    return fail(SHCI_ERR_HIP, "selection count copy failed");
   *n_out = (int64_t)h;
-  return done(SHCI_OK);
+  return SHCI_OK;
+}
+
+int shci_pt2_alias_table(shci_pt2_ctx* ctx, const double* c, int64_t n_det, void* ws, size_t ws_bytes,
+                         void* stream, uint64_t* threshold, uint32_t* alias) {
+  if (!ctx || !c || !threshold || !alias) return fail(SHCI_ERR_ARG, "ctx, c, threshold and alias must be non-NULL");
+  if (n_det < 1 || n_det >= (int64_t)0xffffffffll) return fail(SHCI_ERR_ARG, "n_det must be in [1, 2^32 - 1)");
+  CHK(ws_check(ws, ws_bytes));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Arena AR(ctx, s, ws, ws_bytes);
+  k_fill_u32<<<1, 64, 0, s>>>(ctx->dflag, 4, 0u);
+  CHK(build_alias(AR, c, n_det, threshold, alias, s));
+  uint32_t hf = 0;
+  HIPCHK(hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hf & 2u) return fail(SHCI_ERR_NONFINITE, "c contains a non-finite value");
+  if (hf & 64u) return fail(SHCI_ERR_NONFINITE, "every coefficient is zero");
+  return SHCI_OK;
+}
+
+int shci_pt2_draws(shci_pt2_ctx* ctx, const double* c, int64_t n_det, uint64_t seed, int32_t n_samples,
+                   int32_t n_draws, void* ws, size_t ws_bytes, void* stream, uint32_t* draws) {
+  if (!ctx || !c || !draws) return fail(SHCI_ERR_ARG, "ctx, c and draws must be non-NULL");
+  if (n_det < 1 || n_det >= (int64_t)0xffffffffll) return fail(SHCI_ERR_ARG, "n_det must be in [1, 2^32 - 1)");
+  if (n_samples < 1 || n_draws < 1) return fail(SHCI_ERR_ARG, "need n_samples >= 1 and n_draws >= 1");
+  if ((int64_t)n_samples * n_draws >= ((int64_t)1 << 31))
+    return fail(SHCI_ERR_ARG, "n_samples * n_draws must be < 2^31");
+  CHK(ws_check(ws, ws_bytes));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Arena AR(ctx, s, ws, ws_bytes);
+  k_fill_u32<<<1, 64, 0, s>>>(ctx->dflag, 4, 0u);
+  CHK(seed_draws(AR, c, n_det, seed, n_samples, n_draws, draws, s));
+  uint32_t hf = 0;
+  HIPCHK(hipMemcpyAsync(&hf, ctx->dflag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hf & 2u) return fail(SHCI_ERR_NONFINITE, "c contains a non-finite value");
+  if (hf & 64u) return fail(SHCI_ERR_NONFINITE, "every coefficient is zero");
+  return SHCI_OK;
 }
 
 int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, void* stream,
@@ -1567,7 +1992,6 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   if (passes == 0) passes = 1;
   // workspace: string tables, groups, two pair-sort buffer sets per spin,
   // histograms, group starts, singles counts and offsets
-  DevBuf ws, wl[2];
   struct Plan {
     uint32_t *slot[2], *grp[2], *k0[2], *v0[2], *k1[2], *v1[2], *hist, *hoffs, *scnt[2], *cnt_tmp, *pval;
     uint64_t *start[2], *soff[2], *tot, *oth0[2], *oth1[2], *pkey;
@@ -1600,18 +2024,11 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
     P.sh.carve(cv, 256 * ntiles);
     P.ss.carve(cv, n + 1);
   };
-  {
-    Carver cv(nullptr);
-    plan(cv);
-    CHK(ws.ensure(cv.off, ctx->ws_limit));
-    Carver cv2(ws.p);
-    plan(cv2);
-  }
+  // the context's grow-only buffers (no allocation once they are large enough)
+  Arena AR(ctx, s, nullptr, 0);
+  CHK(carve_region(AR, SL_HC, plan));
   auto done = [&](int code) {
     (void)hipStreamSynchronize(s);
-    ws.release();
-    wl[0].release();
-    wl[1].release();
     return code;
   };
   const int g1 = (int)((n + 255) / 256);
@@ -1668,8 +2085,10 @@ int shci_pt2_hc(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_
   if (hf & 1u) return done(fail(SHCI_ERR_DET, "a determinant has a wrong electron count or an orbital >= n_orb"));
   if (hf & 2u) return done(fail(SHCI_ERR_NONFINITE, "c holds a NaN or Inf"));
   for (int sp = 0; sp < 2; ++sp) {
-    if (int r = wl[sp].ensure(std::max<uint64_t>(1, nsl[sp]) * sizeof(uint32_t), ctx->ws_limit)) return done(r);
-    sa[sp].list = static_cast<uint32_t*>(wl[sp].p);
+    void* lp = nullptr;
+    if (int r = AR.take(sp ? SL_HCL1 : SL_HCL0, std::max<uint64_t>(1, nsl[sp]) * sizeof(uint32_t), &lp))
+      return done(r);
+    sa[sp].list = static_cast<uint32_t*>(lp);
     if (nsl[sp]) k_str_singles<true><<<gw, 256, 0, s>>>(sa[sp]);
   }
   HcArgs ha{};

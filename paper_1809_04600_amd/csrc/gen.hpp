@@ -73,6 +73,7 @@ struct GenArgs {
   double smarg;            // rounding margin, in units of the bound U_pr
   LookupArgs L;
   double* grad;
+  int pay_pos;             // payload: the record's own position (keep-mode adjoint) instead of the source
 };
 
 SHCI_DEV int tri_inv(int u) {
@@ -266,7 +267,7 @@ SHCI_DEV void gen_body(const GenArgs& a) {
 #pragma unroll
           for (int q = 0; q < KW; ++q) a.out.k[q][pos] = key[q];
           a.out.haa[pos] = haa;
-          if (a.out.pay) a.out.pay[pos] = (uint32_t)i;
+          if (a.out.pay) a.out.pay[pos] = a.pay_pos ? (uint32_t)pos : (uint32_t)i;
         }
         cursor += (uint64_t)__popcll(bal);
       } else {  // GEN_GRAD
@@ -714,13 +715,30 @@ __global__ void k_grad_scatter(const double* gitem, const uint32_t* it_det, int6
   if (u < count) grad[it_det[u]] += scale * gitem[u];
 }
 
+// grad[s] (+)= sum of the parts of source s's work items (divided by c_s
+// when c is given: the keep-mode parts hold t * 2 A_a / D_a with t = H_ai c_i)
 __global__ void k_grad_sum(const uint32_t* nsplit, const uint64_t* off, const double* part, int64_t n_src,
-                           double* grad, int accumulate) {
+                           double* grad, int accumulate, const double* c = nullptr) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n_src) return;
   double g = 0.0;
   for (uint32_t j = 0; j < nsplit[s]; ++j) g += part[off[s] + j];
+  if (c) g = g == 0.0 ? 0.0 : g / c[s];
   grad[s] = accumulate ? grad[s] + g : g;  // hash batches add in batch order
+}
+
+// keep-mode adjoint: part[item] = sum of the per-record terms of the item's
+// records (generation order; one wavefront per item, fixed butterfly)
+__global__ void k_keep_item_sum(const uint64_t* offs, int64_t n_items, const double* contrib, double* part) {
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= n_items) return;
+  const uint64_t lo = offs[item], hi = offs[item + 1];
+  double s = 0.0;
+  for (uint64_t r = lo + lane; r < hi; r += 64) s += contrib[r];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) part[item] = s;
 }
 
 // Work split: a source whose heat-bath walks are long (small eps2 / |c_i|) is

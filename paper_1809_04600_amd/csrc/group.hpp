@@ -451,6 +451,7 @@ struct RedArgs {
   const uint64_t* bstart;   // [nbucket + 1] bucket start offsets (nullable: binary search)
   const uint32_t* blist;    // buckets to process (nullable: all)
   const uint32_t* nlist;    // device count of blist
+  double* contrib;          // keep-mode adjoint (nullable): contrib[pay] = t * 2 A_a / D_a (0 for a in V)
 };
 
 // membership of a packed determinant key (det bits only) in the hash set of V;
@@ -789,6 +790,14 @@ __global__ void __launch_bounds__(256) k_reduce(RedArgs a) {
         nzero += Dd == 0.0;
         dmn = fmin(dmn, fabs(Dd));
       }
+      if constexpr (!SAMPLE) {
+        if (a.contrib) {
+          for (int j = j0; j < j1; ++j) {
+            const int id = R.sb.ia[j];
+            a.contrib[a.in.pay[lo + id]] = inv ? 0.0 : (double)R.v[id] * g;
+          }
+        }
+      }
       if (a.want_u) {
         const int64_t o = lo + s;
 #pragma unroll
@@ -898,6 +907,66 @@ __global__ void __launch_bounds__(256) k_final_partial(Partials P, int64_t nb, i
   }
 }
 
+// first level of the final reduction over the block kernel's buckets only:
+// block b sums the per-bucket partials of the buckets marked in `bits` among
+// [b*chunk, (b+1)*chunk) into slot b of Q; thread t takes the bitmap words
+// t, t + 256, ... of the range (fixed order)
+__global__ void __launch_bounds__(256) k_final_partial_marked(Partials P, const uint32_t* bits, int64_t nb,
+                                                              int64_t chunk, Partials Q) {
+  __shared__ double r1[256], r2[256], r3[256], r4[256];
+  __shared__ int64_t i1[256], i2[256], i3[256], i4[256], i5[256];
+  const int t = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(nb, lo + chunk);
+  double e = 0.0, d = 0.0, q = 0.0, mn = INFINITY;
+  int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
+  for (int64_t wd = lo / 32 + t; wd * 32 < hi; wd += 256) {
+    uint32_t m = bits[wd];
+    while (m) {
+      const int64_t b = wd * 32 + __ffs(m) - 1;
+      m &= m - 1;
+      if (b < lo || b >= hi) continue;
+      e += P.e2[b];
+      d += P.de0[b];
+      q += P.e2sq[b];
+      mn = fmin(mn, P.mind[b]);
+      nt += P.nterm[b];
+      ng += P.ngen[b];
+      nu += P.nuniq[b];
+      ni += P.nintr[b];
+      nz += P.nzero[b];
+    }
+  }
+  r1[t] = e; r2[t] = d; r3[t] = mn; r4[t] = q;
+  i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      r1[t] += r1[t + o];
+      r2[t] += r2[t + o];
+      r4[t] += r4[t + o];
+      r3[t] = fmin(r3[t], r3[t + o]);
+      i1[t] += i1[t + o];
+      i2[t] += i2[t + o];
+      i3[t] += i3[t + o];
+      i4[t] += i4[t + o];
+      i5[t] += i5[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int b = blockIdx.x;
+    Q.e2[b] = r1[0];
+    Q.de0[b] = r2[0];
+    Q.e2sq[b] = r4[0];
+    Q.mind[b] = r3[0];
+    Q.nterm[b] = i1[0];
+    Q.ngen[b] = i2[0];
+    Q.nuniq[b] = (int32_t)i3[0];
+    Q.nintr[b] = (int32_t)i4[0];
+    Q.nzero[b] = (int32_t)i5[0];
+  }
+}
+
 struct DevResult {
   double e2, de0, mind, e2sq;
   int64_t nterm, ngen, nuniq, nintr, nzero;
@@ -972,6 +1041,75 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
       res->overflow = *overflow;
       res->flags = *flags;
     }
+  }
+}
+
+// Sample mode, one block per sample s of the chunk: the per-wavefront slots
+// Pw[s][0..nwaves) and the per-bucket partials of the block kernel's buckets
+// of s (marked in `bits`, buckets [s << bits_hash, (s + 1) << bits_hash)),
+// each thread over a fixed range, then a fixed tree.
+__global__ void __launch_bounds__(1024) k_final_sample(Partials Pw, int64_t nwaves, Partials P, const uint32_t* bits,
+                                                       int bits_hash, DevResult* res, double* per_sample,
+                                                       double* per_sample_de0, double sample_scale) {
+  __shared__ double r1[1024], r2[1024], r3[1024];
+  __shared__ int64_t i1[1024], i2[1024], i3[1024], i4[1024], i5[1024];
+  const int t = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  double e = 0.0, d = 0.0, mn = INFINITY;
+  int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
+  auto add = [&](const Partials& Q, int64_t i) {
+    e += Q.e2[i];
+    d += Q.de0[i];
+    mn = fmin(mn, Q.mind[i]);
+    nt += Q.nterm[i];
+    ng += Q.ngen[i];
+    nu += Q.nuniq[i];
+    ni += Q.nintr[i];
+    nz += Q.nzero[i];
+  };
+  const int64_t per = (nwaves + 1023) / 1024;
+  for (int64_t w = t * per; w < min(nwaves, (int64_t)(t + 1) * per); ++w) add(Pw, s * nwaves + w);
+  const int64_t b0 = s << bits_hash, nbk = (int64_t)1 << bits_hash;
+  if (nbk >= 32) {
+    const int64_t w0 = b0 / 32, nw = nbk / 32;
+    const int64_t pw = (nw + 1023) / 1024;
+    for (int64_t wd = w0 + t * pw; wd < w0 + min(nw, (int64_t)(t + 1) * pw); ++wd) {
+      uint32_t m = bits[wd];
+      while (m) {
+        add(P, wd * 32 + __ffs(m) - 1);
+        m &= m - 1;
+      }
+    }
+  } else if (t == 0) {
+    for (int64_t b = b0; b < b0 + nbk; ++b)
+      if ((bits[b >> 5] >> (b & 31)) & 1u) add(P, b);
+  }
+  r1[t] = e; r2[t] = d; r3[t] = mn;
+  i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) {
+      r1[t] += r1[t + o];
+      r2[t] += r2[t + o];
+      r3[t] = fmin(r3[t], r3[t + o]);
+      i1[t] += i1[t + o];
+      i2[t] += i2[t + o];
+      i3[t] += i3[t + o];
+      i4[t] += i4[t + o];
+      i5[t] += i5[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    per_sample[s] = sample_scale * r1[0];
+    if (per_sample_de0) per_sample_de0[s] = sample_scale * r2[0];
+    atomicAdd((unsigned long long*)&res->nterm, (unsigned long long)i1[0]);
+    atomicAdd((unsigned long long*)&res->ngen, (unsigned long long)i2[0]);
+    atomicAdd((unsigned long long*)&res->nuniq, (unsigned long long)i3[0]);
+    atomicAdd((unsigned long long*)&res->nintr, (unsigned long long)i4[0]);
+    atomicAdd((unsigned long long*)&res->nzero, (unsigned long long)i5[0]);
+    // |D| >= 0: the bit patterns of non-negative doubles order like the values
+    atomicMin((unsigned long long*)&res->mind, (unsigned long long)__double_as_longlong(r3[0]));
   }
 }
 

@@ -1,17 +1,25 @@
 // Bucket reduce, one wavefront per bucket.
 //
-// After the hash partition a bucket holds on average ~100 records (at most
-// WCAP are handled here).  A wavefront loads the bucket's keys, forms 32-bit
-// sort keys (24 hash bits below the bucket id, with the record's position in
-// the low byte) and sorts them by a bitonic network in registers, so equal
-// determinants become adjacent in record order.  The sorted keys and the full
-// hash of every record are kept in LDS (3 KB per wavefront): keys and values
-// are read again from global memory (cache-resident) when a segment head sums
-// its segment, looks the determinant up in the hash set of V, takes H_aa from
-// the record and accumulates the contribution.  No block-wide barrier is
-// involved.  Buckets larger than WCAP, or in which two different determinants
-// share all sorted hash bits, are listed for the block kernel (k_reduce),
-// which sorts by the full key.
+// After the hash partition a bucket holds on average 64-128 records (at most
+// WCAP are handled here).  A wavefront reads each record of its bucket from
+// memory exactly once, with coalesced loads: the key words and H_aa stay in
+// registers (lane = position mod 64), the values and the flag bit go to LDS by
+// position.  The 32-bit sort keys (24 hash bits below the bucket id, the
+// record's position in the low byte) are sorted by a bitonic network in
+// registers, so equal determinants become adjacent in record order; each
+// sorted element then takes its key and H_aa from the lane that holds them
+// (cross-lane reads), adjacent elements with equal sort bits are checked to
+// have equal keys, and each segment head sums its segment's values from LDS,
+// looks the determinant up in the hash set of V (hash from LDS) and adds the
+// contribution to per-lane accumulators.  No block-wide barrier is involved.
+// Buckets larger than WCAP, or in which two different determinants share all
+// sorted hash bits, are listed (and marked in a bitmap) for the block kernel
+// (k_reduce), which sorts by the full key.
+//
+// Partial sums: each wavefront writes its accumulators once (deterministic
+// mode) or once per sample it visited, zeros for the samples it skipped
+// (sample mode); block-kernel buckets write per-bucket partials, which the
+// final reduction reads through the bitmap in bucket order.
 #pragma once
 #include "group.hpp"
 
@@ -52,11 +60,15 @@ SHCI_DEV void wave_bitonic(uint32_t (&v)[R]) {
   }
 }
 
-// per-wavefront LDS: the sorted keys of the current bucket and the
-// determinant hash of each record (by position)
+// per-wavefront LDS: the sorted keys of the current bucket, and by record
+// position the determinant hash, the value(s) and the flag bit
+template <typename VT, bool SAMPLE>
 struct WaveStage {
   uint32_t sk[WCAP];
   uint64_t h[WCAP];
+  VT v[WCAP];
+  VT v2[SAMPLE ? WCAP : 1];
+  uint8_t fl[WCAP];
 };
 
 struct WaveRedArgs {
@@ -64,32 +76,11 @@ struct WaveRedArgs {
   const uint64_t* bstart;  // [nbucket + 1]
   uint32_t* slow_list;     // buckets for the block kernel
   uint32_t* slow_count;
-  Partials Pw;             // per-wavefront partials (deterministic mode)
+  uint32_t* slow_bits;     // [nbucket / 32 + 1] bitmap of the block kernel's buckets (zeroed)
+  Partials Pw;             // per-wavefront partials; sample mode: [nsamp][nwaves]
+  int64_t nwaves;
+  int32_t nsamp;
 };
-
-// load the bucket's keys, sort their 32-bit sort keys (R*64 >= M) and leave
-// them in W.sk, the hashes in W.h
-template <int KW, int R>
-SHCI_DEV void wave_stage_sort(const RedArgs& a, WaveStage& W, int64_t lo, int M) {
-  const int lane = lane_id();
-  const int bh = a.G.bits_hash;
-  uint32_t sk[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = r * 64 + lane;
-    sk[r] = ~0u;
-    if (j < M) {
-      uint64_t k[KW];
-      load_key<KW>(a.in, lo + j, k);
-      const uint64_t h = det_hash<KW>(k, a.n);
-      W.h[j] = h;
-      sk[r] = ((uint32_t)((h << bh) >> 32) & ~0xffu) | (uint32_t)j;
-    }
-  }
-  wave_bitonic<R>(sk);
-#pragma unroll
-  for (int r = 0; r < R; ++r) W.sk[r * 64 + lane] = sk[r];
-}
 
 struct SegAcc {
   double e2p = 0.0, de0p = 0.0, e2sq = 0.0, dmn = INFINITY;
@@ -138,12 +129,34 @@ SHCI_DEV void wave_zero_partials(const Partials& P, int64_t b) {
   P.mind[b] = INFINITY;
 }
 
+// value of register array v at element `pos` (element r*64 + lane of the
+// wavefront), read from the lane that holds it
+template <int R>
+SHCI_DEV uint64_t wave_fetch(const uint64_t (&v)[R], int pos) {
+  const int src = pos & 63;
+  uint64_t out = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t x = __shfl(v[r], src);
+    out = ((pos >> 6) == r) ? x : out;
+  }
+  return out;
+}
+
+// value of v at the previous sorted element (element e - 1 for e = t*64 + lane)
+template <int R>
+SHCI_DEV uint64_t wave_prev(const uint64_t (&v)[R], int t) {
+  const int lane = lane_id();
+  uint64_t x = __shfl(v[t], (lane + 63) & 63);
+  if (lane == 0) x = (t > 0) ? __shfl(v[t > 0 ? t - 1 : 0], 63) : ~0ull;
+  return x;
+}
+
 // Returns false if the bucket was handed to the block kernel.  Contributions
-// accumulate in acc (per lane); in sample mode the caller reduces acc per
-// bucket, otherwise once per wavefront at the end.
-template <int KW, bool SAMPLE, typename VT>
-SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo, int M,
-                          uint32_t* slow_list, uint32_t* slow_count, SegAcc& acc) {
+// accumulate in acc (per lane).
+template <int KW, int R, bool SAMPLE, typename VT>
+SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b, int64_t lo, int M,
+                          const WaveRedArgs& A, SegAcc& acc) {
   const int lane = lane_id();
   const int n = a.n;
   const int bh = a.G.bits_hash;
@@ -151,61 +164,100 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
   const uint64_t am = 1ull << (a.auxbit & 63);
   const VT* vin = static_cast<const VT*>(a.in.v);
   const VT* v2in = static_cast<const VT*>(a.in.v2);
-  const uint64_t* auxw = a.in.k[0];  // key word holding the flag bit
+  // ---- stage: every record read once ----
+  uint64_t kr[KW][R];  // key words (flag bit cleared) by position
+  uint64_t hr[R];      // H_aa bits by position
+  uint32_t sk[R];
 #pragma unroll
-  for (int w = 1; w < KW; ++w)
-    if (w == aw) auxw = a.in.k[w];
-  auto key_of = [&](int id, uint64_t (&k)[KW]) {
-    load_key<KW>(a.in, lo + id, k);
-    clear_aux<KW>(k, a.auxbit);
-  };
-  // equal sort bits must mean equal determinants
+  for (int r = 0; r < R; ++r) {
+    const int j = r * 64 + lane;
+    sk[r] = ~0u;
+    hr[r] = 0;
+#pragma unroll
+    for (int w = 0; w < KW; ++w) kr[w][r] = 0;
+    if (j < M) {
+      uint64_t k[KW];
+      load_key<KW>(a.in, lo + j, k);
+      uint64_t fw = 0;
+#pragma unroll
+      for (int w = 0; w < KW; ++w) fw = (w == aw) ? k[w] : fw;
+      W.fl[j] = (fw & am) ? 1 : 0;
+      clear_aux<KW>(k, a.auxbit);
+#pragma unroll
+      for (int w = 0; w < KW; ++w) kr[w][r] = k[w];
+      const uint64_t h = det_hash<KW>(k, n);
+      W.h[j] = h;
+      W.v[j] = vin[lo + j];
+      if constexpr (SAMPLE) W.v2[j] = v2in[lo + j];
+      hr[r] = __double_as_longlong(a.in.haa[lo + j]);
+      sk[r] = ((uint32_t)((h << bh) >> 32) & ~0xffu) | (uint32_t)j;
+    }
+  }
+  wave_bitonic<R>(sk);
+#pragma unroll
+  for (int r = 0; r < R; ++r) W.sk[r * 64 + lane] = sk[r];
+  // ---- key and H_aa of each sorted element ----
+  uint64_t ks[KW][R], hs[R];
+  uint32_t psk[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int pos = (int)(sk[t] & 0xffu);
+#pragma unroll
+    for (int w = 0; w < KW; ++w) ks[w][t] = wave_fetch<R>(kr[w], pos);
+    hs[t] = wave_fetch<R>(hr, pos);
+    uint32_t p = (uint32_t)__shfl((int)sk[t], (lane + 63) & 63);
+    if (lane == 0) p = (t > 0) ? (uint32_t)__shfl((int)sk[t > 0 ? t - 1 : 0], 63) : ~0u;
+    psk[t] = p;
+  }
+  // ---- equal sort bits must mean equal determinants ----
   bool clash = false;
-#pragma unroll 1
-  for (int e = lane + 1; e < M; e += 64) {
-    const uint32_t cur = W.sk[e], prv = W.sk[e - 1];
-    if ((cur >> 8) == (prv >> 8)) {
-      uint64_t kx[KW], ky[KW];
-      key_of((int)(cur & 0xff), kx);
-      key_of((int)(prv & 0xff), ky);
-      bool eq = true;
 #pragma unroll
-      for (int w = 0; w < KW; ++w) eq = eq && (kx[w] == ky[w]);
-      clash = clash || !eq;
+  for (int t = 0; t < R; ++t) {
+    const int e = t * 64 + lane;
+    const bool same = e > 0 && e < M && (sk[t] >> 8) == (psk[t] >> 8);
+    if (ballot(same)) {
+#pragma unroll
+      for (int w = 0; w < KW; ++w) {
+        const uint64_t pk = wave_prev<R>(ks[w], t);
+        clash = clash || (same && pk != ks[w][t]);
+      }
     }
   }
   if (ballot(clash)) {
-    if (lane == 0) slow_list[atomicAdd(slow_count, 1u)] = (uint32_t)b;
+    if (lane == 0) {
+      A.slow_list[atomicAdd(A.slow_count, 1u)] = (uint32_t)b;
+      atomicOr(&A.slow_bits[b >> 5], 1u << (b & 31));
+    }
     return false;
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // ---- segments: heads sum from LDS ----
   int nbefore = 0;
-#pragma unroll 1
-  for (int base = 0; base < M; base += 64) {
-    const int e0 = base + lane;
-    const uint32_t s0 = (e0 < M) ? W.sk[e0] : 0u;
-    const bool head = e0 < M && (e0 == 0 || (s0 >> 8) != (W.sk[e0 - 1] >> 8));
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int e0 = t * 64 + lane;
+    const uint32_t s0 = sk[t];
+    const bool head = e0 < M && (e0 == 0 || (s0 >> 8) != (psk[t] >> 8));
     const uint64_t hb = ballot(head);
     if (head) {
       int e1 = e0 + 1;
       while (e1 < M && (W.sk[e1] >> 8) == (s0 >> 8)) ++e1;
-      const int first = (int)(s0 & 0xff);
+      const int first = (int)(s0 & 0xffu);
       SegSum<VT> sum;
       for (int e = e0; e < e1; ++e) {
-        const int id = (e == e0) ? first : (int)(W.sk[e] & 0xff);
+        const int id = (e == e0) ? first : (int)(W.sk[e] & 0xffu);
         if constexpr (SAMPLE)
-          sum.add_sample(vin[lo + id], v2in[lo + id], (auxw[lo + id] & am) != 0ull);
+          sum.add_sample(W.v[id], W.v2[id], W.fl[id] != 0);
         else
-          sum.add(vin[lo + id], (auxw[lo + id] & am) != 0ull);
+          sum.add(W.v[id], W.fl[id] != 0);
       }
       sum.finish();
       const double X = sum.X;
-      uint64_t k[KW];
-      key_of(first, k);
-      uint64_t a0, a1, b0, b1;
-      unpack_det<KW>(k, n, a0, a1, b0, b1);
-      uint64_t dk[KW];
+      uint64_t k[KW], dk[KW];
 #pragma unroll
-      for (int w = 0; w < KW; ++w) dk[w] = k[w];
+      for (int w = 0; w < KW; ++w) k[w] = dk[w] = ks[w][t];
       mask_det<KW>(dk, n);  // determinant bits only (no sample id)
       const uint64_t h = W.h[first];
       const bool inv = vset_contains_h<KW>(a.V, dk, h, n);
@@ -213,7 +265,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
       acc.ngen += cntk;
       double Dd = 0.0, g = 0.0, gd = 0.0, gG = 0.0;
       if (!inv) {
-        const double haa = a.in.haa[lo + first];
+        const double haa = __longlong_as_double((long long)hs[t]);
         Dd = a.e0 - haa;
         const double rd = 1.0 / Dd;
         double contrib;
@@ -240,6 +292,14 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
         acc.nzero += Dd == 0.0;
         acc.dmn = fmin(acc.dmn, fabs(Dd));
       }
+      if constexpr (!SAMPLE) {
+        if (a.contrib) {
+          for (int e = e0; e < e1; ++e) {
+            const int id = (e == e0) ? first : (int)(W.sk[e] & 0xffu);
+            a.contrib[a.in.pay[lo + id]] = inv ? 0.0 : (double)W.v[id] * g;
+          }
+        }
+      }
       if (a.want_u) {
         const int64_t o = lo + nbefore + rank_below(hb);
 #pragma unroll
@@ -255,63 +315,80 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage& W, int64_t b, int64_t lo,
     }
     nbefore += __popcll(hb);
   }
-  // the contributions stay in acc; the caller writes them once per run of
-  // buckets (sample mode) or once per wavefront
-  if (lane == 0) wave_zero_partials(a.P, b);
-  if (lane == 0) {
+  if (a.want_u && lane == 0) {
     a.P.nseg[b] = nbefore;
-    if (a.want_u) a.U.start[b] = (uint64_t)lo;
+    a.U.start[b] = (uint64_t)lo;
   }
   return true;
 }
 
 template <int KW, bool SAMPLE, typename VT>
-__global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_per_eu(6, 8))) k_reduce_wave(WaveRedArgs A) {
-  __shared__ WaveStage WS[WRED_WAVES];
+__global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_reduce_wave(WaveRedArgs A) {
+  __shared__ WaveStage<VT, SAMPLE> WS[WRED_WAVES];
   const RedArgs& a = A.r;
   const int t = threadIdx.x;
   const int wv = t >> 6;
   const int lane = t & 63;
-  WaveStage& W = WS[wv];
-  const int64_t nwaves = (int64_t)gridDim.x * WRED_WAVES;
+  WaveStage<VT, SAMPLE>& W = WS[wv];
+  const int64_t wave = (int64_t)blockIdx.x * WRED_WAVES + wv;
   const int bh = a.G.bits_hash;
   SegAcc acc;
-  // sample mode: the buckets of one sample that this wavefront reduced add
-  // up in acc and are written into the partials of the last of them (the
-  // others hold zeros), so the cross-lane reduction runs once per sample
-  int64_t last_ok = -1;
-  for (int64_t b = (int64_t)blockIdx.x * WRED_WAVES + wv; b < a.G.nbucket; b += nwaves) {
+  // sample mode: the buckets of a sample that this wavefront visits are
+  // consecutive in its sequence; the accumulators are written once per
+  // sample into slot [sample][wave], zeros into the slots of samples it
+  // skips
+  int64_t cur_s = -1, next_s = 0;
+  for (int64_t b = wave; b < a.G.nbucket; b += A.nwaves) {
     if constexpr (SAMPLE) {
-      if (last_ok >= 0 && (b >> bh) != (last_ok >> bh)) {
-        wave_write_partials(a.P, last_ok, acc);
-        acc = SegAcc();
-        last_ok = -1;
+      const int64_t s = b >> bh;
+      if (s != cur_s) {
+        if (cur_s >= 0) {
+          wave_write_partials(A.Pw, cur_s * A.nwaves + wave, acc);
+          acc = SegAcc();
+          next_s = cur_s + 1;
+        }
+        if (lane == 0)
+          for (int64_t z = next_s; z < s; ++z) wave_zero_partials(A.Pw, z * A.nwaves + wave);
+        next_s = s;
+        cur_s = s;
       }
     }
     const int64_t lo = (int64_t)A.bstart[b];
     const int64_t M = (int64_t)A.bstart[b + 1] - lo;
     if (M > WCAP) {
-      if (lane == 0) A.slow_list[atomicAdd(A.slow_count, 1u)] = (uint32_t)b;
+      if (lane == 0) {
+        A.slow_list[atomicAdd(A.slow_count, 1u)] = (uint32_t)b;
+        atomicOr(&A.slow_bits[b >> 5], 1u << (b & 31));
+      }
+      continue;
+    }
+    if (M == 0) {
+      if (a.want_u && lane == 0) {
+        a.P.nseg[b] = 0;
+        a.U.start[b] = (uint64_t)lo;
+      }
       continue;
     }
     if (M <= 64)
-      wave_stage_sort<KW, 1>(a, W, lo, (int)M);
+      wave_bucket<KW, 1, SAMPLE, VT>(a, W, b, lo, (int)M, A, acc);
     else if (M <= 128)
-      wave_stage_sort<KW, 2>(a, W, lo, (int)M);
+      wave_bucket<KW, 2, SAMPLE, VT>(a, W, b, lo, (int)M, A, acc);
     else
-      wave_stage_sort<KW, 4>(a, W, lo, (int)M);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (wave_bucket<KW, SAMPLE, VT>(a, W, b, lo, (int)M, A.slow_list, A.slow_count, acc)) last_ok = b;
+      wave_bucket<KW, 4, SAMPLE, VT>(a, W, b, lo, (int)M, A, acc);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if constexpr (SAMPLE) {
-    if (last_ok >= 0) wave_write_partials(a.P, last_ok, acc);
+    if (cur_s >= 0) {
+      wave_write_partials(A.Pw, cur_s * A.nwaves + wave, acc);
+      next_s = cur_s + 1;
+    }
+    if (lane == 0)
+      for (int64_t z = next_s; z < A.nsamp; ++z) wave_zero_partials(A.Pw, z * A.nwaves + wave);
   } else {
-    wave_write_partials(A.Pw, (int64_t)blockIdx.x * WRED_WAVES + wv, acc);
+    wave_write_partials(A.Pw, wave, acc);
   }
 }
 

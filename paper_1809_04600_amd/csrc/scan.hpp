@@ -62,13 +62,14 @@ __global__ void k_scan_add(TO* out, int64_t n, const TO* tile_offs) {
 struct ScanTmp {
   void* lvl[4] = {nullptr, nullptr, nullptr, nullptr};
   void* off[4] = {nullptr, nullptr, nullptr, nullptr};
+  // words: 64-bit words per element (2 for 128-bit sums)
   template <class CV>
-  void carve(CV& cv, int64_t n) {
+  void carve(CV& cv, int64_t n, int words = 1) {
     int64_t m = n;
     for (int l = 0; l < 4; ++l) {
       m = (m + SCAN_TILE - 1) / SCAN_TILE;
-      lvl[l] = cv.template take<uint64_t>(m + 1);
-      off[l] = cv.template take<uint64_t>(m + 1);
+      lvl[l] = cv.template take<uint64_t>(words * (m + 1));
+      off[l] = cv.template take<uint64_t>(words * (m + 1));
       if (m <= 1) break;
     }
   }

@@ -69,11 +69,14 @@ def _exact_distribution(t: ref.AliasTable):
     return p
 
 
-@pytest.mark.parametrize("n,zeros,seed", [(1, 0, 0), (2, 0, 1), (7, 0, 2), (37, 3, 3), (200, 10, 4)])
+@pytest.mark.parametrize("n,zeros,seed", [(1, 0, 0), (2, 0, 1), (7, 0, 2), (37, 3, 3), (200, 10, 4), (3000, 900, 5)])
 def test_alias_table_masses_and_distribution(n, zeros, seed):
     c = _coefficients(np.random.default_rng(seed), n, zeros)
     t = ref.alias_table(c)
     _check_masses(t)
+    # every sum of masses or bucket deficits fits 128 bits (a device
+    # construction by prefix sums forms them)
+    assert n * t.capacity < 2**127
     # sampled distribution against p_i = |c_i| / sum |c| in exact rationals
     exact = _exact_distribution(t)
     tot = sum(Fraction(abs(float(v))) for v in c)

@@ -1,16 +1,27 @@
 """Benchmark: screened PT2 terms/s and E2 wall time on one MI355X.
 
-Default workload w1: deterministic screened PT2, (8 alpha, 8 beta) electrons in
-40 orbitals, N_var = 5e4, eps2 = 1e-5, seeded synthetic inputs (the paper's
-molecular data are not available).  One step = one shci_pt2_det call on inputs
-already resident in HBM (validation, hash set of V, excitation generation,
-hash partition, bucket sort + segmented reduce + H_aa, E2 reduction).
---workload w3 times the semistochastic 76-orbital, 1e6-determinant workload:
-one step = the deterministic part at eps2^d plus 256 samples of 2000 draws at
-eps2 (shci_pt2_det + shci_pt2_sample).  The heat-bath tables are built once per
-integral set (context) and timed apart.  H c on the same variational space
-(shci_pt2_hc, string lists + rows) is timed after the steps and reported
-under "hc"; it is not part of the step.
+Default workload w3: semistochastic PT2, (14 alpha, 14 beta) electrons in 76
+orbitals (the Cr2 active-space shape of the paper's section VII), N_var = 1e6,
+seeded synthetic inputs (the paper's molecular data are not available).  One
+step is one pass of the whole hot path on inputs already resident in HBM:
+  - shci_pt2_det at eps2^d = 2e-5 (validation, hash set of V, excitation
+    generation, hash partition, bucket sort + segmented reduce + H_aa, E2
+    reduction), and
+  - shci_pt2_sample on the seed path: the alias table of p_i = |c_i|/sum|c|
+    and 256 x 2000 draws made on the device, then the per-sample estimators at
+    eps2 = 1e-7 minus eps2^d, in chunks of samples.
+Both calls use a caller-owned workspace (torch memory), so the step allocates
+nothing.  The FP32-compensated step is timed beside the FP64 one.  The
+heat-bath tables are built once per integral set and timed apart.  H c on the
+same variational space (shci_pt2_hc) is timed after the steps ("hc"); it is
+not part of the step.
+
+--workload w1 times the deterministic 40-orbital workload (one shci_pt2_det
+per step).  --workload w4 times the 10^7-determinant workload: FP32c forward
+(deterministic part and 512 x 4000 samples) and both recomputing adjoints per
+step, with the device memory footprint and the statistical error, plus a
+labelled sensitivity run with E0' (the Rayleigh quotient over HF and its MP1
+doubles) beside the literal E0.
 
 Prints one JSON line.  --gpus above 1 is rejected: the benchmark runs on one GPU.
 """
@@ -18,7 +29,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,16 +39,21 @@ if ROOT not in sys.path:
 
 METRIC = ("PT2 screened terms/s + E2 wall time, FP32-comp vs FP64 at ≤1e-6 Ha; HBM GB/s")
 HBM_PEAK_GBS = 8000.0
+# plain 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="w1")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; w4: 1)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 3; w4: 0)")
+    ap.add_argument("--fp32c-steps", type=int, default=None,
+                    help="timed FP32c steps (default: min(steps, 5))")
+    ap.add_argument("--workload", default="w3")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-hc", action="store_true", help="skip the H c timing")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -58,33 +73,19 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def kernel_names(kind, kw, sampled):
-    """Full FP64 kernel names behind a bench kernel label."""
-    smp = "true" if sampled else "false"
-    return {"k_gen(count)": [f"void shci::k_gen_count<{kw}, {smp}, double>(shci::GenArgs)"],
-            "k_gen(write)": [f"void shci::k_gen_write_sample<{kw}, double>(shci::GenArgs)" if sampled
-                             else f"void shci::k_gen_write<{kw}, double>(shci::GenArgs)"],
-            "partition": [f"void shci::k_part_hist<{kw}>(shci::PassArgs)",
-                          f"void shci::k_part_scatter<{kw}, double, {smp}, false>(shci::PassArgs)"],
-            "k_reduce": [f"void shci::k_reduce_wave<{kw}, {smp}, double>(shci::WaveRedArgs)"]}[kind]
-
-
-def measured_traffic(workload, names):
-    """HBM bytes per launch (per pass for the partition) of the named kernels,
-    from the committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
-    plain copy's readings); None when missing or taken with other kernel
-    sources."""
-    f = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+def measured(workload, kernel):
+    """Counter figures of one kernel from the committed summary
+    (profiles/counters_<workload>.json): HBM bytes per launch (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy's readings) and VALU lane operations
+    per launch; None when missing or taken with other kernel sources."""
+    f = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
     if not os.path.exists(f):
         return None
     with open(f) as fh:
         t = json.load(fh)
     if t.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    ks = t.get("kernels", {})
-    if not all(n in ks for n in names):
-        return None
-    return sum(ks[n]["hbm_bytes_per_launch"] for n in names)
+    return t.get("kernels", {}).get(kernel)
 
 
 def copy_probe(mib):
@@ -101,66 +102,154 @@ def copy_probe(mib):
 
 
 SUM_KEYS = ("n_terms", "n_terms_gen", "n_unique", "n_intruder", "n_records", "ms_gen", "ms_sort",
-            "ms_reduce", "ms_total", "ms_k_count", "ms_k_write", "ms_k_reduce")
+            "ms_reduce", "ms_total", "ms_k_count", "ms_k_write", "ms_k_reduce", "ms_k_part",
+            "n_part_launches", "n_part_records", "n_chunks")
 
 
-def one_step(ctx, x, dets, c, draws, prec):
-    """One pass of the hot path: the deterministic part (at eps2^d for a
-    semistochastic workload) and, if the workload samples, every sample."""
-    wl = x.wl
-    r = ctx.det(dets, c, x.e0, wl.eps2, prec)
-    st = dict(r.stats)
-    e2 = r.e2
-    if draws is not None:
-        _, mean, sem, ss = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, draws, prec)
-        e2 = e2 + mean
-        st["sem"] = sem
-        st["sample"] = ss
-        for k in SUM_KEYS:
-            st[k] = st[k] + ss[k]
-        st["n_buckets"] = max(st["n_buckets"], ss["n_buckets"])
-        st["min_abs_denom"] = min(st["min_abs_denom"], ss["min_abs_denom"])
-    return e2, st
+class Step:
+    """One pass of the hot path on resident inputs."""
+
+    def __init__(self, ctx, x, dets, c, ws, grad=False, e0=None):
+        self.ctx, self.x, self.dets, self.c, self.ws, self.grad = ctx, x, dets, c, ws, grad
+        self.e0 = x.e0 if e0 is None else e0
+
+    def __call__(self, prec):
+        ctx, x, wl = self.ctx, self.x, self.x.wl
+        st = {}
+        if self.grad:
+            e2, _, _, sd = ctx.grad(self.dets, self.c, self.e0, wl.eps2, prec, mode="recompute", ws=self.ws)
+        else:
+            r = ctx.det(self.dets, self.c, self.e0, wl.eps2, prec, ws=self.ws)
+            e2, sd = r.e2, r.stats
+        st["det"] = sd
+        if wl.n_samples:
+            kw = dict(seed=wl.draw_seed, n_samples=wl.n_samples, n_draws=wl.n_draws, ws=self.ws)
+            if self.grad:
+                _, mean, sem, _, _, ss = ctx.sample_grad(self.dets, self.c, self.e0, wl.eps2_sto, wl.eps2, None,
+                                                         prec, **kw)
+            else:
+                _, mean, sem, ss = ctx.sample(self.dets, self.c, self.e0, wl.eps2_sto, wl.eps2, None, prec, **kw)
+            st["sample"] = ss
+            st["sem"] = sem
+            st["e2_det"] = e2
+            e2 = e2 + mean
+        tot = {k: st["det"][k] + (st["sample"][k] if "sample" in st else 0) for k in SUM_KEYS}
+        tot["min_abs_denom"] = min(st["det"]["min_abs_denom"], st.get("sample", st["det"])["min_abs_denom"])
+        tot["key_words"] = st.get("sample", st["det"])["key_words"]
+        tot["value_bytes"] = st.get("sample", st["det"])["value_bytes"]
+        st["total"] = tot
+        return e2, st
 
 
-def timed(ctx, x, dets, c, draws, prec, steps):
+def timed(step, prec, steps):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    runs = []
     e2 = None
     for _ in range(steps):
-        e2, st = one_step(ctx, x, dets, c, draws, prec)
-        stats.append(st)
+        e2, st = step(prec)
+        runs.append(st)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    avg = {k: sum(s[k] for s in stats) / len(stats) for k in stats[0]
-           if isinstance(stats[0][k], float)}
-    return wall, e2, stats[-1], avg
+    avg = {k: sum(r["total"][k] for r in runs) / len(runs) for k in SUM_KEYS}
+    return wall, e2, runs[-1], avg
+
+
+def roofline(kernel, bound, alg_bytes, launches, ms, measured_kernel):
+    """Roofline object of one kernel: algorithmic bytes per launch over its
+    average launch duration (HIP events on the library's stream)."""
+    if launches <= 0 or ms <= 0:
+        return None
+    per_launch = alg_bytes / launches
+    avg_s = ms * 1e-3 / launches
+    achieved = per_launch / avg_s / 1e9
+    out = {"bound": bound, "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "alg_bytes": per_launch, "launches": launches,
+           "avg_ms": ms / launches}
+    if measured_kernel:
+        out["traffic"] = measured_kernel.get("hbm_bytes_per_launch")
+        if bound == "alu" and measured_kernel.get("valu_lane_ops_per_launch"):
+            ops = measured_kernel["valu_lane_ops_per_launch"] / avg_s / 1e9
+            out.update({"achieved": ops, "peak": VALU_PEAK_GOPS, "unit": "G lane-ops/s",
+                        "frac": ops / VALU_PEAK_GOPS, "hbm_gbs": achieved})
+    if bound == "alu" and out["unit"] == "GB/s":
+        out["note"] = "VALU counters not taken for these kernel sources; HBM rate shown"
+    return out
+
+
+def kernel_rooflines(wl, run, avg, prec):
+    """Per-kernel rooflines of one step.  Algorithmic bytes: the generator
+    writes each record once; the partition reads and writes it once per pass;
+    the reduce reads it once (key words, value(s), H_aa)."""
+    tot = run["total"]
+    kw, vb = tot["key_words"], tot["value_bytes"]
+    rec = 8 * kw + vb + 8 + 4            # key words, value(s), H_aa, bucket id
+    red = 8 * kw + vb + 8                # the reduce does not read the bucket id
+    nrec = avg["n_records"]
+    launches = avg["n_chunks"]           # one generator and one reduce launch per chunk / batch
+    sampled = wl.n_samples > 0
+    smp = "true" if sampled else "false"
+    vt = "double" if prec == "fp64" else "float"
+    names = {
+        "k_gen_write": (f"void shci::k_gen_write_sample<{kw}, {vt}>(shci::GenArgs)" if sampled
+                        else f"void shci::k_gen_write<{kw}, {vt}>(shci::GenArgs)"),
+        "k_gen_count": f"void shci::k_gen_count<{kw}, {smp}, {vt}>(shci::GenArgs)",
+        "k_part_scatter": f"void shci::k_part_scatter<{kw}, {vt}, {smp}, false>(shci::PassArgs)",
+        "k_reduce_wave": f"void shci::k_reduce_wave<{kw}, {smp}, {vt}>(shci::WaveRedArgs)",
+    }
+    # the deterministic part uses one key word fewer on w3's orbitals when no
+    # sample id is packed; its records are a small share and are counted with
+    # the sample records' sizes
+    out = {
+        "k_part_scatter": roofline("k_part_scatter", "hbm", 2.0 * rec * avg["n_part_records"],
+                                   avg["n_part_launches"], avg["ms_k_part"],
+                                   measured(wl.name, names["k_part_scatter"])),
+        "k_reduce_wave": roofline("k_reduce_wave", "hbm", red * nrec, launches, avg["ms_k_reduce"],
+                                  measured(wl.name, names["k_reduce_wave"])),
+        "k_gen_write": roofline("k_gen_write", "alu", rec * nrec, launches, avg["ms_k_write"],
+                                measured(wl.name, names["k_gen_write"])),
+        "k_gen_count": roofline("k_gen_count", "alu", 0.0, launches, avg["ms_k_count"],
+                                measured(wl.name, names["k_gen_count"])),
+    }
+    ms = {"k_part_scatter": avg["ms_k_part"], "k_reduce_wave": avg["ms_k_reduce"],
+          "k_gen_write": avg["ms_k_write"], "k_gen_count": avg["ms_k_count"]}
+    return out, ms, rec
 
 
 def cpu_baseline(x, budget_s):
-    """The CPU reference on a bounded sample: the first M determinants of V
-    (HF first), M chosen so the run takes about budget_s seconds."""
+    """The CPU oracle on a bounded sample of the step: the deterministic part
+    on the first M determinants of V (HF first), and for a sampled workload
+    the first sample (same seed-path draws) at eps2 - eps2^d."""
     from oracle import ref
     wl = x.wl
     n, na, nb = wl.n_orb, wl.n_alpha, wl.n_beta
+    t_s, terms_s, desc_s = 0.0, 0, ""
+    if wl.n_samples:
+        draws = ref.alias_draws(x.c, 1, wl.n_draws, wl.draw_seed)
+        t0 = time.perf_counter()
+        _, cnt = ref.pt2_sample_counts(n, na, nb, x.h1, x.eri, x.dets, x.c, x.e0, wl.eps2_sto, wl.eps2, draws)
+        t_s = time.perf_counter() - t0
+        terms_s = int(cnt[0])
+        desc_s = f"; sample 0 ({wl.n_draws} draws) at eps2={wl.eps2_sto:g}: {terms_s} terms in {t_s:.2f} s"
 
     def run(m):
         t0 = time.perf_counter()
         r = ref.pt2_det(n, na, nb, x.h1, x.eri, x.dets[:m], x.c[:m], x.e0, wl.eps2, unique=False)
         return time.perf_counter() - t0, r
 
-    m = min(2000 if wl.n_orb <= 50 else 100, len(x.c))
+    left = max(budget_s - t_s, budget_s / 4)
+    m = min(2000 if wl.n_orb <= 50 else 200, len(x.c))
     t, r = run(m)
-    if t < budget_s / 3 and m < len(x.c):
-        m = min(len(x.c), int(m * budget_s / max(t, 1e-3)))
+    if t < left / 3 and m < len(x.c):
+        m = min(len(x.c), int(m * left / max(t, 1e-3)))
         t, r = run(m)
-    return {"value": r.n_terms / t, "unit": "screened terms/s", "cores": ref.max_threads(),
+    total_t = t + t_s
+    return {"value": (r.n_terms + terms_s) / total_t, "unit": "screened terms/s", "cores": ref.max_threads(),
             "kind": "oracle",
-            "sample": f"first {m} of {len(x.c)} variational determinants of {wl.name} "
-                      f"(HF first), eps2={wl.eps2:g}; {r.n_terms} screened terms in {t:.2f} s",
-            "e2_sample": r.e2, "seconds": t}
+            "sample": f"first {m} of {len(x.c)} variational determinants of {wl.name} (HF first) at "
+                      f"eps2={wl.eps2:g}: {r.n_terms} terms in {t:.2f} s{desc_s}",
+            "seconds": total_t}
 
 
 def hc_timing(ctx, x, dets, c, reps=3):
@@ -173,6 +262,20 @@ def hc_timing(ctx, x, dets, c, reps=3):
     return {"ms_total": st["ms_total"], "ms_lists": st["ms_gen"], "ms_rows": st["ms_reduce"],
             "connections": st["n_terms"], "connections_per_s": st["n_terms"] / (st["ms_total"] * 1e-3),
             "e_var_minus_e0": ev - x.e0}
+
+
+def e0_prime(ctx, x, dets, c):
+    """E0' = <c'|H|c'>/<c'|c'> over HF and its MP1 doubles (their c as
+    stored), by H c on that subspace on the device."""
+    import numpy as np
+    import torch
+
+    from synth import generator as G
+    mask = G.double_of_hf_mask(x.levels)
+    mask[0] = True
+    idx = torch.from_numpy(np.nonzero(mask)[0]).to(dets.device)
+    _, _, ev, _ = ctx.hc(dets[idx].contiguous(), c[idx].contiguous())
+    return float(ev), int(mask.sum())
 
 
 def main():
@@ -190,6 +293,11 @@ def main():
     import paper_1809_04600_amd as P
     from synth import store
 
+    big = a.workload == "w4"
+    steps = a.steps if a.steps is not None else (1 if big else 20)
+    warmup = a.warmup if a.warmup is not None else (0 if big else 3)
+    steps32 = a.fp32c_steps if a.fp32c_steps is not None else min(steps, 5)
+    print(f"bench: loading {a.workload}", file=sys.stderr, flush=True)
     x = store.load(a.workload)
     wl = x.wl
     dev = "cuda:0"
@@ -202,87 +310,96 @@ def main():
     ctx = P.Context(h1, eri, wl.n_alpha, wl.n_beta)
     torch.cuda.synchronize()
     table_ms = (time.perf_counter() - t0) * 1e3
-
-    draws = None
-    if wl.n_samples:
-        # draws proportional to |c_i| (sampling-probability equation), drawn
-        # on the host before timing
-        import numpy as np
-        p = np.abs(x.c) / np.abs(x.c).sum()
-        dr = np.random.default_rng(wl.draw_seed).choice(len(x.c), size=(wl.n_samples, wl.n_draws), p=p)
-        draws = torch.from_numpy(dr.astype(np.uint32).view(np.int32)).to(dev)
-    for _ in range(a.warmup):
-        one_step(ctx, x, dets, c, draws, "fp64")
-        one_step(ctx, x, dets, c, draws, "fp32c")
-    w64, e2_64, s64, avg64 = timed(ctx, x, dets, c, draws, "fp64", a.steps)
-    w32, e2_32, s32, avg32 = timed(ctx, x, dets, c, draws, "fp32c", a.steps)
-
-    n_terms = s64["n_terms"]
-    n_rec = s64["n_records"]
-    # roofline of the part that dominates the step: the samples of a
-    # semistochastic workload, else the deterministic call (HIP-event times)
-    sampled = "sample" in s64
-    src = s64["sample"] if sampled else s64
-    tsrc = src if sampled else avg64
-    kw = src["key_words"]
-    launches = src["n_chunks"] if sampled else 1
-    # record bytes: packed key + value(s) + H_aa (FP64) + bucket id
-    rec64 = 8 * kw + src["value_bytes"] + 8 + 4
-    rec32 = 8 * kw + (s32["sample"] if sampled else s32)["value_bytes"] + 8 + 4
-    nrec_src = src["n_records"]
-    npass = math.ceil(math.log2(max(src["n_buckets"], 1)) / 8) if src["n_buckets"] > 1 else 0
-    kernels = {"k_gen(count)": tsrc["ms_k_count"], "k_gen(write)": tsrc["ms_k_write"],
-               "partition": tsrc["ms_sort"], "k_reduce": tsrc["ms_k_reduce"]}
-    dom = max(kernels, key=kernels.get)
-    # algorithmic bytes over all launches of each kernel
-    alg = {"k_gen(count)": 40.0 * len(x.c),             # each source det read once
-           "k_gen(write)": rec64 * nrec_src + 40.0 * len(x.c),
-           "partition": (2.0 * rec64 + 4.0) * nrec_src * npass,  # hist reads ids; scatter reads + writes
-           "k_reduce": rec64 * nrec_src}                 # each record read once
-    per_launch = launches * (npass if dom == "partition" else 1)
-    achieved = alg[dom] / (kernels[dom] * 1e-3) / 1e9
-    reduce_gbs = alg["k_reduce"] / (avg64["ms_k_reduce"] * 1e-3) / 1e9
-    sort_gbs = alg["partition"] / (avg64["ms_sort"] * 1e-3) / 1e9 if npass else None
+    del eri
+    torch.cuda.empty_cache()
+    # caller-owned workspace: the calls allocate nothing (w4 uses the
+    # library's own grow-only buffers, so that the footprint can be read)
+    ws = None
+    if not big:
+        free, _ = torch.cuda.mem_get_info()
+        ws = torch.empty(int(0.8 * free) // 256 * 256, dtype=torch.uint8, device=dev)
+    step = Step(ctx, x, dets, c, ws, grad=big)
+    prec_main = "fp32c" if big else "fp64"
+    for k in range(warmup):
+        print(f"bench: warmup {k}", file=sys.stderr, flush=True)
+        step(prec_main)
+        if not big:
+            step("fp32c")
+    print(f"bench: timing {steps} {prec_main} steps", file=sys.stderr, flush=True)
+    w_main, e2_main, run_main, avg_main = timed(step, prec_main, steps)
+    out32 = None
+    if not big and steps32 > 0:
+        print(f"bench: timing {steps32} fp32c steps", file=sys.stderr, flush=True)
+        w32, e2_32, run32, avg32 = timed(step, "fp32c", steps32)
+        rl32, ms32, _ = kernel_rooflines(wl, run32, avg32, "fp32c")
+        out32 = {"e2": e2_32, "e2_wall_ms": w32 * 1e3, "steps": steps32,
+                 "terms_per_s": run32["total"]["n_terms"] / w32, "speedup_vs_fp64": w_main / w32,
+                 "abs_diff_vs_fp64_gpu": abs(e2_32 - e2_main), "kernel_ms": ms32,
+                 "record_bytes": 8 * run32["total"]["key_words"] + run32["total"]["value_bytes"] + 12}
+    tot = run_main["total"]
+    n_terms = tot["n_terms"]
+    rl, ms, rec = kernel_rooflines(wl, run_main, avg_main, prec_main)
+    dom = max(ms, key=ms.get)
+    if rl[dom] is None:
+        dom = "k_part_scatter"
     out = {
         "metric": METRIC,
-        "value": n_terms / w64,
+        "value": n_terms / w_main,
         "unit": "screened terms/s",
         "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": w64 * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": w_main * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec_main == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.description}", "n_orb": wl.n_orb,
                    "n_alpha": wl.n_alpha, "n_beta": wl.n_beta, "n_var": len(x.c),
-                   "eps2": wl.eps2, "n_terms": n_terms, "n_records": n_rec,
-                   "n_unique": s64["n_unique"], "parallelism": "single GPU",
+                   "eps2": wl.eps2, "n_terms": n_terms, "n_records": tot["n_records"],
+                   "n_unique": tot["n_unique"], "parallelism": "single GPU",
+                   "precision": prec_main,
+                   "workspace_bytes": int(ws.numel()) if ws is not None else None,
                    **({"eps2_sto": wl.eps2_sto, "n_samples": wl.n_samples, "n_draws": wl.n_draws,
-                       "e2_sem": s64["sem"], "sample_chunks": s64["sample"]["n_chunks"]}
+                       "draws": f"seed path, seed {wl.draw_seed}", "e2_sem": run_main["sem"],
+                       "sample_chunks": run_main["sample"]["n_chunks"]}
                       if wl.n_samples else {}),
-                   "min_abs_denom": s64["min_abs_denom"], "n_intruder": s64["n_intruder"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(wl.name, kernel_names(dom, kw, sampled)),
-                     "alg_bytes": alg[dom] / max(1, per_launch), "launches": per_launch},
-        "e2_fp64": e2_64,
-        "e2_wall_ms_fp64": w64 * 1e3,
-        "fp32c": {"e2": e2_32, "e2_wall_ms": w32 * 1e3, "terms_per_s": n_terms / w32,
-                  "speedup_vs_fp64": w64 / w32, "abs_diff_vs_fp64_gpu": abs(e2_32 - e2_64),
-                  "ms_k_reduce": avg32["ms_k_reduce"], "ms_k_write": avg32["ms_k_write"]},
-        "kernel_ms_fp64": kernels,
-        "phase_ms_fp64": {"gen": avg64["ms_gen"], "sort": avg64["ms_sort"],
-                          "reduce": avg64["ms_reduce"], "total_device": avg64["ms_total"]},
-        "sort_gbs_fp64": sort_gbs,
-        "reduce_gbs_fp64": reduce_gbs,
-        "record_bytes": {"fp64": rec64, "fp32c": rec32},
+                   "min_abs_denom": tot["min_abs_denom"], "n_intruder": tot["n_intruder"]},
+        "roofline": rl[dom],
+        "roofline_kernels": rl,
+        "alg_efficiency": {"bytes_per_term": 80.0, "gbs": 80.0 * n_terms / w_main / 1e9,
+                           "frac": 80.0 * n_terms / w_main / 1e9 / HBM_PEAK_GBS},
+        "e2": e2_main,
+        "e2_wall_ms": w_main * 1e3,
+        "kernel_ms": ms,
+        "phase_ms": {"gen": avg_main["ms_gen"], "sort": avg_main["ms_sort"], "reduce": avg_main["ms_reduce"],
+                     "total_device": avg_main["ms_total"]},
+        "record_bytes": rec,
         "table_build_ms": table_ms,
-        "hc": hc_timing(ctx, x, dets, c),
     }
+    if wl.n_samples:
+        out["e2_det"] = run_main["e2_det"]
+    if out32:
+        out["fp32c"] = out32
+    if big:
+        free, total = torch.cuda.mem_get_info()
+        out["hbm_footprint_gib"] = (total - free) / 2**30
+        out["e2_stat_error"] = run_main["sem"]
+        ep, nsub = e0_prime(ctx, x, dets, c)
+        sens = Step(ctx, x, dets, c, None, grad=False, e0=ep)
+        ts = time.perf_counter()
+        e2p, runp = sens("fp32c")
+        torch.cuda.synchronize()
+        out["sensitivity_e0_prime"] = {
+            "label": "E0' = Rayleigh quotient over HF and its MP1 doubles (not the workload's E0)",
+            "e0_prime": ep, "e0": x.e0, "subspace": nsub, "e2": e2p, "e2_sem": runp["sem"],
+            "min_abs_denom": runp["total"]["min_abs_denom"], "n_intruder": runp["total"]["n_intruder"],
+            "wall_s": time.perf_counter() - ts}
+    if not a.no_hc:
+        out["hc"] = hc_timing(ctx, x, dets, c)
     if not a.no_cpu:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         cb = cpu_baseline(x, a.cpu_seconds)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     ctx.close()

@@ -121,6 +121,9 @@ typedef struct {
   int32_t key_words;     /* 64-bit words per packed key */
   int32_t value_bytes;   /* bytes per record value (8 FP64, 4 FP32C; x2 in sample mode) */
   int32_t n_chunks;      /* hash batches (det, grad) or sample chunks (sample) evaluated */
+  int32_t n_part_launches; /* partition scatter launches (passes summed over chunks) */
+  double ms_k_part;      /* partition scatter kernels, summed over their launches */
+  int64_t n_part_records; /* records moved by the scatter launches (records x passes, summed) */
 } shci_pt2_stats;
 
 /* Optional device outputs of shci_pt2_det (any pointer may be NULL).

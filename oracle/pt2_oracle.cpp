@@ -712,7 +712,7 @@ int oracle_det_batch(int n, int na, int nb, const double* h1, const double* eri,
 static int sample_core(const System& S, const Det* V, int64_t nd, const double* c, const double* c_ref,
                        double e0, double eps2, double eps2_d, int32_t ns, int32_t ndraw,
                        const uint32_t* draws, double* out, double* grad, double* de0,
-                       int32_t n_batches = 1, const int32_t* sbatch = nullptr) {
+                       int32_t n_batches = 1, const int32_t* sbatch = nullptr, int64_t* nterm = nullptr) {
   int st = validate(S, V, c_ref, nd);
   if (st) return st;
   if (ndraw < 2 || ns < 1 || !(eps2 >= 0.0) || !(eps2_d >= eps2)) {
@@ -794,6 +794,7 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
     const int64_t ngroups = (int64_t)heads.size() - 1;
     const int nthr = omp_get_max_threads();
     std::vector<Neumaier> part(nthr), dpart(nthr);
+    std::vector<int64_t> kept_terms(nthr, 0);  // terms of a outside V
     // per group: X, X^d and 1 / (D Nd (Nd-1)) (0 for members of V)
     std::vector<double> gX(grad ? ngroups : 0), gXd(grad ? ngroups : 0), gG(grad ? ngroups : 0);
 #pragma omp parallel for schedule(static)
@@ -804,6 +805,7 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
         continue;
       }
       Acc acc;
+      kept_terms[omp_get_thread_num()] += (int64_t)(j - k0);
       for (size_t m = k0; m < j; ++m) {
         acc.X.add(terms[m].x);
         acc.Y.add(terms[m].y);
@@ -832,6 +834,10 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
     }
     // one batch of P per sample: the estimate is scaled by the number of batches
     out[s] = (double)n_batches * tot.value();
+    if (nterm) {
+      nterm[s] = 0;
+      for (int t = 0; t < nthr; ++t) nterm[s] += kept_terms[t];
+    }
     if (de0) de0[s] = (double)n_batches * dtot.value();
     if (grad) {
       // terms in (a, i) order; per source i the sum runs in that order
@@ -849,6 +855,16 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
   if (grad)
     for (int64_t i = 0; i < nd; ++i) grad[i] = gacc[i].value() / (double)ns;
   return 0;
+}
+
+// The per-sample estimates and, per sample, the number of kept terms whose a
+// lies outside V.
+int oracle_pt2_sample_counts(int n, int na, int nb, const double* h1, const double* eri, const uint64_t* dets,
+                             const double* c, int64_t nd, double e0, double eps2, double eps2_d, int32_t ns,
+                             int32_t ndraw, const uint32_t* draws, double* out, int64_t* nterm) {
+  System S{n, na, nb, h1, eri};
+  return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c, e0, eps2, eps2_d, ns, ndraw, draws, out,
+                     nullptr, nullptr, 1, nullptr, nterm);
 }
 
 int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri,

@@ -57,6 +57,9 @@ def lib():
         L.oracle_pt2_sample.restype = _i
         L.oracle_pt2_sample.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d,
                                         C.c_int32, C.c_int32, _p, _p]
+        L.oracle_pt2_sample_counts.restype = _i
+        L.oracle_pt2_sample_counts.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d,
+                                               C.c_int32, C.c_int32, _p, _p, _p]
         L.oracle_det_batch.restype = _i
         L.oracle_det_batch.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d, _i, _i, _p, _p]
         L.oracle_pt2_sample_batched.restype = _i
@@ -223,6 +226,24 @@ def pt2_sample(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
     if st:
         raise OracleError(st, L.oracle_last_error().decode())
     return out
+
+
+def pt2_sample_counts(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
+    """(per-sample estimates, per-sample kept terms with a outside V) on explicit draws."""
+    h1, eri = _sys(h1, eri)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    draws = np.ascontiguousarray(draws, dtype=np.uint32)
+    ns, nd = draws.shape
+    out = np.zeros(ns)
+    cnt = np.zeros(ns, dtype=np.int64)
+    L = lib()
+    st = L.oracle_pt2_sample_counts(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
+                                    float(e0), float(eps2), float(eps2_d), ns, nd, _ptr(draws), _ptr(out),
+                                    _ptr(cnt))
+    if st:
+        raise OracleError(st, L.oracle_last_error().decode())
+    return out, cnt
 
 
 def det_batch(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_hi, n_batches, batch):

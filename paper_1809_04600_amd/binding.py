@@ -42,7 +42,8 @@ class Stats(C.Structure):
                 ("ms_gen", C.c_double), ("ms_sort", C.c_double), ("ms_reduce", C.c_double),
                 ("ms_total", C.c_double), ("ms_k_count", C.c_double), ("ms_k_write", C.c_double),
                 ("ms_k_reduce", C.c_double), ("n_records", C.c_int64), ("key_words", C.c_int32),
-                ("value_bytes", C.c_int32), ("n_chunks", C.c_int32)]
+                ("value_bytes", C.c_int32), ("n_chunks", C.c_int32), ("n_part_launches", C.c_int32),
+                ("ms_k_part", C.c_double), ("n_part_records", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

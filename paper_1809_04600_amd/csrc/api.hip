@@ -121,6 +121,7 @@ struct shci_pt2_ctx {
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
   DevResult* dres = nullptr;
   hipEvent_t ev[10] = {};
+  hipEvent_t evp[16] = {};  // around the partition scatter launches of a job (first 8 passes)
 };
 
 namespace {
@@ -425,7 +426,9 @@ struct Job {
   // results
   DevResult res;
   int32_t nbucket = 0, retries = 0;
-  float ms_gen = 0, ms_sort = 0, ms_reduce = 0, ms_k_count = 0, ms_k_write = 0, ms_k_reduce = 0;
+  float ms_gen = 0, ms_sort = 0, ms_reduce = 0, ms_k_count = 0, ms_k_write = 0, ms_k_reduce = 0, ms_k_part = 0;
+  int32_t n_part = 0;
+  int64_t n_part_rec = 0;
   int64_t nrec = 0;
   int kw = 0, vbytes = 0;
   int32_t nbatch = 1;
@@ -503,19 +506,20 @@ void plan_big(CV& cv, const BigDims& d, BigPlan& o) {
   o.contrib = d.keep ? cv.template take<double>(d.nrec) : nullptr;
 }
 
-// hash set of V: 2^ceil(log2 2N) slots, presence filter of ~16 bits per member
+// hash set of V: 2^ceil(log2 2N) slots; presence filter of 2^fbits 64-bit
+// words, at least 32 bits per member
 void vset_dims(int64_t ndet, uint64_t& vcap, int& fbits, int64_t& fwords) {
   vcap = 1024;
   while (vcap < 2 * (uint64_t)ndet) vcap <<= 1;
-  fbits = 10;  // false positives ~6%
-  while (fbits < 32 && ((uint64_t)1 << fbits) < 16 * (uint64_t)ndet) ++fbits;
-  fwords = ((int64_t)1 << fbits) / 32;
+  fbits = 8;
+  while (fbits < 40 && ((uint64_t)64 << fbits) < 32 * (uint64_t)ndet) ++fbits;
+  fwords = (int64_t)1 << fbits;
 }
 
 struct Phase0 {  // per source: work split; hash set of V
   uint32_t* nsplit = nullptr;
   uint64_t *soff = nullptr, *vtab = nullptr, *total = nullptr;
-  uint32_t* vfilt = nullptr;
+  uint64_t* vfilt = nullptr;
   ScanTmp sc0;
 };
 template <class CV>
@@ -523,7 +527,7 @@ void plan_phase0(CV& cv, Phase0& p, int64_t nsrc, uint64_t vcap, int64_t fwords)
   p.nsplit = cv.template take<uint32_t>(nsrc + 1);
   p.soff = cv.template take<uint64_t>(nsrc + 1);
   p.vtab = cv.template take<uint64_t>(vcap);
-  p.vfilt = cv.template take<uint32_t>(fwords);
+  p.vfilt = cv.template take<uint64_t>(fwords);
   p.total = cv.template take<uint64_t>(4);
   p.sc0.carve(cv, nsrc + 1);
 }
@@ -567,7 +571,7 @@ int run_job(Job& J) {
   CHK(carve_region(AR, SL_V, [&](Carver& cv) { plan_phase0(cv, p0, nsrc, vcap, fwords); }));
   uint32_t* nsplit = p0.nsplit;
   uint64_t *soff = p0.soff, *vtab = p0.vtab, *total = p0.total;
-  uint32_t* vfilt = p0.vfilt;
+  uint64_t* vfilt = p0.vfilt;
   ScanTmp& sc0 = p0.sc0;
   uint32_t* dflag = X->dflag;
   uint32_t* counter = X->dflag + 1;
@@ -581,7 +585,7 @@ int run_job(Job& J) {
   V.mask = vcap - 1;
   V.filt = vfilt;
   V.fbits = fbits;
-  k_fill_u32<<<(int)std::min<int64_t>(4096, (fwords + 255) / 256), 256, 0, st>>>(vfilt, fwords, 0u);
+  k_fill_u64<<<(int)std::min<int64_t>(4096, (fwords + 255) / 256), 256, 0, st>>>(vfilt, fwords, 0ull);
   V.dets = J.dets;
   k_fill_u64<<<std::min<int64_t>(4096, (vcap + 255) / 256), 256, 0, st>>>(vtab, (int64_t)vcap, ~0ull);
   k_vset_insert<KW><<<(int)((J.ndet + 255) / 256), 256, 0, st>>>(V, J.ndet, n, dflag);
@@ -784,10 +788,12 @@ int run_job(Job& J) {
         const int pgrid = (int)(8 * ((ntiles + 7) / 8));
         k_part_hist<KW><<<pgrid, 256, 0, st>>>(pa);
         CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
+        if (pass < 8) HIPCHK(hipEventRecord(X->evp[2 * pass], st));
         if (pay)
           k_part_scatter<KW, VT, SAMPLE, true><<<pgrid, PTHREADS, 0, st>>>(pa);
         else
           k_part_scatter<KW, VT, SAMPLE, false><<<pgrid, PTHREADS, 0, st>>>(pa);
+        if (pass < 8) HIPCHK(hipEventRecord(X->evp[2 * pass + 1], st));
         HIPCHK(hipGetLastError());
         std::swap(cur, oth);
         shift += dbits;
@@ -893,6 +899,13 @@ int run_job(Job& J) {
     J.ms_k_write = ms;
     HIPCHK(hipEventElapsedTime(&ms, X->ev[8], X->ev[9]));
     J.ms_k_reduce = ms;
+    J.ms_k_part = 0;
+    for (int p = 0; p < std::min(npass, 8); ++p) {
+      HIPCHK(hipEventElapsedTime(&ms, X->evp[2 * p], X->evp[2 * p + 1]));
+      J.ms_k_part += ms;
+    }
+    J.n_part = npass;
+    J.n_part_rec = nrec * npass;
     J.nrec = nrec;
     J.kw = KW;
     J.vbytes = (int)sizeof(VT) * (SAMPLE ? 2 : 1);
@@ -997,6 +1010,9 @@ void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
   st->key_words = J.kw;
   st->value_bytes = J.vbytes;
   st->n_chunks = J.nbatch;
+  st->n_part_launches = J.n_part;
+  st->ms_k_part = J.ms_k_part;
+  st->n_part_records = J.n_part_rec;
 }
 
 // Records one pass may materialise: the record limit if set, else what free
@@ -1114,6 +1130,10 @@ int run_det_batched(const Job& proto, Job& acc) {
       acc.ms_k_count += J.ms_k_count;
       acc.ms_k_write += J.ms_k_write;
       acc.ms_k_reduce += J.ms_k_reduce;
+      acc.ms_k_part += J.ms_k_part;
+      acc.n_part += J.n_part;
+    acc.n_part_rec += J.n_part_rec;
+      acc.n_part_rec += J.n_part_rec;
       acc.nrec += J.nrec;
       acc.kw = J.kw;
       acc.vbytes = J.vbytes;
@@ -1337,6 +1357,8 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
   }
   for (auto& e : X->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+  for (auto& e : X->evp)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
   if (hipMemcpyAsync(T.h1, h1, n2 * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return bail(fail(SHCI_ERR_HIP, "copy of h1 failed"));
   k_fill_u32<<<1, 64, 0, st>>>(X->dflag, 16, 0u);
@@ -1355,6 +1377,8 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
   for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->evp)
     if (e) (void)hipEventDestroy(e);
   ctx->tables.release();
   for (auto& b : ctx->slot) b.release();
@@ -1694,6 +1718,9 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
     acc.ms_k_count += J.ms_k_count;
     acc.ms_k_write += J.ms_k_write;
     acc.ms_k_reduce += J.ms_k_reduce;
+    acc.ms_k_part += J.ms_k_part;
+    acc.n_part += J.n_part;
+    acc.n_part_rec += J.n_part_rec;
     acc.nrec += J.nrec;
     acc.kw = std::max(acc.kw, J.kw);
     acc.vbytes = J.vbytes;
@@ -1815,6 +1842,9 @@ int shci_pt2_det_batches(shci_pt2_ctx* ctx, const uint64_t* dets, const double* 
     acc.ms_k_count += J.ms_k_count;
     acc.ms_k_write += J.ms_k_write;
     acc.ms_k_reduce += J.ms_k_reduce;
+    acc.ms_k_part += J.ms_k_part;
+    acc.n_part += J.n_part;
+    acc.n_part_rec += J.n_part_rec;
     acc.nrec += J.nrec;
     acc.kw = J.kw;
     acc.vbytes = J.vbytes;

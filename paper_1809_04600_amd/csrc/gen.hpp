@@ -27,10 +27,11 @@ struct VSet {
   uint64_t* tab = nullptr;  // slots: fingerprint << 32 | index; ~0 = empty
   uint64_t mask = 0;
   const uint64_t* dets = nullptr;
-  // presence filter: bit (h >> (64 - fbits)) is set for every member.  It
-  // is small enough to stay in L2, and the lookups of one bucket (equal top
-  // hash bits) fall into the same few bytes of it.
-  uint32_t* filt = nullptr;
+  // presence filter (blocked, two bits per member in one 64-bit word):
+  // word h >> (64 - fbits), bits (h >> 20) & 63 and (h >> 26) & 63 are set
+  // for every member.  ~32 bits per member (false positives ~0.5%); the
+  // lookups of one bucket (equal top hash bits) fall into the same few words.
+  uint64_t* filt = nullptr;
   int fbits = 0;
 };
 

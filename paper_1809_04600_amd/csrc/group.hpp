@@ -454,12 +454,18 @@ struct RedArgs {
   double* contrib;          // keep-mode adjoint (nullable): contrib[pay] = t * 2 A_a / D_a (0 for a in V)
 };
 
-// membership of a packed determinant key (det bits only) in the hash set of V;
-// h is hash_key(k)
+// the two presence-filter bits of a determinant hash
+SHCI_DEV uint64_t vfilt_bits(uint64_t h) { return (1ull << ((h >> 20) & 63)) | (1ull << ((h >> 26) & 63)); }
+
+// false: certainly not in V; true: look the table up
+SHCI_DEV bool vfilt_maybe(const VSet& V, uint64_t h) {
+  const uint64_t m = vfilt_bits(h);
+  return (V.filt[h >> (64 - V.fbits)] & m) == m;
+}
+
+// membership in the hash set of V of a determinant that passed the filter
 template <int KW>
-SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
-  const uint64_t fb = h >> (64 - V.fbits);
-  if (!((V.filt[fb >> 5] >> (fb & 31)) & 1u)) return false;
+SHCI_DEV bool vset_probe(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
   uint64_t slot = h & V.mask;
   const uint32_t fp = (uint32_t)(h >> 32);
   for (uint64_t probe = 0; probe <= V.mask; ++probe) {
@@ -479,6 +485,13 @@ SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h
   return false;
 }
 
+// membership of a packed determinant key (det bits only) in the hash set of V;
+// h is det_hash(k)
+template <int KW>
+SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
+  return vfilt_maybe(V, h) && vset_probe<KW>(V, k, h, n);
+}
+
 template <int KW>
 SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
   return vset_contains_h<KW>(V, k, det_hash<KW>(k, n), n);
@@ -493,8 +506,7 @@ __global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
   const uint64_t h = det_hash<KW>(k, n);
   const uint32_t fp = (uint32_t)(h >> 32);
   const uint64_t entry = ((uint64_t)fp << 32) | (uint64_t)i;
-  const uint64_t fb = h >> (64 - V.fbits);
-  atomicOr(&V.filt[fb >> 5], 1u << (fb & 31));
+  atomicOr((unsigned long long*)&V.filt[h >> (64 - V.fbits)], (unsigned long long)vfilt_bits(h));
   uint64_t slot = h & V.mask;
   for (uint64_t probe = 0; probe <= V.mask; ++probe) {
     const unsigned long long old =

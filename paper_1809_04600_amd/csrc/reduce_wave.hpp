@@ -1,31 +1,36 @@
-// Bucket reduce, one wavefront per bucket.
+// Bucket reduce, one wavefront per bucket, in registers.
 //
-// After the hash partition a bucket holds on average 64-128 records (at most
-// WCAP are handled here).  A wavefront reads each record of its bucket from
-// memory exactly once, with coalesced loads: the key words and H_aa stay in
-// registers (lane = position mod 64), the values and the flag bit go to LDS by
-// position.  The 32-bit sort keys (24 hash bits below the bucket id, the
-// record's position in the low byte) are sorted by a bitonic network in
-// registers, so equal determinants become adjacent in record order; each
-// sorted element then takes its key and H_aa from the lane that holds them
-// (cross-lane reads), adjacent elements with equal sort bits are checked to
-// have equal keys, and each segment head sums its segment's values from LDS,
-// looks the determinant up in the hash set of V (hash from LDS) and adds the
-// contribution to per-lane accumulators.  No block-wide barrier is involved.
-// Buckets larger than WCAP, or in which two different determinants share all
-// sorted hash bits, are listed (and marked in a bitmap) for the block kernel
-// (k_reduce), which sorts by the full key.
+// After the hash partition a bucket holds on average 32-128 records; the
+// wavefront path takes buckets of at most WCAP = 128 (one or two records per
+// lane).  It reads each record of its bucket from memory exactly once, with
+// coalesced loads, and keeps everything in registers (no LDS): lane l holds
+// the records at positions l and 64 + l.  While the loads and the presence
+// filter words of V are in flight, 32-bit sort keys (24 hash bits below the
+// bucket id, the record's position in the low byte) are sorted by a bitonic
+// network across lanes, so equal determinants become adjacent in record
+// order; each sorted element then takes its key, value(s), flag, H_aa and
+// filter bit from the lane that holds them.  Adjacent elements with equal
+// sort bits are checked to have equal keys (otherwise the bucket goes to the
+// block kernel), and each segment head adds its members' values, read from
+// the following lanes in a loop as long as any segment of the wavefront
+// continues; a head looks its determinant up in the hash set of V only when
+// the filter does not rule it out, and adds the contribution to per-lane
+// accumulators.  Buckets larger than WCAP, or with two different
+// determinants sharing the sorted hash bits, are listed (and marked in a
+// bitmap) for the block kernel (k_reduce), which sorts by the full key.
 //
 // Partial sums: each wavefront writes its accumulators once (deterministic
 // mode) or once per sample it visited, zeros for the samples it skipped
 // (sample mode); block-kernel buckets write per-bucket partials, which the
 // final reduction reads through the bitmap in bucket order.
 #pragma once
+#include <type_traits>
+
 #include "group.hpp"
 
 namespace shci {
 
-constexpr int WCAP = 256;       // records per wavefront bucket
+constexpr int WCAP = 128;       // records per wavefront bucket
 constexpr int WRED_WAVES = 8;   // wavefronts per block
 
 // ascending bitonic sort of R*64 keys held as v[r] at element r*64 + lane
@@ -59,17 +64,6 @@ SHCI_DEV void wave_bitonic(uint32_t (&v)[R]) {
     }
   }
 }
-
-// per-wavefront LDS: the sorted keys of the current bucket, and by record
-// position the determinant hash, the value(s) and the flag bit
-template <typename VT, bool SAMPLE>
-struct WaveStage {
-  uint32_t sk[WCAP];
-  uint64_t h[WCAP];
-  VT v[WCAP];
-  VT v2[SAMPLE ? WCAP : 1];
-  uint8_t fl[WCAP];
-};
 
 struct WaveRedArgs {
   RedArgs r;
@@ -131,32 +125,45 @@ SHCI_DEV void wave_zero_partials(const Partials& P, int64_t b) {
 
 // value of register array v at element `pos` (element r*64 + lane of the
 // wavefront), read from the lane that holds it
-template <int R>
-SHCI_DEV uint64_t wave_fetch(const uint64_t (&v)[R], int pos) {
+template <int R, typename T>
+SHCI_DEV T wave_fetch(const T (&v)[R], int pos) {
   const int src = pos & 63;
-  uint64_t out = 0;
+  T out = v[0];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const uint64_t x = __shfl(v[r], src);
+    const T x = __shfl(v[r], src);
     out = ((pos >> 6) == r) ? x : out;
   }
   return out;
 }
 
-// value of v at the previous sorted element (element e - 1 for e = t*64 + lane)
-template <int R>
-SHCI_DEV uint64_t wave_prev(const uint64_t (&v)[R], int t) {
+// value of v at sorted element e + k (e = t*64 + lane, 1 <= k < 64; slot
+// t + 1 for the lanes that wrap; `fill` past the last slot)
+// (every lane executes both cross-lane reads: a lane that is not active
+// does not provide its value to them)
+template <int R, typename T>
+SHCI_DEV T wave_ahead(const T (&v)[R], int t, int k, T fill) {
   const int lane = lane_id();
-  uint64_t x = __shfl(v[t], (lane + 63) & 63);
-  if (lane == 0) x = (t > 0) ? __shfl(v[t > 0 ? t - 1 : 0], 63) : ~0ull;
-  return x;
+  const int src = (lane + k) & 63;
+  const T a = __shfl(v[t], src);
+  const T b = __shfl(v[t + 1 < R ? t + 1 : t], src);
+  return (lane + k < 64) ? a : ((t + 1 < R) ? b : fill);
+}
+
+// value of v at the previous sorted element (element e - 1 for e = t*64 + lane)
+template <int R, typename T>
+SHCI_DEV T wave_prev(const T (&v)[R], int t, T fill) {
+  const int lane = lane_id();
+  const T x = __shfl(v[t], (lane + 63) & 63);
+  const T y = __shfl(v[t > 0 ? t - 1 : 0], 63);
+  return lane > 0 ? x : (t > 0 ? y : fill);
 }
 
 // Returns false if the bucket was handed to the block kernel.  Contributions
 // accumulate in acc (per lane).
 template <int KW, int R, bool SAMPLE, typename VT>
-SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b, int64_t lo, int M,
-                          const WaveRedArgs& A, SegAcc& acc) {
+SHCI_DEV bool wave_bucket(const RedArgs& a, int64_t b, int64_t lo, int M, const WaveRedArgs& A, SegAcc& acc) {
+  using VB = typename std::conditional<sizeof(VT) == 4, uint32_t, uint64_t>::type;  // value bits
   const int lane = lane_id();
   const int n = a.n;
   const int bh = a.G.bits_hash;
@@ -164,15 +171,17 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
   const uint64_t am = 1ull << (a.auxbit & 63);
   const VT* vin = static_cast<const VT*>(a.in.v);
   const VT* v2in = static_cast<const VT*>(a.in.v2);
-  // ---- stage: every record read once ----
-  uint64_t kr[KW][R];  // key words (flag bit cleared) by position
-  uint64_t hr[R];      // H_aa bits by position
-  uint32_t sk[R];
+  // ---- stage: every record read once, by position ----
+  uint64_t kr[KW][R], hr[R], hh[R];
+  VB vr[R], v2r[R];
+  uint32_t fr[R], sk[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = r * 64 + lane;
     sk[r] = ~0u;
-    hr[r] = 0;
+    hr[r] = hh[r] = 0;
+    vr[r] = v2r[r] = 0;
+    fr[r] = 0;
 #pragma unroll
     for (int w = 0; w < KW; ++w) kr[w][r] = 0;
     if (j < M) {
@@ -181,34 +190,38 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
       uint64_t fw = 0;
 #pragma unroll
       for (int w = 0; w < KW; ++w) fw = (w == aw) ? k[w] : fw;
-      W.fl[j] = (fw & am) ? 1 : 0;
       clear_aux<KW>(k, a.auxbit);
 #pragma unroll
       for (int w = 0; w < KW; ++w) kr[w][r] = k[w];
       const uint64_t h = det_hash<KW>(k, n);
-      W.h[j] = h;
-      W.v[j] = vin[lo + j];
-      if constexpr (SAMPLE) W.v2[j] = v2in[lo + j];
-      hr[r] = __double_as_longlong(a.in.haa[lo + j]);
+      hh[r] = h;
+      const uint64_t fm = vfilt_bits(h);
+      const uint64_t fword = a.V.filt[h >> (64 - a.V.fbits)];
+      fr[r] = ((fw & am) ? 1u : 0u) | (((fword & fm) == fm) ? 2u : 0u);
+      vr[r] = __builtin_bit_cast(VB, vin[lo + j]);
+      if constexpr (SAMPLE) v2r[r] = __builtin_bit_cast(VB, v2in[lo + j]);
+      hr[r] = (uint64_t)__double_as_longlong(a.in.haa[lo + j]);
       sk[r] = ((uint32_t)((h << bh) >> 32) & ~0xffu) | (uint32_t)j;
     }
   }
   wave_bitonic<R>(sk);
-#pragma unroll
-  for (int r = 0; r < R; ++r) W.sk[r * 64 + lane] = sk[r];
-  // ---- key and H_aa of each sorted element ----
-  uint64_t ks[KW][R], hs[R];
-  uint32_t psk[R];
+  // ---- every sorted element takes its record from the lane that holds it ----
+  uint64_t ks[KW][R], hs[R], hsh[R];
+  VB vs[R], v2s[R];
+  uint32_t fs[R], psk[R];
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int pos = (int)(sk[t] & 0xffu);
 #pragma unroll
     for (int w = 0; w < KW; ++w) ks[w][t] = wave_fetch<R>(kr[w], pos);
     hs[t] = wave_fetch<R>(hr, pos);
-    uint32_t p = (uint32_t)__shfl((int)sk[t], (lane + 63) & 63);
-    if (lane == 0) p = (t > 0) ? (uint32_t)__shfl((int)sk[t > 0 ? t - 1 : 0], 63) : ~0u;
-    psk[t] = p;
+    hsh[t] = wave_fetch<R>(hh, pos);
+    vs[t] = wave_fetch<R>(vr, pos);
+    if constexpr (SAMPLE) v2s[t] = wave_fetch<R>(v2r, pos);
+    fs[t] = wave_fetch<R>(fr, pos);
   }
+#pragma unroll
+  for (int t = 0; t < R; ++t) psk[t] = wave_prev<R>(sk, t, ~0u);
   // ---- equal sort bits must mean equal determinants ----
   bool clash = false;
 #pragma unroll
@@ -218,7 +231,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
     if (ballot(same)) {
 #pragma unroll
       for (int w = 0; w < KW; ++w) {
-        const uint64_t pk = wave_prev<R>(ks[w], t);
+        const uint64_t pk = wave_prev<R>(ks[w], t, ~(uint64_t)0);
         clash = clash || (same && pk != ks[w][t]);
       }
     }
@@ -230,10 +243,7 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
     }
     return false;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // ---- segments: heads sum from LDS ----
+  // ---- segments: each head adds the values of the following lanes ----
   int nbefore = 0;
 #pragma unroll
   for (int t = 0; t < R; ++t) {
@@ -241,29 +251,42 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
     const uint32_t s0 = sk[t];
     const bool head = e0 < M && (e0 == 0 || (s0 >> 8) != (psk[t] >> 8));
     const uint64_t hb = ballot(head);
+    SegSum<VT> sum;
     if (head) {
-      int e1 = e0 + 1;
-      while (e1 < M && (W.sk[e1] >> 8) == (s0 >> 8)) ++e1;
-      const int first = (int)(s0 & 0xffu);
-      SegSum<VT> sum;
-      for (int e = e0; e < e1; ++e) {
-        const int id = (e == e0) ? first : (int)(W.sk[e] & 0xffu);
-        if constexpr (SAMPLE)
-          sum.add_sample(W.v[id], W.v2[id], W.fl[id] != 0);
-        else
-          sum.add(W.v[id], W.fl[id] != 0);
+      if constexpr (SAMPLE)
+        sum.add_sample(__builtin_bit_cast(VT, vs[t]), __builtin_bit_cast(VT, v2s[t]), (fs[t] & 1u) != 0);
+      else
+        sum.add(__builtin_bit_cast(VT, vs[t]), (fs[t] & 1u) != 0);
+    }
+    int cnt = 1;
+    bool open = head;
+    for (int k = 1; k < 64 * R; ++k) {
+      const uint32_t sa = wave_ahead<R>(sk, t, k, ~0u);
+      open = open && (e0 + k < M) && (sa >> 8) == (s0 >> 8);
+      if (!ballot(open)) break;
+      const VB va = wave_ahead<R>(vs, t, k, (VB)0);
+      const uint32_t fa = wave_ahead<R>(fs, t, k, 0u);
+      if constexpr (SAMPLE) {
+        const VB va2 = wave_ahead<R>(v2s, t, k, (VB)0);
+        if (open) sum.add_sample(__builtin_bit_cast(VT, va), __builtin_bit_cast(VT, va2), (fa & 1u) != 0);
+      } else {
+        if (open) sum.add(__builtin_bit_cast(VT, va), (fa & 1u) != 0);
       }
+      cnt += open ? 1 : 0;
+    }
+    bool inv = false;
+    double g = 0.0;
+    if (head) {
       sum.finish();
       const double X = sum.X;
       uint64_t k[KW], dk[KW];
 #pragma unroll
       for (int w = 0; w < KW; ++w) k[w] = dk[w] = ks[w][t];
       mask_det<KW>(dk, n);  // determinant bits only (no sample id)
-      const uint64_t h = W.h[first];
-      const bool inv = vset_contains_h<KW>(a.V, dk, h, n);
-      const int cntk = e1 - e0;
-      acc.ngen += cntk;
-      double Dd = 0.0, g = 0.0, gd = 0.0, gG = 0.0;
+      const uint64_t h = hsh[t];
+      inv = (fs[t] & 2u) && vset_probe<KW>(a.V, dk, h, n);
+      acc.ngen += cnt;
+      double Dd = 0.0, gd = 0.0, gG = 0.0;
       if (!inv) {
         const double haa = __longlong_as_double((long long)hs[t]);
         Dd = a.e0 - haa;
@@ -286,19 +309,11 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
         }
         acc.e2p += contrib;
         acc.e2sq += contrib * contrib;
-        acc.nterm += cntk;
+        acc.nterm += cnt;
         acc.nuniq += 1;
         acc.nintr += Dd > 0.0;
         acc.nzero += Dd == 0.0;
         acc.dmn = fmin(acc.dmn, fabs(Dd));
-      }
-      if constexpr (!SAMPLE) {
-        if (a.contrib) {
-          for (int e = e0; e < e1; ++e) {
-            const int id = (e == e0) ? first : (int)(W.sk[e] & 0xffu);
-            a.contrib[a.in.pay[lo + id]] = inv ? 0.0 : (double)W.v[id] * g;
-          }
-        }
       }
       if (a.want_u) {
         const int64_t o = lo + nbefore + rank_below(hb);
@@ -310,7 +325,22 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
         a.U.A[o] = SAMPLE ? gd : X;
         a.U.D[o] = SAMPLE ? gG : Dd;
         a.U.g[o] = g;
-        a.U.cnt[o] = inv ? -cntk : cntk;
+        a.U.cnt[o] = inv ? -cnt : cnt;
+      }
+    }
+    if constexpr (!SAMPLE) {
+      // keep-mode adjoint: every record of the segment gets t * 2 A_a / D_a
+      if (a.contrib) {
+        const uint32_t pos0 = sk[t] & 0xffu;
+        if (head) a.contrib[a.in.pay[lo + pos0]] = inv ? 0.0 : (double)__builtin_bit_cast(VT, vs[t]) * g;
+        bool op = head;
+        for (int k = 1; k < 64 * R; ++k) {
+          const uint32_t sa = wave_ahead<R>(sk, t, k, ~0u);
+          op = op && (e0 + k < M) && (sa >> 8) == (s0 >> 8);
+          if (!ballot(op)) break;
+          const VB va = wave_ahead<R>(vs, t, k, (VB)0);
+          if (op) a.contrib[a.in.pay[lo + (sa & 0xffu)]] = inv ? 0.0 : (double)__builtin_bit_cast(VT, va) * g;
+        }
       }
     }
     nbefore += __popcll(hb);
@@ -325,12 +355,10 @@ SHCI_DEV bool wave_bucket(const RedArgs& a, WaveStage<VT, SAMPLE>& W, int64_t b,
 template <int KW, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(64 * WRED_WAVES) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_reduce_wave(WaveRedArgs A) {
-  __shared__ WaveStage<VT, SAMPLE> WS[WRED_WAVES];
   const RedArgs& a = A.r;
   const int t = threadIdx.x;
   const int wv = t >> 6;
   const int lane = t & 63;
-  WaveStage<VT, SAMPLE>& W = WS[wv];
   const int64_t wave = (int64_t)blockIdx.x * WRED_WAVES + wv;
   const int bh = a.G.bits_hash;
   SegAcc acc;
@@ -339,7 +367,18 @@ k_reduce_wave(WaveRedArgs A) {
   // sample into slot [sample][wave], zeros into the slots of samples it
   // skips
   int64_t cur_s = -1, next_s = 0;
+  int64_t lo_n = 0, hi_n = 0;  // bounds of the next bucket, loaded one bucket ahead
+  if (wave < a.G.nbucket) {
+    lo_n = (int64_t)A.bstart[wave];
+    hi_n = (int64_t)A.bstart[wave + 1];
+  }
   for (int64_t b = wave; b < a.G.nbucket; b += A.nwaves) {
+    const int64_t lo = lo_n, M = hi_n - lo_n;
+    const int64_t bn = b + A.nwaves;
+    if (bn < a.G.nbucket) {
+      lo_n = (int64_t)A.bstart[bn];
+      hi_n = (int64_t)A.bstart[bn + 1];
+    }
     if constexpr (SAMPLE) {
       const int64_t s = b >> bh;
       if (s != cur_s) {
@@ -354,8 +393,6 @@ k_reduce_wave(WaveRedArgs A) {
         cur_s = s;
       }
     }
-    const int64_t lo = (int64_t)A.bstart[b];
-    const int64_t M = (int64_t)A.bstart[b + 1] - lo;
     if (M > WCAP) {
       if (lane == 0) {
         A.slow_list[atomicAdd(A.slow_count, 1u)] = (uint32_t)b;
@@ -371,14 +408,9 @@ k_reduce_wave(WaveRedArgs A) {
       continue;
     }
     if (M <= 64)
-      wave_bucket<KW, 1, SAMPLE, VT>(a, W, b, lo, (int)M, A, acc);
-    else if (M <= 128)
-      wave_bucket<KW, 2, SAMPLE, VT>(a, W, b, lo, (int)M, A, acc);
+      wave_bucket<KW, 1, SAMPLE, VT>(a, b, lo, (int)M, A, acc);
     else
-      wave_bucket<KW, 4, SAMPLE, VT>(a, W, b, lo, (int)M, A, acc);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_bucket<KW, 2, SAMPLE, VT>(a, b, lo, (int)M, A, acc);
   }
   if constexpr (SAMPLE) {
     if (cur_s >= 0) {

@@ -86,8 +86,8 @@ def run_samples(x) -> dict:
     wl = x.wl
     t = time.time()
     draws = ref.alias_draws(x.c, wl.n_samples, wl.n_draws, wl.draw_seed)
-    out = ref.pt2_sample(wl.n_orb, wl.n_alpha, wl.n_beta, x.h1, x.eri, x.dets, x.c, x.e0,
-                         wl.eps2_sto, wl.eps2, draws)
+    out, cnt = ref.pt2_sample_counts(wl.n_orb, wl.n_alpha, wl.n_beta, x.h1, x.eri, x.dets, x.c, x.e0,
+                                     wl.eps2_sto, wl.eps2, draws)
     dt = time.time() - t
     return {
         "workload": "w3",
@@ -99,6 +99,8 @@ def run_samples(x) -> dict:
         "seed": wl.draw_seed,
         "draws_digest": hashlib.sha256(np.ascontiguousarray(draws, dtype="<u4").tobytes()).hexdigest(),
         "per_sample": [float(v) for v in out],
+        "per_sample_terms": [int(v) for v in cnt],
+        "n_terms": int(cnt.sum()),
         "mean": float(np.mean(out)),
         "oracle_seconds": dt,
         "oracle_threads": ref.max_threads(),

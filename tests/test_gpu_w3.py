@@ -1,114 +1,135 @@
 """The 76-orbital, 10^6-determinant semistochastic workload (w3) at full
-size, in the launch configuration of the benchmark.  The CPU reference cannot
-evaluate the whole sums in seconds here, so parity is checked on sampled
-outputs it can compute one by one (A_a, D_a and term counts of sampled a;
-every kept term of sampled sources; whole per-sample estimates of sampled
-samples) and through properties that hold at any size."""
-import math
+size, against stored oracle results (tests/golden/w3_*_oracle.json, written
+by tests/golden/make_w3_oracle.py from oracle/ alone).
+
+Deterministic part at eps2^d (screened PT2 equation): the whole set of
+perturbative determinants with their kept-term counts (SHA-256 of the sorted
+keys and counts) and the term counts bit-exact, E2 within 1e-9 Ha in FP64 and
+1e-6 Ha in FP32c, and 1024 determinants spread over the sorted set with A_a
+and E0 - H_aa.  Stochastic part (stochastic PT2 equation): the seed path's
+draws bit-exact (digest), the total kept-term count exact, and all 256
+per-sample estimates within 1e-9 relative (FP64) and 1e-6 Ha (FP32c).
+"""
+import hashlib
+import json
+import os
 
 import numpy as np
 import pytest
 import torch
 
-from oracle import ref
 from synth import store
-from tests.gpu_util import context, keys_np, sort_keys
+from tests.gpu_util import context
 
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DET_GOLD = os.path.join(HERE, "golden", "w3_det_oracle.json")
+SMP_GOLD = os.path.join(HERE, "golden", "w3_samples_oracle.json")
 
 
 @pytest.fixture(scope="module")
 def w3():
     x = store.load("w3")
     ctx, dets, c = context(x)
-    return x, ctx, dets, c
+    yield x, ctx, dets, c
+    ctx.close()
 
 
-def _draws(x):
-    wl = x.wl
-    p = np.abs(x.c) / np.abs(x.c).sum()
-    return np.random.default_rng(wl.draw_seed).choice(len(x.c), size=(wl.n_samples, wl.n_draws),
-                                                      p=p).astype(np.uint32)
+def _sorted_unique(u):
+    """GPU-exported unique keys and counts in ascending (word 3, ..., word 0)
+    order: stable sorts from the least significant word (unsigned order via
+    the sign-bit flip)."""
+    keys = u["keys"]
+    cnt = u["cnt"]
+    n = keys.shape[0]
+    perm = torch.arange(n, device=keys.device)
+    flip = torch.tensor(-(2 ** 63), dtype=torch.int64, device=keys.device)
+    for w in range(4):
+        k = keys[perm, w] ^ flip
+        _, idx = torch.sort(k, stable=True)
+        perm = perm[idx]
+    return keys[perm].cpu().numpy().view(np.uint64), cnt[perm].cpu().numpy().astype(np.int64), perm
 
 
-def test_w3_deterministic_part(w3):
+def _find(sorted_keys, key):
+    lo, hi = 0, len(sorted_keys)
+    t = tuple(int(v) for v in key[::-1])
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if tuple(int(v) for v in sorted_keys[mid][::-1]) < t:
+            lo = mid + 1
+        else:
+            hi = mid
+    return lo
+
+
+def test_w3_deterministic_part_vs_stored_oracle(w3):
+    with open(DET_GOLD) as f:
+        g = json.load(f)
     x, ctx, dets, c = w3
     wl = x.wl
-    n, na, nb = wl.n_orb, wl.n_alpha, wl.n_beta
-    r = ctx.det(dets, c, x.e0, wl.eps2, "fp64", unique_cap=60_000_000)
+    assert g["eps2"] == wl.eps2 and g["e0"] == x.e0
+    r = ctx.det(dets, c, x.e0, wl.eps2, "fp64", unique_cap=g["n_unique"] + 1024)
     st = r.stats
-    print(f"w3 det: E2={r.e2!r} stats={st}", flush=True)
+    print(f"w3 det: E2 gpu={r.e2!r} oracle={g['e2']!r} |d|={abs(r.e2 - g['e2']):.3e} stats={st}", flush=True)
+    for k in ("n_terms", "n_terms_gen", "n_unique", "n_intruder"):
+        assert st[k] == g[k], k
+    assert abs(r.e2 - g["e2"]) <= 1e-9
+    assert abs(st["min_abs_denom"] - g["min_abs_denom"]) <= 1e-12 * max(1.0, abs(x.e0))
     u = r.unique
-    nu = u["n"]
-    assert nu == st["n_unique"]
-    keys = keys_np(u["keys"])
-    A = u["A"].cpu().numpy()
-    D = u["D"].cpu().numpy()
-    cnt = u["cnt"].cpu().numpy()
-    # properties: counts add up, E2 is the sum of the exported contributions
-    assert int(cnt.astype(np.int64).sum()) == st["n_terms"]
-    assert (cnt > 0).all()
-    e2_host = math.fsum((A * A / D).tolist())
-    assert abs(e2_host - r.e2) <= 1e-9
-    assert int((D > 0).sum()) == st["n_intruder"]
-    assert np.abs(D).min() == st["min_abs_denom"]
-    # sampled a: A_a, D_a and counts one by one
-    rng = np.random.default_rng(31)
-    pick = rng.choice(nu, size=400, replace=False)
-    oA, oD, oc, inv = ref.pt2_at(n, na, nb, x.h1, x.eri, x.dets, x.c, x.e0, wl.eps2, keys[pick])
-    assert not inv.any()
-    assert np.array_equal(cnt[pick], oc)
-    assert np.abs(A[pick] - oA).max() <= 1e-13 * max(1.0, np.abs(oA).max())
-    assert np.abs(D[pick] - oD).max() <= 1e-12 * np.abs(oD).max()
-    # sampled sources (HF, a large MP1 double, random others): every kept term
-    # with a outside V reaches a unique a of the export
-    big = int(np.argsort(-np.abs(x.c[1:]))[0]) + 1
-    srcs = np.concatenate([[0, big], rng.choice(len(x.c), size=60, replace=False)])
-    tk, th, tw = ref.terms_of(n, na, nb, x.h1, x.eri, x.dets, x.c, wl.eps2, srcs)
-    print(f"sampled sources: {len(srcs)}, kept terms {len(tk)}", flush=True)
-    order = sort_keys(keys)
-    sk = keys[order]
-    ok = sort_keys(tk)
-    tks = tk[ok]
-    # merge: every term key must be present among the unique keys
-    j = 0
-    missing = 0
-    for row in tks:
-        while j < len(sk) and tuple(sk[j][::-1]) < tuple(row[::-1]):
-            j += 1
-        if j >= len(sk) or not np.array_equal(sk[j], row):
-            missing += 1
-    assert missing == 0
-    # FP32-compensated form against FP64 at full size
+    assert u["n"] == g["n_unique"]
+    keys, cnt, perm = _sorted_unique(u)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(keys, dtype="<u8").tobytes())
+    h.update(np.ascontiguousarray(cnt, dtype="<i8").tobytes())
+    assert h.hexdigest() == g["unique_digest"]
+    # sampled determinants: A_a and E0 - H_aa
+    A = u["A"][perm].cpu().numpy()
+    D = u["D"][perm].cpu().numpy()
+    smp = g["sampled"]
+    gk = np.array([[int(w, 16) for w in k] for k in smp["keys"]], dtype=np.uint64)
+    gA, gD = np.array(smp["A"]), np.array(smp["D"])
+    for j, k in enumerate(gk):
+        i = _find(keys, k)
+        assert i == smp["index"][j] and np.array_equal(keys[i], k)
+        assert cnt[i] == smp["count"][j]
+    idx = np.array(smp["index"])
+    assert np.abs(A[idx] - gA).max() <= 1e-13 * max(1.0, np.abs(gA).max())
+    assert np.abs(D[idx] - gD).max() <= 1e-12 * np.abs(gD).max()
+    # FP32-compensated form against the oracle at full size
     r32 = ctx.det(dets, c, x.e0, wl.eps2, "fp32c")
-    print(f"w3 det fp32c: |dE2| vs fp64 = {abs(r32.e2 - r.e2):.3e}", flush=True)
-    assert abs(r32.e2 - r.e2) <= 1e-6
-    assert r32.stats["n_terms"] == st["n_terms"] and r32.stats["n_unique"] == st["n_unique"]
+    print(f"w3 det fp32c: |dE2| vs oracle = {abs(r32.e2 - g['e2']):.3e}", flush=True)
+    assert abs(r32.e2 - g["e2"]) <= 1e-6
+    for k in ("n_terms", "n_terms_gen", "n_unique", "n_intruder"):
+        assert r32.stats[k] == g[k], k
 
 
-def test_w3_samples(w3):
+@pytest.mark.skipif(not os.path.exists(SMP_GOLD), reason="stored oracle samples not written")
+def test_w3_samples_vs_stored_oracle(w3):
+    with open(SMP_GOLD) as f:
+        g = json.load(f)
     x, ctx, dets, c = w3
     wl = x.wl
-    n, na, nb = wl.n_orb, wl.n_alpha, wl.n_beta
-    draws = _draws(x)
-    dr = torch.from_numpy(draws.view(np.int32)).cuda()
-    out, mean, sem, st = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp64")
+    ns, nd, seed = g["n_samples"], g["n_draws"], g["seed"]
+    assert (ns, nd, seed) == (wl.n_samples, wl.n_draws, wl.draw_seed)
+    d = ctx.draws(c, ns, nd, seed).cpu().numpy().astype(np.uint32)
+    assert hashlib.sha256(np.ascontiguousarray(d, dtype="<u4").tobytes()).hexdigest() == g["draws_digest"]
+    want = np.array(g["per_sample"])
+    out, mean, sem, st = ctx.sample(dets, c, x.e0, g["eps2"], g["eps2_d"], None, "fp64", seed=seed, n_samples=ns,
+                                    n_draws=nd)
     out = out.cpu().numpy()
-    print(f"w3 samples: mean {mean!r} +- {sem!r}, stats {st}", flush=True)
-    assert np.isfinite(out).all()
-    assert 0.0 < st["min_abs_denom"] < 1e-3  # intruder-rich: stated with the results
-    assert abs(mean - out.mean()) <= 1e-15 * max(1.0, abs(mean))
-    # two whole samples against the CPU reference
-    for s in (0, 137):
-        o = ref.pt2_sample(n, na, nb, x.h1, x.eri, x.dets, x.c, x.e0, wl.eps2_sto, wl.eps2,
-                           draws[s:s + 1])
-        print(f"sample {s}: gpu {out[s]!r} reference {o[0]!r}", flush=True)
-        assert abs(out[s] - o[0]) <= 1e-9 * max(1.0, abs(o[0]))
-    out32, mean32, _, _ = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp32c")
-    out32 = out32.cpu().numpy()
-    print(f"w3 samples fp32c: max |d| per sample {np.abs(out32 - out).max():.3e}, "
-          f"|d mean| {abs(mean32 - mean):.3e}", flush=True)
-    assert np.abs(out32 - out).max() <= 1e-6
+    err = np.abs(out - want) / np.maximum(1.0, np.abs(want))
+    print(f"w3 samples: mean {mean!r} oracle {g['mean']!r}; max rel per-sample err {err.max():.3e}; "
+          f"terms {st['n_terms']} oracle {g['n_terms']}", flush=True)
+    assert st["n_terms"] == g["n_terms"]
+    assert err.max() <= 1e-9
+    out32, _, _, st32 = ctx.sample(dets, c, x.e0, g["eps2"], g["eps2_d"], None, "fp32c", seed=seed, n_samples=ns,
+                                   n_draws=nd)
+    e32 = np.abs(out32.cpu().numpy() - want).max()
+    print(f"w3 samples fp32c: max per-sample |d| vs oracle {e32:.3e}", flush=True)
+    assert st32["n_terms"] == g["n_terms"]
+    assert e32 <= 1e-6
 
 
 def test_w3_sample_adjoint_properties(w3):
@@ -116,16 +137,34 @@ def test_w3_sample_adjoint_properties(w3):
     # (degree-2 homogeneous at frozen draws, p and masks) and FP32c vs FP64
     x, ctx, dets, c = w3
     wl = x.wl
-    draws = _draws(x)[:8]
-    dr = torch.from_numpy(np.ascontiguousarray(draws).view(np.int32)).cuda()
-    out, mean, sem, g, de0, st = ctx.sample_grad(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp64")
+    kw = dict(seed=wl.draw_seed, n_samples=8, n_draws=wl.n_draws)
+    out, mean, sem, g, de0, st = ctx.sample_grad(dets, c, x.e0, wl.eps2_sto, wl.eps2, None, "fp64", **kw)
     g = g.cpu().numpy()
     euler = float(np.dot(x.c, g))
     print(f"w3 sample adjoint: mean {mean!r}, c.g/2 {euler / 2!r}, dE0 {de0!r}, stats {st}", flush=True)
     assert abs(euler - 2.0 * mean) <= 1e-8 * max(abs(mean), 1e-12)
-    o8 = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp64")[0].cpu().numpy()
+    o8 = ctx.sample(dets, c, x.e0, wl.eps2_sto, wl.eps2, None, "fp64", **kw)[0].cpu().numpy()
     assert np.abs(out.cpu().numpy() - o8).max() <= 1e-12 * max(1.0, np.abs(o8).max())
-    _, _, _, g32, _, _ = ctx.sample_grad(dets, c, x.e0, wl.eps2_sto, wl.eps2, dr, "fp32c")
+    _, _, _, g32, _, _ = ctx.sample_grad(dets, c, x.e0, wl.eps2_sto, wl.eps2, None, "fp32c", **kw)
     rel = np.linalg.norm(g32.cpu().numpy() - g) / np.linalg.norm(g)
     print(f"w3 sample adjoint fp32c rel diff {rel:.3e}", flush=True)
     assert rel <= 1e-6
+
+
+def test_w3_gradient_modes(w3):
+    # deterministic adjoint at eps2^d: keep and recompute agree, Euler identity
+    x, ctx, dets, c = w3
+    wl = x.wl
+    e2k, gk, dk, stk = ctx.grad(dets, c, x.e0, wl.eps2, "fp64", mode="keep")
+    e2r, gr, dr, _ = ctx.grad(dets, c, x.e0, wl.eps2, "fp64", mode="recompute")
+    gk, gr = gk.cpu().numpy(), gr.cpu().numpy()
+    with open(DET_GOLD) as f:
+        gold = json.load(f)
+    print(f"w3 grad: E2 {e2k!r}, dE0 {dk!r} (oracle {gold['de2_de0']!r}), keep vs recompute "
+          f"{np.linalg.norm(gk - gr) / np.linalg.norm(gr):.3e}", flush=True)
+    assert e2k == e2r
+    assert np.linalg.norm(gk - gr) <= 1e-12 * np.linalg.norm(gr)
+    assert abs(np.dot(x.c, gk) - 2.0 * e2k) <= 1e-9 * abs(e2k)
+    # -sum A^2/D^2 is dominated by the smallest denominators (min |D| = 2e-6 Ha),
+    # whose relative rounding is ~1e-14 Ha / |D|: a looser relative bar
+    assert abs(dk - gold["de2_de0"]) <= 1e-6 * abs(gold["de2_de0"])

@@ -215,6 +215,19 @@ int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64
                  double e0, double eps2, int precision, void* ws, size_t ws_bytes, void* stream, double* e2,
                  shci_pt2_stats* st, shci_pt2_export* ex);
 
+/* shci_pt2_det for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * call allocates and frees nothing: its workspace is a fixed 128 MiB device
+ * array in the library (one per GPU, held until the process ends, its address
+ * taken once per device when a context is created there).  Terms that do not
+ * fit it are split into hash batches as in shci_pt2_det (at most 256).
+ * n_det <= 500000, else SHCI_ERR_WORKSPACE; SHCI_ERR_WORKSPACE also when one
+ * batch does not fit.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must not be
+ * issued.  Arguments and results as shci_pt2_det (no export). */
+int shci_pt2_det_static(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                        double eps2, int precision, void* stream, double* e2, shci_pt2_stats* st);
+
 /* Stochastic part of the semistochastic PT2 (semistochastic and stochastic
  * PT2 equations).  For each sample s of n_draws draws (indices into V, drawn
  * with replacement with p_i = |c_i| / sum_j |c_j|, the sampling-probability

@@ -96,6 +96,8 @@ def lib():
         L.shci_pt2_det.argtypes = [p, p, p, i64, d, d, i, p, sz, p, C.POINTER(d), C.POINTER(Stats),
                                    C.POINTER(Export)]
         L.shci_pt2_det.restype = i
+        L.shci_pt2_det_static.argtypes = [p, p, p, i64, d, d, i, p, C.POINTER(d), C.POINTER(Stats)]
+        L.shci_pt2_det_static.restype = i
         L.shci_pt2_sample.argtypes = [p, p, p, i64, d, d, d, i32, i32, p, u64, i, p, sz, p, p,
                                       C.POINTER(d), C.POINTER(d), C.POINTER(Stats)]
         L.shci_pt2_sample.restype = i
@@ -261,6 +263,15 @@ class Context:
             r.terms = {"n": ex.t_n, "keys": bufs["t_keys"][:m], "i": bufs["t_i"][:m],
                        "val": bufs["t_val"][:m]}
         return r
+
+    def det_static(self, dets, c, e0, eps2, precision="fp64"):
+        """shci_pt2_det on the library's fixed device workspace (no allocation)."""
+        pd, pc, nd = self._inputs(dets, c)
+        e2 = C.c_double()
+        st = Stats()
+        _check(lib().shci_pt2_det_static(self._ptr, pd, pc, nd, float(e0), float(eps2), _PREC[precision],
+                                         _stream(), C.byref(e2), C.byref(st)))
+        return DetResult(e2.value, st.as_dict())
 
     def grad(self, dets, c, e0, eps2, precision="fp64", mode="auto", ws=None):
         """E2, dE2/dc (device tensor), dE2/dE0, stats.  mode: "auto", "keep"

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1150,7 +1151,41 @@ int run_det_batched(const Job& proto, Job& acc) {
 
 }  // namespace
 
+// Workspace of shci_pt2_det_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name as
+// an address: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current (at context creation).
+constexpr size_t STATIC_WS_BYTES = (size_t)128 << 20;
+constexpr int64_t STATIC_WS_MAX_DETS = 500000;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on device `dev`, which must be current; the
+// symbol lookup runs once per device
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(SHCI_ERR_HIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_err[dev] = e;
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  if (g_scratch_err[dev] != hipSuccess)
+    return fail(SHCI_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                hipGetErrorString(g_scratch_err[dev]));
+  *out = g_scratch_ptr[dev];
+  return SHCI_OK;
+}
 
 int ws_check(const void* ws, size_t ws_bytes) {
   if (ws && ((uintptr_t)ws & (WS_ALIGN - 1)))
@@ -1315,6 +1350,13 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     return code;
   };
   if (hipGetDevice(&X->device) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipGetDevice failed"));
+  {
+    // set-up of the allocation-free entry point on this device (its errors
+    // are reported by that entry point)
+    void* sp = nullptr;
+    (void)scratch_address(X->device, &sp);
+    g_msg[0] = 0;
+  }
   Tables& T = X->T;
   const int n = n_orb;
   T.n = n;
@@ -1489,6 +1531,17 @@ int shci_pt2_det(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64
   if (R.res.nzero) return fail(SHCI_ERR_SINGULAR, "%lld kept determinants have E0 - H_aa == 0",
                                (long long)R.res.nzero);
   return SHCI_OK;
+}
+
+int shci_pt2_det_static(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,
+                        double eps2, int precision, void* stream, double* e2, shci_pt2_stats* st) {
+  CHK(common_checks(ctx, dets, c, n_det, e0, eps2, precision));
+  if (n_det > STATIC_WS_MAX_DETS)
+    return fail(SHCI_ERR_WORKSPACE, "shci_pt2_det_static takes at most %lld determinants (got %lld)",
+                (long long)STATIC_WS_MAX_DETS, (long long)n_det);
+  void* ws = nullptr;
+  CHK(scratch_address(ctx->device, &ws));
+  return shci_pt2_det(ctx, dets, c, n_det, e0, eps2, precision, ws, STATIC_WS_BYTES, stream, e2, st, nullptr);
 }
 
 int shci_pt2_grad(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c, int64_t n_det, double e0,

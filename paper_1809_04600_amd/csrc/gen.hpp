@@ -156,6 +156,10 @@ SHCI_DEV void gen_body(const GenArgs& a) {
     const double absc = fabs(ci);
     double pr = 1.0;
     if constexpr (SAMPLE) pr = absc / a.sum_abs;
+    // per-source factors of the stochastic estimator: x = (w / p) c H and
+    // z = (w (N_d - 1) / p) (c H)^2 (the divisions once per source)
+    const double wp = SAMPLE ? w / pr : 1.0;
+    const double wq = SAMPLE ? w * (a.nd - 1.0) / pr : 1.0;
 
     // occupied / virtual lists of both spins in LDS (wave-private)
     {
@@ -250,8 +254,8 @@ SHCI_DEV void gen_body(const GenArgs& a) {
             if (fabs(H) * absc > a.eps2_d) put_bits<KW>(key, 1ull, 0ull, a.auxbit);
             const double ch = ci * H;
             // x and z = x^2 + y of the stochastic estimator (see SegSum)
-            const double xv = w * ch / pr;
-            const double zv = (w * (a.nd - 1.0) / pr) * ch * ch;
+            const double xv = wp * ch;
+            const double zv = wq * ch * ch;
             static_cast<VT*>(a.out.v)[pos] = (VT)xv;
             static_cast<VT*>(a.out.v2)[pos] = (VT)zv;
           } else {
@@ -284,14 +288,14 @@ SHCI_DEV void gen_body(const GenArgs& a) {
               // as the forward: 2 (X - x_i) w H / p + 2 w (N_d - 1) / p c H^2,
               // minus the same with X_d for terms above eps2_d (stored
               // factors 2 X G, 2 X_d G and G; x_i rounded as stored)
-              const double wh = w * H / pr;
+              const double wh = wp * H;
               const double G = a.L.U.D[o];
               const bool dflag = fabs(H) * absc > a.eps2_d;
               if (dflag) {
                 gacc += (a.L.U.g[o] - a.L.U.A[o]) * wh;
               } else {
-                const double xi = (double)(VT)(w * (ci * H) / pr);
-                gacc += (a.L.U.g[o] - 2.0 * xi * G) * wh + 2.0 * (w * (a.nd - 1.0) / pr) * ci * H * H * G;
+                const double xi = (double)(VT)(wp * (ci * H));
+                gacc += (a.L.U.g[o] - 2.0 * xi * G) * wh + 2.0 * wq * ci * H * H * G;
               }
             } else {
               gacc += H * a.L.U.g[o];

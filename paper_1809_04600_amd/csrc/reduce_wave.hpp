@@ -367,17 +367,21 @@ k_reduce_wave(WaveRedArgs A) {
   // sample into slot [sample][wave], zeros into the slots of samples it
   // skips
   int64_t cur_s = -1, next_s = 0;
+  // each wavefront takes a contiguous range of buckets: the memory line that
+  // two neighbouring buckets share is read once, and the sample of its
+  // buckets never decreases
+  const int64_t per = (a.G.nbucket + A.nwaves - 1) / A.nwaves;
+  const int64_t b_lo = wave * per, b_hi = min(a.G.nbucket, b_lo + per);
   int64_t lo_n = 0, hi_n = 0;  // bounds of the next bucket, loaded one bucket ahead
-  if (wave < a.G.nbucket) {
-    lo_n = (int64_t)A.bstart[wave];
-    hi_n = (int64_t)A.bstart[wave + 1];
+  if (b_lo < b_hi) {
+    lo_n = (int64_t)A.bstart[b_lo];
+    hi_n = (int64_t)A.bstart[b_lo + 1];
   }
-  for (int64_t b = wave; b < a.G.nbucket; b += A.nwaves) {
+  for (int64_t b = b_lo; b < b_hi; ++b) {
     const int64_t lo = lo_n, M = hi_n - lo_n;
-    const int64_t bn = b + A.nwaves;
-    if (bn < a.G.nbucket) {
-      lo_n = (int64_t)A.bstart[bn];
-      hi_n = (int64_t)A.bstart[bn + 1];
+    if (b + 1 < b_hi) {
+      lo_n = hi_n;
+      hi_n = (int64_t)A.bstart[b + 2];
     }
     if constexpr (SAMPLE) {
       const int64_t s = b >> bh;

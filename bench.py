@@ -103,7 +103,8 @@ def copy_probe(mib):
 
 SUM_KEYS = ("n_terms", "n_terms_gen", "n_unique", "n_intruder", "n_records", "ms_gen", "ms_sort",
             "ms_reduce", "ms_total", "ms_k_count", "ms_k_write", "ms_k_reduce", "ms_k_part",
-            "n_part_launches", "n_part_records", "n_chunks")
+            "n_part_launches", "n_part_records", "n_chunks", "n_terms_all", "n_hashes", "n_singletons",
+            "ms_k_split")
 
 
 class Step:
@@ -178,10 +179,23 @@ def roofline(kernel, bound, alg_bytes, launches, ms, measured_kernel):
     return out
 
 
+def split_bytes_per_hash(per_launch):
+    """HBM bytes per listed hash of the singleton split's kernels: per
+    partition pass the histogram reads the hash (8) and the scatter reads and
+    writes hash and work item (24); the bucket bounds read the hash (8), the
+    repeat finder and the marks read hash and work item (12 each)."""
+    import math
+    nbits = max(1, math.ceil(math.log2(max(1.0, (per_launch + 127) // 128))))
+    npass = (nbits + 7) // 8
+    return 32.0 * npass + 32.0, npass
+
+
 def kernel_rooflines(wl, run, avg, prec):
     """Per-kernel rooflines of one step.  Algorithmic bytes: the generator
     writes each record once; the partition reads and writes it once per pass;
-    the reduce reads it once (key words, value(s), H_aa)."""
+    the reduce reads it once (key words, value(s), H_aa).  With the singleton
+    split only the terms whose grouping hash repeats are records; every term
+    leaves a listed hash (8) and work item (4) from the count walk."""
     tot = run["total"]
     kw, vb = tot["key_words"], tot["value_bytes"]
     rec = 8 * kw + vb + 8 + 4            # key words, value(s), H_aa, bucket id
@@ -209,11 +223,17 @@ def kernel_rooflines(wl, run, avg, prec):
                                   measured(wl.name, names["k_reduce_wave"])),
         "k_gen_write": roofline("k_gen_write", "alu", rec * nrec, launches, avg["ms_k_write"],
                                 measured(wl.name, names["k_gen_write"])),
-        "k_gen_count": roofline("k_gen_count", "alu", 0.0, launches, avg["ms_k_count"],
+        "k_gen_count": roofline("k_gen_count", "alu", 12.0 * avg["n_hashes"], launches, avg["ms_k_count"],
                                 measured(wl.name, names["k_gen_count"])),
     }
+    if avg["n_hashes"] > 0:
+        bph, npass = split_bytes_per_hash(avg["n_hashes"] / max(1.0, launches))
+        r = roofline("split", "hbm", bph * avg["n_hashes"], launches, avg["ms_k_split"], None)
+        if r:
+            r["kernels"] = f"k_hpart_hist + k_hpart_scatter ({npass} passes), k_hbounds, k_hdup, k_hmark"
+        out["split"] = r
     ms = {"k_part_scatter": avg["ms_k_part"], "k_reduce_wave": avg["ms_k_reduce"],
-          "k_gen_write": avg["ms_k_write"], "k_gen_count": avg["ms_k_count"]}
+          "k_gen_write": avg["ms_k_write"], "k_gen_count": avg["ms_k_count"], "split": avg["ms_k_split"]}
     return out, ms, rec
 
 
@@ -339,9 +359,7 @@ def main():
     tot = run_main["total"]
     n_terms = tot["n_terms"]
     rl, ms, rec = kernel_rooflines(wl, run_main, avg_main, prec_main)
-    dom = max(ms, key=ms.get)
-    if rl[dom] is None:
-        dom = "k_part_scatter"
+    dom = max((k for k in ms if rl.get(k)), key=ms.get)
     out = {
         "metric": METRIC,
         "value": n_terms / w_main,
@@ -358,6 +376,7 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.description}", "n_orb": wl.n_orb,
                    "n_alpha": wl.n_alpha, "n_beta": wl.n_beta, "n_var": len(x.c),
                    "eps2": wl.eps2, "n_terms": n_terms, "n_records": tot["n_records"],
+                   "n_singletons": tot["n_singletons"], "n_hashes": tot["n_hashes"],
                    "n_unique": tot["n_unique"], "parallelism": "single GPU",
                    "precision": prec_main,
                    "workspace_bytes": int(ws.numel()) if ws is not None else None,

@@ -124,6 +124,10 @@ typedef struct {
   int32_t n_part_launches; /* partition scatter launches (passes summed over chunks) */
   double ms_k_part;      /* partition scatter kernels, summed over their launches */
   int64_t n_part_records; /* records moved by the scatter launches (records x passes, summed) */
+  int64_t n_terms_all;   /* screened terms generated (records plus terms reduced in place) */
+  int64_t n_hashes;      /* singleton split: grouping hashes listed and partitioned (fillers included) */
+  int64_t n_singletons;  /* singleton split: terms reduced in place by the write walk (no record) */
+  double ms_k_split;     /* singleton split: hash partition, repeat finder and marks */
 } shci_pt2_stats;
 
 /* Optional device outputs of shci_pt2_det (any pointer may be NULL).
@@ -199,6 +203,25 @@ int shci_pt2_workspace_size(const shci_pt2_ctx* ctx, int op, int64_t n_det, int6
  * section IV).  shci_pt2_sample instead evaluates its samples in chunks of
  * consecutive samples.  st->n_chunks reports the batches or chunks used. */
 int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records);
+
+/* How the screened terms are grouped by perturbative determinant a (the sums
+ * A_a = sum_i H_ai c_i of the screened PT2 equation, section II.B; the paper
+ * accumulates them in a hash table, section V.C).
+ *   SHCI_GROUP_AUTO (default): singleton split.  The count pass lists a
+ *     64-bit grouping hash per term (determinant hash, sample id mixed in);
+ *     the list is partitioned and hashes that occur more than once are set in
+ *     a presence filter.  The write pass makes records only of terms whose
+ *     hash passes the filter (every a with two or more terms, plus false
+ *     positives) and adds the contribution of every other term, alone in its
+ *     group, in place.  Same terms, groups and counts as SHCI_GROUP_RECORDS;
+ *     E2 differs by summation order only.  Calls that export or keep
+ *     per-term or per-a data (unique export, term export, adjoints) group
+ *     every term as a record.
+ *   SHCI_GROUP_RECORDS: every term becomes a record (key, value, H_aa).
+ * The limit of shci_pt2_ctx_set_record_limit applies to the terms of a pass
+ * in either mode. */
+enum { SHCI_GROUP_AUTO = 0, SHCI_GROUP_RECORDS = 1 };
+int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode);
 
 /* Deterministic screened PT2 (screened PT2 equation).
  *   dets  device uint64 [n_det][4], unique, with n_alpha / n_beta electrons;

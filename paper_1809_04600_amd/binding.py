@@ -43,7 +43,8 @@ class Stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_k_count", C.c_double), ("ms_k_write", C.c_double),
                 ("ms_k_reduce", C.c_double), ("n_records", C.c_int64), ("key_words", C.c_int32),
                 ("value_bytes", C.c_int32), ("n_chunks", C.c_int32), ("n_part_launches", C.c_int32),
-                ("ms_k_part", C.c_double), ("n_part_records", C.c_int64)]
+                ("ms_k_part", C.c_double), ("n_part_records", C.c_int64), ("n_terms_all", C.c_int64),
+                ("n_hashes", C.c_int64), ("n_singletons", C.c_int64), ("ms_k_split", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +91,8 @@ def lib():
         L.shci_pt2_ctx_set_workspace_limit.restype = i
         L.shci_pt2_ctx_set_record_limit.argtypes = [p, C.c_int64]
         L.shci_pt2_ctx_set_record_limit.restype = i
+        L.shci_pt2_ctx_set_grouping.argtypes = [p, i]
+        L.shci_pt2_ctx_set_grouping.restype = i
         u64, sz, i32 = C.c_uint64, C.c_size_t, C.c_int32
         L.shci_pt2_workspace_size.argtypes = [p, i, i64, i64, i32, i32, i, C.POINTER(sz)]
         L.shci_pt2_workspace_size.restype = i
@@ -215,6 +218,14 @@ class Context:
         """Records per generation pass (0 = automatic); above it the
         deterministic paths use hash batches and sampling uses chunks."""
         _check(lib().shci_pt2_ctx_set_record_limit(self._ptr, int(max_records)))
+
+    def set_grouping(self, mode: str):
+        """"auto" (singleton split where the call needs no per-a output) or
+        "records" (every screened term becomes a record)."""
+        m = {"auto": 0, "records": 1}
+        if mode not in m:
+            raise ValueError(f"grouping must be one of {sorted(m)}")
+        _check(lib().shci_pt2_ctx_set_grouping(self._ptr, m[mode]))
 
     def _inputs(self, dets, c):
         nd = c.shape[0]

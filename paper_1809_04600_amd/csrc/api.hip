@@ -13,6 +13,7 @@
 #include "../../include/shci_pt2.h"
 #include "alias.hpp"
 #include "group.hpp"
+#include "hashsplit.hpp"
 #include "hc.hpp"
 #include "reduce_wave.hpp"
 #include "scan.hpp"
@@ -100,7 +101,10 @@ struct Carver {
 // workspace every region is carved from it in call order (stack discipline:
 // mark / reset), and the call allocates nothing; without one, each region is
 // the context's grow-only buffer of that purpose.
-enum Slot { SL_V, SL_ITEMS, SL_REC, SL_SAMPLE, SL_DRAWS, SL_ALIAS, SL_TABLE, SL_SEL, SL_HC, SL_HCL0, SL_HCL1, NSLOT };
+enum Slot {
+  SL_V, SL_ITEMS, SL_SPLIT, SL_FILT, SL_HASH, SL_HASH2, SL_REC, SL_SAMPLE, SL_DRAWS, SL_ALIAS, SL_TABLE, SL_SEL,
+  SL_HC, SL_HCL0, SL_HCL1, NSLOT
+};
 
 constexpr size_t WS_ALIGN = 256;
 
@@ -119,10 +123,15 @@ struct shci_pt2_ctx {
   DevBuf slot[NSLOT];
   size_t ws_limit = 0;
   int64_t rec_limit = 0;  // records per pass (0: from device memory)
+  int grouping = SHCI_GROUP_AUTO;
+  double split_rate[2] = {0.0, 0.0};  // kept terms per work item of the last split job (det, sample)
+  double split_rep[2] = {0.0, 0.0};   // repeated hashes per listed hash of the last split job
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
+  unsigned long long* dctr = nullptr;  // device 64-bit counters: hash-list claims, repeated hashes
   DevResult* dres = nullptr;
   hipEvent_t ev[10] = {};
   hipEvent_t evp[16] = {};  // around the partition scatter launches of a job (first 8 passes)
+  hipEvent_t evh[2] = {};   // around the singleton split (hash partition, repeat finder, marks)
 };
 
 namespace {
@@ -433,6 +442,11 @@ struct Job {
   int64_t nrec = 0;
   int kw = 0, vbytes = 0;
   int32_t nbatch = 1;
+  // singleton split
+  int64_t nrec_all = 0;  // kept terms (records or in place)
+  int64_t nhash = 0;     // listed hashes (fillers included)
+  int64_t nmulti = 0;    // terms written as records
+  float ms_k_split = 0;  // hash partition, repeat finder and marks
 };
 
 // Layout of the record region of one pass.
@@ -493,7 +507,7 @@ void plan_big(CV& cv, const BigDims& d, BigPlan& o) {
   o.hsc.carve(cv, std::max<int64_t>((int64_t)256 * d.ntiles, nb + 1));
   plan_partials(cv, o.P, nb, true);
   plan_partials(cv, o.Pw, d.npart, false);
-  plan_partials(cv, o.Pq, 1024, false);
+  plan_partials(cv, o.Pq, 1536, false);
   if (d.want_u) {
     for (int w = 0; w < d.kw; ++w) o.U.k[w] = cv.template take<uint64_t>(d.nrec);
     o.U.h2 = cv.template take<uint32_t>(d.nrec);
@@ -548,6 +562,177 @@ void plan_phase1(CV& cv, Phase1& p, int64_t ni, int64_t nsrc, bool grad, bool sa
   p.gpart = grad ? cv.template take<double>(ni + 1) : nullptr;
   p.gitem = (grad && sample) ? cv.template take<double>(nsrc + 1) : nullptr;
   p.sc.carve(cv, ni + 1);
+}
+
+// ---- singleton split (hashsplit.hpp) ----
+// the list takes 12 bytes a slot, twice (partition), plus the filter (at
+// most half a byte a slot), tile histograms and bucket bounds
+constexpr double HASH_BYTES_PER_ENTRY = 25.5;
+constexpr uint64_t HASH_CAP = (uint64_t)1 << 31;  // slots of one list (32-bit partition offsets)
+
+struct SplitPlan {
+  int64_t ni = 0;
+  uint32_t* mcount = nullptr;  // [ni + 1] terms of each work item written as records
+  uint64_t* moffs = nullptr;   // [ni + 1] their exclusive scan, moffs[ni] = total
+  ScanTmp msc;
+  Partials PI;                 // [ni] in-place sums of each work item
+  uint64_t* ib = nullptr;      // [nsamp + 1] sample mode: first work item of each sample
+  uint64_t* filt = nullptr;    // filter of repeated hashes: fwords_max words, 2^fbits in use
+  uint64_t fwords_max = 0;
+  int fbits = 0;
+};
+template <class CV>
+void plan_split(CV& cv, SplitPlan& p, int64_t ni, int32_t nsamp) {
+  p.ni = ni;
+  p.mcount = cv.template take<uint32_t>(ni + 1);
+  p.moffs = cv.template take<uint64_t>(ni + 1);
+  p.msc.carve(cv, ni + 1);
+  plan_partials(cv, p.PI, std::max<int64_t>(ni, 1), false);
+  p.ib = cv.template take<uint64_t>((int64_t)nsamp + 2);
+}
+struct HashList {
+  uint64_t* k = nullptr;
+  uint32_t* i = nullptr;
+};
+template <class CV>
+void plan_hash_list(CV& cv, HashList& h, int64_t n) {
+  h.k = cv.template take<uint64_t>(std::max<int64_t>(n, 1));
+  h.i = cv.template take<uint32_t>(std::max<int64_t>(n, 1));
+}
+
+// the split needs no per-a output: no unique store, no records kept for an
+// adjoint or an export
+bool split_allowed(const Job& J) {
+  return J.ctx->grouping == SHCI_GROUP_AUTO && !J.want_u && !J.want_pay && !J.keep && !J.grad;
+}
+
+// list slots the memory allows: what the caller workspace has left, or a
+// share of free device memory (plus the context's list buffers)
+int64_t split_budget(const Arena& A) {
+  shci_pt2_ctx* X = A.X;
+  double avail;
+  if (A.caller()) {
+    const double r = (double)A.remaining() - (double)(64u << 20);
+    avail = r > 0 ? r : 0.0;
+  } else {
+    size_t fr = 0, tt = 0;
+    if (hipMemGetInfo(&fr, &tt) != hipSuccess) {
+      (void)hipGetLastError();
+      fr = 0;
+    }
+    double a = (double)fr + (double)X->slot[SL_FILT].cap + (double)X->slot[SL_HASH].cap +
+               (double)X->slot[SL_HASH2].cap;
+    if (X->ws_limit) a = std::min(a, (double)X->ws_limit);
+    avail = 0.6 * a;
+  }
+  return (int64_t)(avail / HASH_BYTES_PER_ENTRY);
+}
+
+// Partition of the hash list, repeated hashes into the filter, marks per
+// work item and their scan; J.nmulti = terms that become records.
+int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t st, int cus) {
+  shci_pt2_ctx* X = J.ctx;
+  Arena& AR = *J.ar;
+  // buckets of ~100 hashes, as for the records
+  const int nbits =
+      std::min(30, std::max(1, ceil_log2((uint64_t)std::max<int64_t>(1, (nent + 127) / 128))));
+  const int npass = (nbits + 7) / 8;
+  const int64_t nbucket = (int64_t)1 << nbits;
+  const int64_t ntiles = std::max<int64_t>(1, (nent + PTILE - 1) / PTILE);
+  HashList HB;
+  uint32_t *hist = nullptr, *hoffs = nullptr;
+  ScanTmp hsc;
+  uint64_t* bst = nullptr;
+  CHK(carve_region(AR, SL_HASH2, [&](Carver& cv) {
+    plan_hash_list(cv, HB, nent);
+    hist = cv.take<uint32_t>((size_t)256 * ntiles);
+    hoffs = cv.take<uint32_t>((size_t)256 * ntiles + 1);
+    hsc.carve(cv, (int64_t)256 * ntiles);
+    bst = cv.take<uint64_t>(nbucket + 1);
+  }));
+  HIPCHK(hipEventRecord(X->evh[0], st));
+  HashList* cur = &HL;
+  HashList* oth = &HB;
+  int shift = 0;
+  const int pgrid = (int)(8 * ((ntiles + 7) / 8));
+  for (int pass = 0; pass < npass; ++pass) {
+    const int dbits = nbits / npass + (pass < nbits % npass ? 1 : 0);
+    HPassArgs pa{};
+    pa.kin = cur->k;
+    pa.iin = cur->i;
+    pa.kout = oth->k;
+    pa.iout = oth->i;
+    pa.n = nent;
+    pa.nbits = nbits;
+    pa.shift = shift;
+    pa.dbits = dbits;
+    pa.hist = hist;
+    pa.offs = hoffs;
+    pa.ntiles = (int)ntiles;
+    k_hpart_hist<<<pgrid, 256, 0, st>>>(pa);
+    CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
+    k_hpart_scatter<<<pgrid, PTHREADS, 0, st>>>(pa);
+    HIPCHK(hipGetLastError());
+    std::swap(cur, oth);
+    shift += dbits;
+  }
+  k_hbounds<<<(int)std::min<int64_t>(8192, (nent + 256) / 256), 256, 0, st>>>(cur->k, nent, nbits, nbucket, bst);
+  // filter of 32-64 bits per repeated hash: its size is a function of the
+  // number of repeated hashes (so the records, and the sums, do not depend on
+  // an earlier call); first guessed from the last job's rate, then again if
+  // the guess was not that size
+  const int sidx = J.sample ? 1 : 0;
+  auto words_for = [&](double rep) {
+    uint64_t w = 1024;
+    while (w < SP.fwords_max && (double)w * 2.0 < rep) w <<= 1;
+    return w;
+  };
+  uint64_t words = words_for(X->split_rep[sidx] * (double)nent);
+  const int64_t dblocks = std::min<int64_t>((nbucket + HDUP_WAVES - 1) / HDUP_WAVES, (int64_t)cus * 8);
+  unsigned long long nrep = 0;
+  for (int attempt = 0;; ++attempt) {
+    const int fbits = ceil_log2(words);
+    k_fill_u64<<<(int)std::min<int64_t>(4096, ((int64_t)words + 255) / 256), 256, 0, st>>>(SP.filt, (int64_t)words,
+                                                                                           0ull);
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(X->dctr + 1), 1, 0ull);
+    HDupArgs da{};
+    da.g = cur->k;
+    da.item = cur->i;
+    da.bstart = bst;
+    da.n = nent;
+    da.nbucket = nbucket;
+    da.nbits = nbits;
+    da.nwaves = dblocks * HDUP_WAVES;
+    da.filt = SP.filt;
+    da.fbits = fbits;
+    da.nrep = X->dctr + 1;
+    k_hdup<<<(int)dblocks, 64 * HDUP_WAVES, 0, st>>>(da);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&nrep, X->dctr + 1, sizeof nrep, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    SP.fbits = fbits;
+    const uint64_t want = words_for((double)nrep);
+    if (want != words && attempt == 0) {
+      words = want;
+      continue;
+    }
+    break;
+  }
+  X->split_rep[sidx] = nent > 0 ? (double)nrep / (double)nent : 0.0;
+  k_fill_u32<<<(int)std::min<int64_t>(4096, (SP.ni + 256) / 256), 256, 0, st>>>(SP.mcount, SP.ni + 1, 0u);
+  k_hmark<<<(int)std::min<int64_t>(8192, (nent + 255) / 256 + 1), 256, 0, st>>>(cur->k, cur->i, nent, SP.filt,
+                                                                                SP.fbits, SP.mcount);
+  CHK(scan_exclusive<uint32_t, uint64_t>(SP.mcount, SP.moffs, SP.ni, SP.msc, SP.moffs + SP.ni, st));
+  HIPCHK(hipEventRecord(X->evh[1], st));
+  HIPCHK(hipGetLastError());
+  uint64_t nm = 0;
+  HIPCHK(hipMemcpyAsync(&nm, SP.moffs + SP.ni, sizeof nm, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  J.nmulti = (int64_t)nm;
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, X->evh[0], X->evh[1]));
+  J.ms_k_split = ms;
+  return SHCI_OK;
 }
 
 template <int KW, typename VT, bool SAMPLE>
@@ -662,25 +847,134 @@ int run_job(Job& J) {
   g.pay_pos = J.keep ? 1 : 0;
   singles_ref(T, J.dets, st);
   const int gen_grid = cus * GEN_BLOCKS_PER_CU;
-  k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
-  HIPCHK(hipEventRecord(X->ev[4], st));
-  k_gen_count<KW, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
-  HIPCHK(hipEventRecord(X->ev[5], st));
-  HIPCHK(hipGetLastError());
-  // offs[ni] = total: the write walk checks every item's end against it
-  CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, offs + ni, st));
-  HIPCHK(hipMemcpyAsync(hostv, offs + ni, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const int64_t nrec = (int64_t)hostv[0];
-  if (J.max_records > 0 && nrec > J.max_records) {
-    J.nrec = nrec;
-    J.max_records_eff = J.max_records;
+  const int64_t gen_waves = (int64_t)gen_grid * 4;
+
+  // ---- count walk; with the singleton split it also lists the grouping
+  // hashes (hashsplit.hpp) ----
+  bool split = split_allowed(J);
+  SplitPlan SP;
+  HashList HL;
+  uint64_t hcap = 0;
+  double& rate = X->split_rate[SAMPLE ? 1 : 0];  // kept terms per work item, last split job
+  // runs of 64 to 512 slots (a run must take one emission of up to 64
+  // terms), shorter for fewer terms: the unused tails of the runs (at most
+  // one per wavefront) are partitioned too
+  double run_terms = 0.0;  // expected terms, for the run length
+  auto pick_run = [&](double terms) {
+    int r = 512;
+    while (r > 64 && (double)r * (double)gen_waves * 16.0 > terms) r >>= 1;
+    return r;
+  };
+  if (split) {
+    CHK(carve_region(AR, SL_SPLIT, [&](Carver& cv) { plan_split(cv, SP, ni, J.nsamp); }));
+    // list capacity: what the caller workspace has left, or (context memory)
+    // an estimate from the last job of this kind; none: a plain count first
+    const uint64_t lim = std::min<uint64_t>(HASH_CAP, (uint64_t)split_budget(AR));
+    run_terms = rate > 0.0 ? 1.3 * rate * (double)ni : (double)lim;
+    if (AR.caller())
+      hcap = lim;
+    else if (rate > 0.0)
+      hcap = std::min<uint64_t>(lim, (uint64_t)run_terms + (uint64_t)gen_waves * (uint64_t)pick_run(run_terms));
+  }
+  int hrun = 0;
+  size_t list_mark = 0;
+  auto count_walk = [&](bool list) -> int {
+    hrun = 0;
+    g.hkey = nullptr;
+    g.hitem = nullptr;
+    g.hcap = 0;
+    if (list) {
+      hrun = pick_run(std::min((double)hcap, run_terms));
+      // the filter (kept for the write walk), then the list
+      uint64_t fw = 1024;
+      while (fw < ((uint64_t)1 << 27) && fw * 16 < hcap) fw <<= 1;
+      SP.fwords_max = fw;
+      CHK(carve_region(AR, SL_FILT, [&](Carver& cv) { SP.filt = cv.take<uint64_t>(fw); }));
+      list_mark = AR.mark();
+      CHK(carve_region(AR, SL_HASH, [&](Carver& cv) { plan_hash_list(cv, HL, (int64_t)hcap); }));
+      g.hkey = HL.k;
+      g.hitem = HL.i;
+      g.hcap = hcap;
+      g.hclaim = X->dctr;
+      g.hrun = hrun;
+    }
+    k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(X->dctr), 4, 0ull);
+    HIPCHK(hipEventRecord(X->ev[4], st));
+    k_gen_count<KW, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
+    HIPCHK(hipEventRecord(X->ev[5], st));
+    HIPCHK(hipGetLastError());
+    // offs[ni] = total: the write walk checks every item's end against it
+    CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, offs + ni, st));
+    HIPCHK(hipMemcpyAsync(hostv, offs + ni, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hostv + 1, X->dctr, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SHCI_OK;
+  };
+  const size_t hash_mark = AR.mark();
+  bool counted = false;
+  if (split && hcap == 0) {
+    // no estimate yet: count first, then size the list for every term
+    CHK(count_walk(false));
+    counted = true;
+    run_terms = (double)hostv[0];
+    hcap = std::min<uint64_t>(std::min<uint64_t>(HASH_CAP, (uint64_t)split_budget(AR)),
+                              hostv[0] + (uint64_t)gen_waves * (uint64_t)pick_run(run_terms));
+  }
+  // a caller workspace with too little room for a list of runs of 64 slots:
+  // every term becomes a record
+  if (split && AR.caller() && hcap < (uint64_t)gen_waves * 64 * 2) split = false;
+  if (split) {
+    CHK(count_walk(true));
+    counted = true;
+    if (hostv[1] > hcap && !AR.caller() && hcap < HASH_CAP) {
+      // the estimate was short: list again with room for every term
+      AR.reset(hash_mark);
+      run_terms = (double)hostv[0];
+      hcap = std::min<uint64_t>(std::min<uint64_t>(HASH_CAP, (uint64_t)split_budget(AR)),
+                                hostv[0] + (uint64_t)gen_waves * (uint64_t)pick_run(run_terms));
+      CHK(count_walk(true));
+    }
+  }
+  if (!counted) CHK(count_walk(false));
+  const int64_t nrec_all = (int64_t)hostv[0];
+  if (split && ni > 0) rate = std::max(1.0, (double)nrec_all / (double)ni);
+  const int64_t lim_rec = split ? X->rec_limit : J.max_records;
+  if (lim_rec > 0 && nrec_all > lim_rec) {
+    J.nrec = nrec_all;
+    J.max_records_eff = lim_rec;
     AR.reset(job_mark);
     return JOB_TOO_BIG;
   }
+  int64_t nrec = nrec_all;
+  J.nrec_all = nrec_all;
+  J.nhash = 0;
+  J.ms_k_split = 0;
+  if (split) {
+    const uint64_t nent = hostv[1];
+    if (nent > hcap) {
+      // the list did not fit: hash batches or smaller sample chunks, sized
+      // by the terms that would have fit
+      J.nrec = nrec_all;
+      J.max_records_eff = std::max<int64_t>(1, (int64_t)hcap - gen_waves * hrun);
+      AR.reset(job_mark);
+      return JOB_TOO_BIG;
+    }
+    CHK(find_repeats(J, SP, HL, (int64_t)nent, st, cus));
+    nrec = J.nmulti;
+    J.nhash = (int64_t)nent;
+    // the hash list is not read again: the records take its memory
+    AR.reset(list_mark);
+    g.offs = SP.moffs;
+    g.mfilt = SP.filt;
+    g.mfbits = SP.fbits;
+    g.V = V;
+    g.e0 = J.e0;
+    g.inv_ndd = SAMPLE ? 1.0 / (J.nd * (J.nd - 1.0)) : 0.0;
+    g.PI = SP.PI;
+  }
   if (nrec >= (int64_t)0xffffffffll)
-    return fail(SHCI_ERR_WORKSPACE, "%lld screened terms exceed the 2^32-1 records of one pass",
-                (long long)nrec);
+    return fail(SHCI_ERR_WORKSPACE, "%lld screened terms exceed the 2^32-1 records of one pass", (long long)nrec);
 
   // ---- plan the grouping ----
   GroupPlan G;
@@ -853,8 +1147,11 @@ int run_job(Job& J) {
     HIPCHK(hipGetLastError());
     k_zero_result<<<1, 1, 0, st>>>(X->dres);
     if (SAMPLE) {
+      if (split)
+        k_item_bounds<<<(J.nsamp + 256) / 256, 256, 0, st>>>(w_src, J.it_s, ni, J.nsamp, SP.ib);
       k_final_sample<<<J.nsamp, 1024, 0, st>>>(Pw, nwv, P, BP.slow_bits, G.bits_hash, X->dres, J.per_sample,
-                                                J.per_sample_de0, J.sample_scale);
+                                                J.per_sample_de0, J.sample_scale, SP.PI,
+                                                split ? SP.ib : nullptr);
     } else {
       // the block kernel's bucket partials (through the bitmap, in bucket
       // order) and the per-wavefront partials, summed in a fixed order
@@ -867,8 +1164,19 @@ int run_job(Job& J) {
       Q2.nuniq += fblocks; Q2.nintr += fblocks; Q2.nzero += fblocks; Q2.mind += fblocks;
       k_final_partial_marked<<<(int)fblocks, 256, 0, st>>>(P, BP.slow_bits, G.nbucket, fchunk, Q);
       k_final_partial<<<(int)wfblocks, 256, 0, st>>>(Pw, nwv, wchunk, Q2);
-      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0, nullptr,
-                                   1.0);
+      // and the in-place partials of the work items (singleton split)
+      int64_t ifblocks = 0;
+      if (split && ni > 0) {
+        const int64_t ichunk = std::max<int64_t>(4096, ((ni + 255) / 256 + 31) / 32 * 32);
+        ifblocks = (ni + ichunk - 1) / ichunk;
+        Partials Q3 = Pq;
+        const int64_t o3 = fblocks + wfblocks;
+        Q3.e2 += o3; Q3.de0 += o3; Q3.e2sq += o3; Q3.nterm += o3; Q3.ngen += o3;
+        Q3.nuniq += o3; Q3.nintr += o3; Q3.nzero += o3; Q3.mind += o3;
+        k_final_partial<<<(int)ifblocks, 256, 0, st>>>(SP.PI, ni, ichunk, Q3);
+      }
+      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks + ifblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0,
+                                   nullptr, 1.0);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(X->ev[3], st));
@@ -908,6 +1216,7 @@ int run_job(Job& J) {
     J.n_part = npass;
     J.n_part_rec = nrec * npass;
     J.nrec = nrec;
+    if (!split) J.nmulti = nrec;
     J.kw = KW;
     J.vbytes = (int)sizeof(VT) * (SAMPLE ? 2 : 1);
     J.nbucket = (int32_t)G.nbucket;
@@ -952,7 +1261,7 @@ int run_job(Job& J) {
     }
     if (J.ex) {
       J.ex->u_n = J.res.nuniq;
-      J.ex->t_n = nrec;
+      J.ex->t_n = split ? nrec_all : nrec;
     }
     HIPCHK(hipStreamSynchronize(st));
     AR.reset(job_mark);
@@ -1014,6 +1323,10 @@ void fill_stats(shci_pt2_stats* st, const Job& J, float ms_total) {
   st->n_part_launches = J.n_part;
   st->ms_k_part = J.ms_k_part;
   st->n_part_records = J.n_part_rec;
+  st->n_terms_all = J.nrec_all;
+  st->n_hashes = J.nhash;
+  st->n_singletons = J.nrec_all - J.nmulti;
+  st->ms_k_split = J.ms_k_split;
 }
 
 // Records one pass may materialise: the record limit if set, else what free
@@ -1133,9 +1446,12 @@ int run_det_batched(const Job& proto, Job& acc) {
       acc.ms_k_reduce += J.ms_k_reduce;
       acc.ms_k_part += J.ms_k_part;
       acc.n_part += J.n_part;
-    acc.n_part_rec += J.n_part_rec;
       acc.n_part_rec += J.n_part_rec;
       acc.nrec += J.nrec;
+      acc.nrec_all += J.nrec_all;
+      acc.nhash += J.nhash;
+      acc.nmulti += J.nmulti;
+      acc.ms_k_split += J.ms_k_split;
       acc.kw = J.kw;
       acc.vbytes = J.vbytes;
     }
@@ -1386,6 +1702,7 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
       T.g8 = cv.take<double>(npair * (npair + 1) / 2);
     }
     X->dflag = cv.take<uint32_t>(16);
+    X->dctr = cv.take<unsigned long long>(4);
     X->dres = cv.take<DevResult>(1);
 
   };
@@ -1400,6 +1717,8 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
   for (auto& e : X->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
   for (auto& e : X->evp)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+  for (auto& e : X->evh)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
   if (hipMemcpyAsync(T.h1, h1, n2 * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return bail(fail(SHCI_ERR_HIP, "copy of h1 failed"));
@@ -1422,6 +1741,8 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->evp)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->evh)
+    if (e) (void)hipEventDestroy(e);
   ctx->tables.release();
   for (auto& b : ctx->slot) b.release();
   delete ctx;
@@ -1431,6 +1752,13 @@ int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records) {
   if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
   if (max_records < 0) return fail(SHCI_ERR_ARG, "max_records must be >= 0");
   ctx->rec_limit = max_records;
+  return SHCI_OK;
+}
+
+int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
+  if (mode != SHCI_GROUP_AUTO && mode != SHCI_GROUP_RECORDS) return fail(SHCI_ERR_ARG, "unknown grouping mode");
+  ctx->grouping = mode;
   return SHCI_OK;
 }
 
@@ -1693,8 +2021,14 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
   // the workspace: one generation / partition / reduce launch sequence per
   // chunk covers all its samples (sample id in the key).  The chunk length
   // adapts to the records per sample seen so far.
-  const int64_t max_rec = record_budget(
-      AR, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false, grad != nullptr));
+  // (with the singleton split a term takes a list slot, not a record)
+  const bool split_ok = ctx->grouping == SHCI_GROUP_AUTO && grad == nullptr;
+  const int64_t max_rec =
+      split_ok ? (ctx->rec_limit > 0 ? ctx->rec_limit
+                                     : std::max<int64_t>(1, std::min<int64_t>((int64_t)(0.9 * (double)HASH_CAP),
+                                                                              split_budget(AR))))
+               : record_budget(AR, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false,
+                                                grad != nullptr));
   if (grad) k_fill_u64<<<(int)std::min<int64_t>(4096, (n_det + 255) / 256), 256, 0, s>>>(
       reinterpret_cast<uint64_t*>(grad), n_det, 0ull);
   Job acc{};
@@ -1775,11 +2109,15 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
     acc.n_part += J.n_part;
     acc.n_part_rec += J.n_part_rec;
     acc.nrec += J.nrec;
+    acc.nrec_all += J.nrec_all;
+    acc.nhash += J.nhash;
+    acc.nmulti += J.nmulti;
+    acc.ms_k_split += J.ms_k_split;
     acc.kw = std::max(acc.kw, J.kw);
     acc.vbytes = J.vbytes;
     s0 += k;
     // next chunk: as many samples as the budget allows at this chunk's rate
-    const double per = (double)std::max<int64_t>(1, J.nrec) / k;
+    const double per = (double)std::max<int64_t>(1, J.nrec_all) / k;
     k = pow2_floor(std::max<int64_t>(1, (int64_t)std::min<double>(n_samples, 0.9 * (double)max_rec / per)));
   }
   std::vector<double> ps(n_samples);

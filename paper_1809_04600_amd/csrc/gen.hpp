@@ -35,6 +35,72 @@ struct VSet {
   int fbits = 0;
 };
 
+// two bits of a hash in one 64-bit word of a blocked presence filter:
+// word h >> (64 - fbits), bits (h >> 20) & 63 and (h >> 26) & 63
+SHCI_DEV uint64_t filt_bits(uint64_t h) { return (1ull << ((h >> 20) & 63)) | (1ull << ((h >> 26) & 63)); }
+
+// false: certainly never inserted; true: maybe
+SHCI_DEV bool filt_maybe(const uint64_t* words, int fbits, uint64_t h) {
+  const uint64_t m = filt_bits(h);
+  return (words[h >> (64 - fbits)] & m) == m;
+}
+
+SHCI_DEV void filt_insert(uint64_t* words, int fbits, uint64_t h) {
+  atomicOr((unsigned long long*)&words[h >> (64 - fbits)], (unsigned long long)filt_bits(h));
+}
+
+SHCI_DEV uint64_t vfilt_bits(uint64_t h) { return filt_bits(h); }
+SHCI_DEV bool vfilt_maybe(const VSet& V, uint64_t h) { return filt_maybe(V.filt, V.fbits, h); }
+
+// membership in the hash set of V of a determinant that passed the filter
+template <int KW>
+SHCI_DEV bool vset_probe(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
+  uint64_t slot = h & V.mask;
+  const uint32_t fp = (uint32_t)(h >> 32);
+  for (uint64_t probe = 0; probe <= V.mask; ++probe) {
+    const uint64_t e = V.tab[slot];
+    if (e == ~0ull) return false;
+    if ((uint32_t)(e >> 32) == fp) {
+      const uint64_t i = e & 0xffffffffull;
+      uint64_t dk[KW];
+      pack_det<KW>(dk, V.dets[4 * i], V.dets[4 * i + 1], V.dets[4 * i + 2], V.dets[4 * i + 3], n);
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < KW; ++w) eq = eq && (dk[w] == k[w]);
+      if (eq) return true;
+    }
+    slot = (slot + 1) & V.mask;
+  }
+  return false;
+}
+
+// membership of a packed determinant key (det bits only) in the hash set of V;
+// h is det_hash(k)
+template <int KW>
+SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
+  return vfilt_maybe(V, h) && vset_probe<KW>(V, k, h, n);
+}
+
+template <int KW>
+SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
+  return vset_contains_h<KW>(V, k, det_hash<KW>(k, n), n);
+}
+
+// Grouping hash of a term: the determinant hash with the sample id mixed in,
+// so the terms of one a in one sample share it.  Never 0 (0 marks an empty
+// slot of the duplicate finder's tables).
+SHCI_DEV uint64_t group_hash(uint64_t h, uint32_t sid) {
+  const uint64_t g = h ^ ((uint64_t)sid * 0x9e3779b97f4a7c15ull);
+  return g ? g : 1ull;
+}
+// filler of an unused slot p of the hash list: distinct per slot (a
+// bijection of p), its work item is HASH_HOLE
+constexpr uint32_t HASH_HOLE = 0xffffffffu;
+SHCI_DEV uint64_t hole_hash(uint64_t p) {
+  const uint64_t g = fmix64(p ^ 0x5851f42d4c957f2dull);
+  return g ? g : 1ull;
+}
+
 struct LookupArgs {
   Uniq U;
   const int32_t* nseg = nullptr;
@@ -75,6 +141,25 @@ struct GenArgs {
   LookupArgs L;
   double* grad;
   int pay_pos;             // payload: the record's own position (keep-mode adjoint) instead of the source
+  // singleton split.  Count walk: the grouping hash and work item of every
+  // kept term go to hkey / hitem, in runs of hrun >= 64 slots that each
+  // wavefront claims from *hclaim (slots past hcap are not written; unused
+  // slots of a claimed run are filled with hole_hash / HASH_HOLE).
+  uint64_t* hkey;
+  uint32_t* hitem;
+  uint64_t hcap;
+  unsigned long long* hclaim;
+  int hrun;
+  // Write walk: a term whose grouping hash passes the filter mfilt of hashes
+  // seen more than once becomes a record (at offs of its work item, which
+  // count such terms); every other term is the only one of its a, and its
+  // contribution is summed in place into the work item's partials PI.
+  const uint64_t* mfilt;
+  int mfbits;
+  VSet V;
+  double e0;
+  double inv_ndd;  // 1 / (N_d (N_d - 1))
+  Partials PI;
 };
 
 SHCI_DEV int tri_inv(int u) {
@@ -137,6 +222,9 @@ SHCI_DEV void gen_body(const GenArgs& a) {
   // into several items, so a static assignment is balanced)
   const int64_t nwaves_total = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int64_t wave_gid = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  const bool hmode = MODE == GEN_COUNT && a.hkey != nullptr;   // count walk lists grouping hashes
+  const bool fmode = MODE == GEN_WRITE && a.mfilt != nullptr;  // write walk splits off singletons
+  uint64_t hpos = 0, hend = 0;  // this wavefront's claimed run of the hash list (uniform)
   for (int64_t item = wave_gid; item < a.n_items; item += nwaves_total) {
 
     const int64_t src = a.w_src[item];
@@ -224,6 +312,10 @@ SHCI_DEV void gen_body(const GenArgs& a) {
     }
     uint64_t cursor = 0;  // uniform
     double gacc = 0.0;
+    // in-place sums of the singletons of this work item (per lane)
+    double fe2 = 0.0, fde0 = 0.0, fe2sq = 0.0, fdmn = INFINITY;
+    int64_t fnt = 0, fng = 0;
+    int32_t fnu = 0, fni = 0, fnz = 0;
 
     auto emit = [&](bool keep, uint64_t x0, uint64_t x1, uint64_t y0, uint64_t y1, double H, double haa) {
       if (a.bmask) {  // uniform
@@ -236,15 +328,54 @@ SHCI_DEV void gen_body(const GenArgs& a) {
       }
       const uint64_t bal = ballot(keep);
       if constexpr (MODE == GEN_COUNT) {
+        if (hmode) {
+          // grouping hash of every kept term into this wavefront's run of
+          // the hash list (a new run is claimed when the current one is full)
+          uint64_t g = 0;
+          if (keep) {
+            uint64_t key[KW];
+            pack_det<KW>(key, x0, x1, y0, y1, n);
+            g = group_hash(det_hash<KW>(key, n), sid);
+          }
+          const uint64_t cnt = (uint64_t)__popcll(bal);
+          const uint64_t r = (uint64_t)rank_below(bal);
+          const uint64_t room = hend - hpos;
+          uint64_t pos = hpos + r;
+          if (cnt > room) {
+            unsigned long long nb = 0;
+            if (lane == 0) nb = atomicAdd(a.hclaim, (unsigned long long)a.hrun);
+            nb = __shfl(nb, 0);
+            if (r >= room) pos = (uint64_t)nb + (r - room);
+            hpos = (uint64_t)nb + (cnt - room);
+            hend = (uint64_t)nb + (uint64_t)a.hrun;
+          } else {
+            hpos += cnt;
+          }
+          if (keep && pos < a.hcap) {
+            a.hkey[pos] = g;
+            a.hitem[pos] = (uint32_t)item;
+          }
+        }
         cursor += (uint64_t)__popcll(bal);
       } else if constexpr (MODE == GEN_WRITE) {
-        const uint64_t pos = obase + cursor + (uint64_t)rank_below(bal);
-        if (keep && pos < oend) {  // the count walk sized [obase, oend)
-          uint64_t key[KW];
+        uint64_t key[KW];
+        uint64_t h = 0;
+        if (keep) {
           pack_det<KW>(key, x0, x1, y0, y1, n);
+          h = det_hash<KW>(key, n);
+        }
+        bool wr = keep, single = false;
+        if (fmode) {
+          // a grouping hash outside the filter of repeated hashes: this
+          // term is the only one of its a (in its sample)
+          single = keep && !filt_maybe(a.mfilt, a.mfbits, group_hash(h, sid));
+          wr = keep && !single;
+        }
+        const uint64_t bw = fmode ? ballot(wr) : bal;
+        const uint64_t pos = obase + cursor + (uint64_t)rank_below(bw);
+        if (wr && pos < oend) {  // the count walk sized [obase, oend)
           {
             // bucket id: top hash bits of the determinant, sample id above
-            const uint64_t h = det_hash<KW>(key, n);
             uint32_t b = a.bits_hash ? (uint32_t)(h >> (64 - a.bits_hash)) : 0u;
             if constexpr (SAMPLE) b |= sid << a.bits_hash;
             a.out.bid[pos] = b;
@@ -274,7 +405,43 @@ SHCI_DEV void gen_body(const GenArgs& a) {
           a.out.haa[pos] = haa;
           if (a.out.pay) a.out.pay[pos] = a.pay_pos ? (uint32_t)pos : (uint32_t)i;
         }
-        cursor += (uint64_t)__popcll(bal);
+        cursor += (uint64_t)__popcll(bw);
+        if (single) {
+          // the bucket reduce of a segment of one term, in place: a in V
+          // is dropped; otherwise A_a = t (deterministic) or the sample
+          // bracket reduces to z (X^2 - Q = 0 exactly for one term), and a
+          // term above the upper threshold cancels its own contribution
+          fng += 1;
+          if (!vset_contains_h<KW>(a.V, key, h, n)) {
+            const bool up = fabs(H) * absc > a.eps2_d;
+            const double Dd = a.e0 - haa;
+            const double rd = 1.0 / Dd;
+            double contrib;
+            if constexpr (SAMPLE) {
+              const double ch = ci * H;
+              const double z = (double)(VT)(wq * ch * ch);
+              const double G = rd * a.inv_ndd;
+              contrib = (up ? 0.0 : z) * G;
+              fde0 += -contrib * rd;
+            } else {
+              double X;
+              if constexpr (sizeof(VT) == 4)
+                X = (double)((float)H * (float)ci);
+              else
+                X = H * ci;
+              const double a2 = up ? 0.0 : X * X;
+              contrib = a2 * rd;
+              fde0 += -a2 * rd * rd;
+            }
+            fe2 += contrib;
+            fe2sq += contrib * contrib;
+            fnt += 1;
+            fnu += 1;
+            fni += Dd > 0.0;
+            fnz += Dd == 0.0;
+            fdmn = fmin(fdmn, fabs(Dd));
+          }
+        }
       } else {  // GEN_GRAD
         if (keep) {
           uint64_t key[KW];
@@ -452,7 +619,20 @@ SHCI_DEV void gen_body(const GenArgs& a) {
         }
         if constexpr (MODE == GEN_COUNT) {
           if (a.bmask == 0u) {  // uniform
-            cursor += (uint64_t)__popcll(ballot(sure));
+            if (hmode) {
+              // listed without the exact element: only the key is needed
+              uint64_t x0 = A0, x1 = A1, y0 = B0, y1 = B1;
+              if (alpha) {
+                flip(x0, x1, p);
+                flip(x0, x1, r);
+              } else {
+                flip(y0, y1, p);
+                flip(y0, y1, r);
+              }
+              emit(sure, x0, x1, y0, y1, 0.0, 0.0);
+            } else {
+              cursor += (uint64_t)__popcll(ballot(sure));
+            }
             maybe = maybe && !sure;
           }
         }
@@ -523,7 +703,7 @@ SHCI_DEV void gen_body(const GenArgs& a) {
     // and the table value) and written 64 at a time, so the key, hash, H_aa
     // and stores of a write run on full wavefronts.  Plain counting needs
     // no queue.
-    const bool dqueue = MODE != GEN_COUNT || a.bmask != 0u;  // uniform
+    const bool dqueue = MODE != GEN_COUNT || a.bmask != 0u || hmode;  // uniform
     uint32_t* dq = s_dq[wv];
     double* dv = s_dv[wv];
     int dqn = 0;  // uniform
@@ -678,6 +858,32 @@ SHCI_DEV void gen_body(const GenArgs& a) {
     }
     if constexpr (MODE == GEN_WRITE) {
       if (lane == 0 && obase + cursor != oend) atomicOr(a.flag, 32u);
+      if (fmode) {
+        // the work item's singleton partials (fixed butterfly)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          fe2 += __shfl_xor(fe2, o);
+          fde0 += __shfl_xor(fde0, o);
+          fe2sq += __shfl_xor(fe2sq, o);
+          fdmn = fmin(fdmn, __shfl_xor(fdmn, o));
+          fnt += __shfl_xor(fnt, o);
+          fng += __shfl_xor(fng, o);
+          fnu += __shfl_xor(fnu, o);
+          fni += __shfl_xor(fni, o);
+          fnz += __shfl_xor(fnz, o);
+        }
+        if (lane == 0) {
+          a.PI.e2[item] = fe2;
+          a.PI.de0[item] = fde0;
+          a.PI.e2sq[item] = fe2sq;
+          a.PI.mind[item] = fdmn;
+          a.PI.nterm[item] = fnt;
+          a.PI.ngen[item] = fng;
+          a.PI.nuniq[item] = fnu;
+          a.PI.nintr[item] = fni;
+          a.PI.nzero[item] = fnz;
+        }
+      }
     }
     if constexpr (MODE == GEN_GRAD) {
 #pragma unroll
@@ -685,6 +891,14 @@ SHCI_DEV void gen_body(const GenArgs& a) {
       if (lane == 0) a.grad[item] = gacc;  // per work item; summed per source afterwards
     }
     __builtin_amdgcn_wave_barrier();
+  }
+  if (hmode) {
+    // the rest of the last claimed run: distinct fillers without a work item
+    for (uint64_t p = hpos + (uint64_t)lane; p < hend; p += 64)
+      if (p < a.hcap) {
+        a.hkey[p] = hole_hash(p);
+        a.hitem[p] = HASH_HOLE;
+      }
   }
 }
 

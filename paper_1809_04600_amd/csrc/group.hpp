@@ -312,36 +312,22 @@ SHCI_DEV void tile_scatter(ScatterShared& L, const uint64_t (&r)[PW_ITEMS], T* o
   __syncthreads();
 }
 
-template <int KW, typename VT, bool V2, bool PAY>
-__global__ void __launch_bounds__(PTHREADS) k_part_scatter(PassArgs a) {
-  __shared__ ScatterShared L;
-  const int tile = xcd_tile(blockIdx.x, a.ntiles);
-  if (tile >= a.ntiles) return;
+// Local positions of this thread's records of a tile (digits d, stable
+// order): each wavefront ranks its slice by ballot match with running
+// per-digit counts in its LDS slice, one scan places the digits.  Fills
+// L.sdig and L.lstart; L.wc must be zero on entry.
+SHCI_DEV void tile_rank(ScatterShared& L, const uint32_t (&dg)[PW_ITEMS], int tile_n, int dbits,
+                        uint16_t (&lpos)[PW_ITEMS]) {
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-  if (t < 256) {
-#pragma unroll
-    for (int w = 0; w < PWAVES; ++w) L.wc[w][t] = 0;
-    L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + tile] : 0u;
-  }
-  __syncthreads();
-  const int64_t base = (int64_t)tile * PTILE;
-  const int tile_n = (int)((a.n - base < (int64_t)PTILE) ? (a.n - base) : (int64_t)PTILE);
-  const uint32_t dmask = (1u << a.dbits) - 1u;
-  uint16_t lpos[PW_ITEMS];
   uint8_t dig[PW_ITEMS];
   uint16_t* wc = L.wc[wv];
-  // bucket ids of this thread's records, then (in flight during the ranking)
-  // the first key word
-  uint64_t ids[PW_ITEMS], cur[PW_ITEMS], nxt[PW_ITEMS];
-  tile_load<uint32_t>(a.in.bid, base, tile_n, ids);
-  tile_load<uint64_t>(a.in.k[0], base, tile_n, cur);
 #pragma unroll
   for (int j = 0; j < PW_ITEMS; ++j) {
     const int q = tile_slot(wv, lane, j);
     const bool valid = q < tile_n;
-    const uint32_t d = valid ? (((uint32_t)ids[j] >> a.shift) & dmask) : 0u;
+    const uint32_t d = valid ? dg[j] : 0u;
     uint64_t peers = ballot(valid);
-    for (int bb = 0; bb < a.dbits; ++bb) {
+    for (int bb = 0; bb < dbits; ++bb) {
       const bool on = (d >> bb) & 1u;
       const uint64_t m = ballot(on);
       peers &= on ? m : ~m;
@@ -382,6 +368,35 @@ __global__ void __launch_bounds__(PTHREADS) k_part_scatter(PassArgs a) {
     if (q < tile_n) L.sdig[lpos[j]] = dig[j];
   }
   __syncthreads();
+}
+
+template <int KW, typename VT, bool V2, bool PAY>
+__global__ void __launch_bounds__(PTHREADS) k_part_scatter(PassArgs a) {
+  __shared__ ScatterShared L;
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  if (tile >= a.ntiles) return;
+  const int t = threadIdx.x;
+  if (t < 256) {
+#pragma unroll
+    for (int w = 0; w < PWAVES; ++w) L.wc[w][t] = 0;
+    L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + tile] : 0u;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)tile * PTILE;
+  const int tile_n = (int)((a.n - base < (int64_t)PTILE) ? (a.n - base) : (int64_t)PTILE);
+  const uint32_t dmask = (1u << a.dbits) - 1u;
+  uint16_t lpos[PW_ITEMS];
+  // bucket ids of this thread's records, then (in flight during the ranking)
+  // the first key word
+  uint64_t ids[PW_ITEMS], cur[PW_ITEMS], nxt[PW_ITEMS];
+  tile_load<uint32_t>(a.in.bid, base, tile_n, ids);
+  tile_load<uint64_t>(a.in.k[0], base, tile_n, cur);
+  {
+    uint32_t dg[PW_ITEMS];
+#pragma unroll
+    for (int j = 0; j < PW_ITEMS; ++j) dg[j] = ((uint32_t)ids[j] >> a.shift) & dmask;
+    tile_rank(L, dg, tile_n, a.dbits, lpos);
+  }
   // arrays in order: key words, v, [v2], H_aa, [payload], bucket id; the
   // next array's loads are issued before the current one is written
   constexpr int NA = KW + 3 + (V2 ? 1 : 0) + (PAY ? 1 : 0);
@@ -453,49 +468,6 @@ struct RedArgs {
   const uint32_t* nlist;    // device count of blist
   double* contrib;          // keep-mode adjoint (nullable): contrib[pay] = t * 2 A_a / D_a (0 for a in V)
 };
-
-// the two presence-filter bits of a determinant hash
-SHCI_DEV uint64_t vfilt_bits(uint64_t h) { return (1ull << ((h >> 20) & 63)) | (1ull << ((h >> 26) & 63)); }
-
-// false: certainly not in V; true: look the table up
-SHCI_DEV bool vfilt_maybe(const VSet& V, uint64_t h) {
-  const uint64_t m = vfilt_bits(h);
-  return (V.filt[h >> (64 - V.fbits)] & m) == m;
-}
-
-// membership in the hash set of V of a determinant that passed the filter
-template <int KW>
-SHCI_DEV bool vset_probe(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
-  uint64_t slot = h & V.mask;
-  const uint32_t fp = (uint32_t)(h >> 32);
-  for (uint64_t probe = 0; probe <= V.mask; ++probe) {
-    const uint64_t e = V.tab[slot];
-    if (e == ~0ull) return false;
-    if ((uint32_t)(e >> 32) == fp) {
-      const uint64_t i = e & 0xffffffffull;
-      uint64_t dk[KW];
-      pack_det<KW>(dk, V.dets[4 * i], V.dets[4 * i + 1], V.dets[4 * i + 2], V.dets[4 * i + 3], n);
-      bool eq = true;
-#pragma unroll
-      for (int w = 0; w < KW; ++w) eq = eq && (dk[w] == k[w]);
-      if (eq) return true;
-    }
-    slot = (slot + 1) & V.mask;
-  }
-  return false;
-}
-
-// membership of a packed determinant key (det bits only) in the hash set of V;
-// h is det_hash(k)
-template <int KW>
-SHCI_DEV bool vset_contains_h(const VSet& V, const uint64_t (&k)[KW], uint64_t h, int n) {
-  return vfilt_maybe(V, h) && vset_probe<KW>(V, k, h, n);
-}
-
-template <int KW>
-SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
-  return vset_contains_h<KW>(V, k, det_hash<KW>(k, n), n);
-}
 
 template <int KW>
 __global__ void k_vset_insert(VSet V, int64_t nd, int n, uint32_t* flag) {
@@ -1060,9 +1032,12 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
 // Pw[s][0..nwaves) and the per-bucket partials of the block kernel's buckets
 // of s (marked in `bits`, buckets [s << bits_hash, (s + 1) << bits_hash)),
 // each thread over a fixed range, then a fixed tree.
+// With the singleton split, also the in-place partials PI of the sample's
+// work items [ib[s], ib[s + 1]).
 __global__ void __launch_bounds__(1024) k_final_sample(Partials Pw, int64_t nwaves, Partials P, const uint32_t* bits,
                                                        int bits_hash, DevResult* res, double* per_sample,
-                                                       double* per_sample_de0, double sample_scale) {
+                                                       double* per_sample_de0, double sample_scale, Partials PI,
+                                                       const uint64_t* ib) {
   __shared__ double r1[1024], r2[1024], r3[1024];
   __shared__ int64_t i1[1024], i2[1024], i3[1024], i4[1024], i5[1024];
   const int t = threadIdx.x;
@@ -1095,6 +1070,11 @@ __global__ void __launch_bounds__(1024) k_final_sample(Partials Pw, int64_t nwav
   } else if (t == 0) {
     for (int64_t b = b0; b < b0 + nbk; ++b)
       if ((bits[b >> 5] >> (b & 31)) & 1u) add(P, b);
+  }
+  if (ib) {
+    const int64_t lo = (int64_t)ib[s], cnt = (int64_t)ib[s + 1] - lo;
+    const int64_t pi = (cnt + 1023) / 1024;
+    for (int64_t i = lo + t * pi; i < lo + min(cnt, (int64_t)(t + 1) * pi); ++i) add(PI, i);
   }
   r1[t] = e; r2[t] = d; r3[t] = mn;
   i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;

@@ -110,8 +110,10 @@ def test_sample_seed_path():
 
 
 def test_workspace_caller_owned():
+    # every term a record (the sizes below are those of the records)
     x = I.small(12, 3, 3, 300, 3, 11)
     ctx, dets, c = context(x)
+    ctx.set_grouping("records")
     eps2 = 1e-6
     o = ref.pt2_det(12, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2, unique=False)
     r0 = ctx.det(dets, c, x.e0, eps2, "fp64")

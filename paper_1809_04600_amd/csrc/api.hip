@@ -568,7 +568,7 @@ void plan_phase1(CV& cv, Phase1& p, int64_t ni, int64_t nsrc, bool grad, bool sa
 // the list takes 12 bytes a slot, twice (partition), plus the filter (at
 // most half a byte a slot), tile histograms and bucket bounds
 constexpr double HASH_BYTES_PER_ENTRY = 25.5;
-constexpr uint64_t HASH_CAP = (uint64_t)1 << 31;  // slots of one list (32-bit partition offsets)
+constexpr uint64_t HASH_CAP = (uint64_t)1000000000;  // slots of one list
 
 struct SplitPlan {
   int64_t ni = 0;
@@ -633,22 +633,21 @@ int64_t split_budget(const Arena& A) {
 int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t st, int cus) {
   shci_pt2_ctx* X = J.ctx;
   Arena& AR = *J.ar;
-  // buckets of ~100 hashes, as for the records
+  // buckets of ~12k hashes (one LDS table fill each): 16 bits, two passes,
+  // up to ~8e8 hashes
   const int nbits =
-      std::min(30, std::max(1, ceil_log2((uint64_t)std::max<int64_t>(1, (nent + 127) / 128))));
+      std::min(30, std::max(1, ceil_log2((uint64_t)std::max<int64_t>(1, (nent + HDUP_MEAN - 1) / HDUP_MEAN))));
   const int npass = (nbits + 7) / 8;
   const int64_t nbucket = (int64_t)1 << nbits;
   const int64_t ntiles = std::max<int64_t>(1, (nent + PTILE - 1) / PTILE);
   HashList HB;
   uint32_t *hist = nullptr, *hoffs = nullptr;
   ScanTmp hsc;
-  uint64_t* bst = nullptr;
   CHK(carve_region(AR, SL_HASH2, [&](Carver& cv) {
     plan_hash_list(cv, HB, nent);
     hist = cv.take<uint32_t>((size_t)256 * ntiles);
     hoffs = cv.take<uint32_t>((size_t)256 * ntiles + 1);
     hsc.carve(cv, (int64_t)256 * ntiles);
-    bst = cv.take<uint64_t>(nbucket + 1);
   }));
   HIPCHK(hipEventRecord(X->evh[0], st));
   HashList* cur = &HL;
@@ -676,19 +675,21 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     std::swap(cur, oth);
     shift += dbits;
   }
-  k_hbounds<<<(int)std::min<int64_t>(8192, (nent + 256) / 256), 256, 0, st>>>(cur->k, nent, nbits, nbucket, bst);
   // filter of 32-64 bits per repeated hash: its size is a function of the
   // number of repeated hashes (so the records, and the sums, do not depend on
   // an earlier call); first guessed from the last job's rate, then again if
   // the guess was not that size
   const int sidx = J.sample ? 1 : 0;
+  // at most ~4 bits per kept term (a cap that depends on the terms only)
+  uint64_t wcap = 1024;
+  while (wcap < SP.fwords_max && (double)wcap * 16.0 < (double)J.nrec_all) wcap <<= 1;
   auto words_for = [&](double rep) {
     uint64_t w = 1024;
-    while (w < SP.fwords_max && (double)w * 2.0 < rep) w <<= 1;
+    while (w < wcap && (double)w * 2.0 < rep) w <<= 1;
     return w;
   };
   uint64_t words = words_for(X->split_rep[sidx] * (double)nent);
-  const int64_t dblocks = std::min<int64_t>((nbucket + HDUP_WAVES - 1) / HDUP_WAVES, (int64_t)cus * 8);
+  const int64_t dblocks = std::min<int64_t>(nbucket, (int64_t)cus * 4);
   unsigned long long nrep = 0;
   for (int attempt = 0;; ++attempt) {
     const int fbits = ceil_log2(words);
@@ -697,16 +698,13 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(X->dctr + 1), 1, 0ull);
     HDupArgs da{};
     da.g = cur->k;
-    da.item = cur->i;
-    da.bstart = bst;
     da.n = nent;
-    da.nbucket = nbucket;
     da.nbits = nbits;
-    da.nwaves = dblocks * HDUP_WAVES;
+    da.nbucket = nbucket;
     da.filt = SP.filt;
     da.fbits = fbits;
     da.nrep = X->dctr + 1;
-    k_hdup<<<(int)dblocks, 64 * HDUP_WAVES, 0, st>>>(da);
+    k_hdup<<<(int)dblocks, HDUP_THREADS, 0, st>>>(da);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&nrep, X->dctr + 1, sizeof nrep, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

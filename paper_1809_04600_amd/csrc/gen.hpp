@@ -87,19 +87,16 @@ SHCI_DEV bool vset_contains(const VSet& V, const uint64_t (&k)[KW], int n) {
 }
 
 // Grouping hash of a term: the determinant hash with the sample id mixed in,
-// so the terms of one a in one sample share it.  Never 0 (0 marks an empty
-// slot of the duplicate finder's tables).
+// so the terms of one a in one sample share it; even and never 0 (odd values
+// mark the fillers of the hash list).
 SHCI_DEV uint64_t group_hash(uint64_t h, uint32_t sid) {
-  const uint64_t g = h ^ ((uint64_t)sid * 0x9e3779b97f4a7c15ull);
-  return g ? g : 1ull;
+  const uint64_t g = (h ^ ((uint64_t)sid * 0x9e3779b97f4a7c15ull)) & ~1ull;
+  return g ? g : 2ull;
 }
-// filler of an unused slot p of the hash list: distinct per slot (a
-// bijection of p), its work item is HASH_HOLE
+// filler of an unused slot p of the hash list: odd, spread like the hashes;
+// its work item is HASH_HOLE
 constexpr uint32_t HASH_HOLE = 0xffffffffu;
-SHCI_DEV uint64_t hole_hash(uint64_t p) {
-  const uint64_t g = fmix64(p ^ 0x5851f42d4c957f2dull);
-  return g ? g : 1ull;
-}
+SHCI_DEV uint64_t hole_hash(uint64_t p) { return fmix64(p ^ 0x5851f42d4c957f2dull) | 1ull; }
 
 struct LookupArgs {
   Uniq U;

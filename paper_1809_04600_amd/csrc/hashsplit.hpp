@@ -8,9 +8,9 @@
 //     sample id mixed in) and the work item of every kept term, 12 bytes a
 //     term instead of a record of 44-60;
 //  2. the list is partitioned on the top hash bits (the same stable LSD passes
-//     as the records), buckets of ~100 hashes;
-//  3. per bucket, one wavefront finds the hashes that occur more than once
-//     (an LDS hash table per wavefront) and sets them in a presence filter;
+//     as the records), buckets of ~12k hashes (two passes up to ~8e8);
+//  3. per bucket, one workgroup finds the hashes that occur more than once
+//     (an LDS hash table) and sets them in a presence filter;
 //  4. every listed term whose hash passes the filter is counted for its work
 //     item; the scan of these counts places the records.
 // The write walk then writes records only for terms whose hash passes the
@@ -85,131 +85,127 @@ __global__ void __launch_bounds__(PTHREADS) k_hpart_scatter(HPassArgs a) {
   tile_scatter<uint32_t>(L, items, a.iout, tile_n, lpos);
 }
 
-// start[b] = first position of bucket b (top nbits of the hash), start[nb] = n
-__global__ void k_hbounds(const uint64_t* g, int64_t n, int nbits, int64_t nbucket, uint64_t* start) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= n; j += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cur = (j < n) ? (int64_t)(nbits ? (g[j] >> (64 - nbits)) : 0ull) : nbucket;
-    const int64_t prv = (j > 0) ? (int64_t)(nbits ? (g[j - 1] >> (64 - nbits)) : 0ull) : -1;
-    for (int64_t x = prv + 1; x <= cur; ++x) start[x] = (uint64_t)j;
-  }
-}
+constexpr int HDUP_THREADS = 1024;
+constexpr int HDUP_SLOTS = 18432;     // 64-bit hashes in LDS (144 KB of gfx950's 160 KB per workgroup)
+constexpr int HDUP_FILL = 13824;      // hashes per table fill (load <= 3/4); larger buckets go in slices
+constexpr int64_t HDUP_MEAN = 12500;  // bucket size the bucket bits aim at
 
-constexpr int HDUP_WAVES = 4;     // wavefronts per block
-constexpr int HDUP_SLOTS = 512;   // LDS hash table per wavefront
-constexpr int HDUP_MAX = 256;     // hashes per table fill; larger buckets are taken in slices
+// first probe slot of a hash: its low 32 bits scaled to [0, HDUP_SLOTS)
+SHCI_DEV int hdup_slot(uint64_t g) { return (int)(((g & 0xffffffffull) * (uint64_t)HDUP_SLOTS) >> 32); }
+SHCI_DEV int hdup_next(int s) { return s + 1 == HDUP_SLOTS ? 0 : s + 1; }
 
 struct HDupArgs {
   const uint64_t* g;
-  const uint32_t* item;
-  const uint64_t* bstart;
-  int64_t n;  // listed hashes
+  int64_t n;       // listed hashes, sorted by bucket
+  int nbits;       // bucket = top nbits of the hash
   int64_t nbucket;
-  int nbits;
-  int64_t nwaves;
   uint64_t* filt;
   int fbits;
-  unsigned long long* nrep;  // distinct repeated hashes set in the filter
+  unsigned long long* nrep;  // distinct repeated hashes (the filter's sizing)
 };
 
-// Repeated hashes of each bucket into the filter.  Each wavefront takes a
-// contiguous range of buckets.  A bucket's hashes (fillers skipped) go into a
-// wave-private LDS table, linear probing from the low hash bits with
-// compare-and-swap; a hash that finds itself already there marks its slot,
-// and every marked slot is set in the filter once.  A bucket with more
-// distinct hashes than the table holds is taken again in 2^k slices by the
-// hash bits below the bucket bits (a fresh table per slice), so the set of
-// repeated hashes, and with it the filter, depends on the listed terms only.
-// (Past 2^16 slices every hash of the bucket is set: more records, same
-// result.)
-__global__ void __launch_bounds__(64 * HDUP_WAVES) k_hdup(HDupArgs A) {
-  __shared__ unsigned long long tab[HDUP_WAVES][HDUP_SLOTS];
-  __shared__ uint8_t rep[HDUP_WAVES][HDUP_SLOTS];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * HDUP_WAVES + wv;
-  if (wave >= A.nwaves) return;
-  const int64_t per = (A.nbucket + A.nwaves - 1) / A.nwaves;
-  const int64_t b_lo = wave * per, b_hi = min(A.nbucket, b_lo + per);
-  unsigned long long nrep = 0;  // per lane
-  for (int64_t b = b_lo; b < b_hi; ++b) {
-    const int64_t lo = (int64_t)A.bstart[b];
-    const int64_t M = (int64_t)A.bstart[b + 1] - lo;
-    if (M < 2 || lo < 0 || lo + M > A.n) continue;  // uniform
-    int k = 0;            // uniform
+// Repeated hashes of each bucket into the filter, one workgroup per bucket
+// (buckets dealt round-robin; bounds by binary search of the sorted list).
+// The bucket's hashes (odd fillers skipped) go into an LDS hash table of
+// full 64-bit hashes, linear probing with compare-and-swap; a hash that
+// finds itself already there marks its slot; then every marked slot's hash
+// is set in the filter once.  The filter thus holds exactly the hashes that
+// occur more than once, whatever the order, the bucket sizes or the fillers.
+// A bucket of more than HDUP_FILL hashes is taken in 2^k slices by the hash
+// bits below the bucket bits (all copies of a hash share a slice).  (A slice
+// that still does not fit, which needs more than HDUP_SLOTS distinct hashes,
+// makes the next k; past 16, every hash of the bucket is set.)
+__global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
+  __shared__ unsigned long long tab[HDUP_SLOTS];
+  __shared__ uint32_t repb[HDUP_SLOTS / 32];
+  __shared__ int64_t bnd[2];
+  __shared__ int full_s;
+  const int t = threadIdx.x;
+  unsigned long long nrep = 0;  // per thread
+  for (int64_t b = blockIdx.x; b < A.nbucket; b += gridDim.x) {
+    if (t < 2) {
+      const uint64_t target = (uint64_t)(b + t);
+      int64_t lo = 0, hi = A.n;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((A.g[mid] >> (64 - A.nbits)) < target)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      bnd[t] = lo;
+    }
+    __syncthreads();
+    const int64_t lo = bnd[0], M = bnd[1] - bnd[0];
+    __syncthreads();
+    if (M < 2) continue;  // uniform
+    int k = 0;
+    while (((int64_t)HDUP_FILL << k) < M && k < 16) ++k;
     for (;;) {
       const int sshift = 64 - A.nbits - k;
-      unsigned long long found = 0;  // per lane, this attempt
-      bool full = false;             // uniform
+      const uint64_t smask = ((uint64_t)1 << k) - 1;
+      bool full = false;  // uniform after the barrier
+      unsigned long long cnt = 0;
       for (int64_t sl = 0; sl < ((int64_t)1 << k) && !full; ++sl) {
-        for (int s = lane; s < HDUP_SLOTS; s += 64) {
-          tab[wv][s] = 0ull;
-          rep[wv][s] = 0;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int s = t; s < HDUP_SLOTS; s += HDUP_THREADS) tab[s] = 0ull;
+        for (int s = t; s < HDUP_SLOTS / 32; s += HDUP_THREADS) repb[s] = 0u;
+        if (t == 0) full_s = 0;
+        __syncthreads();
         bool miss = false;
-        for (int64_t j0 = 0; j0 < M; j0 += 64) {
-          const int64_t j = j0 + lane;
-          if (j < M && A.item[lo + j] != HASH_HOLE) {
-            const uint64_t g = A.g[lo + j];
-            if (k == 0 || (int64_t)((g >> sshift) & (((uint64_t)1 << k) - 1)) == sl) {
-              int s = (int)(g & (HDUP_SLOTS - 1));
-              bool placed = false;
-              for (int probe = 0; probe < HDUP_SLOTS; ++probe) {
-                const unsigned long long old = atomicCAS(&tab[wv][s], 0ull, (unsigned long long)g);
-                if (old == 0ull) {
-                  placed = true;
-                  break;
-                }
-                if (old == (unsigned long long)g) {
-                  rep[wv][s] = 1;
-                  placed = true;
-                  break;
-                }
-                s = (s + 1) & (HDUP_SLOTS - 1);
-              }
-              miss = miss || !placed;
+        for (int64_t j = t; j < M; j += HDUP_THREADS) {
+          const uint64_t g = A.g[lo + j];
+          if ((g & 1ull) || (k && (int64_t)((g >> sshift) & smask) != sl)) continue;
+          int s = hdup_slot(g);
+          bool placed = false;
+          for (int probe = 0; probe < HDUP_SLOTS; ++probe) {
+            const unsigned long long old = atomicCAS(&tab[s], 0ull, (unsigned long long)g);
+            if (old == 0ull) {
+              placed = true;
+              break;
             }
+            if (old == (unsigned long long)g) {
+              atomicOr(&repb[s >> 5], 1u << (s & 31));
+              placed = true;
+              break;
+            }
+            s = hdup_next(s);
           }
+          miss = miss || !placed;
         }
-        full = ballot(miss) != 0ull;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (miss) full_s = 1;
+        __syncthreads();
+        full = full_s != 0;
         if (!full) {
-          for (int s = lane; s < HDUP_SLOTS; s += 64) {
-            if (rep[wv][s]) {
-              filt_insert(A.filt, A.fbits, tab[wv][s]);
-              found += 1;
+          for (int s = t; s < HDUP_SLOTS; s += HDUP_THREADS) {
+            if ((repb[s >> 5] >> (s & 31)) & 1u) {
+              filt_insert(A.filt, A.fbits, tab[s]);
+              cnt += 1;
             }
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __syncthreads();
       }
       if (!full) {
-        nrep += found;
+        nrep += cnt;
         break;
       }
-      // too many distinct hashes for one table: slices of ~HDUP_MAX hashes
-      int k2 = k + 1;
-      while (((int64_t)HDUP_MAX << k2) < M) ++k2;
-      if (k2 > 16 || A.nbits + k2 >= 64) {
-        for (int64_t j = lane; j < M; j += 64) {
-          if (A.item[lo + j] != HASH_HOLE) {
-            filt_insert(A.filt, A.fbits, A.g[lo + j]);
+      if (k >= 16) {
+        // every hash of the bucket
+        for (int64_t j = t; j < M; j += HDUP_THREADS) {
+          const uint64_t g = A.g[lo + j];
+          if (!(g & 1ull)) {
+            filt_insert(A.filt, A.fbits, g);
             nrep += 1;
           }
         }
         break;
       }
-      k = k2;
+      ++k;
     }
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) nrep += __shfl_xor(nrep, o);
-  if (lane == 0 && nrep) atomicAdd(A.nrep, nrep);
+  if ((t & 63) == 0 && nrep) atomicAdd(A.nrep, nrep);
 }
 
 // per work item, the listed terms whose hash passes the filter (the terms the
@@ -217,8 +213,8 @@ __global__ void __launch_bounds__(64 * HDUP_WAVES) k_hdup(HDupArgs A) {
 __global__ void k_hmark(const uint64_t* g, const uint32_t* item, int64_t n, const uint64_t* filt, int fbits,
                         uint32_t* mcount) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t it = item[j];
-    if (it != HASH_HOLE && filt_maybe(filt, fbits, g[j])) atomicAdd(&mcount[it], 1u);
+    const uint64_t gj = g[j];
+    if (!(gj & 1ull) && filt_maybe(filt, fbits, gj)) atomicAdd(&mcount[item[j]], 1u);
   }
 }
 

@@ -643,11 +643,13 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
   HashList HB;
   uint32_t *hist = nullptr, *hoffs = nullptr;
   ScanTmp hsc;
+  uint64_t* bst = nullptr;
   CHK(carve_region(AR, SL_HASH2, [&](Carver& cv) {
     plan_hash_list(cv, HB, nent);
     hist = cv.take<uint32_t>((size_t)256 * ntiles);
     hoffs = cv.take<uint32_t>((size_t)256 * ntiles + 1);
     hsc.carve(cv, (int64_t)256 * ntiles);
+    bst = cv.take<uint64_t>(nbucket + 1);
   }));
   HIPCHK(hipEventRecord(X->evh[0], st));
   HashList* cur = &HL;
@@ -675,6 +677,7 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     std::swap(cur, oth);
     shift += dbits;
   }
+  k_hbounds<<<(int)((nbucket + 256) / 256), 256, 0, st>>>(cur->k, nent, nbits, nbucket, bst);
   // filter of 32-64 bits per repeated hash: its size is a function of the
   // number of repeated hashes (so the records, and the sums, do not depend on
   // an earlier call); first guessed from the last job's rate, then again if
@@ -698,6 +701,7 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(X->dctr + 1), 1, 0ull);
     HDupArgs da{};
     da.g = cur->k;
+    da.bstart = bst;
     da.n = nent;
     da.nbits = nbits;
     da.nbucket = nbucket;

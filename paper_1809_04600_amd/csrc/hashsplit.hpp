@@ -89,13 +89,31 @@ constexpr int HDUP_THREADS = 1024;
 constexpr int HDUP_SLOTS = 18432;     // 64-bit hashes in LDS (144 KB of gfx950's 160 KB per workgroup)
 constexpr int HDUP_FILL = 13824;      // hashes per table fill (load <= 3/4); larger buckets go in slices
 constexpr int64_t HDUP_MEAN = 12500;  // bucket size the bucket bits aim at
+constexpr int HDUP_PROBES = 1024;     // longest probe run before the table counts as full
 
 // first probe slot of a hash: its low 32 bits scaled to [0, HDUP_SLOTS)
 SHCI_DEV int hdup_slot(uint64_t g) { return (int)(((g & 0xffffffffull) * (uint64_t)HDUP_SLOTS) >> 32); }
 SHCI_DEV int hdup_next(int s) { return s + 1 == HDUP_SLOTS ? 0 : s + 1; }
 
+// start[b] = first position of bucket b (top nbits of the hash) in the
+// sorted list, start[nbucket] = n: one binary search per thread
+__global__ void k_hbounds(const uint64_t* g, int64_t n, int nbits, int64_t nbucket, uint64_t* start) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b > nbucket) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((g[mid] >> (64 - nbits)) < (uint64_t)b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[b] = (uint64_t)lo;
+}
+
 struct HDupArgs {
   const uint64_t* g;
+  const uint64_t* bstart;  // bucket bounds (k_hbounds)
   int64_t n;       // listed hashes, sorted by bucket
   int nbits;       // bucket = top nbits of the hash
   int64_t nbucket;
@@ -105,42 +123,28 @@ struct HDupArgs {
 };
 
 // Repeated hashes of each bucket into the filter, one workgroup per bucket
-// (buckets dealt round-robin; bounds by binary search of the sorted list).
+// (buckets dealt round-robin).
 // The bucket's hashes (odd fillers skipped) go into an LDS hash table of
 // full 64-bit hashes, linear probing with compare-and-swap; a hash that
 // finds itself already there marks its slot; then every marked slot's hash
 // is set in the filter once.  The filter thus holds exactly the hashes that
 // occur more than once, whatever the order, the bucket sizes or the fillers.
-// A bucket of more than HDUP_FILL hashes is taken in 2^k slices by the hash
-// bits below the bucket bits (all copies of a hash share a slice).  (A slice
-// that still does not fit, which needs more than HDUP_SLOTS distinct hashes,
-// makes the next k; past 16, every hash of the bucket is set.)
+// A bucket whose distinct hashes overflow the table is taken again in 2^k
+// slices by the hash bits below the bucket bits (all copies of a hash share
+// a slice), k sized for HDUP_FILL hashes a slice; past k = 16 every hash of
+// the bucket is set.
 __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
   __shared__ unsigned long long tab[HDUP_SLOTS];
   __shared__ uint32_t repb[HDUP_SLOTS / 32];
-  __shared__ int64_t bnd[2];
   __shared__ int full_s;
   const int t = threadIdx.x;
   unsigned long long nrep = 0;  // per thread
   for (int64_t b = blockIdx.x; b < A.nbucket; b += gridDim.x) {
-    if (t < 2) {
-      const uint64_t target = (uint64_t)(b + t);
-      int64_t lo = 0, hi = A.n;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((A.g[mid] >> (64 - A.nbits)) < target)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      bnd[t] = lo;
-    }
-    __syncthreads();
-    const int64_t lo = bnd[0], M = bnd[1] - bnd[0];
-    __syncthreads();
-    if (M < 2) continue;  // uniform
+    const int64_t lo = (int64_t)A.bstart[b], M = (int64_t)A.bstart[b + 1] - lo;
+    if (M < 2 || lo + M > A.n) continue;  // uniform
+    // one table fill first (a large bucket of few distinct hashes fits);
+    // slices only when the table overflows
     int k = 0;
-    while (((int64_t)HDUP_FILL << k) < M && k < 16) ++k;
     for (;;) {
       const int sshift = 64 - A.nbits - k;
       const uint64_t smask = ((uint64_t)1 << k) - 1;
@@ -152,12 +156,14 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         if (t == 0) full_s = 0;
         __syncthreads();
         bool miss = false;
-        for (int64_t j = t; j < M; j += HDUP_THREADS) {
+        for (int64_t j = t; j < M && !miss; j += HDUP_THREADS) {
+          if (*(volatile int*)&full_s) break;  // another thread found the table full
           const uint64_t g = A.g[lo + j];
           if ((g & 1ull) || (k && (int64_t)((g >> sshift) & smask) != sl)) continue;
           int s = hdup_slot(g);
           bool placed = false;
-          for (int probe = 0; probe < HDUP_SLOTS; ++probe) {
+          // a probe run this long means the table is (nearly) full
+          for (int probe = 0; probe < HDUP_PROBES; ++probe) {
             const unsigned long long old = atomicCAS(&tab[s], 0ull, (unsigned long long)g);
             if (old == 0ull) {
               placed = true;
@@ -170,9 +176,11 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
             }
             s = hdup_next(s);
           }
-          miss = miss || !placed;
+          if (!placed) {
+            miss = true;
+            full_s = 1;
+          }
         }
-        if (miss) full_s = 1;
         __syncthreads();
         full = full_s != 0;
         if (!full) {
@@ -190,7 +198,7 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         break;
       }
       if (k >= 16) {
-        // every hash of the bucket
+        // every hash of the bucket (needs > 2^16 HDUP_SLOTS distinct hashes)
         for (int64_t j = t; j < M; j += HDUP_THREADS) {
           const uint64_t g = A.g[lo + j];
           if (!(g & 1ull)) {
@@ -200,7 +208,9 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         }
         break;
       }
-      ++k;
+      int k2 = k + 1;
+      while (((int64_t)HDUP_FILL << k2) < M && k2 < 16) ++k2;
+      k = k2;
     }
   }
 #pragma unroll

@@ -6,7 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
+#include <string>
+#include <thread>
 #include <new>
 #include <vector>
 
@@ -116,14 +119,13 @@ int ceil_log2(uint64_t x) {
 
 }  // namespace
 
-struct shci_pt2_ctx {
-  int device = 0;
-  Tables T;
-  DevBuf tables;
+namespace {
+// What one evaluation in flight uses besides its workspace: device scratch
+// words, events, the grow-only buffers of context memory and the split's
+// size estimates.  The context is lane 0; a second lane lets two sample
+// chunks run at once.
+struct Lane {
   DevBuf slot[NSLOT];
-  size_t ws_limit = 0;
-  int64_t rec_limit = 0;  // records per pass (0: from device memory)
-  int grouping = SHCI_GROUP_AUTO;
   double split_rate[2] = {0.0, 0.0};  // kept terms per work item of the last split job (det, sample)
   double split_rep[2] = {0.0, 0.0};   // repeated hashes per listed hash of the last split job
   uint32_t* dflag = nullptr;   // device scratch words (flags, counters)
@@ -133,16 +135,30 @@ struct shci_pt2_ctx {
   hipEvent_t evp[16] = {};  // around the partition scatter launches of a job (first 8 passes)
   hipEvent_t evh[2] = {};   // around the singleton split (hash partition, repeat finder, marks)
 };
+}  // namespace
+
+struct shci_pt2_ctx : Lane {
+  int device = 0;
+  Tables T;
+  DevBuf tables;
+  size_t ws_limit = 0;
+  int64_t rec_limit = 0;  // records per pass (0: from device memory)
+  int grouping = SHCI_GROUP_AUTO;
+  Lane lane1;                     // second lane (sample chunks two at a time)
+  hipStream_t lane1_stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 
 namespace {
 
 struct Arena {
   shci_pt2_ctx* X = nullptr;
+  Lane* L = nullptr;     // whose grow-only buffers serve context memory
   hipStream_t st = nullptr;
   char* base = nullptr;  // caller workspace, or nullptr: the context's buffers
   size_t cap = 0, off = 0;
-  Arena(shci_pt2_ctx* x, hipStream_t s, void* ws, size_t bytes)
-      : X(x), st(s), base(static_cast<char*>(ws)), cap(ws ? bytes : 0) {}
+  Arena(shci_pt2_ctx* x, hipStream_t s, void* ws, size_t bytes, Lane* lane = nullptr)
+      : X(x), L(lane ? lane : x), st(s), base(static_cast<char*>(ws)), cap(ws ? bytes : 0) {}
   bool caller() const { return base != nullptr; }
   size_t mark() const { return off; }
   void reset(size_t m) { off = m; }
@@ -161,8 +177,8 @@ struct Arena {
       off = o + bytes;
       return SHCI_OK;
     }
-    CHK(X->slot[slot].ensure(bytes, X->ws_limit, st));
-    *p = X->slot[slot].p;
+    CHK(L->slot[slot].ensure(bytes, X->ws_limit, st));
+    *p = L->slot[slot].p;
     return SHCI_OK;
   }
 };
@@ -447,6 +463,7 @@ struct Job {
   int64_t nhash = 0;     // listed hashes (fillers included)
   int64_t nmulti = 0;    // terms written as records
   float ms_k_split = 0;  // hash partition, repeat finder and marks
+  Lane* lane = nullptr;  // scratch words, events and estimates (nullptr: the context's own)
 };
 
 // Layout of the record region of one pass.
@@ -620,8 +637,8 @@ int64_t split_budget(const Arena& A) {
       (void)hipGetLastError();
       fr = 0;
     }
-    double a = (double)fr + (double)X->slot[SL_FILT].cap + (double)X->slot[SL_HASH].cap +
-               (double)X->slot[SL_HASH2].cap;
+    double a = (double)fr + (double)A.L->slot[SL_FILT].cap + (double)A.L->slot[SL_HASH].cap +
+               (double)A.L->slot[SL_HASH2].cap;
     if (X->ws_limit) a = std::min(a, (double)X->ws_limit);
     avail = 0.6 * a;
   }
@@ -632,6 +649,7 @@ int64_t split_budget(const Arena& A) {
 // work item and their scan; J.nmulti = terms that become records.
 int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t st, int cus) {
   shci_pt2_ctx* X = J.ctx;
+  Lane& R = J.lane ? *J.lane : *X;
   Arena& AR = *J.ar;
   // buckets of ~12k hashes (one LDS table fill each): 16 bits, two passes,
   // up to ~8e8 hashes
@@ -651,7 +669,7 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     hsc.carve(cv, (int64_t)256 * ntiles);
     bst = cv.take<uint64_t>(nbucket + 1);
   }));
-  HIPCHK(hipEventRecord(X->evh[0], st));
+  HIPCHK(hipEventRecord(R.evh[0], st));
   HashList* cur = &HL;
   HashList* oth = &HB;
   int shift = 0;
@@ -691,14 +709,14 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     while (w < wcap && (double)w * 2.0 < rep) w <<= 1;
     return w;
   };
-  uint64_t words = words_for(X->split_rep[sidx] * (double)nent);
+  uint64_t words = words_for(R.split_rep[sidx] * (double)nent);
   const int64_t dblocks = std::min<int64_t>(nbucket, (int64_t)cus * 4);
   unsigned long long nrep = 0;
   for (int attempt = 0;; ++attempt) {
     const int fbits = ceil_log2(words);
     k_fill_u64<<<(int)std::min<int64_t>(4096, ((int64_t)words + 255) / 256), 256, 0, st>>>(SP.filt, (int64_t)words,
                                                                                            0ull);
-    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(X->dctr + 1), 1, 0ull);
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(R.dctr + 1), 1, 0ull);
     HDupArgs da{};
     da.g = cur->k;
     da.bstart = bst;
@@ -707,10 +725,10 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     da.nbucket = nbucket;
     da.filt = SP.filt;
     da.fbits = fbits;
-    da.nrep = X->dctr + 1;
+    da.nrep = R.dctr + 1;
     k_hdup<<<(int)dblocks, HDUP_THREADS, 0, st>>>(da);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&nrep, X->dctr + 1, sizeof nrep, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&nrep, R.dctr + 1, sizeof nrep, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     SP.fbits = fbits;
     const uint64_t want = words_for((double)nrep);
@@ -720,19 +738,19 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     }
     break;
   }
-  X->split_rep[sidx] = nent > 0 ? (double)nrep / (double)nent : 0.0;
+  R.split_rep[sidx] = nent > 0 ? (double)nrep / (double)nent : 0.0;
   k_fill_u32<<<(int)std::min<int64_t>(4096, (SP.ni + 256) / 256), 256, 0, st>>>(SP.mcount, SP.ni + 1, 0u);
   k_hmark<<<(int)std::min<int64_t>(8192, (nent + 255) / 256 + 1), 256, 0, st>>>(cur->k, cur->i, nent, SP.filt,
                                                                                 SP.fbits, SP.mcount);
   CHK(scan_exclusive<uint32_t, uint64_t>(SP.mcount, SP.moffs, SP.ni, SP.msc, SP.moffs + SP.ni, st));
-  HIPCHK(hipEventRecord(X->evh[1], st));
+  HIPCHK(hipEventRecord(R.evh[1], st));
   HIPCHK(hipGetLastError());
   uint64_t nm = 0;
   HIPCHK(hipMemcpyAsync(&nm, SP.moffs + SP.ni, sizeof nm, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   J.nmulti = (int64_t)nm;
   float ms = 0;
-  HIPCHK(hipEventElapsedTime(&ms, X->evh[0], X->evh[1]));
+  HIPCHK(hipEventElapsedTime(&ms, R.evh[0], R.evh[1]));
   J.ms_k_split = ms;
   return SHCI_OK;
 }
@@ -740,6 +758,7 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
 template <int KW, typename VT, bool SAMPLE>
 int run_job(Job& J) {
   shci_pt2_ctx* X = J.ctx;
+  Lane& R = J.lane ? *J.lane : *X;
   const Tables& T = X->T;
   const int n = T.n;
   hipStream_t st = J.st;
@@ -761,11 +780,11 @@ int run_job(Job& J) {
   uint64_t *soff = p0.soff, *vtab = p0.vtab, *total = p0.total;
   uint64_t* vfilt = p0.vfilt;
   ScanTmp& sc0 = p0.sc0;
-  uint32_t* dflag = X->dflag;
-  uint32_t* counter = X->dflag + 1;
-  uint32_t* overflow = X->dflag + 2;
+  uint32_t* dflag = R.dflag;
+  uint32_t* counter = R.dflag + 1;
+  uint32_t* overflow = R.dflag + 2;
 
-  HIPCHK(hipEventRecord(X->ev[0], st));
+  HIPCHK(hipEventRecord(R.ev[0], st));
   k_fill_u32<<<1, 64, 0, st>>>(dflag, 4, 0u);
   k_validate<<<(int)((J.ndet + 255) / 256), 256, 0, st>>>(J.dets, J.c, J.ndet, n, T.na, T.nb, dflag);
   VSet V;
@@ -857,7 +876,7 @@ int run_job(Job& J) {
   SplitPlan SP;
   HashList HL;
   uint64_t hcap = 0;
-  double& rate = X->split_rate[SAMPLE ? 1 : 0];  // kept terms per work item, last split job
+  double& rate = R.split_rate[SAMPLE ? 1 : 0];  // kept terms per work item, last split job
   // runs of 64 to 512 slots (a run must take one emission of up to 64
   // terms), shorter for fewer terms: the unused tails of the runs (at most
   // one per wavefront) are partitioned too
@@ -897,19 +916,19 @@ int run_job(Job& J) {
       g.hkey = HL.k;
       g.hitem = HL.i;
       g.hcap = hcap;
-      g.hclaim = X->dctr;
+      g.hclaim = R.dctr;
       g.hrun = hrun;
     }
     k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
-    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(X->dctr), 4, 0ull);
-    HIPCHK(hipEventRecord(X->ev[4], st));
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(R.dctr), 4, 0ull);
+    HIPCHK(hipEventRecord(R.ev[4], st));
     k_gen_count<KW, SAMPLE, VT><<<gen_grid, 256, 0, st>>>(g);
-    HIPCHK(hipEventRecord(X->ev[5], st));
+    HIPCHK(hipEventRecord(R.ev[5], st));
     HIPCHK(hipGetLastError());
     // offs[ni] = total: the write walk checks every item's end against it
     CHK(scan_exclusive<uint32_t, uint64_t>(counts, offs, ni, sc, offs + ni, st));
     HIPCHK(hipMemcpyAsync(hostv, offs + ni, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hostv + 1, X->dctr, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hostv + 1, R.dctr, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return SHCI_OK;
   };
@@ -1050,19 +1069,19 @@ int run_job(Job& J) {
       g.out = A;
       g.bits_hash = G.bits_hash;
       k_fill_u32<<<1, 64, 0, st>>>(counter, 1, 0u);
-      HIPCHK(hipEventRecord(X->ev[6], st));
+      HIPCHK(hipEventRecord(R.ev[6], st));
       if constexpr (SAMPLE)
         k_gen_write_sample<KW, VT><<<gen_grid, 256, 0, st>>>(g);
       else
         k_gen_write<KW, VT><<<gen_grid, 256, 0, st>>>(g);
-      HIPCHK(hipEventRecord(X->ev[7], st));
+      HIPCHK(hipEventRecord(R.ev[7], st));
       HIPCHK(hipGetLastError());
       if (J.ex && J.ex->t_keys && J.ex->t_cap > 0 && pay) {
         k_export_terms<KW, VT><<<1024, 256, 0, st>>>(A, nrec, n, J.ex->t_keys, J.ex->t_i, J.ex->t_val,
                                                       J.ex->t_cap);
       }
     }
-    HIPCHK(hipEventRecord(X->ev[1], st));
+    HIPCHK(hipEventRecord(R.ev[1], st));
     // ---- hash partition (LSD over the bucket id) ----
     Recs* cur = &A;
     Recs* oth = &B;
@@ -1085,12 +1104,12 @@ int run_job(Job& J) {
         const int pgrid = (int)(8 * ((ntiles + 7) / 8));
         k_part_hist<KW><<<pgrid, 256, 0, st>>>(pa);
         CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
-        if (pass < 8) HIPCHK(hipEventRecord(X->evp[2 * pass], st));
+        if (pass < 8) HIPCHK(hipEventRecord(R.evp[2 * pass], st));
         if (pay)
           k_part_scatter<KW, VT, SAMPLE, true><<<pgrid, PTHREADS, 0, st>>>(pa);
         else
           k_part_scatter<KW, VT, SAMPLE, false><<<pgrid, PTHREADS, 0, st>>>(pa);
-        if (pass < 8) HIPCHK(hipEventRecord(X->evp[2 * pass + 1], st));
+        if (pass < 8) HIPCHK(hipEventRecord(R.evp[2 * pass + 1], st));
         HIPCHK(hipGetLastError());
         std::swap(cur, oth);
         shift += dbits;
@@ -1103,7 +1122,7 @@ int run_job(Job& J) {
       const uint64_t hb[2] = {0, (uint64_t)nrec};
       HIPCHK(hipMemcpyAsync(bst, hb, sizeof hb, hipMemcpyHostToDevice, st));
     }
-    HIPCHK(hipEventRecord(X->ev[2], st));
+    HIPCHK(hipEventRecord(R.ev[2], st));
     // ---- bucket reduce ----
     RedArgs ra{};
     ra.in = *cur;
@@ -1120,7 +1139,7 @@ int run_job(Job& J) {
     ra.want_u = J.want_u ? 1 : 0;
     ra.bstart = bst;
     ra.contrib = (J.keep && !SAMPLE) ? BP.contrib : nullptr;
-    uint32_t* slow_count = X->dflag + 3;
+    uint32_t* slow_count = R.dflag + 3;
     WaveRedArgs wa;
     wa.r = ra;
     wa.bstart = bst;
@@ -1136,7 +1155,7 @@ int run_job(Job& J) {
       const int64_t nw = G.nbucket / 32 + 1;
       k_fill_u32<<<(int)std::min<int64_t>(4096, (nw + 255) / 256), 256, 0, st>>>(BP.slow_bits, nw, 0u);
     }
-    HIPCHK(hipEventRecord(X->ev[8], st));
+    HIPCHK(hipEventRecord(R.ev[8], st));
     k_reduce_wave<KW, SAMPLE, VT><<<(int)wblocks, 64 * WRED_WAVES, 0, st>>>(wa);
     // buckets the wavefront kernel could not take: block kernel with a full-key sort
     ra.blist = slow;
@@ -1145,13 +1164,13 @@ int run_job(Job& J) {
       const int rgrid = (int)std::min<int64_t>(G.nbucket, (int64_t)cus * 2);
       k_reduce<KW, C, SAMPLE, VT><<<rgrid, 256, 0, st>>>(ra);
     }
-    HIPCHK(hipEventRecord(X->ev[9], st));
+    HIPCHK(hipEventRecord(R.ev[9], st));
     HIPCHK(hipGetLastError());
-    k_zero_result<<<1, 1, 0, st>>>(X->dres);
+    k_zero_result<<<1, 1, 0, st>>>(R.dres);
     if (SAMPLE) {
       if (split)
         k_item_bounds<<<(J.nsamp + 256) / 256, 256, 0, st>>>(w_src, J.it_s, ni, J.nsamp, SP.ib);
-      k_final_sample<<<J.nsamp, 1024, 0, st>>>(Pw, nwv, P, BP.slow_bits, G.bits_hash, X->dres, J.per_sample,
+      k_final_sample<<<J.nsamp, 1024, 0, st>>>(Pw, nwv, P, BP.slow_bits, G.bits_hash, R.dres, J.per_sample,
                                                 J.per_sample_de0, J.sample_scale, SP.PI,
                                                 split ? SP.ib : nullptr);
     } else {
@@ -1177,13 +1196,13 @@ int run_job(Job& J) {
         Q3.nuniq += o3; Q3.nintr += o3; Q3.nzero += o3; Q3.mind += o3;
         k_final_partial<<<(int)ifblocks, 256, 0, st>>>(SP.PI, ni, ichunk, Q3);
       }
-      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks + ifblocks, 0, 1, overflow, dflag, X->dres, nullptr, 0,
+      k_final<<<1, 1024, 0, st>>>(Q, fblocks + wfblocks + ifblocks, 0, 1, overflow, dflag, R.dres, nullptr, 0,
                                    nullptr, 1.0);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(X->ev[3], st));
+    HIPCHK(hipEventRecord(R.ev[3], st));
     uint32_t hov = 0;
-    HIPCHK(hipMemcpyAsync(&J.res, X->dres, sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&J.res, R.dres, sizeof(DevResult), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&hov, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (J.res.flags & 32u)
@@ -1198,21 +1217,21 @@ int run_job(Job& J) {
       continue;
     }
     float ms;
-    HIPCHK(hipEventElapsedTime(&ms, X->ev[0], X->ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms, R.ev[0], R.ev[1]));
     J.ms_gen = ms;
-    HIPCHK(hipEventElapsedTime(&ms, X->ev[1], X->ev[2]));
+    HIPCHK(hipEventElapsedTime(&ms, R.ev[1], R.ev[2]));
     J.ms_sort = ms;
-    HIPCHK(hipEventElapsedTime(&ms, X->ev[2], X->ev[3]));
+    HIPCHK(hipEventElapsedTime(&ms, R.ev[2], R.ev[3]));
     J.ms_reduce = ms;
-    HIPCHK(hipEventElapsedTime(&ms, X->ev[4], X->ev[5]));
+    HIPCHK(hipEventElapsedTime(&ms, R.ev[4], R.ev[5]));
     J.ms_k_count = ms;
-    HIPCHK(hipEventElapsedTime(&ms, X->ev[6], X->ev[7]));
+    HIPCHK(hipEventElapsedTime(&ms, R.ev[6], R.ev[7]));
     J.ms_k_write = ms;
-    HIPCHK(hipEventElapsedTime(&ms, X->ev[8], X->ev[9]));
+    HIPCHK(hipEventElapsedTime(&ms, R.ev[8], R.ev[9]));
     J.ms_k_reduce = ms;
     J.ms_k_part = 0;
     for (int p = 0; p < std::min(npass, 8); ++p) {
-      HIPCHK(hipEventElapsedTime(&ms, X->evp[2 * p], X->evp[2 * p + 1]));
+      HIPCHK(hipEventElapsedTime(&ms, R.evp[2 * p], R.evp[2 * p + 1]));
       J.ms_k_part += ms;
     }
     J.n_part = npass;
@@ -1354,7 +1373,7 @@ int64_t record_budget(const Arena& A, double per_rec) {
       (void)hipGetLastError();
       fr = 0;
     }
-    avail = fr + X->slot[SL_REC].cap;
+    avail = fr + A.L->slot[SL_REC].cap;
     if (X->ws_limit) avail = std::min(avail, X->ws_limit);
   }
   const size_t reserve = (size_t)(num_cus(X->device) * RED_BLOCKS_PER_CU * WRED_WAVES + 1024) * 64 + (2u << 20);
@@ -1706,6 +1725,9 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     X->dflag = cv.take<uint32_t>(16);
     X->dctr = cv.take<unsigned long long>(4);
     X->dres = cv.take<DevResult>(1);
+    X->lane1.dflag = cv.take<uint32_t>(16);
+    X->lane1.dctr = cv.take<unsigned long long>(4);
+    X->lane1.dres = cv.take<DevResult>(1);
 
   };
   {
@@ -1722,6 +1744,19 @@ int shci_pt2_ctx_create(int n_orb, int n_alpha, int n_beta, const double* h1, co
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
   for (auto& e : X->evh)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+  for (Lane* l : {static_cast<Lane*>(&X->lane1)}) {
+    for (auto& e : l->ev)
+      if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+    for (auto& e : l->evp)
+      if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+    for (auto& e : l->evh)
+      if (hipEventCreate(&e) != hipSuccess) return bail(fail(SHCI_ERR_HIP, "hipEventCreate failed"));
+  }
+  if (hipEventCreateWithFlags(&X->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&X->join, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&X->lane1_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(SHCI_ERR_HIP, "stream or event creation failed"));
+  k_fill_u32<<<1, 64, 0, st>>>(X->lane1.dflag, 16, 0u);
   if (hipMemcpyAsync(T.h1, h1, n2 * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return bail(fail(SHCI_ERR_HIP, "copy of h1 failed"));
   k_fill_u32<<<1, 64, 0, st>>>(X->dflag, 16, 0u);
@@ -1745,6 +1780,18 @@ void shci_pt2_ctx_destroy(shci_pt2_ctx* ctx) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->evh)
     if (e) (void)hipEventDestroy(e);
+  for (Lane* l : {static_cast<Lane*>(&ctx->lane1)}) {
+    for (auto& e : l->ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : l->evp)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : l->evh)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& b : l->slot) b.release();
+  }
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
+  if (ctx->lane1_stream) (void)hipStreamDestroy(ctx->lane1_stream);
   ctx->tables.release();
   for (auto& b : ctx->slot) b.release();
   delete ctx;
@@ -2019,80 +2066,33 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
   if (hf & 128u) return done(fail(SHCI_ERR_ARG, "sample_batch entries must lie in [0, n_batches)"));
   if (!(hsum > 0.0) || !std::isfinite(hsum)) return done(fail(SHCI_ERR_NONFINITE, "sum |c| is not positive and finite"));
 
-  // Samples are evaluated in chunks of consecutive samples whose records fit
-  // the workspace: one generation / partition / reduce launch sequence per
-  // chunk covers all its samples (sample id in the key).  The chunk length
-  // adapts to the records per sample seen so far.
+  // Samples are evaluated in chunks of consecutive samples: one generation /
+  // grouping launch sequence per chunk covers all its samples (sample id in
+  // the key).  The first chunk (up to 8 samples) sets the terms per sample;
+  // the others then take as many samples as a pass holds (a power of two).
+  // With a caller workspace the later chunks run two at a time on two lanes
+  // (this thread and the caller's stream; a second thread and stream), each
+  // with half of what is left of the workspace: one chunk's grouping (HBM
+  // bound) runs beside another's generation (VALU bound).  The chunk plan
+  // depends on the inputs and sizes only, so results do not depend on the
+  // timing; a chunk whose terms do not fit is evaluated as two halves.
   // (with the singleton split a term takes a list slot, not a record)
   const bool split_ok = ctx->grouping == SHCI_GROUP_AUTO && grad == nullptr;
-  const int64_t max_rec =
-      split_ok ? (ctx->rec_limit > 0 ? ctx->rec_limit
-                                     : std::max<int64_t>(1, std::min<int64_t>((int64_t)(0.9 * (double)HASH_CAP),
-                                                                              split_budget(AR))))
-               : record_budget(AR, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16, false,
-                                                grad != nullptr));
+  auto max_rec_of = [&](const Arena& A) -> int64_t {
+    return split_ok ? (ctx->rec_limit > 0 ? ctx->rec_limit
+                                          : std::max<int64_t>(1, std::min<int64_t>((int64_t)(0.9 * (double)HASH_CAP),
+                                                                                   split_budget(A))))
+                    : record_budget(A, record_bytes(key_words(ctx->T.n, sbits), precision == SHCI_FP32C ? 8 : 16,
+                                                    false, grad != nullptr));
+  };
   if (grad) k_fill_u64<<<(int)std::min<int64_t>(4096, (n_det + 255) / 256), 256, 0, s>>>(
       reinterpret_cast<uint64_t*>(grad), n_det, 0ull);
-  Job acc{};
-  acc.res.mind = INFINITY;
-  int64_t chunks = 0;
-  // chunks hold a power-of-two number of samples (the sample id then fills
-  // its key bits); the first chunk is small and sets the rate
   auto pow2_floor = [](int64_t v) {
     int32_t p = 1;
     while ((int64_t)p * 2 <= v) p *= 2;
     return p;
   };
-  int32_t k = std::min<int32_t>(n_samples, 8);
-  for (int32_t s0 = 0; s0 < n_samples;) {
-    k = std::min<int32_t>(k, n_samples - s0);
-    k_sample_compact<<<k, 256, 0, s>>>(t_det + (int64_t)s0 * n_draws, t_w + (int64_t)s0 * n_draws,
-                                         ucount + s0, uoff + s0, n_draws, 0, o_det, o_w, o_s);
-    Job J{};
-    J.ctx = ctx;
-    J.ar = &AR;
-    J.st = s;
-    J.dets = dets;
-    J.c = c;
-    J.ndet = n_det;
-    J.e0 = e0;
-    J.eps2 = eps2;
-    J.eps2_d = eps2_d;
-    J.precision = precision;
-    J.sample = true;
-    J.sbits = std::max(1, ceil_log2((uint64_t)k));
-    J.nsamp = k;
-    J.nd = (double)n_draws;
-    J.sum_abs = hsum;
-    J.it_det = o_det + hoff[s0];
-    J.it_w = o_w + hoff[s0];
-    J.it_s = o_s + hoff[s0];
-    J.n_items = (int64_t)(hoff[s0 + k] - hoff[s0]);
-    J.per_sample = per_sample + s0;
-    J.per_sample_de0 = psde0 + s0;
-    J.max_records = (AR.caller() && ctx->rec_limit == 0) ? REC_CAP_AUTO : max_rec;
-    J.samp_off = hoff.data() + s0;
-    if (n_batches > 1) {
-      // one batch of P per sample, the estimate scaled by the number of batches
-      J.bmask = (uint32_t)(n_batches - 1);
-      J.sbatch = sbatch + s0;
-      J.sample_scale = (double)n_batches;
-    }
-    if (grad) {
-      J.want_u = true;
-      J.grad = grad;
-      J.grad_scale = (double)n_batches / (double)n_samples;
-    }
-    int r = dispatch(J);
-    if (r == JOB_TOO_BIG) {
-      if (k == 1) return done(fail(SHCI_ERR_WORKSPACE, "one sample has %lld screened terms; the workspace holds %lld",
-                                   (long long)J.nrec, (long long)J.max_records_eff));
-      const double per = (double)J.nrec / k;
-      k = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(k - 1, (int64_t)(0.9 * (double)J.max_records_eff / per))));
-      continue;
-    }
-    if (r) return done(r);
-    ++chunks;
+  auto add_stats = [](Job& acc, const Job& J) {
     acc.res.nterm += J.res.nterm;
     acc.res.ngen += J.res.ngen;
     acc.res.nuniq += J.res.nuniq;
@@ -2117,11 +2117,122 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
     acc.ms_k_split += J.ms_k_split;
     acc.kw = std::max(acc.kw, J.kw);
     acc.vbytes = J.vbytes;
-    s0 += k;
-    // next chunk: as many samples as the budget allows at this chunk's rate
-    const double per = (double)std::max<int64_t>(1, J.nrec_all) / k;
-    k = pow2_floor(std::max<int64_t>(1, (int64_t)std::min<double>(n_samples, 0.9 * (double)max_rec / per)));
+  };
+  // one chunk [s0, s0 + k) on an arena, lane and stream; halves when its
+  // terms do not fit
+  std::function<int(int32_t, int32_t, Arena&, Lane*, hipStream_t, int64_t, Job&)> run_chunk =
+      [&](int32_t s0, int32_t k, Arena& A, Lane* lane, hipStream_t strm, int64_t max_rec, Job& acc) -> int {
+    k_sample_compact<<<k, 256, 0, strm>>>(t_det + (int64_t)s0 * n_draws, t_w + (int64_t)s0 * n_draws,
+                                            ucount + s0, uoff + s0, n_draws, 0, o_det, o_w, o_s);
+    Job J{};
+    J.ctx = ctx;
+    J.ar = &A;
+    J.lane = lane;
+    J.st = strm;
+    J.dets = dets;
+    J.c = c;
+    J.ndet = n_det;
+    J.e0 = e0;
+    J.eps2 = eps2;
+    J.eps2_d = eps2_d;
+    J.precision = precision;
+    J.sample = true;
+    J.sbits = std::max(1, ceil_log2((uint64_t)k));
+    J.nsamp = k;
+    J.nd = (double)n_draws;
+    J.sum_abs = hsum;
+    J.it_det = o_det + hoff[s0];
+    J.it_w = o_w + hoff[s0];
+    J.it_s = o_s + hoff[s0];
+    J.n_items = (int64_t)(hoff[s0 + k] - hoff[s0]);
+    J.per_sample = per_sample + s0;
+    J.per_sample_de0 = psde0 + s0;
+    J.max_records = (A.caller() && ctx->rec_limit == 0) ? REC_CAP_AUTO : max_rec;
+    J.samp_off = hoff.data() + s0;
+    if (n_batches > 1) {
+      // one batch of P per sample, the estimate scaled by the number of batches
+      J.bmask = (uint32_t)(n_batches - 1);
+      J.sbatch = sbatch + s0;
+      J.sample_scale = (double)n_batches;
+    }
+    if (grad) {
+      J.want_u = true;
+      J.grad = grad;
+      J.grad_scale = (double)n_batches / (double)n_samples;
+    }
+    const int r = dispatch(J);
+    if (r == JOB_TOO_BIG) {
+      if (k == 1)
+        return fail(SHCI_ERR_WORKSPACE, "one sample has %lld screened terms; the workspace holds %lld",
+                    (long long)J.nrec, (long long)J.max_records_eff);
+      const int32_t h = k / 2;
+      CHK(run_chunk(s0, h, A, lane, strm, max_rec, acc));
+      return run_chunk(s0 + h, k - h, A, lane, strm, max_rec, acc);
+    }
+    if (r) return r;
+    add_stats(acc, J);
+    acc.nbatch += 1;  // chunks evaluated
+    return SHCI_OK;
+  };
+  Job acc{};
+  acc.res.mind = INFINITY;
+  acc.nbatch = 0;
+  const int64_t max_rec0 = max_rec_of(AR);
+  const int32_t k0 = std::min<int32_t>(n_samples, 8);
+  if (int r = run_chunk(0, k0, AR, nullptr, s, max_rec0, acc)) return done(r);
+  if (k0 < n_samples) {
+    const bool two = AR.caller();
+    // the rest: chunks of kr samples (the budget of one lane when two run)
+    Arena half0(ctx, s, nullptr, 0), half1(ctx, ctx->lane1_stream, nullptr, 0, &ctx->lane1);
+    if (two) {
+      const size_t o = (AR.off + WS_ALIGN - 1) & ~(WS_ALIGN - 1);
+      const size_t left = AR.cap > o ? AR.cap - o : 0;
+      const size_t h = (left / 2) & ~(WS_ALIGN - 1);
+      half0 = Arena(ctx, s, AR.base + o, h);
+      half1 = Arena(ctx, ctx->lane1_stream, AR.base + o + h, left - h, &ctx->lane1);
+    }
+    const int64_t max_rec = two ? max_rec_of(half0) : max_rec0;
+    const double per = (double)std::max<int64_t>(1, acc.nrec_all) / k0;
+    const int32_t kr = pow2_floor(std::max<int64_t>(1, (int64_t)std::min<double>(n_samples, 0.9 * (double)max_rec / per)));
+    std::vector<std::pair<int32_t, int32_t>> plan;
+    for (int32_t s0 = k0; s0 < n_samples; s0 += kr) plan.emplace_back(s0, std::min<int32_t>(kr, n_samples - s0));
+    if (!two || plan.size() < 2) {
+      for (auto& ch : plan)
+        if (int r = run_chunk(ch.first, ch.second, two ? half0 : AR, nullptr, s, max_rec, acc)) return done(r);
+    } else {
+      // lane 1 starts after the work queued so far on the caller's stream
+      if (hipEventRecord(ctx->fork, s) != hipSuccess || hipStreamWaitEvent(ctx->lane1_stream, ctx->fork, 0) != hipSuccess)
+        return done(fail(SHCI_ERR_HIP, "stream fork failed"));
+      Job acc1{};
+      acc1.res.mind = INFINITY;
+      acc1.nbatch = 0;
+      int r1 = SHCI_OK;
+      std::string msg1;
+      std::thread t1([&] {
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+          r1 = fail(SHCI_ERR_HIP, "hipSetDevice failed");
+        } else {
+          for (size_t i = 1; i < plan.size() && r1 == SHCI_OK; i += 2)
+            r1 = run_chunk(plan[i].first, plan[i].second, half1, &ctx->lane1, ctx->lane1_stream, max_rec, acc1);
+        }
+        if (r1) msg1 = shci_pt2_last_error();
+        (void)hipStreamSynchronize(ctx->lane1_stream);
+      });
+      int r0 = SHCI_OK;
+      for (size_t i = 0; i < plan.size() && r0 == SHCI_OK; i += 2)
+        r0 = run_chunk(plan[i].first, plan[i].second, half0, nullptr, s, max_rec, acc);
+      t1.join();
+      // the caller's stream continues after lane 1's work
+      if (hipEventRecord(ctx->join, ctx->lane1_stream) != hipSuccess || hipStreamWaitEvent(s, ctx->join, 0) != hipSuccess)
+        return done(fail(SHCI_ERR_HIP, "stream join failed"));
+      if (r0) return done(r0);
+      if (r1) return done(fail(r1, "%s", msg1.c_str()));
+      // lane 0 took the even chunks, lane 1 the odd ones
+      add_stats(acc, acc1);
+      acc.nbatch += acc1.nbatch;
+    }
   }
+  const int64_t chunks = acc.nbatch;
   std::vector<double> ps(n_samples);
   if (hipMemcpyAsync(ps.data(), per_sample, n_samples * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

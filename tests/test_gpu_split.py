@@ -204,3 +204,34 @@ def test_split_two_thresholds():
     o = ref.pt2_sample_batched(*args, eps2, eps_psto, draws, 8, sb)
     assert np.abs(out.cpu().numpy() - o).max() <= 1e-9 * max(1.0, np.abs(o).max())
     ctx.close()
+
+
+def test_two_lanes_same_bits():
+    # with a caller workspace the later sample chunks run two at a time (two
+    # streams, two host threads); the chunk plan does not depend on that, so
+    # the results equal the one-lane run on context memory bit for bit
+    x = I.small(10, 3, 3, 200, 3, 9)
+    ctx, dets, c = context(x)
+    eps2, eps2_d = 1e-6, 1e-4
+    kw = dict(seed=5, n_samples=40, n_draws=50)
+    out1, m1, _, st1 = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", **kw)
+    ctx.set_record_limit(max(1, st1["n_terms_all"] // 12))
+    ws = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    try:
+        outl, ml, _, stl = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", **kw)
+        outw, mw, _, stw = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", ws=ws, **kw)
+        outw2 = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", ws=ws, **kw)[0]
+    finally:
+        ctx.set_record_limit(0)
+    print(f"two lanes: chunks {stl['n_chunks']} / {stw['n_chunks']}", flush=True)
+    assert stw["n_chunks"] >= 4 and stw["n_chunks"] == stl["n_chunks"]
+    assert torch.equal(outw, outl) and torch.equal(outw, outw2)
+    for k in COUNTS + ("n_terms_all",):
+        assert stw[k] == stl[k] == st1[k], k
+    # the records (repeated hashes and the filter's false positives) depend
+    # on the chunk plan only
+    assert stw["n_records"] == stl["n_records"]
+    draws = ctx.draws(c, 40, 50, 5).cpu().numpy().astype(np.uint32)
+    o = ref.pt2_sample(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2, eps2_d, draws)
+    assert np.abs(outw.cpu().numpy() - o).max() <= 1e-9 * max(1.0, np.abs(o).max())
+    ctx.close()

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle_pt2.so")
+# ORACLE_LIB: another build of the same sources (the sanitizer test)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle_pt2.so")
 _lib = None
 
 _d = C.c_double

@@ -175,3 +175,33 @@ def test_w3_gradient_modes(w3):
     # -sum A^2/D^2 is dominated by the smallest denominators (min |D| = 2e-6 Ha),
     # whose relative rounding is ~1e-14 Ha / |D|: a looser relative bar
     assert abs(dk - gold["de2_de0"]) <= 1e-6 * abs(gold["de2_de0"])
+
+
+def test_w3_three_step_paper_sizes(w3):
+    # the 3-step correction (section IV) at the paper's minimum sizes: 16
+    # pseudo-stochastic batches of P, 16 samples (>= 10) of 2000 draws, one
+    # of 16 batches of P per sample.  A vanishing target evaluates every
+    # pseudo-stochastic batch, which then equals the difference of two
+    # deterministic evaluations; the stochastic part equals the batched
+    # sampling call on the same seed.
+    x, ctx, dets, c = w3
+    wl = x.wl
+    eps_dtm, eps_psto, eps2 = wl.eps2, 2e-6, wl.eps2_sto
+    kw = dict(seed=wl.draw_seed, n_samples=16, n_draws=wl.n_draws)
+    res, per = ctx.three_step(dets, c, x.e0, eps_dtm, eps_psto, eps2, 1e-30, 16, 16, None, None, "fp64", **kw)
+    d_dtm = ctx.det(dets, c, x.e0, eps_dtm, "fp64")
+    d_psto = ctx.det(dets, c, x.e0, eps_psto, "fp64")
+    out, mean, sem, _ = ctx.sample_batched(dets, c, x.e0, eps2, eps_psto, None, 16, None, "fp64", **kw)
+    print(f"w3 3-step: {res}; det(dtm) {d_dtm.e2!r} det(psto) {d_psto.e2!r} sampled {mean!r} +- {sem!r}",
+          flush=True)
+    assert res["psto_batches_used"] == 16 and res["err_psto"] == 0.0
+    assert abs(res["e2_dtm"] - d_dtm.e2) <= 1e-12 * abs(d_dtm.e2)
+    assert abs(res["e2_psto"] - (d_psto.e2 - d_dtm.e2)) <= 1e-10 * abs(d_psto.e2)
+    assert abs(res["e2_sto"] - mean) <= 1e-12 * max(abs(mean), 1e-12)
+    assert torch.equal(per, out)
+    assert abs(res["e2"] - (res["e2_dtm"] + res["e2_psto"] + res["e2_sto"])) <= 1e-12
+    # a loose target stops after the first batches with an error estimate
+    res1, _ = ctx.three_step(dets, c, x.e0, eps_dtm, eps_psto, eps2, 1e-3, 16, 16, None, None, "fp64", **kw)
+    print(f"w3 3-step, target 1e-3 Ha: {res1}", flush=True)
+    assert 1 <= res1["psto_batches_used"] <= 16
+    assert res1["err"] > 0.0

@@ -53,9 +53,12 @@ def parse():
     ap.add_argument("--workload", default="w3")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-hc", action="store_true", help="skip the H c timing")
+    ap.add_argument("--no-three-step", action="store_true", help="skip the 3-step run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="only summarise the rocprofv3 runs under DIR into profiles/")
     return ap.parse_args()
 
 
@@ -86,6 +89,91 @@ def measured(workload, kernel):
     if t.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     return t.get("kernels", {}).get(kernel)
+
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def _db(path):
+    """The rocpd SQLite database under a rocprofv3 output directory."""
+    import glob
+    import sqlite3
+    f = sorted(glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True))
+    if not f:
+        raise SystemExit(f"no rocprofv3 results database under {path}")
+    return sqlite3.connect(f[0])
+
+
+def _counters(path):
+    """Per kernel name: dispatches and the mean of each counter per dispatch."""
+    import collections
+    cur = _db(path).cursor()
+    tot = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for name, cn, val, did in cur.execute(
+            "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        tot[name][cn] += val
+        disp[name].add(did)
+    return {k: {"dispatches": len(disp[k]), **{c: v / len(disp[k]) for c, v in tot[k].items()}} for k in tot}
+
+
+def profile_summary(root, workload):
+    """Reads the rocprofv3 runs of the profiling recipe
+    under `root` (kernel trace: prof/; counter passes: pmc_fetch/, pmc_write/,
+    pmc_sq1/, pmc_sq2/; copy calibration: pmc_cfetch/, pmc_cwrite/) and writes
+    profiles/counters_<workload>.json (per kernel: HBM bytes per launch from
+    FETCH_SIZE and WRITE_SIZE scaled by the plain copy's readings, VALU-busy
+    lane slots per launch, the counters; with the SHA-256 of the HIP sources)
+    and profiles/kernels_<workload>.md."""
+    cur = _db(os.path.join(root, "prof")).cursor()
+    # kernel durations in ns
+    trace = [(n, int(c), float(t), float(t) / int(c)) for n, c, t in
+             cur.execute("select name, count(*), sum(duration) from kernels group by name "
+                         "order by sum(duration) desc")]
+    cal = {}
+    for kind, sub in (("FETCH_SIZE", "pmc_cfetch"), ("WRITE_SIZE", "pmc_cwrite")):
+        c = _counters(os.path.join(root, sub)).get(COPY_KERNEL, {})
+        # the probe copies 1 GiB three times: bytes read = bytes written = 2^30
+        kib = [v for k, v in c.items() if k == kind]
+        cal[kind] = (2.0 ** 30) / (kib[0] * 1024.0) if kib and kib[0] > 0 else None
+    per = {}
+    for sub in ("pmc_fetch", "pmc_write", "pmc_sq1", "pmc_sq2"):
+        if os.path.isdir(os.path.join(root, sub)):
+            for k, v in _counters(os.path.join(root, sub)).items():
+                per.setdefault(k, {}).update(v)
+    kernels = {}
+    for name, v in per.items():
+        e = {"dispatches": v.get("dispatches"), "counters": {c: x for c, x in v.items() if c != "dispatches"}}
+        if cal.get("FETCH_SIZE") and cal.get("WRITE_SIZE") and "FETCH_SIZE" in v and "WRITE_SIZE" in v:
+            e["hbm_bytes_per_launch"] = 1024.0 * (v["FETCH_SIZE"] * cal["FETCH_SIZE"] + v["WRITE_SIZE"] * cal["WRITE_SIZE"])
+        if "SQ_ACTIVE_INST_VALU" in v:
+            # SQ_ACTIVE_INST_VALU counts quad-cycles: 4 cycles x 16 lanes of a SIMD
+            e["valu_busy_lane_slots_per_launch"] = 64.0 * v["SQ_ACTIVE_INST_VALU"]
+        kernels[name] = e
+    out = {"workload": workload, "kernel_sources_sha256": kernel_sources_sha256(),
+           "calibration": {"copy_bytes": 2 ** 30, "fetch_factor": cal.get("FETCH_SIZE"),
+                           "write_factor": cal.get("WRITE_SIZE")},
+           "kernels": kernels}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"counters_{workload}.json"), "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    lines = [f"# Kernels of the {workload} benchmark step (MI355X)", "",
+             "Kernel trace (rocprofv3 --kernel-trace --stats), per kernel:", "",
+             "| kernel | calls | total ms | average ms | HBM bytes / launch (counters) | VALU busy |", "|---|---|---|---|---|---|"]
+    for n, c, t, a in trace[:24]:
+        k = kernels.get(n, {})
+        hb = k.get("hbm_bytes_per_launch")
+        busy = None
+        if k.get("valu_busy_lane_slots_per_launch") and a > 0:
+            busy = k["valu_busy_lane_slots_per_launch"] / (a * 1e-9) / (VALU_PEAK_GOPS * 1e9)
+        lines.append(f"| `{n[:90]}` | {c} | {t / 1e6:.2f} | {a / 1e6:.3f} | "
+                     f"{'' if hb is None else f'{hb / 1e9:.3f} GB'} | {'' if busy is None else f'{busy:.1%}'} |")
+    lines += ["", f"Calibration: FETCH_SIZE x {cal.get('FETCH_SIZE')}, WRITE_SIZE x {cal.get('WRITE_SIZE')} "
+              "(a plain 1 GiB device copy reads and writes 2^30 bytes).",
+              f"HIP sources SHA-256: {out['kernel_sources_sha256']}"]
+    with open(os.path.join(ROOT, "profiles", f"kernels_{workload}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps({"written": [f"profiles/counters_{workload}.json", f"profiles/kernels_{workload}.md"]}))
 
 
 def copy_probe(mib):
@@ -170,9 +258,11 @@ def roofline(kernel, bound, alg_bytes, launches, ms, measured_kernel):
            "avg_ms": ms / launches}
     if measured_kernel:
         out["traffic"] = measured_kernel.get("hbm_bytes_per_launch")
-        if bound == "alu" and measured_kernel.get("valu_lane_ops_per_launch"):
-            ops = measured_kernel["valu_lane_ops_per_launch"] / avg_s / 1e9
-            out.update({"achieved": ops, "peak": VALU_PEAK_GOPS, "unit": "G lane-ops/s",
+        if bound == "alu" and measured_kernel.get("valu_busy_lane_slots_per_launch"):
+            # VALU-busy lane slots (SQ_ACTIVE_INST_VALU x 64) per second against
+            # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+            ops = measured_kernel["valu_busy_lane_slots_per_launch"] / avg_s / 1e9
+            out.update({"achieved": ops, "peak": VALU_PEAK_GOPS, "unit": "G VALU lane-slots/s",
                         "frac": ops / VALU_PEAK_GOPS, "hbm_gbs": achieved})
     if bound == "alu" and out["unit"] == "GB/s":
         out["note"] = "VALU counters not taken for these kernel sources; HBM rate shown"
@@ -185,7 +275,7 @@ def split_bytes_per_hash(per_launch):
     writes hash and work item (24); the bucket bounds read the hash (8), the
     repeat finder and the marks read hash and work item (12 each)."""
     import math
-    nbits = max(1, math.ceil(math.log2(max(1.0, (per_launch + 127) // 128))))
+    nbits = max(1, math.ceil(math.log2(max(1.0, math.ceil(per_launch / 12500.0)))))
     npass = (nbits + 7) // 8
     return 32.0 * npass + 32.0, npass
 
@@ -284,6 +374,24 @@ def hc_timing(ctx, x, dets, c, reps=3):
             "e_var_minus_e0": ev - x.e0}
 
 
+def three_step_run(ctx, x, dets, c, ws):
+    """The 3-step correction (section IV) once, at the paper's minimum sizes:
+    16 pseudo-stochastic batches of P at eps2_psto = 2e-6 (evaluated until the
+    error of the rest is below 0.4 x 1e-4 Ha), 16 samples of the workload's
+    draws with one of 16 batches of P each; outside the timed steps."""
+    import torch
+    wl = x.wl
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = ctx.three_step(dets, c, x.e0, wl.eps2, 2e-6, wl.eps2_sto, 1e-4, 16, 16, None, None, "fp64",
+                            seed=wl.draw_seed, n_samples=16, n_draws=wl.n_draws, ws=ws)
+    torch.cuda.synchronize()
+    res["wall_ms"] = (time.perf_counter() - t0) * 1e3
+    res.update({"eps2_dtm": wl.eps2, "eps2_psto": 2e-6, "eps2": wl.eps2_sto, "nb_psto": 16, "nb_sto": 16,
+                "n_samples": 16, "target_error": 1e-4})
+    return res
+
+
 def e0_prime(ctx, x, dets, c):
     """E0' = <c'|H|c'>/<c'|c'> over HF and its MP1 doubles (their c as
     stored), by H c on that subspace on the device."""
@@ -307,6 +415,9 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.profile_summary:
+        profile_summary(a.profile_summary, a.workload)
         return
     import torch
 
@@ -359,7 +470,9 @@ def main():
     tot = run_main["total"]
     n_terms = tot["n_terms"]
     rl, ms, rec = kernel_rooflines(wl, run_main, avg_main, prec_main)
-    dom = max((k for k in ms if rl.get(k)), key=ms.get)
+    # the dominant kernel by its own launch time (the split's figure spans
+    # several kernels and, with two lanes, the other lane's kernels)
+    dom = max((k for k in ms if rl.get(k) and k != "split"), key=ms.get)
     out = {
         "metric": METRIC,
         "value": n_terms / w_main,
@@ -415,6 +528,8 @@ def main():
             "e0_prime": ep, "e0": x.e0, "subspace": nsub, "e2": e2p, "e2_sem": runp["sem"],
             "min_abs_denom": runp["total"]["min_abs_denom"], "n_intruder": runp["total"]["n_intruder"],
             "wall_s": time.perf_counter() - ts}
+    if wl.n_samples and not big and not a.no_three_step:
+        out["three_step"] = three_step_run(ctx, x, dets, c, ws)
     if not a.no_hc:
         out["hc"] = hc_timing(ctx, x, dets, c)
     if not a.no_cpu:

@@ -43,7 +43,12 @@
  *
  * Streams: all work is enqueued on `stream` (a hipStream_t, NULL = default
  * stream).  Calls that return host scalars synchronise that stream before
- * returning.
+ * returning.  Exception: the sampling calls with a workspace evaluate every
+ * other chunk of samples on a second stream owned by the context, from a
+ * second host thread, with half of the workspace left; that stream starts
+ * after the work already queued on `stream`, and `stream` waits for it before
+ * the call returns.  The chunk plan does not depend on this, so the results
+ * are the same bits as with one stream.
  *
  * Errors: every entry point returns an shci_status; nothing is thrown across
  * the ABI.  shci_pt2_last_error() returns a thread-local message for the last

@@ -90,6 +90,7 @@ constexpr int HDUP_SLOTS = 18432;     // 64-bit hashes in LDS (144 KB of gfx950'
 constexpr int HDUP_FILL = 13824;      // hashes per table fill (load <= 3/4); larger buckets go in slices
 constexpr int64_t HDUP_MEAN = 12500;  // bucket size the bucket bits aim at
 constexpr int HDUP_PROBES = 1024;     // longest probe run before the table counts as full
+constexpr int HDUP_PER_THREAD = 16;   // hashes a thread loads at once (buckets up to 16k)
 
 // first probe slot of a hash: its low 32 bits scaled to [0, HDUP_SLOTS)
 SHCI_DEV int hdup_slot(uint64_t g) { return (int)(((g & 0xffffffffull) * (uint64_t)HDUP_SLOTS) >> 32); }
@@ -156,31 +157,40 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         if (t == 0) full_s = 0;
         __syncthreads();
         bool miss = false;
-        for (int64_t j = t; j < M && !miss; j += HDUP_THREADS) {
-          if (*(volatile int*)&full_s) break;  // another thread found the table full
-          const uint64_t g = A.g[lo + j];
-          if ((g & 1ull) || (k && (int64_t)((g >> sshift) & smask) != sl)) continue;
+        // places g (odd fillers and other slices skipped); false: table full
+        auto place = [&](uint64_t g) -> bool {
+          if ((g & 1ull) || (k && (int64_t)((g >> sshift) & smask) != sl)) return true;
           int s = hdup_slot(g);
-          bool placed = false;
           // a probe run this long means the table is (nearly) full
           for (int probe = 0; probe < HDUP_PROBES; ++probe) {
             const unsigned long long old = atomicCAS(&tab[s], 0ull, (unsigned long long)g);
-            if (old == 0ull) {
-              placed = true;
-              break;
-            }
+            if (old == 0ull) return true;
             if (old == (unsigned long long)g) {
               atomicOr(&repb[s >> 5], 1u << (s & 31));
-              placed = true;
-              break;
+              return true;
             }
             s = hdup_next(s);
           }
-          if (!placed) {
-            miss = true;
-            full_s = 1;
+          return false;
+        };
+        if (M <= (int64_t)HDUP_PER_THREAD * HDUP_THREADS) {
+          // a bucket of typical size: all of this thread's hashes loaded at
+          // once (fillers in place of the missing ones), then placed
+          uint64_t gv[HDUP_PER_THREAD];
+#pragma unroll
+          for (int i = 0; i < HDUP_PER_THREAD; ++i) {
+            const int64_t j = t + (int64_t)i * HDUP_THREADS;
+            gv[i] = j < M ? A.g[lo + j] : 1ull;
+          }
+#pragma unroll
+          for (int i = 0; i < HDUP_PER_THREAD; ++i) miss = miss || !place(gv[i]);
+        } else {
+          for (int64_t j = t; j < M && !miss; j += HDUP_THREADS) {
+            if (*(volatile int*)&full_s) break;  // another thread found the table full
+            miss = !place(A.g[lo + j]);
           }
         }
+        if (miss) full_s = 1;
         __syncthreads();
         full = full_s != 0;
         if (!full) {

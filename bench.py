@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-hc", action="store_true", help="skip the H c timing")
     ap.add_argument("--no-three-step", action="store_true", help="skip the 3-step run")
+    ap.add_argument("--lanes", type=int, default=2, help="sample chunks in flight at once (1 or 2)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
@@ -362,6 +363,26 @@ def cpu_baseline(x, budget_s):
             "seconds": total_t}
 
 
+def achievable_copy_gbs(mib=2048, reps=5):
+    """Bytes read plus written per second of a plain device copy of `mib` MiB
+    (torch's copy kernel), the practical HBM rate next to the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def hc_timing(ctx, x, dets, c, reps=3):
     """H c on the same V (string lists and rows), outside the PT2 step:
     device time of the last of `reps` calls, connections per second, and the
@@ -441,6 +462,7 @@ def main():
     ctx = P.Context(h1, eri, wl.n_alpha, wl.n_beta)
     torch.cuda.synchronize()
     table_ms = (time.perf_counter() - t0) * 1e3
+    ctx.set_lanes(a.lanes)
     del eri
     torch.cuda.empty_cache()
     # caller-owned workspace: the calls allocate nothing (w4 uses the
@@ -451,6 +473,7 @@ def main():
         ws = torch.empty(int(0.8 * free) // 256 * 256, dtype=torch.uint8, device=dev)
     step = Step(ctx, x, dets, c, ws, grad=big)
     prec_main = "fp32c" if big else "fp64"
+    copy_gbs = achievable_copy_gbs() if ws is not None else None
     for k in range(warmup):
         print(f"bench: warmup {k}", file=sys.stderr, flush=True)
         step(prec_main)
@@ -491,7 +514,7 @@ def main():
                    "eps2": wl.eps2, "n_terms": n_terms, "n_records": tot["n_records"],
                    "n_singletons": tot["n_singletons"], "n_hashes": tot["n_hashes"],
                    "n_unique": tot["n_unique"], "parallelism": "single GPU",
-                   "precision": prec_main,
+                   "precision": prec_main, "lanes": a.lanes,
                    "workspace_bytes": int(ws.numel()) if ws is not None else None,
                    **({"eps2_sto": wl.eps2_sto, "n_samples": wl.n_samples, "n_draws": wl.n_draws,
                        "draws": f"seed path, seed {wl.draw_seed}", "e2_sem": run_main["sem"],
@@ -500,6 +523,7 @@ def main():
                    "min_abs_denom": tot["min_abs_denom"], "n_intruder": tot["n_intruder"]},
         "roofline": rl[dom],
         "roofline_kernels": rl,
+        "achievable_copy_gbs": copy_gbs,
         "alg_efficiency": {"bytes_per_term": 80.0, "gbs": 80.0 * n_terms / w_main / 1e9,
                            "frac": 80.0 * n_terms / w_main / 1e9 / HBM_PEAK_GBS},
         "e2": e2_main,

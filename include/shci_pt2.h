@@ -228,6 +228,12 @@ int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records);
 enum { SHCI_GROUP_AUTO = 0, SHCI_GROUP_RECORDS = 1 };
 int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode);
 
+/* Sample chunks in flight at once in the sampling calls with a workspace: 2
+ * (default; a second stream and host thread take every other chunk, see
+ * Streams above) or 1 (every chunk on `stream`, in order).  The results are
+ * the same bits either way; 1 gives each kernel the whole GPU (profiling). */
+int shci_pt2_ctx_set_lanes(shci_pt2_ctx* ctx, int lanes);
+
 /* Deterministic screened PT2 (screened PT2 equation).
  *   dets  device uint64 [n_det][4], unique, with n_alpha / n_beta electrons;
  *   c     device FP64 [n_det];

@@ -93,6 +93,8 @@ def lib():
         L.shci_pt2_ctx_set_record_limit.restype = i
         L.shci_pt2_ctx_set_grouping.argtypes = [p, i]
         L.shci_pt2_ctx_set_grouping.restype = i
+        L.shci_pt2_ctx_set_lanes.argtypes = [p, i]
+        L.shci_pt2_ctx_set_lanes.restype = i
         u64, sz, i32 = C.c_uint64, C.c_size_t, C.c_int32
         L.shci_pt2_workspace_size.argtypes = [p, i, i64, i64, i32, i32, i, C.POINTER(sz)]
         L.shci_pt2_workspace_size.restype = i
@@ -226,6 +228,10 @@ class Context:
         if mode not in m:
             raise ValueError(f"grouping must be one of {sorted(m)}")
         _check(lib().shci_pt2_ctx_set_grouping(self._ptr, m[mode]))
+
+    def set_lanes(self, lanes: int):
+        """Sample chunks in flight at once with a caller workspace (1 or 2)."""
+        _check(lib().shci_pt2_ctx_set_lanes(self._ptr, int(lanes)))
 
     def _inputs(self, dets, c):
         nd = c.shape[0]

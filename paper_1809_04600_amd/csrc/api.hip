@@ -144,6 +144,7 @@ struct shci_pt2_ctx : Lane {
   size_t ws_limit = 0;
   int64_t rec_limit = 0;  // records per pass (0: from device memory)
   int grouping = SHCI_GROUP_AUTO;
+  int lanes = 2;                  // sample chunks in flight at once with a caller workspace
   Lane lane1;                     // second lane (sample chunks two at a time)
   hipStream_t lane1_stream = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -1811,6 +1812,13 @@ int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode) {
   return SHCI_OK;
 }
 
+int shci_pt2_ctx_set_lanes(shci_pt2_ctx* ctx, int lanes) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
+  if (lanes != 1 && lanes != 2) return fail(SHCI_ERR_ARG, "lanes must be 1 or 2");
+  ctx->lanes = lanes;
+  return SHCI_OK;
+}
+
 int shci_pt2_ctx_set_workspace_limit(shci_pt2_ctx* ctx, size_t bytes) {
   if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
   ctx->ws_limit = bytes;
@@ -2181,7 +2189,7 @@ static int sample_impl(shci_pt2_ctx* ctx, const uint64_t* dets, const double* c,
   const int32_t k0 = std::min<int32_t>(n_samples, 8);
   if (int r = run_chunk(0, k0, AR, nullptr, s, max_rec0, acc)) return done(r);
   if (k0 < n_samples) {
-    const bool two = AR.caller();
+    const bool two = AR.caller() && ctx->lanes == 2;
     // the rest: chunks of kr samples (the budget of one lane when two run)
     Arena half0(ctx, s, nullptr, 0), half1(ctx, ctx->lane1_stream, nullptr, 0, &ctx->lane1);
     if (two) {

@@ -221,11 +221,14 @@ def test_two_lanes_same_bits():
         outl, ml, _, stl = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", **kw)
         outw, mw, _, stw = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", ws=ws, **kw)
         outw2 = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", ws=ws, **kw)[0]
+        ctx.set_lanes(1)
+        outw1 = ctx.sample(dets, c, x.e0, eps2, eps2_d, None, "fp64", ws=ws, **kw)[0]
     finally:
         ctx.set_record_limit(0)
+        ctx.set_lanes(2)
     print(f"two lanes: chunks {stl['n_chunks']} / {stw['n_chunks']}", flush=True)
     assert stw["n_chunks"] >= 4 and stw["n_chunks"] == stl["n_chunks"]
-    assert torch.equal(outw, outl) and torch.equal(outw, outw2)
+    assert torch.equal(outw, outl) and torch.equal(outw, outw2) and torch.equal(outw, outw1)
     for k in COUNTS + ("n_terms_all",):
         assert stw[k] == stl[k] == st1[k], k
     # the records (repeated hashes and the filter's false positives) depend

@@ -900,9 +900,9 @@ SHCI_DEV void gen_body(const GenArgs& a) {
 }
 
 // The walks of the generator.  The count walk carries the least state and
-// gains from six wavefronts per SIMD, the deterministic write walk from five;
-// the sample write walk and the adjoint walk keep the compiler's choice (all
-// measured).
+// gains from six wavefronts per SIMD, the deterministic write walk from five,
+// the sample write walk (in-place sums of the singleton split) from four; the
+// adjoint walk keeps the compiler's choice (all measured).
 template <int KW, bool SAMPLE, typename VT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_gen_count(GenArgs a) {
   gen_body<KW, GEN_COUNT, SAMPLE, VT>(a);
@@ -912,7 +912,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   gen_body<KW, GEN_WRITE, false, VT>(a);
 }
 template <int KW, typename VT>
-__global__ void __launch_bounds__(256) k_gen_write_sample(GenArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_gen_write_sample(GenArgs a) {
   gen_body<KW, GEN_WRITE, true, VT>(a);
 }
 template <int KW, bool SAMPLE, typename VT>

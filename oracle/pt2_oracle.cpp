@@ -709,10 +709,14 @@ int oracle_det_batch(int n, int na, int nb, const double* h1, const double* eri,
 //            + 2 (w_i (Nd-1)/p_i - w_i^2/p_i^2) c_i H_ai^2 - (the same over the
 //            eps2_d terms, with X_a^d) ] / ((E0 - H_aa) Nd (Nd-1)),
 // and per sample de0[s] = dS_s/dE0 = -sum_a [...] / ((E0 - H_aa)^2 Nd (Nd-1)).
+// sens[s] = sum_a |[...]| / ((E0 - H_aa)^2 Nd (Nd-1)) = sum_a |contribution_a| /
+// |E0 - H_aa|: to first order, a change delta of every denominator moves S_s
+// by at most delta * sens[s] (the conditioning of the estimate on H_aa).
 static int sample_core(const System& S, const Det* V, int64_t nd, const double* c, const double* c_ref,
                        double e0, double eps2, double eps2_d, int32_t ns, int32_t ndraw,
                        const uint32_t* draws, double* out, double* grad, double* de0,
-                       int32_t n_batches = 1, const int32_t* sbatch = nullptr, int64_t* nterm = nullptr) {
+                       int32_t n_batches = 1, const int32_t* sbatch = nullptr, int64_t* nterm = nullptr,
+                       double* sens = nullptr) {
   int st = validate(S, V, c_ref, nd);
   if (st) return st;
   if (ndraw < 2 || ns < 1 || !(eps2 >= 0.0) || !(eps2_d >= eps2)) {
@@ -793,7 +797,7 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
     heads.push_back(terms.size());
     const int64_t ngroups = (int64_t)heads.size() - 1;
     const int nthr = omp_get_max_threads();
-    std::vector<Neumaier> part(nthr), dpart(nthr);
+    std::vector<Neumaier> part(nthr), dpart(nthr), spart(nthr);
     std::vector<int64_t> kept_terms(nthr, 0);  // terms of a outside V
     // per group: X, X^d and 1 / (D Nd (Nd-1)) (0 for members of V)
     std::vector<double> gX(grad ? ngroups : 0), gXd(grad ? ngroups : 0), gG(grad ? ngroups : 0);
@@ -819,6 +823,7 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
       double bracket = (X * X + Y) - (Xd * Xd + Yd);
       part[omp_get_thread_num()].add(bracket / (Dd * Nd * (Nd - 1.0)));
       dpart[omp_get_thread_num()].add(-bracket / (Dd * Dd * Nd * (Nd - 1.0)));
+      spart[omp_get_thread_num()].add(std::fabs(bracket / (Dd * Dd * Nd * (Nd - 1.0))));
       if (grad) {
         gX[g] = X;
         gXd[g] = Xd;
@@ -839,6 +844,14 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
       for (int t = 0; t < nthr; ++t) nterm[s] += kept_terms[t];
     }
     if (de0) de0[s] = (double)n_batches * dtot.value();
+    if (sens) {
+      Neumaier stot;
+      for (int t = 0; t < nthr; ++t) {
+        stot.add(spart[t].s);
+        stot.add(spart[t].c);
+      }
+      sens[s] = (double)n_batches * stot.value();
+    }
     if (grad) {
       // terms in (a, i) order; per source i the sum runs in that order
       for (int64_t g = 0; g < ngroups; ++g) {
@@ -858,13 +871,13 @@ static int sample_core(const System& S, const Det* V, int64_t nd, const double* 
 }
 
 // The per-sample estimates and, per sample, the number of kept terms whose a
-// lies outside V.
+// lies outside V and (sens, nullable) the conditioning on H_aa (sample_core).
 int oracle_pt2_sample_counts(int n, int na, int nb, const double* h1, const double* eri, const uint64_t* dets,
                              const double* c, int64_t nd, double e0, double eps2, double eps2_d, int32_t ns,
-                             int32_t ndraw, const uint32_t* draws, double* out, int64_t* nterm) {
+                             int32_t ndraw, const uint32_t* draws, double* out, int64_t* nterm, double* sens) {
   System S{n, na, nb, h1, eri};
   return sample_core(S, reinterpret_cast<const Det*>(dets), nd, c, c, e0, eps2, eps2_d, ns, ndraw, draws, out,
-                     nullptr, nullptr, 1, nullptr, nterm);
+                     nullptr, nullptr, 1, nullptr, nterm, sens);
 }
 
 int oracle_pt2_sample(int n, int na, int nb, const double* h1, const double* eri,

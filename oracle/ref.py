@@ -60,7 +60,7 @@ def lib():
                                         C.c_int32, C.c_int32, _p, _p]
         L.oracle_pt2_sample_counts.restype = _i
         L.oracle_pt2_sample_counts.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d,
-                                               C.c_int32, C.c_int32, _p, _p, _p]
+                                               C.c_int32, C.c_int32, _p, _p, _p, _p]
         L.oracle_det_batch.restype = _i
         L.oracle_det_batch.argtypes = [_i, _i, _i, _p, _p, _p, _p, _i64, _d, _d, _d, _i, _i, _p, _p]
         L.oracle_pt2_sample_batched.restype = _i
@@ -229,8 +229,11 @@ def pt2_sample(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
     return out
 
 
-def pt2_sample_counts(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
-    """(per-sample estimates, per-sample kept terms with a outside V) on explicit draws."""
+def pt2_sample_counts(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws, *, sens=False):
+    """(per-sample estimates, per-sample kept terms with a outside V) on
+    explicit draws; with sens=True also, per sample, sum_a |contribution_a| /
+    |E0 - H_aa| (a change delta of every denominator moves the estimate by at
+    most delta times this, to first order)."""
     h1, eri = _sys(h1, eri)
     dets = np.ascontiguousarray(dets, dtype=np.uint64)
     c = np.ascontiguousarray(c, dtype=np.float64)
@@ -238,13 +241,14 @@ def pt2_sample_counts(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_d, draws):
     ns, nd = draws.shape
     out = np.zeros(ns)
     cnt = np.zeros(ns, dtype=np.int64)
+    sv = np.zeros(ns)
     L = lib()
     st = L.oracle_pt2_sample_counts(n, na, nb, _ptr(h1), _ptr(eri), _ptr(dets), _ptr(c), len(c),
                                     float(e0), float(eps2), float(eps2_d), ns, nd, _ptr(draws), _ptr(out),
-                                    _ptr(cnt))
+                                    _ptr(cnt), _ptr(sv) if sens else None)
     if st:
         raise OracleError(st, L.oracle_last_error().decode())
-    return out, cnt
+    return (out, cnt, sv) if sens else (out, cnt)
 
 
 def det_batch(n, na, nb, h1, eri, dets, c, e0, eps2, eps2_hi, n_batches, batch):

@@ -17,7 +17,8 @@ samples: the per-sample stochastic estimates S_s(eps2) - S_s(eps2^d)
 (stochastic PT2 equation) of 256 samples of 2000 draws made by the oracle's
 alias sampler from the seed (draws of sample s, draw k: outputs 2(s N_d + k) + 1
 and + 2 of SplitMix64 seeded with the workload's draw seed), with a digest of
-the draws.
+the draws, and per sample sum_a |contribution_a| / |E0 - H_aa|, the
+estimate's first-order sensitivity to the rounding of the denominators.
 """
 from __future__ import annotations
 
@@ -86,8 +87,8 @@ def run_samples(x) -> dict:
     wl = x.wl
     t = time.time()
     draws = ref.alias_draws(x.c, wl.n_samples, wl.n_draws, wl.draw_seed)
-    out, cnt = ref.pt2_sample_counts(wl.n_orb, wl.n_alpha, wl.n_beta, x.h1, x.eri, x.dets, x.c, x.e0,
-                                     wl.eps2_sto, wl.eps2, draws)
+    out, cnt, sens = ref.pt2_sample_counts(wl.n_orb, wl.n_alpha, wl.n_beta, x.h1, x.eri, x.dets, x.c, x.e0,
+                                           wl.eps2_sto, wl.eps2, draws, sens=True)
     dt = time.time() - t
     return {
         "workload": "w3",
@@ -100,6 +101,7 @@ def run_samples(x) -> dict:
         "draws_digest": hashlib.sha256(np.ascontiguousarray(draws, dtype="<u4").tobytes()).hexdigest(),
         "per_sample": [float(v) for v in out],
         "per_sample_terms": [int(v) for v in cnt],
+        "per_sample_sensitivity": [float(v) for v in sens],
         "n_terms": int(cnt.sum()),
         "mean": float(np.mean(out)),
         "oracle_seconds": dt,

@@ -399,3 +399,23 @@ def test_hc_rows_rejects_bad_rows(space_227):
     x, dets, index, H, W = space_227
     with pytest.raises(ref.OracleError):
         ref.hc_rows(7, 3, 2, x.h1, x.eri, W[:5], np.ones(5), np.array([5]))
+
+
+def test_sample_sensitivity_bounds_the_e0_derivative():
+    # sum_a |contribution_a| / |D_a| bounds |dS_s/dE0| = |sum_a contribution_a / D_a|
+    # and equals it when every group has the same sign of contribution / D
+    x = I.small(8, 2, 2, 40, 2, 3)
+    a = (8, 2, 2, x.h1, x.eri)
+    rng = np.random.default_rng(3)
+    p = np.abs(x.c) / np.abs(x.c).sum()
+    dr = rng.choice(len(x.c), size=(4, 9), p=p).astype(np.uint32)
+    out, cnt, sens = ref.pt2_sample_counts(*a, x.dets, x.c, x.e0, 1e-7, 1e-5, dr, sens=True)
+    o2, _, de0 = ref.pt2_sample_grad(*a, x.dets, x.c, x.e0, 1e-7, 1e-5, dr)
+    assert np.array_equal(out, o2)
+    assert np.all(sens >= np.abs(de0) * (1 - 1e-12))
+    # a single-reference system far below its perturbers: every D_a < 0 and
+    # every bracket > 0, so sens = |dS/dE0|
+    one = np.zeros((1, 8), dtype=np.uint32)
+    o1, _, s1 = ref.pt2_sample_counts(*a, x.dets[:1], np.array([1.0]), x.e0 - 50.0, 0.0, 1e9, one, sens=True)
+    _, _, d1 = ref.pt2_sample_grad(*a, x.dets[:1], np.array([1.0]), x.e0 - 50.0, 0.0, 1e9, one)
+    assert abs(s1[0] - abs(d1[0])) <= 1e-12 * abs(d1[0])

@@ -119,24 +119,30 @@ def _counters(path):
 
 
 def profile_summary(root, workload):
-    """Reads the rocprofv3 runs of the profiling recipe
-    under `root` (kernel trace: prof/; counter passes: pmc_fetch/, pmc_write/,
-    pmc_sq1/, pmc_sq2/; copy calibration: pmc_cfetch/, pmc_cwrite/) and writes
+    """Reads the rocprofv3 runs of the profiling recipe (the commands listed at
+    the head of profiles/kernels_<workload>.md) under `root` (kernel traces:
+    prof/, prof1/; counter passes: pmc_fetch/, pmc_write/, pmc_sq1/, pmc_sq2/;
+    copy calibration: pmc_cfetch/, pmc_cwrite/) and writes
     profiles/counters_<workload>.json (per kernel: HBM bytes per launch from
     FETCH_SIZE and WRITE_SIZE scaled by the plain copy's readings, VALU-busy
     lane slots per launch, the counters; with the SHA-256 of the HIP sources)
     and profiles/kernels_<workload>.md."""
-    cur = _db(os.path.join(root, "prof")).cursor()
-    # kernel durations in ns
-    trace = [(n, int(c), float(t), float(t) / int(c)) for n, c, t in
-             cur.execute("select name, count(*), sum(duration) from kernels group by name "
-                         "order by sum(duration) desc")]
+    def trace_of(sub):
+        cur = _db(os.path.join(root, sub)).cursor()
+        # kernel durations in ns
+        return [(n, int(c), float(t), float(t) / int(c)) for n, c, t in
+                cur.execute("select name, count(*), sum(duration) from kernels group by name "
+                            "order by sum(duration) desc")]
+    trace = trace_of("prof")
     cal = {}
     for kind, sub in (("FETCH_SIZE", "pmc_cfetch"), ("WRITE_SIZE", "pmc_cwrite")):
-        c = _counters(os.path.join(root, sub)).get(COPY_KERNEL, {})
-        # the probe copies 1 GiB three times: bytes read = bytes written = 2^30
-        kib = [v for k, v in c.items() if k == kind]
-        cal[kind] = (2.0 ** 30) / (kib[0] * 1024.0) if kib and kib[0] > 0 else None
+        # the probe's copies of 1 GiB read and write 2^30 bytes each; other
+        # dispatches of the copy kernel (small transfers) are left out
+        cur = _db(os.path.join(root, sub)).cursor()
+        kib = [v for (v,) in cur.execute("select value from counters_collection where kernel_name = ? and "
+                                         "counter_name = ?", (COPY_KERNEL, kind))]
+        big = max(kib) if kib else 0.0
+        cal[kind] = (2.0 ** 30) / (big * 1024.0) if big > 0 else None
     per = {}
     for sub in ("pmc_fetch", "pmc_write", "pmc_sq1", "pmc_sq2"):
         if os.path.isdir(os.path.join(root, sub)):
@@ -158,19 +164,44 @@ def profile_summary(root, workload):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"counters_{workload}.json"), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
+    def table(tr, title):
+        rows = [title, "",
+                "| kernel | calls | total ms | average ms | HBM bytes / launch (counters) | HBM GB/s | VALU busy |",
+                "|---|---|---|---|---|---|---|"]
+        for n, c, t, a in tr[:24]:
+            k = kernels.get(n, {})
+            hb = k.get("hbm_bytes_per_launch")
+            busy = None
+            if k.get("valu_busy_lane_slots_per_launch") and a > 0:
+                busy = k["valu_busy_lane_slots_per_launch"] / (a * 1e-9) / (VALU_PEAK_GOPS * 1e9)
+            gbs = hb / a if (hb is not None and a > 0) else None
+            rows.append(f"| `{n[:90]}` | {c} | {t / 1e6:.2f} | {a / 1e6:.3f} | "
+                        f"{'' if hb is None else f'{hb / 1e9:.3f} GB'} | {'' if gbs is None else f'{gbs:.0f}'} | "
+                        f"{'' if busy is None else f'{busy:.1%}'} |")
+        return rows
+    b = "bench.py --steps 1 --warmup 0 --fp32c-steps 0 --no-cpu --no-hc --no-three-step"
     lines = [f"# Kernels of the {workload} benchmark step (MI355X)", "",
-             "Kernel trace (rocprofv3 --kernel-trace --stats), per kernel:", "",
-             "| kernel | calls | total ms | average ms | HBM bytes / launch (counters) | VALU busy |", "|---|---|---|---|---|---|"]
-    for n, c, t, a in trace[:24]:
-        k = kernels.get(n, {})
-        hb = k.get("hbm_bytes_per_launch")
-        busy = None
-        if k.get("valu_busy_lane_slots_per_launch") and a > 0:
-            busy = k["valu_busy_lane_slots_per_launch"] / (a * 1e-9) / (VALU_PEAK_GOPS * 1e9)
-        lines.append(f"| `{n[:90]}` | {c} | {t / 1e6:.2f} | {a / 1e6:.3f} | "
-                     f"{'' if hb is None else f'{hb / 1e9:.3f} GB'} | {'' if busy is None else f'{busy:.1%}'} |")
-    lines += ["", f"Calibration: FETCH_SIZE x {cal.get('FETCH_SIZE')}, WRITE_SIZE x {cal.get('WRITE_SIZE')} "
+             "Commands (repository root, TMPDIR=/tmp), then `python3 bench.py --profile-summary <dir>`:", "", "```",
+             f"rocprofv3 --kernel-trace --stats -d <dir>/prof -o w3 -- python3 {b}",
+             f"rocprofv3 --pmc FETCH_SIZE -d <dir>/pmc_fetch -o w3 -- python3 {b}",
+             f"rocprofv3 --pmc WRITE_SIZE -d <dir>/pmc_write -o w3 -- python3 {b}",
+             f"rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_BUSY_CYCLES "
+             f"SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_SALU GRBM_GUI_ACTIVE -d <dir>/pmc_sq1 -o w3 -- python3 {b}",
+             f"rocprofv3 --pmc SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_INT32 "
+             f"SQ_INSTS_VALU_FLOPS_FP64 SQ_WAIT_INST_LDS SQ_LDS_BANK_CONFLICT -d <dir>/pmc_sq2 -o w3 -- python3 {b}",
+             "rocprofv3 --pmc FETCH_SIZE -d <dir>/pmc_cfetch -o copy -- python3 bench.py --copy-probe 1024",
+             "rocprofv3 --pmc WRITE_SIZE -d <dir>/pmc_cwrite -o copy -- python3 bench.py --copy-probe 1024",
+             f"rocprofv3 --kernel-trace --stats -d <dir>/prof1 -o w3 -- python3 {b} --lanes 1",
+             "```", ""]
+    lines += table(trace, "Kernel trace of the benchmark command (two lanes: kernels of two sample chunks overlap):")
+    if os.path.isdir(os.path.join(root, "prof1")):
+        lines += [""] + table(trace_of("prof1"), "Kernel trace with one lane (every kernel alone on the GPU):")
+    lines += ["", "HBM bytes: FETCH_SIZE and WRITE_SIZE per dispatch (KiB) scaled by a plain copy's readings; "
+              "FETCH_SIZE counts L2 fills from the fabric, MALL hits included.",
+              f"Calibration: FETCH_SIZE x {cal.get('FETCH_SIZE')}, WRITE_SIZE x {cal.get('WRITE_SIZE')} "
               "(a plain 1 GiB device copy reads and writes 2^30 bytes).",
+              "VALU busy: SQ_ACTIVE_INST_VALU x 64 lane slots per launch over the average launch time, against "
+              "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.",
               f"HIP sources SHA-256: {out['kernel_sources_sha256']}"]
     with open(os.path.join(ROOT, "profiles", f"kernels_{workload}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")

@@ -473,6 +473,7 @@ struct BigDims {
   bool v2 = false, pay = false, want_u = false, keep = false;
   int64_t nrec = 0, nbucket = 1, ntiles = 1;
   int64_t npart = 1;  // per-wavefront partial slots (waves, times the sample slots in sample mode)
+  int64_t nqslot = 1536;  // first-level slots of the final sums
   int npass = 0;
 };
 struct BigPlan {
@@ -525,7 +526,7 @@ void plan_big(CV& cv, const BigDims& d, BigPlan& o) {
   o.hsc.carve(cv, std::max<int64_t>((int64_t)256 * d.ntiles, nb + 1));
   plan_partials(cv, o.P, nb, true);
   plan_partials(cv, o.Pw, d.npart, false);
-  plan_partials(cv, o.Pq, 1536, false);
+  plan_partials(cv, o.Pq, d.nqslot, false);
   if (d.want_u) {
     for (int w = 0; w < d.kw; ++w) o.U.k[w] = cv.template take<uint64_t>(d.nrec);
     o.U.h2 = cv.template take<uint32_t>(d.nrec);
@@ -1038,6 +1039,7 @@ int run_job(Job& J) {
     const int64_t nwv = wblocks * WRED_WAVES;
     const int64_t nslots = SAMPLE ? ((int64_t)1 << G.sbits) : 1;
     bd.npart = nwv * nslots;
+    bd.nqslot = std::max<int64_t>(1536, nslots);
     BigPlan BP;
     if (AR.caller()) {
       // the records must fit what the workspace has left; otherwise report
@@ -1171,9 +1173,12 @@ int run_job(Job& J) {
     if (SAMPLE) {
       if (split)
         k_item_bounds<<<(J.nsamp + 256) / 256, 256, 0, st>>>(w_src, J.it_s, ni, J.nsamp, SP.ib);
-      k_final_sample<<<J.nsamp, 1024, 0, st>>>(Pw, nwv, P, BP.slow_bits, G.bits_hash, R.dres, J.per_sample,
-                                                J.per_sample_de0, J.sample_scale, SP.PI,
-                                                split ? SP.ib : nullptr);
+      // slices per sample: up to 32, within the 1536 slots of Pq
+      const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(32, 1536 / std::max<int32_t>(1, J.nsamp)));
+      k_final_sample_part<<<J.nsamp * gs, 256, 0, st>>>(Pw, nwv, P, BP.slow_bits, G.bits_hash, SP.PI,
+                                                          split ? SP.ib : nullptr, gs, Pq);
+      k_final_sample_sum<<<(J.nsamp + 255) / 256, 256, 0, st>>>(Pq, gs, J.nsamp, R.dres, J.per_sample,
+                                                                 J.per_sample_de0, J.sample_scale);
     } else {
       // the block kernel's bucket partials (through the bitmap, in bucket
       // order) and the per-wavefront partials, summed in a fixed order

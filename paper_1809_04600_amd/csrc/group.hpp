@@ -1028,58 +1028,62 @@ __global__ void __launch_bounds__(1024) k_final(Partials P, int64_t nb, int64_t 
   }
 }
 
-// Sample mode, one block per sample s of the chunk: the per-wavefront slots
-// Pw[s][0..nwaves) and the per-bucket partials of the block kernel's buckets
-// of s (marked in `bits`, buckets [s << bits_hash, (s + 1) << bits_hash)),
-// each thread over a fixed range, then a fixed tree.
-// With the singleton split, also the in-place partials PI of the sample's
-// work items [ib[s], ib[s + 1]).
-__global__ void __launch_bounds__(1024) k_final_sample(Partials Pw, int64_t nwaves, Partials P, const uint32_t* bits,
-                                                       int bits_hash, DevResult* res, double* per_sample,
-                                                       double* per_sample_de0, double sample_scale, Partials PI,
-                                                       const uint64_t* ib) {
-  __shared__ double r1[1024], r2[1024], r3[1024];
-  __shared__ int64_t i1[1024], i2[1024], i3[1024], i4[1024], i5[1024];
+// Sample mode, first level: block b = s * G + g sums slice g (of G) of
+// sample s's per-wavefront slots Pw[s][0..nwaves), of the block kernel's
+// buckets of s (marked in `bits`, buckets [s << bits_hash, (s + 1) <<
+// bits_hash)) and, with the singleton split, of the in-place partials PI of
+// its work items [ib[s], ib[s + 1]), into slot b of Q; fixed ranges per
+// thread, then a fixed tree.
+template <class F>
+SHCI_DEV void slice_of(int64_t n, int g, int G, F&& f) {
+  const int64_t lo = n * g / G, hi = n * (g + 1) / G;
+  const int64_t per = (hi - lo + 255) / 256;
+  const int64_t b0 = lo + (int64_t)threadIdx.x * per, b1 = min(hi, b0 + per);
+  for (int64_t i = b0; i < b1; ++i) f(i);
+}
+
+__global__ void __launch_bounds__(256) k_final_sample_part(Partials Pw, int64_t nwaves, Partials P, const uint32_t* bits,
+                                                           int bits_hash, Partials PI, const uint64_t* ib, int G,
+                                                           Partials Q) {
+  __shared__ double r1[256], r2[256], r3[256];
+  __shared__ int64_t i1[256], i2[256], i3[256], i4[256], i5[256];
   const int t = threadIdx.x;
-  const int64_t s = blockIdx.x;
+  const int64_t s = blockIdx.x / G;
+  const int g = (int)(blockIdx.x % G);
   double e = 0.0, d = 0.0, mn = INFINITY;
   int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
-  auto add = [&](const Partials& Q, int64_t i) {
-    e += Q.e2[i];
-    d += Q.de0[i];
-    mn = fmin(mn, Q.mind[i]);
-    nt += Q.nterm[i];
-    ng += Q.ngen[i];
-    nu += Q.nuniq[i];
-    ni += Q.nintr[i];
-    nz += Q.nzero[i];
+  auto add = [&](const Partials& X, int64_t i) {
+    e += X.e2[i];
+    d += X.de0[i];
+    mn = fmin(mn, X.mind[i]);
+    nt += X.nterm[i];
+    ng += X.ngen[i];
+    nu += X.nuniq[i];
+    ni += X.nintr[i];
+    nz += X.nzero[i];
   };
-  const int64_t per = (nwaves + 1023) / 1024;
-  for (int64_t w = t * per; w < min(nwaves, (int64_t)(t + 1) * per); ++w) add(Pw, s * nwaves + w);
+  slice_of(nwaves, g, G, [&](int64_t w) { add(Pw, s * nwaves + w); });
   const int64_t b0 = s << bits_hash, nbk = (int64_t)1 << bits_hash;
   if (nbk >= 32) {
-    const int64_t w0 = b0 / 32, nw = nbk / 32;
-    const int64_t pw = (nw + 1023) / 1024;
-    for (int64_t wd = w0 + t * pw; wd < w0 + min(nw, (int64_t)(t + 1) * pw); ++wd) {
-      uint32_t m = bits[wd];
+    slice_of(nbk / 32, g, G, [&](int64_t wd) {
+      uint32_t m = bits[b0 / 32 + wd];
       while (m) {
-        add(P, wd * 32 + __ffs(m) - 1);
+        add(P, (b0 / 32 + wd) * 32 + __ffs(m) - 1);
         m &= m - 1;
       }
-    }
-  } else if (t == 0) {
+    });
+  } else if (g == 0 && t == 0) {
     for (int64_t b = b0; b < b0 + nbk; ++b)
       if ((bits[b >> 5] >> (b & 31)) & 1u) add(P, b);
   }
   if (ib) {
-    const int64_t lo = (int64_t)ib[s], cnt = (int64_t)ib[s + 1] - lo;
-    const int64_t pi = (cnt + 1023) / 1024;
-    for (int64_t i = lo + t * pi; i < lo + min(cnt, (int64_t)(t + 1) * pi); ++i) add(PI, i);
+    const int64_t lo = (int64_t)ib[s];
+    slice_of((int64_t)ib[s + 1] - lo, g, G, [&](int64_t i) { add(PI, lo + i); });
   }
   r1[t] = e; r2[t] = d; r3[t] = mn;
   i1[t] = nt; i2[t] = ng; i3[t] = nu; i4[t] = ni; i5[t] = nz;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
+  for (int o = 128; o > 0; o >>= 1) {
     if (t < o) {
       r1[t] += r1[t + o];
       r2[t] += r2[t + o];
@@ -1093,16 +1097,45 @@ __global__ void __launch_bounds__(1024) k_final_sample(Partials Pw, int64_t nwav
     __syncthreads();
   }
   if (t == 0) {
-    per_sample[s] = sample_scale * r1[0];
-    if (per_sample_de0) per_sample_de0[s] = sample_scale * r2[0];
-    atomicAdd((unsigned long long*)&res->nterm, (unsigned long long)i1[0]);
-    atomicAdd((unsigned long long*)&res->ngen, (unsigned long long)i2[0]);
-    atomicAdd((unsigned long long*)&res->nuniq, (unsigned long long)i3[0]);
-    atomicAdd((unsigned long long*)&res->nintr, (unsigned long long)i4[0]);
-    atomicAdd((unsigned long long*)&res->nzero, (unsigned long long)i5[0]);
-    // |D| >= 0: the bit patterns of non-negative doubles order like the values
-    atomicMin((unsigned long long*)&res->mind, (unsigned long long)__double_as_longlong(r3[0]));
+    const int64_t b = blockIdx.x;
+    Q.e2[b] = r1[0];
+    Q.de0[b] = r2[0];
+    Q.mind[b] = r3[0];
+    Q.nterm[b] = i1[0];
+    Q.ngen[b] = i2[0];
+    Q.nuniq[b] = (int32_t)i3[0];
+    Q.nintr[b] = (int32_t)i4[0];
+    Q.nzero[b] = (int32_t)i5[0];
   }
+}
+
+// second level, one thread per sample: its G slots in order
+__global__ void k_final_sample_sum(Partials Q, int G, int32_t nsamp, DevResult* res, double* per_sample,
+                                   double* per_sample_de0, double sample_scale) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= nsamp) return;
+  double e = 0.0, d = 0.0, mn = INFINITY;
+  int64_t nt = 0, ng = 0, nu = 0, ni = 0, nz = 0;
+  for (int g = 0; g < G; ++g) {
+    const int64_t b = s * G + g;
+    e += Q.e2[b];
+    d += Q.de0[b];
+    mn = fmin(mn, Q.mind[b]);
+    nt += Q.nterm[b];
+    ng += Q.ngen[b];
+    nu += Q.nuniq[b];
+    ni += Q.nintr[b];
+    nz += Q.nzero[b];
+  }
+  per_sample[s] = sample_scale * e;
+  if (per_sample_de0) per_sample_de0[s] = sample_scale * d;
+  atomicAdd((unsigned long long*)&res->nterm, (unsigned long long)nt);
+  atomicAdd((unsigned long long*)&res->ngen, (unsigned long long)ng);
+  atomicAdd((unsigned long long*)&res->nuniq, (unsigned long long)nu);
+  atomicAdd((unsigned long long*)&res->nintr, (unsigned long long)ni);
+  atomicAdd((unsigned long long*)&res->nzero, (unsigned long long)nz);
+  // |D| >= 0: the bit patterns of non-negative doubles order like the values
+  atomicMin((unsigned long long*)&res->mind, (unsigned long long)__double_as_longlong(mn));
 }
 
 }  // namespace shci

@@ -86,14 +86,16 @@ __global__ void __launch_bounds__(PTHREADS) k_hpart_scatter(HPassArgs a) {
 }
 
 constexpr int HDUP_THREADS = 1024;
-constexpr int HDUP_SLOTS = 18432;     // 64-bit hashes in LDS (144 KB of gfx950's 160 KB per workgroup)
-constexpr int HDUP_FILL = 13824;      // hashes per table fill (load <= 3/4); larger buckets go in slices
-constexpr int64_t HDUP_MEAN = 12500;  // bucket size the bucket bits aim at
+constexpr int HDUP_SLOTS = 36864;     // 32-bit tags in LDS (144 KB of gfx950's 160 KB per workgroup)
+constexpr int HDUP_FILL = 18432;      // distinct tags a slice aims at when a bucket overflows (load 1/2)
+constexpr int64_t HDUP_MEAN = 12500;  // bucket size the bucket bits aim at (load ~1/3)
 constexpr int HDUP_PROBES = 1024;     // longest probe run before the table counts as full
 constexpr int HDUP_PER_THREAD = 16;   // hashes a thread loads at once (buckets up to 16k)
 
-// first probe slot of a hash: its low 32 bits scaled to [0, HDUP_SLOTS)
-SHCI_DEV int hdup_slot(uint64_t g) { return (int)(((g & 0xffffffffull) * (uint64_t)HDUP_SLOTS) >> 32); }
+// 32-bit tag of a hash (bits 8..39, low bit forced so that 0 marks an empty
+// slot) and its first probe slot, a function of the tag alone
+SHCI_DEV uint32_t hdup_tag(uint64_t g) { return (uint32_t)(g >> 8) | 1u; }
+SHCI_DEV int hdup_slot(uint32_t tag) { return (int)(((uint64_t)tag * (uint64_t)HDUP_SLOTS) >> 32); }
 SHCI_DEV int hdup_next(int s) { return s + 1 == HDUP_SLOTS ? 0 : s + 1; }
 
 // start[b] = first position of bucket b (top nbits of the hash) in the
@@ -120,22 +122,30 @@ struct HDupArgs {
   int64_t nbucket;
   uint64_t* filt;
   int fbits;
-  unsigned long long* nrep;  // distinct repeated hashes (the filter's sizing)
+  unsigned long long* nrep;  // distinct repeated tags (the filter's sizing)
 };
 
 // Repeated hashes of each bucket into the filter, one workgroup per bucket
-// (buckets dealt round-robin).
-// The bucket's hashes (odd fillers skipped) go into an LDS hash table of
-// full 64-bit hashes, linear probing with compare-and-swap; a hash that
-// finds itself already there marks its slot; then every marked slot's hash
-// is set in the filter once.  The filter thus holds exactly the hashes that
-// occur more than once, whatever the order, the bucket sizes or the fillers.
-// A bucket whose distinct hashes overflow the table is taken again in 2^k
-// slices by the hash bits below the bucket bits (all copies of a hash share
-// a slice), k sized for HDUP_FILL hashes a slice; past k = 16 every hash of
-// the bucket is set.
+// (buckets dealt round-robin), in two sweeps over the bucket's hashes (odd
+// fillers skipped):
+//  1. each hash's 32-bit tag goes into an LDS table, linear probing with
+//     compare-and-swap from a first slot that depends on the tag alone; a tag
+//     that finds itself already there marks its slot.  All copies of a tag
+//     walk the same probe sequence and slots are never emptied, so every copy
+//     after the first stops at the first one: a slot is marked exactly when
+//     its tag occurs more than once, whatever the order;
+//  2. each hash finds its tag again (read-only probes) and, if the slot is
+//     marked, sets itself in the filter.
+// The filter thus holds exactly the hashes whose tag occurs more than once in
+// their bucket: every repeated hash, plus the rare pairs of distinct hashes
+// that share a bucket and a tag (they only become records).  Low load (~1/3
+// at the mean bucket size) keeps the probe runs, which a wavefront waits out
+// in lockstep, short.  A bucket whose distinct tags overflow the table is
+// taken again in 2^k slices by the hash bits below the bucket bits (all
+// copies of a hash share a slice), k sized for HDUP_FILL hashes a slice; past
+// k = 16 every hash of the bucket is set.
 __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
-  __shared__ unsigned long long tab[HDUP_SLOTS];
+  __shared__ uint32_t tab[HDUP_SLOTS];
   __shared__ uint32_t repb[HDUP_SLOTS / 32];
   __shared__ int full_s;
   const int t = threadIdx.x;
@@ -143,7 +153,27 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
   for (int64_t b = blockIdx.x; b < A.nbucket; b += gridDim.x) {
     const int64_t lo = (int64_t)A.bstart[b], M = (int64_t)A.bstart[b + 1] - lo;
     if (M < 2 || lo + M > A.n) continue;  // uniform
-    // one table fill first (a large bucket of few distinct hashes fits);
+    const uint64_t* gp = A.g + lo;
+    // a bucket of typical size: all of this thread's hashes loaded at once
+    // (every load issued, clamped into the bucket; fillers in place of the
+    // missing ones) and kept for both sweeps
+    const bool regs = M <= (int64_t)HDUP_PER_THREAD * HDUP_THREADS;
+    uint64_t gv[HDUP_PER_THREAD];
+    if (regs) {
+      const int mlast = (int)M - 1;
+      // (the thread index passed through an empty asm, so the compiler
+      // cannot hoist the sixteen per-thread offsets out of the bucket loop
+      // and keep them in registers)
+      int tt = t;
+      asm volatile("" : "+v"(tt));
+#pragma unroll
+      for (int i = 0; i < HDUP_PER_THREAD; ++i) {
+        const int j = tt + i * HDUP_THREADS;
+        const uint64_t v = gp[j < mlast ? j : mlast];
+        gv[i] = j <= mlast ? v : 1ull;
+      }
+    }
+    // one table fill first (a large bucket of few distinct tags fits);
     // slices only when the table overflows
     int k = 0;
     for (;;) {
@@ -152,20 +182,23 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
       bool full = false;  // uniform after the barrier
       unsigned long long cnt = 0;
       for (int64_t sl = 0; sl < ((int64_t)1 << k) && !full; ++sl) {
-        for (int s = t; s < HDUP_SLOTS; s += HDUP_THREADS) tab[s] = 0ull;
+        // fillers and hashes of other slices take no part
+        auto live = [&](uint64_t g) { return !(g & 1ull) && (k == 0 || (int64_t)((g >> sshift) & smask) == sl); };
+        for (int s = t; s < HDUP_SLOTS; s += HDUP_THREADS) tab[s] = 0u;
         for (int s = t; s < HDUP_SLOTS / 32; s += HDUP_THREADS) repb[s] = 0u;
         if (t == 0) full_s = 0;
         __syncthreads();
         bool miss = false;
-        // places g (odd fillers and other slices skipped); false: table full
+        // sweep 1 for one hash; false: table full
         auto place = [&](uint64_t g) -> bool {
-          if ((g & 1ull) || (k && (int64_t)((g >> sshift) & smask) != sl)) return true;
-          int s = hdup_slot(g);
+          if (!live(g)) return true;
+          const uint32_t tag = hdup_tag(g);
+          int s = hdup_slot(tag);
           // a probe run this long means the table is (nearly) full
           for (int probe = 0; probe < HDUP_PROBES; ++probe) {
-            const unsigned long long old = atomicCAS(&tab[s], 0ull, (unsigned long long)g);
-            if (old == 0ull) return true;
-            if (old == (unsigned long long)g) {
+            const uint32_t old = atomicCAS(&tab[s], 0u, tag);
+            if (old == 0u) return true;
+            if (old == tag) {
               atomicOr(&repb[s >> 5], 1u << (s & 31));
               return true;
             }
@@ -173,33 +206,40 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
           }
           return false;
         };
-        if (M <= (int64_t)HDUP_PER_THREAD * HDUP_THREADS) {
-          // a bucket of typical size: all of this thread's hashes loaded at
-          // once (fillers in place of the missing ones), then placed
-          uint64_t gv[HDUP_PER_THREAD];
-#pragma unroll
-          for (int i = 0; i < HDUP_PER_THREAD; ++i) {
-            const int64_t j = t + (int64_t)i * HDUP_THREADS;
-            gv[i] = j < M ? A.g[lo + j] : 1ull;
+        // sweep 2 for one hash (its tag is in the table)
+        auto mark = [&](uint64_t g) {
+          if (!live(g)) return;
+          const uint32_t tag = hdup_tag(g);
+          int s = hdup_slot(tag);
+          for (int probe = 0; probe < HDUP_PROBES && tab[s] != tag; ++probe) s = hdup_next(s);
+          if ((repb[s >> 5] >> (s & 31)) & 1u) {
+            // (through an empty asm, so the filter word and bits of every
+            // hash are not computed ahead and held for this rare branch)
+            uint64_t gg = g;
+            asm volatile("" : "+v"(gg));
+            filt_insert(A.filt, A.fbits, gg);
           }
+        };
+        if (regs) {
 #pragma unroll
           for (int i = 0; i < HDUP_PER_THREAD; ++i) miss = miss || !place(gv[i]);
         } else {
           for (int64_t j = t; j < M && !miss; j += HDUP_THREADS) {
             if (*(volatile int*)&full_s) break;  // another thread found the table full
-            miss = !place(A.g[lo + j]);
+            miss = !place(gp[j]);
           }
         }
         if (miss) full_s = 1;
         __syncthreads();
         full = full_s != 0;
         if (!full) {
-          for (int s = t; s < HDUP_SLOTS; s += HDUP_THREADS) {
-            if ((repb[s >> 5] >> (s & 31)) & 1u) {
-              filt_insert(A.filt, A.fbits, tab[s]);
-              cnt += 1;
-            }
+          if (regs) {
+#pragma unroll
+            for (int i = 0; i < HDUP_PER_THREAD; ++i) mark(gv[i]);
+          } else {
+            for (int64_t j = t; j < M; j += HDUP_THREADS) mark(gp[j]);
           }
+          for (int w = t; w < HDUP_SLOTS / 32; w += HDUP_THREADS) cnt += (unsigned long long)__popc(repb[w]);
         }
         __syncthreads();
       }
@@ -208,9 +248,9 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         break;
       }
       if (k >= 16) {
-        // every hash of the bucket (needs > 2^16 HDUP_SLOTS distinct hashes)
+        // every hash of the bucket (needs > 2^16 HDUP_SLOTS distinct tags)
         for (int64_t j = t; j < M; j += HDUP_THREADS) {
-          const uint64_t g = A.g[lo + j];
+          const uint64_t g = gp[j];
           if (!(g & 1ull)) {
             filt_insert(A.filt, A.fbits, g);
             nrep += 1;

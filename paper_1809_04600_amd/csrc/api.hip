@@ -692,7 +692,10 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
     pa.ntiles = (int)ntiles;
     k_hpart_hist<<<pgrid, 256, 0, st>>>(pa);
     CHK(scan_exclusive<uint32_t, uint32_t>(hist, hoffs, ((int64_t)1 << dbits) * ntiles, hsc, nullptr, st));
-    k_hpart_scatter<<<pgrid, PTHREADS, 0, st>>>(pa);
+    if (pass == 0)
+      k_hpart_scatter_first<<<pgrid, PTHREADS, 0, st>>>(pa);
+    else
+      k_hpart_scatter<<<pgrid, PTHREADS, 0, st>>>(pa);
     HIPCHK(hipGetLastError());
     std::swap(cur, oth);
     shift += dbits;

@@ -283,8 +283,9 @@ SHCI_DEV void tile_load(const T* in, int64_t base, int tile_n, uint64_t (&r)[PW_
   }
 }
 
-template <typename T>
-SHCI_DEV void tile_scatter(ScatterShared& L, const uint64_t (&r)[PW_ITEMS], T* out, int tile_n,
+// (S: any shared layout with stage, sdig, lstart and gbase as ScatterShared)
+template <typename T, typename S>
+SHCI_DEV void tile_scatter(S& L, const uint64_t (&r)[PW_ITEMS], T* out, int tile_n,
                            const uint16_t (&lpos)[PW_ITEMS]) {
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   T* st = reinterpret_cast<T*>(L.stage);
@@ -315,9 +316,10 @@ SHCI_DEV void tile_scatter(ScatterShared& L, const uint64_t (&r)[PW_ITEMS], T* o
 // Local positions of this thread's records of a tile (digits d, stable
 // order): each wavefront ranks its slice by ballot match with running
 // per-digit counts in its LDS slice, one scan places the digits.  Fills
-// L.sdig and L.lstart; L.wc must be zero on entry.
-SHCI_DEV void tile_rank(ScatterShared& L, const uint32_t (&dg)[PW_ITEMS], int tile_n, int dbits,
-                        uint16_t (&lpos)[PW_ITEMS]) {
+// L.sdig and L.lstart; L.wc must be zero on entry.  (S: any shared layout
+// with wc, wb, lstart, scan and sdig as ScatterShared)
+template <typename S>
+SHCI_DEV void tile_rank(S& L, const uint32_t (&dg)[PW_ITEMS], int tile_n, int dbits, uint16_t (&lpos)[PW_ITEMS]) {
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   uint8_t dig[PW_ITEMS];
   uint16_t* wc = L.wc[wv];

@@ -57,9 +57,62 @@ __global__ void __launch_bounds__(256) k_hpart_hist(HPassArgs a) {
   if (threadIdx.x < (1 << a.dbits)) a.hist[(int64_t)threadIdx.x * a.ntiles + tile] = cnt[threadIdx.x];
 }
 
-// one stable LSD pass over (hash, work item) pairs, as k_part_scatter
-__global__ void __launch_bounds__(PTHREADS) k_hpart_scatter(HPassArgs a) {
-  __shared__ ScatterShared L;
+// One stable LSD pass over (hash, work item) pairs (every pass after the
+// first must keep the order of the one before): the ranking of
+// k_part_scatter, with a 4-byte stage through which the hashes go in two
+// halves, so that the shared layout (59 KB) lets two blocks share a compute
+// unit.
+struct HStableShared {
+  uint16_t wc[PWAVES][256];
+  uint16_t wb[PWAVES][256];
+  uint32_t lstart[256];
+  uint32_t gbase[256];
+  uint32_t scan[256];
+  uint8_t sdig[PTILE];
+  uint32_t stage[PTILE];
+};
+
+// tile_scatter for 8-byte values through a 4-byte stage: low halves, then
+// high halves, each placed and read back in digit order
+template <typename S>
+SHCI_DEV void tile_scatter_halves(S& L, const uint64_t (&r)[PW_ITEMS], uint64_t* out, int tile_n,
+                                  const uint16_t (&lpos)[PW_ITEMS]) {
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  uint32_t lo[PW_ITEMS];
+  int64_t dst[PW_ITEMS];
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j)
+    if (tile_slot(wv, lane, j) < tile_n) L.stage[lpos[j]] = (uint32_t)r[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    const int q = j * PTHREADS + t;
+    const int qq = q < tile_n ? q : 0;
+    const uint32_t d = L.sdig[qq];
+    dst[j] = (int64_t)L.gbase[d] + (qq - (int)L.lstart[d]);
+    lo[j] = L.stage[qq];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j)
+    if (tile_slot(wv, lane, j) < tile_n) L.stage[lpos[j]] = (uint32_t)(r[j] >> 32);
+  __syncthreads();
+  uint64_t val[PW_ITEMS];
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    const int q = j * PTHREADS + t;
+    const int qq = q < tile_n ? q : 0;
+    val[j] = ((uint64_t)L.stage[qq] << 32) | lo[j];
+  }
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j)
+    if (j * PTHREADS + t < tile_n) out[dst[j]] = val[j];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(PTHREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_hpart_scatter(HPassArgs a) {
+  __shared__ HStableShared L;
   const int tile = xcd_tile(blockIdx.x, a.ntiles);
   if (tile >= a.ntiles) return;
   const int t = threadIdx.x;
@@ -81,6 +134,63 @@ __global__ void __launch_bounds__(PTHREADS) k_hpart_scatter(HPassArgs a) {
     for (int j = 0; j < PW_ITEMS; ++j) dg[j] = hdigit(keys[j], a);
     tile_rank(L, dg, tile_n, a.dbits, lpos);
   }
+  tile_scatter_halves(L, keys, a.kout, tile_n, lpos);
+  tile_scatter<uint32_t>(L, items, a.iout, tile_n, lpos);
+}
+
+// The first LSD pass over (hash, work item) pairs need not be stable: the
+// list is in no particular order to begin with (only a later pass must keep
+// the order of the one before, and a single pass only groups).  So each tile
+// ranks its pairs by LDS atomics on 256 per-digit counters instead of ballot
+// matching, and the smaller shared layout (76 KB) lets two blocks share a
+// compute unit, one loading while the other writes.  The pairs of a digit run
+// are still written contiguously (LDS staging), at the tile's offsets from
+// the histogram pass.
+struct HScatterShared {
+  uint32_t cnt[256];     // per-digit counts of the tile, then ranks
+  uint32_t lstart[256];  // first local position of each digit
+  uint32_t gbase[256];   // first output position of each digit for this tile
+  uint32_t scan[256];
+  uint8_t sdig[PTILE];   // digit of each local position
+  uint64_t stage[PTILE];
+};
+
+__global__ void __launch_bounds__(PTHREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_hpart_scatter_first(HPassArgs a) {
+  __shared__ HScatterShared L;
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  if (tile >= a.ntiles) return;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  if (t < 256) {
+    L.cnt[t] = 0u;
+    L.gbase[t] = (t < (1 << a.dbits)) ? a.offs[(int64_t)t * a.ntiles + tile] : 0u;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)tile * PTILE;
+  const int tile_n = (int)((a.n - base < (int64_t)PTILE) ? (a.n - base) : (int64_t)PTILE);
+  uint64_t keys[PW_ITEMS], items[PW_ITEMS];
+  tile_load<uint64_t>(a.kin, base, tile_n, keys);
+  tile_load<uint32_t>(a.iin, base, tile_n, items);
+  uint32_t dg[PW_ITEMS];
+  uint16_t lpos[PW_ITEMS];
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    dg[j] = hdigit(keys[j], a);
+    lpos[j] = 0;
+    if (tile_slot(wv, lane, j) < tile_n) lpos[j] = (uint16_t)atomicAdd(&L.cnt[dg[j]], 1u);
+  }
+  __syncthreads();
+  const uint32_t ex = digit_scan(t < 256 ? L.cnt[t] : 0u, L.scan);
+  if (t < 256) L.lstart[t] = ex;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PW_ITEMS; ++j) {
+    if (tile_slot(wv, lane, j) < tile_n) {
+      lpos[j] = (uint16_t)(lpos[j] + L.lstart[dg[j]]);
+      L.sdig[lpos[j]] = (uint8_t)dg[j];
+    }
+  }
+  __syncthreads();
   tile_scatter<uint64_t>(L, keys, a.kout, tile_n, lpos);
   tile_scatter<uint32_t>(L, items, a.iout, tile_n, lpos);
 }

@@ -260,29 +260,35 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
   __shared__ int full_s;
   const int t = threadIdx.x;
   unsigned long long nrep = 0;  // per thread
+  // A bucket of typical size has all of this thread's hashes loaded at once
+  // (every load issued, clamped into the bucket; fillers in place of the
+  // missing ones) and kept for both sweeps.  The next bucket's are loaded as
+  // soon as the current one's second sweep is done, so that their latency
+  // overlaps the count, the barriers and the next table clear.
+  uint64_t gv[HDUP_PER_THREAD];
+  int64_t have = -1;  // bucket whose hashes gv holds
+  auto typical = [&](int64_t lo, int64_t M) { return M >= 2 && lo + M <= A.n && M <= (int64_t)HDUP_PER_THREAD * HDUP_THREADS; };
+  auto load = [&](int64_t lo, int64_t M) {
+    const int mlast = (int)M - 1;
+    // (the thread index passed through an empty asm, so the compiler cannot
+    // hoist the sixteen per-thread offsets out of the bucket loop and keep
+    // them in registers)
+    int tt = t;
+    asm volatile("" : "+v"(tt));
+#pragma unroll
+    for (int i = 0; i < HDUP_PER_THREAD; ++i) {
+      const int j = tt + i * HDUP_THREADS;
+      const uint64_t v = A.g[lo + (j < mlast ? j : mlast)];
+      gv[i] = j <= mlast ? v : 1ull;
+    }
+  };
   for (int64_t b = blockIdx.x; b < A.nbucket; b += gridDim.x) {
     const int64_t lo = (int64_t)A.bstart[b], M = (int64_t)A.bstart[b + 1] - lo;
     if (M < 2 || lo + M > A.n) continue;  // uniform
     const uint64_t* gp = A.g + lo;
-    // a bucket of typical size: all of this thread's hashes loaded at once
-    // (every load issued, clamped into the bucket; fillers in place of the
-    // missing ones) and kept for both sweeps
     const bool regs = M <= (int64_t)HDUP_PER_THREAD * HDUP_THREADS;
-    uint64_t gv[HDUP_PER_THREAD];
-    if (regs) {
-      const int mlast = (int)M - 1;
-      // (the thread index passed through an empty asm, so the compiler
-      // cannot hoist the sixteen per-thread offsets out of the bucket loop
-      // and keep them in registers)
-      int tt = t;
-      asm volatile("" : "+v"(tt));
-#pragma unroll
-      for (int i = 0; i < HDUP_PER_THREAD; ++i) {
-        const int j = tt + i * HDUP_THREADS;
-        const uint64_t v = gp[j < mlast ? j : mlast];
-        gv[i] = j <= mlast ? v : 1ull;
-      }
-    }
+    if (regs && have != b) load(lo, M);
+    have = -1;
     // one table fill first (a large bucket of few distinct tags fits);
     // slices only when the table overflows
     int k = 0;
@@ -346,6 +352,16 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
           if (regs) {
 #pragma unroll
             for (int i = 0; i < HDUP_PER_THREAD; ++i) mark(gv[i]);
+            // the last slice of this bucket is done with gv: load the next
+            // bucket's hashes now
+            const int64_t nb = b + gridDim.x;
+            if (sl + 1 == ((int64_t)1 << k) && nb < A.nbucket) {
+              const int64_t nlo = (int64_t)A.bstart[nb], nM = (int64_t)A.bstart[nb + 1] - nlo;
+              if (typical(nlo, nM)) {
+                load(nlo, nM);
+                have = nb;
+              }
+            }
           } else {
             for (int64_t j = t; j < M; j += HDUP_THREADS) mark(gp[j]);
           }

@@ -654,9 +654,12 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
   Lane& R = J.lane ? *J.lane : *X;
   Arena& AR = *J.ar;
   // buckets of ~12k hashes (one LDS table fill each): 16 bits, two passes,
-  // up to ~8e8 hashes
-  const int nbits =
-      std::min(30, std::max(1, ceil_log2((uint64_t)std::max<int64_t>(1, (nent + HDUP_MEAN - 1) / HDUP_MEAN))));
+  // up to ~8e8 hashes.  The bits follow the number of listed terms, not the
+  // list's length (its fillers depend on the run sizes, which follow earlier
+  // calls): the hashes that share a bucket and a tag, which the filter takes
+  // as repeated, then depend on the hashes alone.
+  const int64_t nreal = std::max<int64_t>(1, J.nrec_all);
+  const int nbits = std::min(30, std::max(1, ceil_log2((uint64_t)((nreal + HDUP_MEAN - 1) / HDUP_MEAN))));
   const int npass = (nbits + 7) / 8;
   const int64_t nbucket = (int64_t)1 << nbits;
   const int64_t ntiles = std::max<int64_t>(1, (nent + PTILE - 1) / PTILE);

@@ -306,29 +306,32 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         __syncthreads();
         bool miss = false;
         // sweep 1 for one hash; false: table full
-        auto place = [&](uint64_t g) -> bool {
+        // (at the slot where the tag now is, or -1 for a hash that takes
+        // no part)
+        auto place = [&](uint64_t g, int& at) -> bool {
+          at = -1;
           if (!live(g)) return true;
           const uint32_t tag = hdup_tag(g);
           int s = hdup_slot(tag);
           // a probe run this long means the table is (nearly) full
           for (int probe = 0; probe < HDUP_PROBES; ++probe) {
             const uint32_t old = atomicCAS(&tab[s], 0u, tag);
-            if (old == 0u) return true;
+            if (old == 0u) {
+              at = s;
+              return true;
+            }
             if (old == tag) {
               atomicOr(&repb[s >> 5], 1u << (s & 31));
+              at = s;
               return true;
             }
             s = hdup_next(s);
           }
           return false;
         };
-        // sweep 2 for one hash (its tag is in the table)
-        auto mark = [&](uint64_t g) {
-          if (!live(g)) return;
-          const uint32_t tag = hdup_tag(g);
-          int s = hdup_slot(tag);
-          for (int probe = 0; probe < HDUP_PROBES && tab[s] != tag; ++probe) s = hdup_next(s);
-          if ((repb[s >> 5] >> (s & 31)) & 1u) {
+        // sweep 2 for one hash at the slot of its tag
+        auto mark_at = [&](uint64_t g, int s) {
+          if (s >= 0 && ((repb[s >> 5] >> (s & 31)) & 1u)) {
             // (through an empty asm, so the filter word and bits of every
             // hash are not computed ahead and held for this rare branch)
             uint64_t gg = g;
@@ -336,13 +339,27 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
             filt_insert(A.filt, A.fbits, gg);
           }
         };
+        // the same for a hash whose slot was not kept: found again
+        auto mark = [&](uint64_t g) {
+          if (!live(g)) return;
+          const uint32_t tag = hdup_tag(g);
+          int s = hdup_slot(tag);
+          for (int probe = 0; probe < HDUP_PROBES && tab[s] != tag; ++probe) s = hdup_next(s);
+          mark_at(g, s);
+        };
+        uint16_t at[HDUP_PER_THREAD];  // slot of each held hash's tag (0xffff: none)
         if (regs) {
 #pragma unroll
-          for (int i = 0; i < HDUP_PER_THREAD; ++i) miss = miss || !place(gv[i]);
+          for (int i = 0; i < HDUP_PER_THREAD; ++i) {
+            int s = -1;
+            miss = miss || !place(gv[i], s);
+            at[i] = s < 0 ? (uint16_t)0xffffu : (uint16_t)s;
+          }
         } else {
           for (int64_t j = t; j < M && !miss; j += HDUP_THREADS) {
             if (*(volatile int*)&full_s) break;  // another thread found the table full
-            miss = !place(gp[j]);
+            int s;
+            miss = !place(gp[j], s);
           }
         }
         if (miss) full_s = 1;
@@ -351,7 +368,7 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
         if (!full) {
           if (regs) {
 #pragma unroll
-            for (int i = 0; i < HDUP_PER_THREAD; ++i) mark(gv[i]);
+            for (int i = 0; i < HDUP_PER_THREAD; ++i) mark_at(gv[i], at[i] == 0xffffu ? -1 : (int)at[i]);
             // the last slice of this bucket is done with gv: load the next
             // bucket's hashes now
             const int64_t nb = b + gridDim.x;

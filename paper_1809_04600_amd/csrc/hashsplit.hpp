@@ -201,6 +201,7 @@ constexpr int HDUP_FILL = 18432;      // distinct tags a slice aims at when a bu
 constexpr int64_t HDUP_MEAN = 12500;  // bucket size the bucket bits aim at (load ~1/3)
 constexpr int HDUP_PROBES = 1024;     // longest probe run before the table counts as full
 constexpr int HDUP_PER_THREAD = 16;   // hashes a thread loads at once (buckets up to 16k)
+static_assert(HDUP_SLOTS % 128 == 0, "the table and its mark bits are cleared 16 bytes at a time");
 
 // 32-bit tag of a hash (bits 8..39, low bit forced so that 0 marks an empty
 // slot) and its first probe slot, a function of the tag alone
@@ -255,8 +256,8 @@ struct HDupArgs {
 // copies of a hash share a slice), k sized for HDUP_FILL hashes a slice; past
 // k = 16 every hash of the bucket is set.
 __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
-  __shared__ uint32_t tab[HDUP_SLOTS];
-  __shared__ uint32_t repb[HDUP_SLOTS / 32];
+  __shared__ __align__(16) uint32_t tab[HDUP_SLOTS];
+  __shared__ __align__(16) uint32_t repb[HDUP_SLOTS / 32];
   __shared__ int full_s;
   const int t = threadIdx.x;
   unsigned long long nrep = 0;  // per thread
@@ -300,8 +301,9 @@ __global__ void __launch_bounds__(HDUP_THREADS) k_hdup(HDupArgs A) {
       for (int64_t sl = 0; sl < ((int64_t)1 << k) && !full; ++sl) {
         // fillers and hashes of other slices take no part
         auto live = [&](uint64_t g) { return !(g & 1ull) && (k == 0 || (int64_t)((g >> sshift) & smask) == sl); };
-        for (int s = t; s < HDUP_SLOTS; s += HDUP_THREADS) tab[s] = 0u;
-        for (int s = t; s < HDUP_SLOTS / 32; s += HDUP_THREADS) repb[s] = 0u;
+        // (16-byte stores)
+        for (int s = t; s < HDUP_SLOTS / 4; s += HDUP_THREADS) reinterpret_cast<uint4*>(tab)[s] = make_uint4(0u, 0u, 0u, 0u);
+        for (int s = t; s < HDUP_SLOTS / 128; s += HDUP_THREADS) reinterpret_cast<uint4*>(repb)[s] = make_uint4(0u, 0u, 0u, 0u);
         if (t == 0) full_s = 0;
         __syncthreads();
         bool miss = false;

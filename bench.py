@@ -304,12 +304,13 @@ def roofline(kernel, bound, alg_bytes, launches, ms, measured_kernel):
 def split_bytes_per_hash(per_launch):
     """HBM bytes per listed hash of the singleton split's kernels: per
     partition pass the histogram reads the hash (8) and the scatter reads and
-    writes hash and work item (24); the bucket bounds read the hash (8), the
-    repeat finder and the marks read hash and work item (12 each)."""
+    writes hash and work item (24); the repeat finder reads the hash (8), the
+    marks read hash and work item (12).  (The bucket bounds read a few hashes
+    per bucket.)"""
     import math
     nbits = max(1, math.ceil(math.log2(max(1.0, math.ceil(per_launch / 12500.0)))))
     npass = (nbits + 7) // 8
-    return 32.0 * npass + 32.0, npass
+    return 32.0 * npass + 20.0, npass
 
 
 def kernel_rooflines(wl, run, avg, prec):

@@ -528,6 +528,12 @@ def main():
     # the dominant kernel by its own launch time (the split's figure spans
     # several kernels and, with two lanes, the other lane's kernels)
     dom = max((k for k in ms if rl.get(k) and k != "split"), key=ms.get)
+    if a.lanes > 1 and wl.n_samples:
+        for r in rl.values():
+            if r:
+                r["timing"] = ("HIP events around each launch while two sample chunks are in flight: the "
+                               "other chunk's kernels share the GPU, so a launch takes longer than alone "
+                               "(the w3 kernel summary under profiles/ has a single-lane trace)")
     out = {
         "metric": METRIC,
         "value": n_terms / w_main,

@@ -212,7 +212,7 @@ int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records);
 /* How the screened terms are grouped by perturbative determinant a (the sums
  * A_a = sum_i H_ai c_i of the screened PT2 equation, section II.B; the paper
  * accumulates them in a hash table, section V.C).
- *   SHCI_GROUP_AUTO (default): singleton split.  The count pass lists a
+ *   SHCI_GROUP_SPLIT: singleton split.  The count pass lists a
  *     64-bit grouping hash per term (determinant hash, sample id mixed in);
  *     the list is partitioned and hashes that occur more than once are set in
  *     a presence filter.  The write pass makes records only of terms whose
@@ -223,9 +223,14 @@ int shci_pt2_ctx_set_record_limit(shci_pt2_ctx* ctx, int64_t max_records);
  *     per-term or per-a data (unique export, term export, adjoints) group
  *     every term as a record.
  *   SHCI_GROUP_RECORDS: every term becomes a record (key, value, H_aa).
+ *   SHCI_GROUP_AUTO (default): the singleton split for the passes of the
+ *     sampling calls, and for deterministic passes of 1e8 kept terms or
+ *     more; a smaller deterministic pass groups every term as a record (its
+ *     count pass still lists the hashes; the choice follows the exact count,
+ *     so a repeat makes the same one).
  * The limit of shci_pt2_ctx_set_record_limit applies to the terms of a pass
- * in either mode. */
-enum { SHCI_GROUP_AUTO = 0, SHCI_GROUP_RECORDS = 1 };
+ * in every mode. */
+enum { SHCI_GROUP_AUTO = 0, SHCI_GROUP_RECORDS = 1, SHCI_GROUP_SPLIT = 2 };
 int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode);
 
 /* Sample chunks in flight at once in the sampling calls with a workspace: 2

@@ -222,9 +222,10 @@ class Context:
         _check(lib().shci_pt2_ctx_set_record_limit(self._ptr, int(max_records)))
 
     def set_grouping(self, mode: str):
-        """"auto" (singleton split where the call needs no per-a output) or
-        "records" (every screened term becomes a record)."""
-        m = {"auto": 0, "records": 1}
+        """"split" (singleton split where the call needs no per-a output),
+        "records" (every screened term becomes a record) or "auto" (split for
+        sampling passes and deterministic passes of 1e8 terms or more)."""
+        m = {"auto": 0, "records": 1, "split": 2}
         if mode not in m:
             raise ValueError(f"grouping must be one of {sorted(m)}")
         _check(lib().shci_pt2_ctx_set_grouping(self._ptr, m[mode]))

@@ -1,5 +1,6 @@
-"""Singleton split (grouping mode "auto") against the CPU oracle and against
-the all-records grouping, through the C ABI.
+"""Singleton split (grouping mode "split") against the CPU oracle and against
+the all-records grouping, through the C ABI; mode "auto" (the default) picks
+records for small deterministic passes and the split otherwise.
 
 The split decides which terms become records, never which terms belong to
 one perturbative determinant: term, determinant and intruder counts are
@@ -16,7 +17,7 @@ import torch
 from oracle import ref
 from synth import store
 from tests import inputs as I
-from tests.gpu_util import context
+from tests.gpu_util import context as _context
 
 pytestmark = pytest.mark.gpu
 
@@ -30,12 +31,19 @@ def _oracle(x, eps2, **kw):
     return ref.pt2_det(wl.n_orb, wl.n_alpha, wl.n_beta, x.h1, x.eri, x.dets, x.c, x.e0, eps2, **kw)
 
 
+def context(x):
+    """A context that splits every pass it may (whatever its size)."""
+    ctx, dets, c = _context(x)
+    ctx.set_grouping("split")
+    return ctx, dets, c
+
+
 def _records(ctx, fn):
     ctx.set_grouping("records")
     try:
         return fn()
     finally:
-        ctx.set_grouping("auto")
+        ctx.set_grouping("split")
 
 
 def _rel(a, b):
@@ -237,4 +245,23 @@ def test_two_lanes_same_bits():
     draws = ctx.draws(c, 40, 50, 5).cpu().numpy().astype(np.uint32)
     o = ref.pt2_sample(10, 3, 3, x.h1, x.eri, x.dets, x.c, x.e0, eps2, eps2_d, draws)
     assert np.abs(outw.cpu().numpy() - o).max() <= 1e-9 * max(1.0, np.abs(o).max())
+    ctx.close()
+
+
+def test_auto_grouping_by_size():
+    # "auto": a deterministic pass under 1e8 kept terms groups every term as
+    # a record (the same bits as "records"); a sampling pass splits
+    x = store.load("w1")
+    ctx, dets, c = _context(x)
+    eps2 = x.wl.eps2
+    ra = ctx.det(dets, c, x.e0, eps2, "fp64")
+    rr = _records(ctx, lambda: ctx.det(dets, c, x.e0, eps2, "fp64"))
+    ctx.set_grouping("auto")
+    rs = ctx.det(dets, c, x.e0, eps2, "fp64")
+    print(f"auto: {ra.stats['n_singletons']} singletons, E2 {ra.e2!r}; records {rr.e2!r}", flush=True)
+    assert ra.stats["n_singletons"] == 0 and ra.stats["n_records"] == rr.stats["n_records"]
+    assert ra.e2 == rr.e2 and ra.e2 == rs.e2
+    kw = dict(seed=7, n_samples=4, n_draws=200)
+    out, _, _, st = ctx.sample(dets, c, x.e0, 1e-7, eps2, None, "fp64", **kw)
+    assert st["n_singletons"] > 0
     ctx.close()

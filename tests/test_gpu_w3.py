@@ -100,8 +100,13 @@ def test_w3_deterministic_part_vs_stored_oracle(w3):
     idx = np.array(smp["index"])
     assert np.abs(A[idx] - gA).max() <= 1e-13 * max(1.0, np.abs(gA).max())
     assert np.abs(D[idx] - gD).max() <= 1e-12 * np.abs(gD).max()
-    # singleton split (no per-a export asked): same counts, E2 against the oracle
-    rs = ctx.det(dets, c, x.e0, wl.eps2, "fp64")
+    # singleton split (no per-a export asked; forced, as "auto" groups a pass
+    # of this size as records): same counts, E2 against the oracle
+    ctx.set_grouping("split")
+    try:
+        rs = ctx.det(dets, c, x.e0, wl.eps2, "fp64")
+    finally:
+        ctx.set_grouping("auto")
     print(f"w3 det split: |dE2| vs oracle = {abs(rs.e2 - g['e2']):.3e}, singletons {rs.stats['n_singletons']} "
           f"of {rs.stats['n_terms_all']}", flush=True)
     for k in ("n_terms", "n_terms_gen", "n_unique", "n_intruder"):

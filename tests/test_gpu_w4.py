@@ -70,7 +70,11 @@ def test_w4_deterministic_part_sampled(w4):
     assert np.abs(D - oD).max() <= 1e-12 * np.abs(oD).max()
     # the singleton split: same terms, determinants and intruders; E2 in
     # another summation order
-    s = ctx.det(dets, c, x.e0, wl.eps2, "fp64")
+    ctx.set_grouping("split")
+    try:
+        s = ctx.det(dets, c, x.e0, wl.eps2, "fp64")
+    finally:
+        ctx.set_grouping("auto")
     print(f"w4 det (split): E2 {s.e2!r}, |dE2| {abs(s.e2 - r.e2):.3e}, singletons "
           f"{s.stats['n_singletons']} of {s.stats['n_terms_all']}", flush=True)
     for k in COUNTS:

@@ -7,18 +7,19 @@
 //  1. the count walk lists the 64-bit grouping hash (determinant hash with the
 //     sample id mixed in) and the work item of every kept term, 12 bytes a
 //     term instead of a record of 44-60;
-//  2. the list is partitioned on the top hash bits (the same stable LSD passes
-//     as the records), buckets of ~12k hashes (two passes up to ~8e8);
-//  3. per bucket, one workgroup finds the hashes that occur more than once
-//     (an LDS hash table) and sets them in a presence filter;
+//  2. the list is partitioned on the top hash bits (LSD passes: the first
+//     needs no stability, the later ones rank as the records' passes do),
+//     buckets of ~12k hashes (two passes up to ~8e8);
+//  3. per bucket, one workgroup finds the 32-bit tags that occur more than
+//     once (an LDS hash table) and sets their hashes in a presence filter;
 //  4. every listed term whose hash passes the filter is counted for its work
 //     item; the scan of these counts places the records.
 // The write walk then writes records only for terms whose hash passes the
-// filter (every term of an a with several terms does, and a few false
-// positives) and sums the contribution of every other term in place.  The
-// decision depends on the hash alone, so all terms of one a take the same
-// side and the records of an a are complete; the split changes the order of
-// the final sums only.
+// filter (every term of an a with several terms does, and a few others:
+// shared tags, filter collisions) and sums the contribution of every other
+// term in place.  The decision depends on the hash alone, so all terms of one
+// a take the same side and the records of an a are complete; the split
+// changes the order of the final sums only.
 #pragma once
 #include "group.hpp"
 

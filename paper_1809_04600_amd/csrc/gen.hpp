@@ -8,13 +8,20 @@
 //    survivors get the exact element h_pr + sum_k [...] accumulated in a
 //    fixed order (occupied alpha ascending, then occupied beta ascending);
 //  * doubles: for every occupied pair the heat-bath list of that pair is
-//    walked 64 entries at a time, in decreasing |value|, and the walk stops at
-//    the first entry that fails the screen (section II.A, heat-bath traversal
+//    walked in decreasing |value| (the first eight entries of eight pairs at
+//    once, longer lists 64 entries at a time), and the walk stops at the
+//    first entry that fails the screen (section II.A, heat-bath traversal
 //    with early exit).  Entries whose target orbitals are occupied are skipped.
 //  * fermion signs come from popcounts of the occupied bits between the
 //    orbitals involved; a same-spin double is p->r then q->s.
 // Lane-parallel emission uses ballot + mbcnt compaction, so the record order
 // is fixed by (source index, generation order) and the run is deterministic.
+// The same walk runs in three modes: the count walk counts the kept terms of
+// each work item (and, for the singleton split, lists each one's grouping
+// hash); the write walk writes records at the counted offsets (in split mode
+// only the terms whose hash passes the filter of repeated hashes, the others
+// summed in place); the adjoint walk adds dE2/dc_i from the kept per-a
+// factors.
 #pragma once
 #include "diag.hpp"
 #include "kernels.hpp"

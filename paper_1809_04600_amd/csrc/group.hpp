@@ -2,19 +2,28 @@
 // of each group to its contribution A_a^2 / (E0 - H_aa).
 //
 // The paper accumulates the partial sums A_a = sum_i H_ai c_i in a concurrent
-// hash table (section V.C).  Here the terms are materialised as records
-// (packed key of a, value) and grouped by sorting instead:
+// hash table (section V.C).  Here the terms that need grouping are
+// materialised as records (packed key of a, value(s), H_aa from the
+// generator) and grouped by a hash partition instead (with the singleton
+// split, hashsplit.hpp, only the terms whose a may have several terms):
 //  1. a least-significant-digit radix partition of the records on the bucket
 //     id (the top bits of a 64-bit hash of the key; in sample mode the sample
-//     id sits above them), 8 bits per pass, stable;
-//  2. per bucket, in LDS: an LSD radix sort on the next 32 hash bits (4 passes
-//     of 8 bits, stable), with a fallback to a full-key LSD sort when two
-//     different keys of a bucket share those bits, so equal keys become
-//     adjacent; then a segmented reduction in record order (deterministic);
-//  3. members of V are dropped by a lookup in a hash set of V; H_aa is
-//     evaluated from LDS copies of h_pp, (pp|qq) and (pp|qq)-(pq|qp); the
-//     contribution and dE2/dE0 term are summed per bucket in a fixed order;
-//  4. the bucket partials are summed by a fixed-shape tree.
+//     id sits above them), 8 bits per pass, stable: per 8192-record tile,
+//     each wavefront ranks its slice by ballot matching, one scan places the
+//     digits, and every array goes out through LDS as contiguous digit runs;
+//  2. per bucket, one wavefront (reduce_wave.hpp): the bucket's records are
+//     read once into registers, 32-bit sort keys (hash bits below the bucket
+//     id, record position) are sorted by a bitonic network across lanes, so
+//     equal keys become adjacent in record order; segment heads add their
+//     members' values (deterministic order); buckets too large, or with two
+//     keys sharing the sorted bits, go to a block kernel that sorts by the
+//     full key;
+//  3. members of V are dropped by a lookup in a hash set of V behind a
+//     presence filter; H_aa is the one the generator computed (an update of
+//     the source's diagonal, diag.hpp), taken from the segment's first
+//     record; the contribution and dE2/dE0 term are summed per wavefront in a
+//     fixed order;
+//  4. the partials are summed by fixed-shape trees.
 #pragma once
 #include "gen.hpp"
 #include "diag.hpp"

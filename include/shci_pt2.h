@@ -239,6 +239,15 @@ int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode);
  * the same bits either way; 1 gives each kernel the whole GPU (profiling). */
 int shci_pt2_ctx_set_lanes(shci_pt2_ctx* ctx, int lanes);
 
+/* Hashes per bucket of the singleton split's repeat finder, in [64, 2^24]
+ * (default 12500: one workgroup's shared-memory table of 36,864 tags takes
+ * a bucket in one fill and holds its hashes in registers).  Larger buckets
+ * are taken from memory, in slices by hash bits when their distinct tags
+ * overflow the table; the results are the same up to the order of the sums
+ * (the terms, groups and counts are exact in every case).  A tuning and
+ * testing knob: the default is the fast one. */
+int shci_pt2_ctx_set_split_bucket(shci_pt2_ctx* ctx, int64_t hashes);
+
 /* Deterministic screened PT2 (screened PT2 equation).
  *   dets  device uint64 [n_det][4], unique, with n_alpha / n_beta electrons;
  *   c     device FP64 [n_det];

@@ -95,6 +95,8 @@ def lib():
         L.shci_pt2_ctx_set_grouping.restype = i
         L.shci_pt2_ctx_set_lanes.argtypes = [p, i]
         L.shci_pt2_ctx_set_lanes.restype = i
+        L.shci_pt2_ctx_set_split_bucket.argtypes = [p, C.c_int64]
+        L.shci_pt2_ctx_set_split_bucket.restype = i
         u64, sz, i32 = C.c_uint64, C.c_size_t, C.c_int32
         L.shci_pt2_workspace_size.argtypes = [p, i, i64, i64, i32, i32, i, C.POINTER(sz)]
         L.shci_pt2_workspace_size.restype = i
@@ -233,6 +235,10 @@ class Context:
     def set_lanes(self, lanes: int):
         """Sample chunks in flight at once with a caller workspace (1 or 2)."""
         _check(lib().shci_pt2_ctx_set_lanes(self._ptr, int(lanes)))
+
+    def set_split_bucket(self, hashes: int):
+        """Hashes per bucket of the singleton split's repeat finder."""
+        _check(lib().shci_pt2_ctx_set_split_bucket(self._ptr, int(hashes)))
 
     def _inputs(self, dets, c):
         nd = c.shape[0]

@@ -145,6 +145,7 @@ struct shci_pt2_ctx : Lane {
   int64_t rec_limit = 0;  // records per pass (0: from device memory)
   int grouping = SHCI_GROUP_AUTO;
   int lanes = 2;                  // sample chunks in flight at once with a caller workspace
+  int64_t split_bucket = HDUP_MEAN;  // hashes a repeat-finder bucket aims at
   Lane lane1;                     // second lane (sample chunks two at a time)
   hipStream_t lane1_stream = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -663,7 +664,8 @@ int find_repeats(Job& J, SplitPlan& SP, HashList& HL, int64_t nent, hipStream_t 
   // calls): the hashes that share a bucket and a tag, which the filter takes
   // as repeated, then depend on the hashes alone.
   const int64_t nreal = std::max<int64_t>(1, J.nrec_all);
-  const int nbits = std::min(30, std::max(1, ceil_log2((uint64_t)((nreal + HDUP_MEAN - 1) / HDUP_MEAN))));
+  const int64_t per = X->split_bucket;
+  const int nbits = std::min(30, std::max(1, ceil_log2((uint64_t)((nreal + per - 1) / per))));
   const int npass = (nbits + 7) / 8;
   const int64_t nbucket = (int64_t)1 << nbits;
   const int64_t ntiles = std::max<int64_t>(1, (nent + PTILE - 1) / PTILE);
@@ -1842,6 +1844,13 @@ int shci_pt2_ctx_set_grouping(shci_pt2_ctx* ctx, int mode) {
   if (mode != SHCI_GROUP_AUTO && mode != SHCI_GROUP_RECORDS && mode != SHCI_GROUP_SPLIT)
     return fail(SHCI_ERR_ARG, "unknown grouping mode");
   ctx->grouping = mode;
+  return SHCI_OK;
+}
+
+int shci_pt2_ctx_set_split_bucket(shci_pt2_ctx* ctx, int64_t hashes) {
+  if (!ctx) return fail(SHCI_ERR_ARG, "ctx is NULL");
+  if (hashes < 64 || hashes > ((int64_t)1 << 24)) return fail(SHCI_ERR_ARG, "bucket size must lie in [64, 2^24]");
+  ctx->split_bucket = hashes;
   return SHCI_OK;
 }
 

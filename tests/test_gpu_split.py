@@ -265,3 +265,39 @@ def test_auto_grouping_by_size():
     out, _, _, st = ctx.sample(dets, c, x.e0, 1e-7, eps2, None, "fp64", **kw)
     assert st["n_singletons"] > 0
     ctx.close()
+
+
+@pytest.mark.parametrize("bucket", [60000, 400000])
+def test_split_large_buckets(bucket):
+    # repeat-finder buckets larger than the threads' registers hold (hashes
+    # read from memory) and with more distinct tags than the shared-memory
+    # table holds (the bucket is taken again in slices): the same counts as
+    # the default buckets and the oracle, E2 within 1e-9 Ha of the oracle and
+    # 1e-12 relative of the default (another set of shared tags, another
+    # order of the sums), the same bits on a repeat
+    x = store.load("w1")
+    ctx, dets, c = context(x)
+    eps2 = x.wl.eps2
+    o = _oracle(x, eps2)
+    r0 = ctx.det(dets, c, x.e0, eps2, "fp64")
+    ctx.set_split_bucket(bucket)
+    r1 = ctx.det(dets, c, x.e0, eps2, "fp64")
+    r2 = ctx.det(dets, c, x.e0, eps2, "fp64")
+    print(f"bucket {bucket}: E2 {r1.e2!r} default {r0.e2!r} oracle {o.e2!r}; singletons "
+          f"{r1.stats['n_singletons']} vs {r0.stats['n_singletons']}, ms split {r1.stats['ms_k_split']:.2f} vs "
+          f"{r0.stats['ms_k_split']:.2f}", flush=True)
+    for k in COUNTS:
+        assert r1.stats[k] == r0.stats[k] == getattr(o, k), k
+    assert r1.stats["n_singletons"] > 0
+    assert abs(r1.e2 - o.e2) <= E2_TOL_FP64
+    assert _rel(r1.e2, r0.e2) <= 1e-12
+    assert r1.e2 == r2.e2
+    kw = dict(seed=11, n_samples=4, n_draws=300)
+    out1, _, _, s1 = ctx.sample(dets, c, x.e0, 1e-7, eps2, None, "fp64", **kw)
+    ctx.set_split_bucket(12500)
+    out0, _, _, s0 = ctx.sample(dets, c, x.e0, 1e-7, eps2, None, "fp64", **kw)
+    assert s1["n_terms"] == s0["n_terms"]
+    assert torch.allclose(out1, out0, rtol=1e-11, atol=1e-15)
+    with pytest.raises(Exception):
+        ctx.set_split_bucket(10)
+    ctx.close()

@@ -80,6 +80,11 @@ def test_w4_deterministic_part_sampled(w4):
     for k in COUNTS:
         assert s.stats[k] == st[k], k
     assert abs(s.e2 - r.e2) <= 1e-9
+    # "auto" splits a deterministic pass of 1e8 kept terms or more: the same
+    # bits as the forced split
+    a = ctx.det(dets, c, x.e0, wl.eps2, "fp64")
+    assert s.stats["n_terms_all"] >= 100_000_000
+    assert a.stats["n_singletons"] == s.stats["n_singletons"] > 0 and a.e2 == s.e2
 
 
 def test_w4_sample_vs_oracle(w4):

@@ -528,12 +528,26 @@ def main():
     # the dominant kernel by its own launch time (the split's figure spans
     # several kernels and, with two lanes, the other lane's kernels)
     dom = max((k for k in ms if rl.get(k) and k != "split"), key=ms.get)
-    if a.lanes > 1 and wl.n_samples:
+    rl_alone = None
+    two_lanes = a.lanes > 1 and wl.n_samples and ws is not None  # lanes need a caller workspace
+    if two_lanes:
         for r in rl.values():
             if r:
                 r["timing"] = ("HIP events around each launch while two sample chunks are in flight: the "
                                "other chunk's kernels share the GPU, so a launch takes longer than alone "
-                               "(the w3 kernel summary under profiles/ has a single-lane trace)")
+                               "(roofline_one_lane: the same figures from one untimed step on one lane)")
+    if two_lanes and steps > 1:
+        # one more step, untimed, with every kernel alone on the GPU: the
+        # kernels' own launch times (not with a single timed step, the
+        # profiling recipe's, whose traces hold the timed step alone)
+        print("bench: one single-lane step (kernel times alone)", file=sys.stderr, flush=True)
+        ctx.set_lanes(1)
+        _, _, run1, avg1 = timed(step, prec_main, 1)
+        ctx.set_lanes(a.lanes)
+        rl_alone, _, _ = kernel_rooflines(wl, run1, avg1, prec_main)
+        for r in rl_alone.values():
+            if r:
+                r["timing"] = "HIP events around each launch, one lane: each kernel alone on the GPU"
     out = {
         "metric": METRIC,
         "value": n_terms / w_main,
@@ -561,6 +575,7 @@ def main():
                    "min_abs_denom": tot["min_abs_denom"], "n_intruder": tot["n_intruder"]},
         "roofline": rl[dom],
         "roofline_kernels": rl,
+        **({"roofline_one_lane": rl_alone[dom], "roofline_kernels_one_lane": rl_alone} if rl_alone else {}),
         "achievable_copy_gbs": copy_gbs,
         "alg_efficiency": {"bytes_per_term": 80.0, "gbs": 80.0 * n_terms / w_main / 1e9,
                            "frac": 80.0 * n_terms / w_main / 1e9 / HBM_PEAK_GBS},
